@@ -1,0 +1,170 @@
+/*
+ * crkfr.h -- C ABI of the MI355X (gfx950) compact Runge-Kutta Flux
+ * Reconstruction step (Babbar & Chen, arXiv 2502.07517).
+ *
+ * One call of crkfr_step advances the nodal solution by one time step of the
+ * time-averaged cRKFR scheme, eq. (crkfr.avg), optionally with the source
+ * average of App. B, eq. (crkfr.source), and with the limiter chain of Sec. 4:
+ * subcell blending, eq. (blended.scheme), with MUSCL-Hancock or first-order
+ * subcells, the flux limiter for admissibility in means (Sec. 4.3), and the
+ * Zhang-Shu scaling limiter (Sec. 3.2).
+ *
+ * Conventions
+ *   - Return codes: 0 = success; negative = error (CRKFR_E*).  After an
+ *     error crkfr_last_error() returns a message (thread-local).
+ *   - Nodal layout everywhere: u[var][ey][ex][q][p], p the x node, q the y
+ *     node, doubles; 1D: u[var][ex][p].  Nodes are the Gauss-Legendre points
+ *     of [0,1] mapped to each element (Sec. 2, eq. soln.points).
+ *   - Host buffers passed in stay owned by the caller and are only read or
+ *     written during the call.  Device buffers the library allocates are
+ *     owned by the solver and freed by crkfr_destroy.
+ *   - Every call is ordered on the stream given to crkfr_create.  Calls that
+ *     return data to the host synchronise that stream; crkfr_step and
+ *     crkfr_advance only enqueue work.
+ *   - No exceptions cross the ABI.  The solver object is not thread-safe.
+ */
+#ifndef CRKFR_H
+#define CRKFR_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CRKFR_OK 0
+#define CRKFR_EINVAL (-1)              /* bad argument or unsupported option */
+#define CRKFR_ENOMEM (-2)              /* device allocation failed */
+#define CRKFR_EHIP (-3)                /* HIP runtime error, text in crkfr_last_error */
+#define CRKFR_EINADMISSIBLE_INPUT (-4) /* set_state: a node violates P_k > 0 */
+#define CRKFR_EINADMISSIBLE_MEAN (-5)  /* last step left an element mean outside U_ad */
+#define CRKFR_ESTATE (-6)              /* call order (e.g. step before set_state) */
+
+/* equations: scalar linear advection u_t + a u_x = 0 (Sec. 5.1.1), 1D Euler
+ * (eq. 1deuler), 2D Euler (eq. 2deuler), ten-moment system (eq. tmp) */
+enum { CRKFR_LINADV1D = 0, CRKFR_EULER1D = 1, CRKFR_EULER2D = 2, CRKFR_TENMOM2D = 3 };
+
+/* boundary kinds (Sec. 3.3): periodic; outflow (ghost values copy the
+ * interior side, so the boundary flux is the interior time-averaged flux, the
+ * paper's rule for fully outflow boundaries); far-field (ghost state fixed to
+ * the boundary traces of the state given to crkfr_set_state, used through the
+ * D2 numerical flux, the paper's inflow rule with a time-constant state) */
+enum { CRKFR_BC_PERIODIC = 0, CRKFR_BC_OUTFLOW = 1, CRKFR_BC_FARFIELD = 2 };
+
+/* arithmetic: FP64 throughout, or FP32 bulk with FP64 element means and
+ * FP64 admissibility roots (the state is held as FP64 means plus FP32
+ * nodal deviations) */
+enum { CRKFR_FP64 = 0, CRKFR_MP32 = 1 };
+
+enum { CRKFR_BLEND_OFF = 0, CRKFR_BLEND_FO = 1, CRKFR_BLEND_MH = 2 };
+
+/* blending coefficient source: the smoothness indicator (Sec. 4), a
+ * constant, a caller-given per-element field, or the learned MLP */
+enum { CRKFR_IND_PAPER = 0, CRKFR_IND_CONST = 1, CRKFR_IND_GIVEN = 2, CRKFR_IND_LEARNED = 3 };
+
+typedef struct {
+    int equation;       /* CRKFR_LINADV1D .. CRKFR_TENMOM2D */
+    int N;              /* polynomial degree, 1..4; the cRK tableau has min(N+1, 4) stages */
+    int nx, ny;         /* elements per direction (ny = 1 in 1D) */
+    int bc[4];          /* x-left, x-right, y-bottom, y-top */
+    int dtype;          /* CRKFR_FP64 or CRKFR_MP32 */
+    double x0, x1, y0, y1;
+    double gamma;       /* Euler: ratio of specific heats */
+    double adv;         /* linear advection speed */
+    double cfl;         /* CFL(N) of eq. time.step.2d; <= 0: the library's Fourier analysis */
+    double cs;          /* safety factor C_s of eq. time.step.2d (paper: 0.98) */
+} crkfr_config;
+
+typedef struct {
+    int blend;          /* CRKFR_BLEND_* */
+    int indicator;      /* CRKFR_IND_* */
+    int smooth_nbr;     /* alpha_e <- max(alpha_e, max over face neighbours alpha / 2) */
+    int flux_limiter;   /* 1: flux limiter for admissibility in means (needs blend != OFF) */
+    int scaling;        /* 1: Zhang-Shu scaling limiter */
+    double alpha_min, alpha_max, alpha_const;
+} crkfr_limiter_opts;
+
+/* ten-moment source (eq. tenmom.source) with the potential
+ * W(x, y) = amp exp(-kappa ((x-xc)^2 + (y-yc)^2)) + gx x + gy y */
+typedef struct {
+    int enabled;
+    double amp, kappa, xc, yc, gx, gy;
+} crkfr_source;
+
+typedef struct {
+    long long n_troubled;          /* elements with alpha_e > 0 */
+    long long n_flux_limited;      /* face points where the flux limiter acted */
+    long long n_lo_inadmissible;   /* face points whose low-order candidate was not admissible */
+    long long n_slope_limited;     /* subcells whose MUSCL-Hancock slope was scaled */
+    long long n_hancock_fallback;  /* subcells that fell back to a zero slope */
+    long long n_scaled;            /* elements changed by the scaling limiter */
+    long long n_mean_inadmissible; /* elements whose mean left the admissible set */
+    double min_theta_flux, min_theta_scale;
+    double t, dt;                  /* time reached and last step size */
+    long long steps;
+} crkfr_diag;
+
+typedef struct crkfr_solver crkfr_solver;
+
+/* Create a solver on the current HIP device, ordered on hip_stream (a
+ * hipStream_t; NULL = the null stream).  Allocates every device buffer the
+ * step needs.  Errors: EINVAL (N outside 1..4, sizes < 1, bad enums),
+ * ENOMEM, EHIP. */
+int crkfr_create(const crkfr_config* cfg, void* hip_stream, crkfr_solver** out);
+void crkfr_destroy(crkfr_solver* s);
+
+/* Limiter options (Sec. 4).  Default: blending off, no limiters. */
+int crkfr_set_limiter(crkfr_solver* s, const crkfr_limiter_opts* opts);
+
+/* Source term (App. B; ten-moment only).  Default: none. */
+int crkfr_set_source(crkfr_solver* s, const crkfr_source* src);
+
+/* Set the nodal state (layout above, nvar*ny*nx*(N+1)^d doubles).  u points
+ * to host memory, or to device memory when on_device = 1.  Also sets t = 0,
+ * computes the element means, the wave-speed rate for eq. time.step.2d and the
+ * far-field ghost states.  Errors: EINADMISSIBLE_INPUT if a node has P_k <= 0. */
+int crkfr_set_state(crkfr_solver* s, const double* u, int on_device);
+
+/* Per-element blending coefficients for CRKFR_IND_GIVEN, [ey][ex] doubles. */
+int crkfr_set_alpha(crkfr_solver* s, const double* alpha, int on_device);
+
+/* Time step of eq. time.step.2d from the current element means (synchronises). */
+int crkfr_compute_dt(crkfr_solver* s, double* dt);
+
+/* One step.  dt > 0: that step size; dt <= 0: the step size of eq.
+ * time.step.2d computed on the device from the current means (no host sync). */
+int crkfr_step(crkfr_solver* s, double dt);
+
+/* Steps with device-computed dt until t_end (last step clipped) or
+ * max_steps; runs the steps as one captured HIP graph per step pair. */
+int crkfr_advance(crkfr_solver* s, double t_end, int max_steps);
+
+/* Read back (synchronise).  get_state writes the nodal state in the layout
+ * above (for MP32 the FP64 sum of mean and deviation); get_means writes
+ * [var][ey][ex]; get_alpha the blending coefficients of the last step. */
+int crkfr_get_state(crkfr_solver* s, double* out, int on_device);
+int crkfr_get_means(crkfr_solver* s, double* out);
+int crkfr_get_alpha(crkfr_solver* s, double* out);
+/* Diagnostics of the last step; returns EINADMISSIBLE_MEAN if it had any. */
+int crkfr_get_diag(crkfr_solver* s, crkfr_diag* out);
+
+/* Number of variables, nodes per element and the CFL number in use. */
+int crkfr_nvar(const crkfr_solver* s);
+int crkfr_nodes_per_element(const crkfr_solver* s);
+double crkfr_cfl_in_use(const crkfr_solver* s);
+
+/* CFL(N) by the library's Fourier analysis of the linear scheme (host only):
+ * the largest lambda dt/dx with spectral radius <= 1 + tol for all wave
+ * numbers; system = 0: wave speed equal to the dissipation speed (scalar
+ * linear flux), system = 1: every ratio of wave to dissipation speed in [0,1]. */
+double crkfr_fourier_cfl(int N, int stages, int system, double tol);
+
+/* Device time per kernel of the last step measured with HIP events (ms):
+ * [0] local cRK, [1] x faces, [2] y faces, [3] update; needs timing = 1. */
+int crkfr_set_timing(crkfr_solver* s, int on);
+int crkfr_get_kernel_times(crkfr_solver* s, float* ms4);
+
+const char* crkfr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

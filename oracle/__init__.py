@@ -1,0 +1,16 @@
+"""Plain FP64 CPU oracle of one cRKFR step (Babbar & Chen, arXiv 2502.07517).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's CPU
+baseline leg use it; the product path never does.  It shares no code with the
+HIP library.  ``crkfr_oracle.c`` holds the arithmetic; this module is ctypes
+marshalling plus the Fourier stability analysis in ``cfl.py``.
+"""
+from .oracle import (  # noqa: F401
+    LINADV1D, EULER1D, EULER2D, TENMOM2D, PERIODIC, OUTFLOW, FARFIELD,
+    BLEND_OFF, BLEND_FO, BLEND_MH, IND_PAPER, IND_CONST, IND_GIVEN,
+    RefConfig, lib, build, gl, diff_matrix, lagrange_at, legendre_orthonormal,
+    tableau, flux, sigma, adm, nvar, nadm, local_crk, indicator_raw,
+    scale_element, compute_dt, step, means, mlp_forward, mlp_loss_grad,
+    boundary_traces, has_farfield,
+)
+from .cfl import cfl_number, amplification_matrix  # noqa: F401

@@ -1,0 +1,103 @@
+/*
+ * crkfr_oracle.h -- plain FP64 CPU oracle for one compact Runge-Kutta Flux
+ * Reconstruction (cRKFR) time step (Babbar & Chen, arXiv 2502.07517).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU
+ * baseline leg of the benchmark may load this library.  It shares no code,
+ * header, table or constant generator with the HIP path.
+ *
+ * Layout of nodal arrays (both 1D and 2D):
+ *     u[var][ey][ex][q][p]      p = x-node (fastest), q = y-node
+ * In 1D, ny = 1 and q takes the single value 0.
+ */
+#ifndef CRKFR_ORACLE_H
+#define CRKFR_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define REF_MAXN 4
+#define REF_MAXND (REF_MAXN + 1)
+#define REF_MAXNP (REF_MAXND * REF_MAXND)
+#define REF_MAXM 6
+
+enum { REF_LINADV1D = 0, REF_EULER1D = 1, REF_EULER2D = 2, REF_TENMOM2D = 3 };
+enum { REF_BC_PERIODIC = 0, REF_BC_OUTFLOW = 1, REF_BC_FARFIELD = 2 };
+enum { REF_BLEND_OFF = 0, REF_BLEND_FO = 1, REF_BLEND_MH = 2 };
+enum { REF_IND_PAPER = 0, REF_IND_CONST = 1, REF_IND_GIVEN = 2 };
+
+typedef struct {
+    int eq, N, nx, ny, stages;
+    int bc[4];            /* x-left, x-right, y-bottom, y-top */
+    int blend, indicator, smooth_nbr, flux_limiter, scaling, source;
+    double x0, x1, y0, y1;
+    double gamma, adv, cfl, cs;
+    double alpha_min, alpha_max, alpha_const;
+    double src_amp, src_kappa, src_xc, src_yc;   /* W = A exp(-kappa r^2) + gx x + gy y */
+    double src_gx, src_gy;
+} ref_config;
+
+typedef struct {
+    long n_troubled;          /* elements with alpha_e > 0 */
+    long n_flux_limited;      /* face points where theta < 1 */
+    long n_lo_inadmissible;   /* face points whose low-order candidate failed */
+    long n_slope_limited;     /* subcells whose MH slope was scaled */
+    long n_hancock_fallback;  /* subcells that fell back to zero slope */
+    long n_scaled;            /* elements where the scaling limiter acted */
+    long n_mean_inadmissible; /* elements whose mean left the admissible set */
+    double min_theta_flux, min_theta_scale;
+} ref_diag;
+
+/* reference element on [0,1] */
+void ref_gl(int N, double* xi, double* w);
+void ref_lagrange_at(int N, const double* xi, double x, double* l);
+void ref_diff_matrix(int N, const double* xi, double* D);
+void ref_legendre_orthonormal(int N, const double* xi, double* L); /* L[k*(N+1)+p] = L_k(xi_p) */
+void ref_tableau(int s, double* a /*4x4*/, double* b /*4*/, double* c /*4*/);
+
+/* physics (exposed for pins) */
+int ref_nvar(int eq);
+int ref_nadm(int eq);
+void ref_flux(int eq, double gamma, double adv, const double* u, double* f, double* g);
+void ref_sigma(int eq, double gamma, double adv, const double* u, double* sx, double* sy);
+double ref_adm(int eq, int k, double gamma, const double* u);
+
+/* local cRK on one element: time averages at the nodes (eq. disc.avg.flux,
+ * time.avg.sol and the source averages of the source-term appendix). */
+void ref_local_crk(const ref_config* c, const double* ue /*[var][q][p]*/, double dt,
+                   double xe0, double ye0, double* F, double* G, double* U, double* S);
+
+/* smoothness indicator of one element (raw, before neighbour smoothing) */
+double ref_indicator_raw(const ref_config* c, const double* ue, double* energy_out);
+
+/* Zhang-Shu scaling of one element in place; returns theta (min over constraints) */
+double ref_scale_element(const ref_config* c, double* ue, int* mean_bad);
+
+/* time step from the element means, eq. time.step.2d */
+double ref_compute_dt(const ref_config* c, const double* u);
+
+/* boundary traces of u at every boundary face point, the ghost states of
+ * far-field boundaries: x-left [ny][N+1][M], x-right [ny][N+1][M],
+ * y-bottom [nx][N+1][M], y-top [nx][N+1][M], concatenated (1D: one point per side) */
+void ref_boundary_traces(const ref_config* c, const double* u, double* ghost);
+
+/* one full step; alpha_given used when indicator == GIVEN; alpha_out (optional)
+ * receives the final blending coefficient per element; ghost (far-field
+ * boundaries only) as written by ref_boundary_traces. */
+int ref_step(const ref_config* c, const double* u_in, double* u_out, double dt,
+             const double* alpha_given, double* alpha_out, ref_diag* diag, const double* ghost);
+
+/* element means [var][ey][ex] */
+void ref_means(const ref_config* c, const double* u, double* ubar);
+
+/* small MLP for the learned indicator: layers 0..nl-1, sizes dims[0..nl] */
+void ref_mlp_forward(int nl, const int* dims, const double* params, int nrows,
+                     const double* x, double* y, double* acts);
+double ref_mlp_loss_grad(int nl, const int* dims, const double* params, int nrows,
+                         const double* x, const double* target, double* grad);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

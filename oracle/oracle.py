@@ -1,0 +1,261 @@
+"""ctypes marshalling for the FP64 CPU oracle (test infrastructure only)."""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+LINADV1D, EULER1D, EULER2D, TENMOM2D = 0, 1, 2, 3
+PERIODIC, OUTFLOW, FARFIELD = 0, 1, 2
+BLEND_OFF, BLEND_FO, BLEND_MH = 0, 1, 2
+IND_PAPER, IND_CONST, IND_GIVEN = 0, 1, 2
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "crkfr_oracle.c")
+_SO = os.path.join(_HERE, "liboracle.so")
+
+
+def build(force=True):
+    """Compile the oracle with gcc: -O3, OpenMP, no fast-math."""
+    if force or not os.path.exists(_SO):
+        cmd = ["gcc", "-O3", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-D_GNU_SOURCE",
+               "-Wall", "-Wno-unused-function", "-o", _SO, _SRC, "-lm"]
+        subprocess.check_call(cmd)
+    return _SO
+
+
+class RefConfig(ctypes.Structure):
+    _fields_ = [
+        ("eq", ctypes.c_int), ("N", ctypes.c_int), ("nx", ctypes.c_int), ("ny", ctypes.c_int),
+        ("stages", ctypes.c_int), ("bc", ctypes.c_int * 4),
+        ("blend", ctypes.c_int), ("indicator", ctypes.c_int), ("smooth_nbr", ctypes.c_int),
+        ("flux_limiter", ctypes.c_int), ("scaling", ctypes.c_int), ("source", ctypes.c_int),
+        ("x0", ctypes.c_double), ("x1", ctypes.c_double), ("y0", ctypes.c_double), ("y1", ctypes.c_double),
+        ("gamma", ctypes.c_double), ("adv", ctypes.c_double), ("cfl", ctypes.c_double), ("cs", ctypes.c_double),
+        ("alpha_min", ctypes.c_double), ("alpha_max", ctypes.c_double), ("alpha_const", ctypes.c_double),
+        ("src_amp", ctypes.c_double), ("src_kappa", ctypes.c_double),
+        ("src_xc", ctypes.c_double), ("src_yc", ctypes.c_double),
+        ("src_gx", ctypes.c_double), ("src_gy", ctypes.c_double),
+    ]
+
+    @staticmethod
+    def make(eq, N, nx, ny=1, *, stages=None, bc=(PERIODIC,) * 4, blend=BLEND_OFF,
+             indicator=IND_PAPER, smooth_nbr=1, flux_limiter=0, scaling=0, source=0,
+             domain=(0.0, 1.0, 0.0, 1.0), gamma=1.4, adv=1.0, cfl=0.0, cs=0.98,
+             alpha_min=1e-3, alpha_max=1.0, alpha_const=0.0,
+             src=(0.0, 0.0, 0.0, 0.0), src_lin=(0.0, 0.0)):
+        c = RefConfig()
+        c.eq, c.N, c.nx, c.ny = eq, N, nx, ny
+        c.stages = stages if stages is not None else min(N + 1, 4)
+        for i in range(4):
+            c.bc[i] = bc[i]
+        c.blend, c.indicator, c.smooth_nbr = blend, indicator, smooth_nbr
+        c.flux_limiter, c.scaling, c.source = flux_limiter, scaling, source
+        c.x0, c.x1, c.y0, c.y1 = domain
+        c.gamma, c.adv, c.cfl, c.cs = gamma, adv, cfl, cs
+        c.alpha_min, c.alpha_max, c.alpha_const = alpha_min, alpha_max, alpha_const
+        c.src_amp, c.src_kappa, c.src_xc, c.src_yc = src
+        c.src_gx, c.src_gy = src_lin
+        return c
+
+
+class RefDiag(ctypes.Structure):
+    _fields_ = [
+        ("n_troubled", ctypes.c_long), ("n_flux_limited", ctypes.c_long),
+        ("n_lo_inadmissible", ctypes.c_long), ("n_slope_limited", ctypes.c_long),
+        ("n_hancock_fallback", ctypes.c_long), ("n_scaled", ctypes.c_long),
+        ("n_mean_inadmissible", ctypes.c_long),
+        ("min_theta_flux", ctypes.c_double), ("min_theta_scale", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+            build()
+        L = ctypes.CDLL(_SO)
+        dp = ctypes.POINTER(ctypes.c_double)
+        cp = ctypes.POINTER(RefConfig)
+        L.ref_gl.argtypes = [ctypes.c_int, dp, dp]
+        L.ref_lagrange_at.argtypes = [ctypes.c_int, dp, ctypes.c_double, dp]
+        L.ref_diff_matrix.argtypes = [ctypes.c_int, dp, dp]
+        L.ref_legendre_orthonormal.argtypes = [ctypes.c_int, dp, dp]
+        L.ref_tableau.argtypes = [ctypes.c_int, dp, dp, dp]
+        L.ref_nvar.argtypes = [ctypes.c_int]
+        L.ref_nadm.argtypes = [ctypes.c_int]
+        L.ref_flux.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, dp, dp, dp]
+        L.ref_sigma.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, dp, dp, dp]
+        L.ref_adm.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, dp]
+        L.ref_adm.restype = ctypes.c_double
+        L.ref_local_crk.argtypes = [cp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp, dp, dp, dp]
+        L.ref_indicator_raw.argtypes = [cp, dp, dp]
+        L.ref_indicator_raw.restype = ctypes.c_double
+        L.ref_scale_element.argtypes = [cp, dp, ctypes.POINTER(ctypes.c_int)]
+        L.ref_scale_element.restype = ctypes.c_double
+        L.ref_compute_dt.argtypes = [cp, dp]
+        L.ref_compute_dt.restype = ctypes.c_double
+        L.ref_step.argtypes = [cp, dp, dp, ctypes.c_double, dp, dp, ctypes.POINTER(RefDiag), dp]
+        L.ref_boundary_traces.argtypes = [cp, dp, dp]
+        L.ref_means.argtypes = [cp, dp, dp]
+        ip = ctypes.POINTER(ctypes.c_int)
+        L.ref_mlp_forward.argtypes = [ctypes.c_int, ip, dp, ctypes.c_int, dp, dp, dp]
+        L.ref_mlp_loss_grad.argtypes = [ctypes.c_int, ip, dp, ctypes.c_int, dp, dp, dp]
+        L.ref_mlp_loss_grad.restype = ctypes.c_double
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def gl(N):
+    xi, w = np.zeros(N + 1), np.zeros(N + 1)
+    lib().ref_gl(N, _p(xi), _p(w))
+    return xi, w
+
+
+def lagrange_at(N, xi, x):
+    l = np.zeros(N + 1)
+    lib().ref_lagrange_at(N, _p(_f64(xi)), float(x), _p(l))
+    return l
+
+
+def diff_matrix(N, xi):
+    D = np.zeros((N + 1, N + 1))
+    lib().ref_diff_matrix(N, _p(_f64(xi)), _p(D))
+    return D
+
+
+def legendre_orthonormal(N, xi):
+    L = np.zeros((N + 1, N + 1))
+    lib().ref_legendre_orthonormal(N, _p(_f64(xi)), _p(L))
+    return L
+
+
+def tableau(s):
+    a, b, c = np.zeros((4, 4)), np.zeros(4), np.zeros(4)
+    lib().ref_tableau(s, _p(a), _p(b), _p(c))
+    return a[:s, :s].copy(), b[:s].copy(), c[:s].copy()
+
+
+def nvar(eq):
+    return lib().ref_nvar(eq)
+
+
+def nadm(eq):
+    return lib().ref_nadm(eq)
+
+
+def flux(eq, u, gamma=1.4, adv=1.0):
+    u = _f64(u)
+    f, g = np.zeros(6), np.zeros(6)
+    lib().ref_flux(eq, gamma, adv, _p(u), _p(f), _p(g))
+    M = nvar(eq)
+    return f[:M], g[:M]
+
+
+def sigma(eq, u, gamma=1.4, adv=1.0):
+    sx, sy = ctypes.c_double(), ctypes.c_double()
+    lib().ref_sigma(eq, gamma, adv, _p(_f64(u)), ctypes.byref(sx), ctypes.byref(sy))
+    return sx.value, sy.value
+
+
+def adm(eq, k, u, gamma=1.4):
+    return lib().ref_adm(eq, k, gamma, _p(_f64(u)))
+
+
+def _np(cfg):
+    nd = cfg.N + 1
+    return nd * nd if cfg.eq >= EULER2D else nd
+
+
+def local_crk(cfg, ue, dt, xe0=0.0, ye0=0.0):
+    M, npn = nvar(cfg.eq), _np(cfg)
+    ue = _f64(ue).reshape(M, npn)
+    F, G, U, S = (np.zeros((M, npn)) for _ in range(4))
+    lib().ref_local_crk(ctypes.byref(cfg), _p(ue), dt, xe0, ye0, _p(F), _p(G), _p(U), _p(S))
+    return F, G, U, S
+
+
+def indicator_raw(cfg, ue):
+    e = np.zeros(cfg.N + 1)
+    a = lib().ref_indicator_raw(ctypes.byref(cfg), _p(_f64(ue)), _p(e))
+    return a, e
+
+
+def scale_element(cfg, ue):
+    ue = _f64(ue).copy()
+    bad = ctypes.c_int()
+    th = lib().ref_scale_element(ctypes.byref(cfg), _p(ue), ctypes.byref(bad))
+    return ue, th, bool(bad.value)
+
+
+def compute_dt(cfg, u):
+    return lib().ref_compute_dt(ctypes.byref(cfg), _p(_f64(u)))
+
+
+def means(cfg, u):
+    M = nvar(cfg.eq)
+    ub = np.zeros((M, cfg.ny, cfg.nx))
+    lib().ref_means(ctypes.byref(cfg), _p(_f64(u)), _p(ub))
+    return ub
+
+
+def boundary_traces(cfg, u):
+    """Ghost states of far-field boundaries: the boundary traces of u."""
+    M, nd = nvar(cfg.eq), cfg.N + 1
+    nq = nd if cfg.eq >= EULER2D else 1
+    n = 2 * cfg.ny * nq * M + (2 * cfg.nx * nd * M if cfg.eq >= EULER2D else 0)
+    g = np.zeros(n)
+    lib().ref_boundary_traces(ctypes.byref(cfg), _p(_f64(u)), _p(g))
+    return g
+
+
+def has_farfield(cfg):
+    return any(cfg.bc[i] == FARFIELD for i in range(4))
+
+
+def step(cfg, u, dt, alpha_given=None, ghost=None):
+    """One cRKFR step; returns (u_new, alpha, diag dict, status)."""
+    u = _f64(u)
+    out = np.empty_like(u)
+    ne = cfg.nx * cfg.ny
+    alpha = np.zeros(ne)
+    ag = _f64(alpha_given).reshape(ne) if alpha_given is not None else np.zeros(ne)
+    if has_farfield(cfg) and ghost is None:
+        raise ValueError("far-field boundaries need the ghost states (boundary_traces of the initial state)")
+    gp = _p(_f64(ghost)) if ghost is not None else None
+    d = RefDiag()
+    st = lib().ref_step(ctypes.byref(cfg), _p(u), _p(out), float(dt), _p(ag), _p(alpha), ctypes.byref(d), gp)
+    return out, alpha, d.as_dict(), st
+
+
+def mlp_forward(dims, params, x):
+    dims_c = (ctypes.c_int * len(dims))(*dims)
+    x = _f64(x)
+    n = x.shape[0]
+    y = np.zeros(n)
+    lib().ref_mlp_forward(len(dims) - 1, dims_c, _p(_f64(params)), n, _p(x), _p(y), None)
+    return y
+
+
+def mlp_loss_grad(dims, params, x, target):
+    dims_c = (ctypes.c_int * len(dims))(*dims)
+    params = _f64(params)
+    x = _f64(x)
+    g = np.zeros_like(params)
+    loss = lib().ref_mlp_loss_grad(len(dims) - 1, dims_c, _p(params), x.shape[0], _p(x),
+                                   _p(_f64(target)), _p(g))
+    return loss, g

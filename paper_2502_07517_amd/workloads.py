@@ -1,0 +1,223 @@
+"""Seeded synthetic inputs for the cRKFR step: initial conditions sampled at
+the Gauss-Legendre solution points (collocation).
+
+This module holds no arithmetic of the method.  It only draws seeded problem
+data and samples analytic initial conditions at node positions, which it takes
+from numpy's Gauss-Legendre rule.  Both the oracle tests and the HIP path read
+their inputs from here.
+
+Node layout of every returned array: ``u[var][ey][ex][q][p]`` (1D: ``u[var][ex][p]``),
+p the x-node, q the y-node.
+"""
+import numpy as np
+
+GAMMA = 1.4
+
+
+def gl_nodes(N):
+    """Gauss-Legendre nodes on [0, 1] from numpy's rule."""
+    x, _ = np.polynomial.legendre.leggauss(N + 1)
+    return 0.5 * (x + 1.0)
+
+
+def node_coords_1d(nx, N, x0, x1):
+    xi = gl_nodes(N)
+    dx = (x1 - x0) / nx
+    return x0 + (np.arange(nx)[:, None] + xi[None, :]) * dx          # [ex][p]
+
+
+def node_coords_2d(nx, ny, N, dom):
+    x0, x1, y0, y1 = dom
+    xi = gl_nodes(N)
+    dx, dy = (x1 - x0) / nx, (y1 - y0) / ny
+    X = x0 + (np.arange(nx)[None, :, None, None] + xi[None, None, None, :]) * dx
+    Y = y0 + (np.arange(ny)[:, None, None, None] + xi[None, None, :, None]) * dy
+    shape = (ny, nx, N + 1, N + 1)
+    return np.broadcast_to(X, shape).copy(), np.broadcast_to(Y, shape).copy()   # [ey][ex][q][p]
+
+
+# ---------------------------------------------------------------- 1D scalar
+def linadv_modes(seed, nx, N, t=0.0, adv=1.0):
+    """u0 = sin(2 pi x) + sum_{k=1..4} a_k sin(2 pi k x + phi_k) on periodic [0,1],
+    a_k ~ U[0, 0.1], phi_k ~ U[0, 2 pi); exact solution is u0(x - adv t)."""
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(0.0, 0.1, 4)
+    ph = rng.uniform(0.0, 2.0 * np.pi, 4)
+    x = node_coords_1d(nx, N, 0.0, 1.0) - adv * t
+    u = np.sin(2 * np.pi * x)
+    for k in range(4):
+        u = u + a[k] * np.sin(2 * np.pi * (k + 1) * x + ph[k])
+    return u[None].copy()
+
+
+# ---------------------------------------------------------------- Euler helpers
+def euler1d_cons(rho, v, p, gamma=GAMMA):
+    return np.stack([rho, rho * v, p / (gamma - 1.0) + 0.5 * rho * v * v])
+
+
+def euler2d_cons(rho, v1, v2, p, gamma=GAMMA):
+    return np.stack([rho, rho * v1, rho * v2, p / (gamma - 1.0) + 0.5 * rho * (v1 * v1 + v2 * v2)])
+
+
+def tenmom_cons(rho, v1, v2, p11, p12, p22):
+    return np.stack([rho, rho * v1, rho * v2,
+                     0.5 * p11 + 0.5 * rho * v1 * v1,
+                     0.5 * p12 + 0.5 * rho * v1 * v2,
+                     0.5 * p22 + 0.5 * rho * v2 * v2])
+
+
+def riemann_states_1d(seed):
+    """Left/right (rho, v, p) with rho ~ U[0.1,2], v ~ U[-1,1], p ~ U[0.1,2]."""
+    rng = np.random.default_rng(seed)
+    L = (rng.uniform(0.1, 2.0), rng.uniform(-1.0, 1.0), rng.uniform(0.1, 2.0))
+    R = (rng.uniform(0.1, 2.0), rng.uniform(-1.0, 1.0), rng.uniform(0.1, 2.0))
+    return L, R
+
+
+# Discontinuities are placed 0.37 of an element off the element faces, so the
+# smoothness indicator sees them at t = 0 (a jump on a face leaves every element
+# constant and the first step unlimited).
+OFF_FACE = 0.37
+
+
+def euler1d_riemann(seed, nx, N, x0=0.0, x1=1.0, xs=None, gamma=GAMMA):
+    """Seeded Riemann data, jump at xs (default: domain centre + 0.37 dx)."""
+    if xs is None:
+        xs = 0.5 * (x0 + x1) + OFF_FACE * (x1 - x0) / nx
+    (rl, vl, pl), (rr, vr, pr) = riemann_states_1d(seed)
+    x = node_coords_1d(nx, N, x0, x1)
+    left = x < xs
+    rho = np.where(left, rl, rr)
+    v = np.where(left, vl, vr)
+    p = np.where(left, pl, pr)
+    return euler1d_cons(rho, v, p, gamma)
+
+
+# ---------------------------------------------------------------- 2D Euler
+def vortex_prim(X, Y, t=0.0, dom=(-5.0, 5.0, -5.0, 5.0), beta=5.0, mach=0.5,
+                angle_deg=45.0, gamma=GAMMA):
+    """Isentropic vortex (Sec. 5.3.1): exact solution at time t is the initial
+    data translated by (u0, v0) t, wrapped periodically on the domain."""
+    a = np.deg2rad(angle_deg)
+    u0, v0 = mach * np.cos(a), mach * np.sin(a)
+    x0, x1, y0, y1 = dom
+    Lx, Ly = x1 - x0, y1 - y0
+    xs = np.mod(X - u0 * t - x0, Lx) + x0
+    ys = np.mod(Y - v0 * t - y0, Ly) + y0
+    r2 = xs * xs + ys * ys
+    rho = (1.0 - beta ** 2 * (gamma - 1.0) / (8.0 * gamma * np.pi ** 2) * np.exp(1.0 - r2)) ** (1.0 / (gamma - 1.0))
+    v1 = u0 - beta * ys / (2 * np.pi) * np.exp(0.5 * (1.0 - r2))
+    v2 = v0 + beta * xs / (2 * np.pi) * np.exp(0.5 * (1.0 - r2))
+    p = rho ** gamma
+    return rho, v1, v2, p
+
+
+def vortex2d(n, N, t=0.0, dom=(-5.0, 5.0, -5.0, 5.0), gamma=GAMMA):
+    X, Y = node_coords_2d(n, n, N, dom)
+    rho, v1, v2, p = vortex_prim(X, Y, t, dom, gamma=gamma)
+    return euler2d_cons(rho, v1, v2, p, gamma)
+
+
+def quadrant_states_euler(seed, rho_rng=(0.1, 2.0), v_rng=(-1.0, 1.0), p_rng=(0.1, 2.0)):
+    rng = np.random.default_rng(seed)
+    return [(rng.uniform(*rho_rng), rng.uniform(*v_rng), rng.uniform(*v_rng), rng.uniform(*p_rng))
+            for _ in range(4)]
+
+
+def _quadrant_fill(X, Y, xs, ys, states):
+    q = (X >= xs).astype(int) + 2 * (Y >= ys).astype(int)   # 0: SW, 1: SE, 2: NW, 3: NE
+    cols = []
+    for c in range(len(states[0])):
+        vals = np.array([s[c] for s in states])
+        cols.append(vals[q])
+    return cols
+
+
+def _split(dom, nx, ny, split):
+    if split is not None:
+        return split
+    return (0.5 * (dom[0] + dom[1]) + OFF_FACE * (dom[1] - dom[0]) / nx,
+            0.5 * (dom[2] + dom[3]) + OFF_FACE * (dom[3] - dom[2]) / ny)
+
+
+def euler2d_quadrants(seed, n, N, dom=(0.0, 1.0, 0.0, 1.0), gamma=GAMMA, states=None, split=None):
+    """Seeded 4-quadrant Riemann data, split lines at the domain centre + 0.37 h."""
+    X, Y = node_coords_2d(n, n, N, dom)
+    st = states if states is not None else quadrant_states_euler(seed)
+    xs, ys = _split(dom, n, n, split)
+    rho, v1, v2, p = _quadrant_fill(X, Y, xs, ys, st)
+    return euler2d_cons(rho, v1, v2, p, gamma)
+
+
+# Lax-Liu configuration 12 as printed in Sec. 5.3.2, ordered SW, SE, NW, NE
+RIEMANN2D_CFG12 = [(0.8, 0.0, 0.0, 1.0), (1.0, 0.0, 0.7276, 1.0),
+                   (1.0, 0.7276, 0.0, 1.0), (0.5313, 0.0, 0.0, 0.4)]
+
+
+def euler2d_smooth_periodic(seed, n, N, dom=(0.0, 1.0, 0.0, 1.0), amp=0.2, gamma=GAMMA):
+    """Smooth positive periodic data with seeded low Fourier modes."""
+    rng = np.random.default_rng(seed)
+    X, Y = node_coords_2d(n, n, N, dom)
+    Lx, Ly = dom[1] - dom[0], dom[3] - dom[2]
+    cols = []
+    for base in (1.0, 0.3, -0.2, 1.0):
+        f = np.full(X.shape, base)
+        for _ in range(3):
+            kx, ky = rng.integers(0, 3, 2)
+            ph = rng.uniform(0, 2 * np.pi)
+            f = f + amp * rng.uniform(0.2, 1.0) * np.sin(2 * np.pi * (kx * X / Lx + ky * Y / Ly) + ph)
+        cols.append(f)
+    rho, v1, v2, p = cols
+    rho = np.abs(rho) + 0.3
+    p = np.abs(p) + 0.3
+    return euler2d_cons(rho, v1, v2, p, gamma)
+
+
+# ---------------------------------------------------------------- ten-moment
+def tenmom_quadrant_states(seed):
+    """rho ~ U[0.5,2], v_i ~ U[-1,1], p11, p22 ~ U[0.5,2], p12 = r sqrt(p11 p22), r ~ U[-0.8,0.8]."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(4):
+        rho = rng.uniform(0.5, 2.0)
+        v1, v2 = rng.uniform(-1.0, 1.0, 2)
+        p11, p22 = rng.uniform(0.5, 2.0, 2)
+        r = rng.uniform(-0.8, 0.8)
+        out.append((rho, v1, v2, p11, r * np.sqrt(p11 * p22), p22))
+    return out
+
+
+def tenmom2d_quadrants(seed, nx, ny, N, dom=(-2.0, 2.0, -0.5, 0.5), split=None):
+    X, Y = node_coords_2d(nx, ny, N, dom)
+    st = tenmom_quadrant_states(seed)
+    xs, ys = _split(dom, nx, ny, split)
+    rho, v1, v2, p11, p12, p22 = _quadrant_fill(X, Y, xs, ys, st)
+    return tenmom_cons(rho, v1, v2, p11, p12, p22)
+
+
+def tenmom2d_smooth(seed, nx, ny, N, dom=(-2.0, 2.0, -0.5, 0.5), amp=0.1):
+    rng = np.random.default_rng(seed)
+    X, Y = node_coords_2d(nx, ny, N, dom)
+    Lx, Ly = dom[1] - dom[0], dom[3] - dom[2]
+
+    def field(base):
+        f = np.full(X.shape, base)
+        for _ in range(2):
+            kx, ky = rng.integers(0, 3, 2)
+            f = f + amp * np.sin(2 * np.pi * (kx * X / Lx + ky * Y / Ly) + rng.uniform(0, 2 * np.pi))
+        return f
+
+    rho, v1, v2 = field(1.0), field(0.2), field(-0.1)
+    p11, p22, p12 = field(1.0), field(0.8), field(0.1)
+    return tenmom_cons(rho, v1, v2, p11, p12, p22)
+
+
+def batch_instances(seed, count, sides=(64, 512), degrees=(2, 3, 4)):
+    """Seeded draw of uneven instances: grid side n ~ U{sides}, N ~ U{degrees}, states per quadrant."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        n = int(rng.integers(sides[0], sides[1] + 1))
+        N = int(rng.choice(degrees))
+        out.append({"n": n, "N": N, "seed": int(rng.integers(0, 2 ** 31 - 1))})
+    return out
