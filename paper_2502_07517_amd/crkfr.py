@@ -1,0 +1,246 @@
+"""Thin ctypes binding of libcrkfr.so (include/crkfr.h): argument marshalling
+only; every step of the scheme runs in the library's HIP kernels.
+
+Arrays may be numpy (host) or torch CUDA tensors (device pointers are passed
+through); torch is used only for device memory and streams.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+LINADV1D, EULER1D, EULER2D, TENMOM2D = 0, 1, 2, 3
+PERIODIC, OUTFLOW, FARFIELD = 0, 1, 2
+FP64, MP32 = 0, 1
+BLEND_OFF, BLEND_FO, BLEND_MH = 0, 1, 2
+IND_PAPER, IND_CONST, IND_GIVEN, IND_LEARNED = 0, 1, 2, 3
+NVAR = {LINADV1D: 1, EULER1D: 3, EULER2D: 4, TENMOM2D: 6}
+EINADMISSIBLE_MEAN = -5
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcrkfr.so")
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("equation", ctypes.c_int), ("N", ctypes.c_int), ("nx", ctypes.c_int), ("ny", ctypes.c_int),
+                ("bc", ctypes.c_int * 4), ("dtype", ctypes.c_int),
+                ("x0", ctypes.c_double), ("x1", ctypes.c_double), ("y0", ctypes.c_double), ("y1", ctypes.c_double),
+                ("gamma", ctypes.c_double), ("adv", ctypes.c_double), ("cfl", ctypes.c_double), ("cs", ctypes.c_double)]
+
+
+class LimiterOpts(ctypes.Structure):
+    _fields_ = [("blend", ctypes.c_int), ("indicator", ctypes.c_int), ("smooth_nbr", ctypes.c_int),
+                ("flux_limiter", ctypes.c_int), ("scaling", ctypes.c_int),
+                ("alpha_min", ctypes.c_double), ("alpha_max", ctypes.c_double), ("alpha_const", ctypes.c_double)]
+
+
+class Source(ctypes.Structure):
+    _fields_ = [("enabled", ctypes.c_int), ("amp", ctypes.c_double), ("kappa", ctypes.c_double),
+                ("xc", ctypes.c_double), ("yc", ctypes.c_double), ("gx", ctypes.c_double), ("gy", ctypes.c_double)]
+
+
+class Diag(ctypes.Structure):
+    _fields_ = [("n_troubled", ctypes.c_longlong), ("n_flux_limited", ctypes.c_longlong),
+                ("n_lo_inadmissible", ctypes.c_longlong), ("n_slope_limited", ctypes.c_longlong),
+                ("n_hancock_fallback", ctypes.c_longlong), ("n_scaled", ctypes.c_longlong),
+                ("n_mean_inadmissible", ctypes.c_longlong),
+                ("min_theta_flux", ctypes.c_double), ("min_theta_scale", ctypes.c_double),
+                ("t", ctypes.c_double), ("dt", ctypes.c_double), ("steps", ctypes.c_longlong)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+SYMBOLS = ["crkfr_create", "crkfr_destroy", "crkfr_set_limiter", "crkfr_set_source", "crkfr_set_state",
+           "crkfr_set_alpha", "crkfr_compute_dt", "crkfr_step", "crkfr_advance", "crkfr_get_state",
+           "crkfr_get_means", "crkfr_get_alpha", "crkfr_get_diag", "crkfr_nvar", "crkfr_nodes_per_element",
+           "crkfr_cfl_in_use", "crkfr_fourier_cfl", "crkfr_set_timing", "crkfr_get_kernel_times",
+           "crkfr_last_error"]
+
+_lib = None
+
+
+def lib():
+    """Load libcrkfr.so; fails loudly when the HIP library was not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} missing: build it with paper_2502_07517_amd/build.py")
+        # torch ships a HIP runtime with the same soname as /opt/rocm's; loading
+        # torch first makes the library bind to that one runtime, so device
+        # pointers and streams are shared (loading it second would map a
+        # second runtime into the process)
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        L = ctypes.CDLL(LIB_PATH)
+        vp, dp, ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int
+        L.crkfr_create.argtypes = [ctypes.POINTER(Config), vp, ctypes.POINTER(vp)]
+        L.crkfr_destroy.argtypes = [vp]
+        L.crkfr_destroy.restype = None
+        L.crkfr_set_limiter.argtypes = [vp, ctypes.POINTER(LimiterOpts)]
+        L.crkfr_set_source.argtypes = [vp, ctypes.POINTER(Source)]
+        L.crkfr_set_state.argtypes = [vp, vp, ip]
+        L.crkfr_set_alpha.argtypes = [vp, vp, ip]
+        L.crkfr_compute_dt.argtypes = [vp, dp]
+        L.crkfr_step.argtypes = [vp, ctypes.c_double]
+        L.crkfr_advance.argtypes = [vp, ctypes.c_double, ip]
+        L.crkfr_get_state.argtypes = [vp, vp, ip]
+        L.crkfr_get_means.argtypes = [vp, vp]
+        L.crkfr_get_alpha.argtypes = [vp, vp]
+        L.crkfr_get_diag.argtypes = [vp, ctypes.POINTER(Diag)]
+        L.crkfr_nvar.argtypes = [vp]
+        L.crkfr_nodes_per_element.argtypes = [vp]
+        L.crkfr_cfl_in_use.argtypes = [vp]
+        L.crkfr_cfl_in_use.restype = ctypes.c_double
+        L.crkfr_fourier_cfl.argtypes = [ip, ip, ip, ctypes.c_double]
+        L.crkfr_fourier_cfl.restype = ctypes.c_double
+        L.crkfr_set_timing.argtypes = [vp, ip]
+        L.crkfr_get_kernel_times.argtypes = [vp, ctypes.POINTER(ctypes.c_float)]
+        L.crkfr_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+class CrkfrError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"crkfr error {code}: {msg}")
+        self.code = code
+
+
+def _check(rc):
+    if rc != 0:
+        raise CrkfrError(rc, lib().crkfr_last_error().decode())
+    return rc
+
+
+def _ptr(a):
+    """(pointer, on_device) of a numpy array or a torch tensor."""
+    if hasattr(a, "data_ptr"):
+        return ctypes.c_void_p(a.data_ptr()), int(a.is_cuda)
+    return ctypes.c_void_p(a.ctypes.data), 0
+
+
+def fourier_cfl(N, stages=0, system=1, tol=1e-10):
+    return lib().crkfr_fourier_cfl(N, stages, system, tol)
+
+
+class Solver:
+    """One cRKFR solver on the current HIP device (see include/crkfr.h)."""
+
+    def __init__(self, equation, N, nx, ny=1, *, bc=(PERIODIC,) * 4, dtype=FP64,
+                 domain=(0.0, 1.0, 0.0, 1.0), gamma=1.4, adv=1.0, cfl=0.0, cs=0.98, stream=None):
+        c = Config()
+        c.equation, c.N, c.nx, c.ny = equation, N, nx, ny
+        for i in range(4):
+            c.bc[i] = bc[i]
+        c.dtype = dtype
+        c.x0, c.x1, c.y0, c.y1 = domain
+        c.gamma, c.adv, c.cfl, c.cs = gamma, adv, cfl, cs
+        self.cfg = c
+        self.M = NVAR[equation]
+        self.dim = 2 if equation >= EULER2D else 1
+        self.np = (N + 1) ** self.dim
+        self.ne = nx * ny
+        h = ctypes.c_void_p()
+        st = ctypes.c_void_p(stream) if stream is not None else None
+        _check(lib().crkfr_create(ctypes.byref(c), st, ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().crkfr_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def shape(self):
+        N1 = self.cfg.N + 1
+        if self.dim == 2:
+            return (self.M, self.cfg.ny, self.cfg.nx, N1, N1)
+        return (self.M, self.cfg.nx, N1)
+
+    def set_limiter(self, blend=BLEND_OFF, indicator=IND_PAPER, smooth_nbr=1, flux_limiter=0, scaling=0,
+                    alpha_min=1e-3, alpha_max=1.0, alpha_const=0.0):
+        o = LimiterOpts(blend, indicator, smooth_nbr, flux_limiter, scaling, alpha_min, alpha_max, alpha_const)
+        _check(lib().crkfr_set_limiter(self.h, ctypes.byref(o)))
+
+    def set_source(self, enabled=1, amp=0.0, kappa=0.0, xc=0.0, yc=0.0, gx=0.0, gy=0.0):
+        s = Source(enabled, amp, kappa, xc, yc, gx, gy)
+        _check(lib().crkfr_set_source(self.h, ctypes.byref(s)))
+
+    def _check_array(self, u, n):
+        if hasattr(u, "data_ptr"):
+            import torch
+            if u.dtype != torch.float64 or not u.is_contiguous() or u.numel() != n:
+                raise ValueError(f"expected a contiguous float64 tensor of {n} values")
+            return u
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        if u.size != n:
+            raise ValueError(f"expected {n} values, got {u.size}")
+        return u
+
+    def set_state(self, u):
+        u = self._check_array(u, self.M * self.ne * self.np)
+        p, dev = _ptr(u)
+        return _check(lib().crkfr_set_state(self.h, p, dev))
+
+    def set_alpha(self, alpha):
+        a = self._check_array(alpha, self.ne)
+        p, dev = _ptr(a)
+        _check(lib().crkfr_set_alpha(self.h, p, dev))
+
+    def compute_dt(self):
+        d = ctypes.c_double()
+        _check(lib().crkfr_compute_dt(self.h, ctypes.byref(d)))
+        return d.value
+
+    def step(self, dt=0.0):
+        _check(lib().crkfr_step(self.h, float(dt)))
+
+    def advance(self, t_end, max_steps):
+        _check(lib().crkfr_advance(self.h, float(t_end), int(max_steps)))
+
+    def get_state(self, out=None):
+        if out is None:
+            out = np.empty(self.shape(), dtype=np.float64)
+        elif hasattr(out, "data_ptr"):
+            self._check_array(out, self.M * self.ne * self.np)
+        elif not (out.dtype == np.float64 and out.flags.c_contiguous and out.size == self.M * self.ne * self.np):
+            raise ValueError("out must be a contiguous float64 array of the state's size")
+        p, dev = _ptr(out)
+        _check(lib().crkfr_get_state(self.h, p, dev))
+        return out
+
+    def get_means(self):
+        out = np.empty((self.M, self.cfg.ny, self.cfg.nx), dtype=np.float64)
+        _check(lib().crkfr_get_means(self.h, ctypes.c_void_p(out.ctypes.data)))
+        return out
+
+    def get_alpha(self):
+        out = np.empty(self.ne, dtype=np.float64)
+        _check(lib().crkfr_get_alpha(self.h, ctypes.c_void_p(out.ctypes.data)))
+        return out
+
+    def get_diag(self, check=False):
+        d = Diag()
+        rc = lib().crkfr_get_diag(self.h, ctypes.byref(d))
+        if check:
+            _check(rc)
+        return d.as_dict(), rc
+
+    def cfl(self):
+        return lib().crkfr_cfl_in_use(self.h)
+
+    def set_timing(self, on=True):
+        _check(lib().crkfr_set_timing(self.h, int(on)))
+
+    def kernel_times(self):
+        ms = (ctypes.c_float * 4)()
+        _check(lib().crkfr_get_kernel_times(self.h, ms))
+        return list(ms)

@@ -1,0 +1,829 @@
+// Host runtime and C ABI of the cRKFR step (declarations in include/crkfr.h).
+//
+// The solver owns its device buffers, precomputes the reference-element
+// operators in FP64 (Sec. 2: Gauss-Legendre points, Lagrange basis,
+// differentiation matrix, boundary values, Radau correction derivatives
+// g_R'(xi_p) = l_p(1)/w_p, g_L'(xi_p) = -l_p(0)/w_p, orthonormal Legendre
+// values for the indicator) and enqueues one step as
+//   k_prep -> k_local -> k_face(x) -> k_face(y) -> k_update
+// on its stream.  CFL(N) of eq. time.step.2d comes from the library's own
+// Fourier analysis unless the caller gives one.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/crkfr.h"
+#include "crkfr_launch.hpp"
+
+using namespace crkfr;
+
+static thread_local std::string g_last_error;
+
+static int fail(int code, const std::string& msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+#define HIP_TRY(call)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(CRKFR_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));       \
+    } while (0)
+
+// ----------------------------------------------------------------------------
+// reference element (FP64, host)
+// ----------------------------------------------------------------------------
+struct RefElem {
+    int N;
+    double xi[MAXND], w[MAXND], D[MAXND][MAXND], l0[MAXND], l1[MAXND], sub[MAXND + 1], L[MAXND][MAXND];
+};
+
+// Legendre P_n and P_n' on [-1,1] by the Bonnet recurrence
+static void legendre_pair(int n, double x, double& P, double& dP)
+{
+    double pm1 = 1.0, p = x;
+    if (n == 0) { P = 1.0; dP = 0.0; return; }
+    for (int k = 1; k < n; ++k) {
+        double pn = ((2 * k + 1) * x * p - k * pm1) / (k + 1);
+        pm1 = p;
+        p = pn;
+    }
+    P = p;
+    dP = n * (pm1 - x * p) / (1.0 - x * x);
+}
+
+static void make_ref(int N, RefElem& r)
+{
+    const int n = N + 1;
+    r.N = N;
+    // Gauss-Legendre nodes: Newton from the asymptotic guess, then weights
+    for (int i = 0; i < n; ++i) {
+        double x = std::cos(M_PI * (4.0 * (n - 1 - i) + 3.0) / (4.0 * n + 2.0));
+        for (int it = 0; it < 50; ++it) {
+            double P, dP;
+            legendre_pair(n, x, P, dP);
+            double step = P / dP;
+            x -= step;
+            if (std::fabs(step) < 1e-17) break;
+        }
+        double P, dP;
+        legendre_pair(n, x, P, dP);
+        r.xi[i] = 0.5 + 0.5 * x;
+        r.w[i] = 1.0 / ((1.0 - x * x) * dP * dP);   // 2/((1-x^2)P'^2) halved for [0,1]
+    }
+    // barycentric weights, Lagrange values at 0 and 1, differentiation matrix
+    double bw[MAXND];
+    for (int j = 0; j < n; ++j) {
+        double prod = 1.0;
+        for (int m = 0; m < n; ++m)
+            if (m != j) prod *= (r.xi[j] - r.xi[m]);
+        bw[j] = 1.0 / prod;
+    }
+    for (int side = 0; side < 2; ++side) {
+        double x = side ? 1.0 : 0.0, den = 0.0, num[MAXND];
+        for (int j = 0; j < n; ++j) {
+            num[j] = bw[j] / (x - r.xi[j]);
+            den += num[j];
+        }
+        for (int j = 0; j < n; ++j) (side ? r.l1 : r.l0)[j] = num[j] / den;
+    }
+    for (int i = 0; i < n; ++i) {
+        double diag = 0.0;
+        for (int j = 0; j < n; ++j) {
+            if (j == i) continue;
+            r.D[i][j] = (bw[j] / bw[i]) / (r.xi[i] - r.xi[j]);
+            diag -= r.D[i][j];
+        }
+        r.D[i][i] = diag;
+    }
+    r.sub[0] = 0.0;
+    for (int p = 0; p < n; ++p) r.sub[p + 1] = r.sub[p] + r.w[p];
+    r.sub[n] = 1.0;
+    for (int k = 0; k < n; ++k)
+        for (int p = 0; p < n; ++p) {
+            double P, dP;
+            legendre_pair(k, 2.0 * r.xi[p] - 1.0, P, dP);
+            r.L[k][p] = std::sqrt(2.0 * k + 1.0) * P;
+        }
+}
+
+template <class real>
+static void fill_tab(const RefElem& r, RefTab<real>& t)
+{
+    std::memset(&t, 0, sizeof(t));
+    for (int i = 0; i <= r.N; ++i) {
+        for (int j = 0; j <= r.N; ++j) {
+            t.D[i][j] = (real)r.D[i][j];
+            t.L[i][j] = (real)r.L[i][j];
+        }
+        t.l0[i] = (real)r.l0[i];
+        t.l1[i] = (real)r.l1[i];
+        t.bR[i] = (real)(r.l1[i] / r.w[i]);
+        t.bL[i] = (real)(r.l0[i] / r.w[i]);
+        t.w[i] = (real)r.w[i];
+        t.xi[i] = (real)r.xi[i];
+    }
+    for (int i = 0; i <= r.N + 1; ++i) t.sub[i] = (real)r.sub[i];
+}
+
+// ----------------------------------------------------------------------------
+// Fourier analysis of the linear scheme for CFL(N)
+//   U = P u, P = sum_i b_i R_i, R_1 = I, R_{i+1} = I - nu_a a_{i+1,i} D R_i
+//   D2 flux with dissipation speed lambda, wave speed a = ratio * lambda
+//   G = I - (nu_a D + b_R (F_R - nu_a l1^T) - b_L (F_L - nu_a l0^T)) P
+// spectral radius from the growth of ||G^(2^j)|| under repeated squaring.
+// ----------------------------------------------------------------------------
+typedef std::complex<double> cplx;
+
+static double spectral_radius(int n, const cplx* G)
+{
+    cplx A[MAXND * MAXND], B[MAXND * MAXND];
+    std::memcpy(A, G, sizeof(cplx) * n * n);
+    double logsum = 0.0, scale = 1.0;
+    for (int j = 0; j < 48; ++j) {
+        double nrm = 0.0;
+        for (int i = 0; i < n * n; ++i) nrm += std::norm(A[i]);
+        nrm = std::sqrt(nrm);
+        if (nrm == 0.0) return 0.0;
+        logsum += std::log(nrm) * scale;
+        for (int i = 0; i < n * n; ++i) A[i] /= nrm;
+        for (int r = 0; r < n; ++r)
+            for (int c = 0; c < n; ++c) {
+                cplx s = 0.0;
+                for (int k = 0; k < n; ++k) s += A[r * n + k] * A[k * n + c];
+                B[r * n + c] = s;
+            }
+        std::memcpy(A, B, sizeof(cplx) * n * n);
+        scale *= 0.5;
+    }
+    return std::exp(logsum);
+}
+
+static double max_growth(const RefElem& r, int S, double nu, double ratio, int nk)
+{
+    const int n = r.N + 1;
+    const double nua = ratio * nu;
+    double P[MAXND][MAXND], R[MAXND][MAXND], T[MAXND][MAXND];
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            R[i][j] = i == j ? 1.0 : 0.0;
+            P[i][j] = tab_b(S, 0) * R[i][j];
+        }
+    for (int st = 1; st < S; ++st) {
+        const double a = tab_a(S, st - 1);
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                double s = 0.0;
+                for (int k = 0; k < n; ++k) s += r.D[i][k] * R[k][j];
+                T[i][j] = (i == j ? 1.0 : 0.0) - nua * a * s;
+            }
+        std::memcpy(R, T, sizeof(R));
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) P[i][j] += tab_b(S, st) * R[i][j];
+    }
+    double worst = 0.0;
+    for (int ik = 0; ik < nk; ++ik) {
+        const double kap = 2.0 * M_PI * ik / (nk - 1);
+        const cplx E = std::polar(1.0, kap), Ec = std::conj(E);
+        cplx op[MAXND * MAXND], G[MAXND * MAXND];
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                cplx FR = 0.5 * nua * (r.l1[j] + E * r.l0[j]) - 0.5 * nu * (E * r.l0[j] - r.l1[j]);
+                cplx FL = 0.5 * nua * (Ec * r.l1[j] + r.l0[j]) - 0.5 * nu * (r.l0[j] - Ec * r.l1[j]);
+                op[i * n + j] = nua * r.D[i][j] + (r.l1[i] / r.w[i]) * (FR - nua * r.l1[j])
+                                - (r.l0[i] / r.w[i]) * (FL - nua * r.l0[j]);
+            }
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                cplx s = 0.0;
+                for (int k = 0; k < n; ++k) s += op[i * n + k] * P[k][j];
+                G[i * n + j] = (i == j ? 1.0 : 0.0) - s;
+            }
+        double rho = spectral_radius(n, G);
+        worst = rho > worst ? rho : worst;
+    }
+    return worst;
+}
+
+extern "C" double crkfr_fourier_cfl(int N, int stages, int system, double tol)
+{
+    if (N < 1 || N > 4) return -1.0;
+    RefElem r;
+    make_ref(N, r);
+    const int S = stages > 0 ? stages : std::min(N + 1, 4);
+    const int nr = system ? 11 : 1, nk = 385;
+    auto stable = [&](double nu) {
+        for (int ir = 0; ir < nr; ++ir) {
+            double ratio = system ? (double)ir / (nr - 1) : 1.0;
+            if (max_growth(r, S, nu, ratio, nk) > 1.0 + tol) return false;
+        }
+        return true;
+    };
+    double lo = 0.0, hi = 1.0;
+    for (int it = 0; it < 40; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (stable(mid)) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+static double cached_cfl(int eq, int N)
+{
+    static std::mutex mu;
+    static double cache[2][5] = {{0}};
+    const int sys = eq == CRKFR_LINADV1D ? 0 : 1;
+    std::lock_guard<std::mutex> lk(mu);
+    if (cache[sys][N] == 0.0) cache[sys][N] = crkfr_fourier_cfl(N, 0, sys, N == 4 ? 1e-5 : 1e-10);
+    return cache[sys][N];
+}
+
+// ----------------------------------------------------------------------------
+// solver
+// ----------------------------------------------------------------------------
+struct crkfr_solver {
+    crkfr_config cfg;
+    crkfr_limiter_opts lim;
+    crkfr_source src;
+    hipStream_t stream;
+    bool own_stream;
+    int M, dim, nd, nq, np, ne, C_max;
+    double cfl;
+    bool mp, has_state;
+    int cur;   // which state buffer is current
+    RefElem ref;
+    void* u[2];
+    double* ubar[2];
+    void *uHp, *trx, *trY, *Fx, *Gy, *dtS, *ghost;
+    double *alpha_raw, *alpha_out, *alpha_given;
+    double *dt_dev, *t_dev;
+    unsigned long long *rate_bits, *diag;
+    long long* steps;
+    bool timing;
+    hipEvent_t ev[6];
+    float kernel_ms[4];
+    hipGraphExec_t graph_exec;
+    double graph_t_end;
+    int graph_cur;
+};
+
+static size_t real_size(const crkfr_solver* s) { return s->mp ? sizeof(float) : sizeof(double); }
+
+static int eq_nvar(int eq)
+{
+    switch (eq) {
+    case CRKFR_LINADV1D: return 1;
+    case CRKFR_EULER1D: return 3;
+    case CRKFR_EULER2D: return 4;
+    case CRKFR_TENMOM2D: return 6;
+    }
+    return 0;
+}
+
+static Phys make_phys(const crkfr_solver* s)
+{
+    Phys P;
+    P.gamma = s->cfg.gamma;
+    P.adv = s->cfg.adv;
+    P.source = s->src.enabled && s->cfg.equation == CRKFR_TENMOM2D;
+    P.amp = s->src.amp;
+    P.kappa = s->src.kappa;
+    P.xc = s->src.xc;
+    P.yc = s->src.yc;
+    P.gx = s->src.gx;
+    P.gy = s->src.gy;
+    return P;
+}
+
+template <class real>
+static StepArgs<real> step_args(const crkfr_solver* s, int in, int out)
+{
+    StepArgs<real> a;
+    std::memset(&a, 0, sizeof(a));
+    a.nx = s->cfg.nx;
+    a.ny = s->cfg.ny;
+    a.ne = s->ne;
+    a.dx = (s->cfg.x1 - s->cfg.x0) / s->cfg.nx;
+    a.dy = s->dim == 2 ? (s->cfg.y1 - s->cfg.y0) / s->cfg.ny : 1.0;
+    a.x0 = s->cfg.x0;
+    a.y0 = s->cfg.y0;
+    for (int i = 0; i < 4; ++i) a.bc[i] = s->cfg.bc[i];
+    if (s->dim == 1) { a.bc[2] = BC_PERIODIC; a.bc[3] = BC_PERIODIC; }
+    a.ubar = s->ubar[in];
+    a.u = (const real*)s->u[in];
+    a.ubar_out = s->ubar[out];
+    a.u_out = (real*)s->u[out];
+    a.uHp = (real*)s->uHp;
+    a.trx = (real*)s->trx;
+    a.trY = (real*)s->trY;
+    a.Fx = (real*)s->Fx;
+    a.Gy = (real*)s->Gy;
+    a.dtS = (s->src.enabled && s->cfg.equation == CRKFR_TENMOM2D) ? (real*)s->dtS : nullptr;
+    a.alpha_raw = s->alpha_raw;
+    a.alpha_out = s->alpha_out;
+    a.alpha_given = s->alpha_given;
+    a.ghost = (const real*)s->ghost;
+    a.dt_dev = s->dt_dev;
+    a.blend = s->lim.blend;
+    a.indicator = s->lim.indicator;
+    a.smooth = s->lim.smooth_nbr;
+    a.flux_limiter = s->lim.flux_limiter;
+    a.scaling = s->lim.scaling;
+    a.C = s->C_max;
+    a.alpha_min = s->lim.alpha_min;
+    a.alpha_max = s->lim.alpha_max;
+    a.alpha_const = s->lim.alpha_const;
+    a.phys = make_phys(s);
+    fill_tab(s->ref, a.R);
+    for (int i = 0; i < MAXND; ++i) a.w64[i] = i <= s->cfg.N ? s->ref.w[i] : 0.0;
+    a.diag = s->diag;
+    a.rate_bits = s->rate_bits;
+    return a;
+}
+
+template <class real>
+static IoArgs<real> io_args(const crkfr_solver* s)
+{
+    IoArgs<real> a;
+    std::memset(&a, 0, sizeof(a));
+    a.nx = s->cfg.nx;
+    a.ny = s->cfg.ny;
+    a.ne = s->ne;
+    a.dx = (s->cfg.x1 - s->cfg.x0) / s->cfg.nx;
+    a.dy = s->dim == 2 ? (s->cfg.y1 - s->cfg.y0) / s->cfg.ny : 1.0;
+    for (int i = 0; i < 4; ++i) a.bc[i] = s->cfg.bc[i];
+    a.ubar = s->ubar[s->cur];
+    a.u = (real*)s->u[s->cur];
+    a.ghost = (real*)s->ghost;
+    a.phys = make_phys(s);
+    fill_tab(s->ref, a.R);
+    for (int i = 0; i < MAXND; ++i) {
+        a.w64[i] = i <= s->cfg.N ? s->ref.w[i] : 0.0;
+        a.l0_64[i] = i <= s->cfg.N ? s->ref.l0[i] : 0.0;
+        a.l1_64[i] = i <= s->cfg.N ? s->ref.l1[i] : 0.0;
+    }
+    a.diag = s->diag;
+    a.rate_bits = s->rate_bits;
+    return a;
+}
+
+static int dispatch_step(const crkfr_solver* s, int phase, int in, int out)
+{
+    const int N = s->cfg.N;
+    const bool lim = s->lim.blend != CRKFR_BLEND_OFF;
+    hipStream_t st = s->stream;
+    int rc = -1;
+    if (s->mp) {
+        StepArgs<float> a = step_args<float>(s, in, out);
+        switch (s->cfg.equation) {
+        case CRKFR_LINADV1D: rc = linadv1d_step_f32(N, lim, phase, a, st); break;
+        case CRKFR_EULER1D: rc = euler1d_step_f32(N, lim, phase, a, st); break;
+        case CRKFR_EULER2D: rc = euler2d_step_f32(N, lim, phase, a, st); break;
+        case CRKFR_TENMOM2D: rc = tenmom2d_step_f32(N, lim, phase, a, st); break;
+        }
+    } else {
+        StepArgs<double> a = step_args<double>(s, in, out);
+        switch (s->cfg.equation) {
+        case CRKFR_LINADV1D: rc = linadv1d_step_f64(N, lim, phase, a, st); break;
+        case CRKFR_EULER1D: rc = euler1d_step_f64(N, lim, phase, a, st); break;
+        case CRKFR_EULER2D: rc = euler2d_step_f64(N, lim, phase, a, st); break;
+        case CRKFR_TENMOM2D: rc = tenmom2d_step_f64(N, lim, phase, a, st); break;
+        }
+    }
+    if (rc) return fail(CRKFR_EINVAL, "no kernel for this configuration");
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(CRKFR_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
+    return 0;
+}
+
+template <class real>
+static int dispatch_io_t(const crkfr_solver* s, int phase, IoArgs<real>& a)
+{
+    const int N = s->cfg.N;
+    hipStream_t st = s->stream;
+    int rc = -1;
+    if constexpr (sizeof(real) == 4) {
+        switch (s->cfg.equation) {
+        case CRKFR_LINADV1D: rc = linadv1d_io_f32(N, phase, a, st); break;
+        case CRKFR_EULER1D: rc = euler1d_io_f32(N, phase, a, st); break;
+        case CRKFR_EULER2D: rc = euler2d_io_f32(N, phase, a, st); break;
+        case CRKFR_TENMOM2D: rc = tenmom2d_io_f32(N, phase, a, st); break;
+        }
+    } else {
+        switch (s->cfg.equation) {
+        case CRKFR_LINADV1D: rc = linadv1d_io_f64(N, phase, a, st); break;
+        case CRKFR_EULER1D: rc = euler1d_io_f64(N, phase, a, st); break;
+        case CRKFR_EULER2D: rc = euler2d_io_f64(N, phase, a, st); break;
+        case CRKFR_TENMOM2D: rc = tenmom2d_io_f64(N, phase, a, st); break;
+        }
+    }
+    if (rc) return fail(CRKFR_EINVAL, "no io kernel for this configuration");
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(CRKFR_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
+    return 0;
+}
+
+static int run_io(const crkfr_solver* s, int phase, const double* uin, double* uout, double* means)
+{
+    if (s->mp) {
+        IoArgs<float> a = io_args<float>(s);
+        a.uin = uin; a.uout = uout; a.means_out = means;
+        return dispatch_io_t<float>(s, phase, a);
+    }
+    IoArgs<double> a = io_args<double>(s);
+    a.uin = uin; a.uout = uout; a.means_out = means;
+    return dispatch_io_t<double>(s, phase, a);
+}
+
+static void free_all(crkfr_solver* s)
+{
+    void* ptrs[] = {s->u[0], s->u[1], s->ubar[0], s->ubar[1], s->uHp, s->trx, s->trY, s->Fx, s->Gy, s->dtS,
+                    s->ghost, s->alpha_raw, s->alpha_out, s->alpha_given, s->dt_dev, s->t_dev,
+                    s->rate_bits, s->diag, s->steps};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    if (s->graph_exec) (void)hipGraphExecDestroy(s->graph_exec);
+    for (int i = 0; i < 6; ++i)
+        if (s->ev[i]) (void)hipEventDestroy(s->ev[i]);
+    if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+}
+
+extern "C" int crkfr_create(const crkfr_config* cfg, void* hip_stream, crkfr_solver** out)
+{
+    if (!cfg || !out) return fail(CRKFR_EINVAL, "null argument");
+    *out = nullptr;
+    if (cfg->equation < 0 || cfg->equation > 3) return fail(CRKFR_EINVAL, "unknown equation");
+    if (cfg->N < 1 || cfg->N > 4) return fail(CRKFR_EINVAL, "N must be in 1..4");
+    const int dim = cfg->equation >= CRKFR_EULER2D ? 2 : 1;
+    if (cfg->nx < 1 || cfg->ny < 1 || (dim == 1 && cfg->ny != 1)) return fail(CRKFR_EINVAL, "bad grid size");
+    if (cfg->dtype != CRKFR_FP64 && cfg->dtype != CRKFR_MP32) return fail(CRKFR_EINVAL, "bad dtype");
+    for (int i = 0; i < (dim == 2 ? 4 : 2); ++i)
+        if (cfg->bc[i] < 0 || cfg->bc[i] > 2) return fail(CRKFR_EINVAL, "bad boundary kind");
+    if ((cfg->bc[0] == CRKFR_BC_PERIODIC) != (cfg->bc[1] == CRKFR_BC_PERIODIC) ||
+        (dim == 2 && (cfg->bc[2] == CRKFR_BC_PERIODIC) != (cfg->bc[3] == CRKFR_BC_PERIODIC)))
+        return fail(CRKFR_EINVAL, "periodic boundaries come in pairs");
+    if (!(cfg->x1 > cfg->x0) || (dim == 2 && !(cfg->y1 > cfg->y0))) return fail(CRKFR_EINVAL, "bad domain");
+
+    crkfr_solver* s = new crkfr_solver();
+    std::memset(s, 0, sizeof(*s));
+    s->cfg = *cfg;
+    s->stream = (hipStream_t)hip_stream;
+    if (!s->stream) {
+        // graph capture needs a stream of its own (default priority)
+        hipError_t e = hipStreamCreate(&s->stream);
+        if (e != hipSuccess) {
+            delete s;
+            return fail(CRKFR_EHIP, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+        }
+        s->own_stream = true;
+    }
+    s->M = eq_nvar(cfg->equation);
+    s->dim = dim;
+    s->nd = cfg->N + 1;
+    s->nq = dim == 2 ? s->nd : 1;
+    s->np = s->nd * s->nq;
+    s->ne = cfg->nx * cfg->ny;
+    s->C_max = 4 * s->M + 1;
+    s->mp = cfg->dtype == CRKFR_MP32;
+    s->cfl = cfg->cfl > 0.0 ? cfg->cfl : cached_cfl(cfg->equation, cfg->N);
+    if (s->cfg.cs <= 0.0) s->cfg.cs = 0.98;
+    s->lim.blend = CRKFR_BLEND_OFF;
+    s->lim.alpha_min = 1e-3;
+    s->lim.alpha_max = 1.0;
+    s->lim.smooth_nbr = 1;
+    make_ref(cfg->N, s->ref);
+
+    const size_t rs = real_size(s), M = s->M, ne = s->ne, np = s->np;
+    const size_t nstate = M * ne * np;
+    auto alloc = [&](void** p, size_t bytes) -> bool {
+        if (bytes == 0) return true;
+        return hipMalloc(p, bytes) == hipSuccess;
+    };
+    bool ok = true;
+    ok &= alloc(&s->u[0], nstate * rs);
+    ok &= alloc(&s->u[1], nstate * rs);
+    if (s->mp) {
+        ok &= alloc((void**)&s->ubar[0], M * ne * sizeof(double));
+        ok &= alloc((void**)&s->ubar[1], M * ne * sizeof(double));
+    }
+    ok &= alloc(&s->uHp, nstate * rs);
+    ok &= alloc(&s->trx, 2 * (size_t)s->C_max * ne * s->nq * rs);
+    if (dim == 2) ok &= alloc(&s->trY, 2 * (size_t)s->C_max * ne * s->nd * rs);
+    ok &= alloc(&s->Fx, M * (size_t)cfg->ny * (cfg->nx + 1) * s->nq * rs);
+    if (dim == 2) ok &= alloc(&s->Gy, M * (size_t)(cfg->ny + 1) * cfg->nx * s->nd * rs);
+    if (cfg->equation == CRKFR_TENMOM2D) ok &= alloc(&s->dtS, nstate * rs);
+    ok &= alloc(&s->ghost, (2 * (size_t)cfg->ny * s->nq + (dim == 2 ? 2 * (size_t)cfg->nx * s->nd : 0)) * M * rs);
+    ok &= alloc((void**)&s->alpha_raw, ne * sizeof(double));
+    ok &= alloc((void**)&s->alpha_out, ne * sizeof(double));
+    ok &= alloc((void**)&s->alpha_given, ne * sizeof(double));
+    ok &= alloc((void**)&s->dt_dev, sizeof(double));
+    ok &= alloc((void**)&s->t_dev, sizeof(double));
+    ok &= alloc((void**)&s->rate_bits, sizeof(unsigned long long));
+    ok &= alloc((void**)&s->diag, D_NCOUNT * sizeof(unsigned long long));
+    ok &= alloc((void**)&s->steps, sizeof(long long));
+    if (!ok) {
+        free_all(s);
+        delete s;
+        return fail(CRKFR_ENOMEM, "device allocation failed");
+    }
+    (void)hipMemsetAsync(s->alpha_raw, 0, ne * sizeof(double), s->stream);
+    (void)hipMemsetAsync(s->alpha_out, 0, ne * sizeof(double), s->stream);
+    (void)hipMemsetAsync(s->alpha_given, 0, ne * sizeof(double), s->stream);
+    (void)hipMemsetAsync(s->diag, 0, D_NCOUNT * sizeof(unsigned long long), s->stream);
+    if (hipStreamSynchronize(s->stream) != hipSuccess) {
+        free_all(s);
+        delete s;
+        return fail(CRKFR_EHIP, "stream synchronize failed");
+    }
+    *out = s;
+    return 0;
+}
+
+extern "C" void crkfr_destroy(crkfr_solver* s)
+{
+    if (!s) return;
+    (void)hipStreamSynchronize(s->stream);
+    free_all(s);
+    delete s;
+}
+
+static void invalidate_graph(crkfr_solver* s)
+{
+    if (s->graph_exec) {
+        (void)hipGraphExecDestroy(s->graph_exec);
+        s->graph_exec = nullptr;
+    }
+}
+
+extern "C" int crkfr_set_limiter(crkfr_solver* s, const crkfr_limiter_opts* o)
+{
+    if (!s || !o) return fail(CRKFR_EINVAL, "null argument");
+    if (o->blend < 0 || o->blend > 2 || o->indicator < 0 || o->indicator > 3)
+        return fail(CRKFR_EINVAL, "bad limiter option");
+    if (o->flux_limiter && o->blend == CRKFR_BLEND_OFF)
+        return fail(CRKFR_EINVAL, "the flux limiter needs a low-order blend (FO or MH)");
+    s->lim = *o;
+    invalidate_graph(s);
+    return 0;
+}
+
+extern "C" int crkfr_set_source(crkfr_solver* s, const crkfr_source* src)
+{
+    if (!s || !src) return fail(CRKFR_EINVAL, "null argument");
+    if (src->enabled && s->cfg.equation != CRKFR_TENMOM2D)
+        return fail(CRKFR_EINVAL, "sources are implemented for the ten-moment system");
+    s->src = *src;
+    invalidate_graph(s);
+    return 0;
+}
+
+extern "C" int crkfr_set_state(crkfr_solver* s, const double* u, int on_device)
+{
+    if (!s || !u) return fail(CRKFR_EINVAL, "null argument");
+    const size_t n = (size_t)s->M * s->ne * s->np;
+    const double* src = u;
+    double* tmp = nullptr;
+    if (!on_device) {
+        HIP_TRY(hipMalloc((void**)&tmp, n * sizeof(double)));
+        HIP_TRY(hipMemcpyAsync(tmp, u, n * sizeof(double), hipMemcpyHostToDevice, s->stream));
+        src = tmp;
+    }
+    s->cur = 0;
+    const double zero = 0.0;
+    HIP_TRY(hipMemcpyAsync(s->t_dev, &zero, sizeof(double), hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipMemsetAsync(s->rate_bits, 0, sizeof(unsigned long long), s->stream));
+    HIP_TRY(hipMemsetAsync(s->diag, 0, D_NCOUNT * sizeof(unsigned long long), s->stream));
+    HIP_TRY(hipMemsetAsync(s->steps, 0, sizeof(long long), s->stream));
+    int rc = run_io(s, PH_IMPORT, src, nullptr, nullptr);
+    if (!rc) rc = run_io(s, PH_GHOST, nullptr, nullptr, nullptr);
+    unsigned long long bad = 0;
+    if (!rc) {
+        HIP_TRY(hipMemcpyAsync(&bad, s->diag + D_MEANBAD, sizeof(bad), hipMemcpyDeviceToHost, s->stream));
+        HIP_TRY(hipStreamSynchronize(s->stream));
+    }
+    if (tmp) (void)hipFree(tmp);
+    HIP_TRY(hipMemsetAsync(s->diag, 0, D_NCOUNT * sizeof(unsigned long long), s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    if (rc) return rc;
+    s->has_state = true;
+    invalidate_graph(s);
+    if (bad) return fail(CRKFR_EINADMISSIBLE_INPUT, std::to_string(bad) + " nodes violate the admissibility constraints");
+    return 0;
+}
+
+extern "C" int crkfr_set_alpha(crkfr_solver* s, const double* alpha, int on_device)
+{
+    if (!s || !alpha) return fail(CRKFR_EINVAL, "null argument");
+    HIP_TRY(hipMemcpyAsync(s->alpha_given, alpha, s->ne * sizeof(double),
+                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return 0;
+}
+
+extern "C" int crkfr_compute_dt(crkfr_solver* s, double* dt)
+{
+    if (!s || !dt) return fail(CRKFR_EINVAL, "null argument");
+    if (!s->has_state) return fail(CRKFR_ESTATE, "no state set");
+    unsigned long long bits = 0;
+    HIP_TRY(hipMemcpyAsync(&bits, s->rate_bits, sizeof(bits), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    double rate;
+    std::memcpy(&rate, &bits, sizeof(rate));
+    *dt = s->cfg.cs * s->cfl / rate;
+    return 0;
+}
+
+static int enqueue_step(crkfr_solver* s, double dt_fixed, double t_end)
+{
+    PrepArgs pa;
+    pa.dt_dev = s->dt_dev;
+    pa.t_dev = s->t_dev;
+    pa.t_end = t_end;
+    pa.dt_fixed = dt_fixed;
+    pa.cfl_cs = s->cfg.cs * s->cfl;
+    pa.rate_bits = s->rate_bits;
+    pa.diag = s->diag;
+    pa.steps = s->steps;
+    hipLaunchKernelGGL(k_prep, dim3(1), dim3(64), 0, s->stream, pa);
+    const int in = s->cur, out = 1 - s->cur;
+    const bool tm = s->timing;
+    if (tm) (void)hipEventRecord(s->ev[0], s->stream);
+    int rc = dispatch_step(s, PH_LOCAL, in, out);
+    if (tm) (void)hipEventRecord(s->ev[1], s->stream);
+    if (!rc) rc = dispatch_step(s, PH_FACE_X, in, out);
+    if (tm) (void)hipEventRecord(s->ev[2], s->stream);
+    if (!rc && s->dim == 2) rc = dispatch_step(s, PH_FACE_Y, in, out);
+    if (tm) (void)hipEventRecord(s->ev[3], s->stream);
+    if (!rc) rc = dispatch_step(s, PH_UPDATE, in, out);
+    if (tm) (void)hipEventRecord(s->ev[4], s->stream);
+    s->cur = out;
+    return rc;
+}
+
+extern "C" int crkfr_step(crkfr_solver* s, double dt)
+{
+    if (!s) return fail(CRKFR_EINVAL, "null argument");
+    if (!s->has_state) return fail(CRKFR_ESTATE, "no state set");
+    return enqueue_step(s, dt > 0.0 ? dt : 0.0, 0.0);
+}
+
+// two steps (ping-pong of the state buffers) captured once as a HIP graph
+static int build_graph(crkfr_solver* s, double t_end)
+{
+    invalidate_graph(s);
+    const bool tm = s->timing;
+    s->timing = false;
+    hipGraph_t g;
+    const int cur0 = s->cur;
+    hipError_t e = hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        s->timing = tm;
+        return fail(CRKFR_EHIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
+    }
+    int rc = enqueue_step(s, 0.0, t_end);
+    if (!rc) rc = enqueue_step(s, 0.0, t_end);
+    e = hipStreamEndCapture(s->stream, &g);
+    s->timing = tm;
+    s->cur = cur0;
+    if (rc) {
+        if (e == hipSuccess) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(CRKFR_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&s->graph_exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(CRKFR_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+    s->graph_t_end = t_end;
+    s->graph_cur = cur0;
+    return 0;
+}
+
+extern "C" int crkfr_advance(crkfr_solver* s, double t_end, int max_steps)
+{
+    if (!s) return fail(CRKFR_EINVAL, "null argument");
+    if (!s->has_state) return fail(CRKFR_ESTATE, "no state set");
+    if (max_steps < 0) return fail(CRKFR_EINVAL, "max_steps < 0");
+    if (!s->graph_exec || s->graph_t_end != t_end || s->graph_cur != s->cur) {
+        int rc = build_graph(s, t_end);
+        if (rc) return rc;
+    }
+    int done = 0;
+    while (done < max_steps) {
+        if (max_steps - done >= 2) {
+            HIP_TRY(hipGraphLaunch(s->graph_exec, s->stream));
+            done += 2;
+        } else {
+            int rc = enqueue_step(s, 0.0, t_end);
+            if (rc) return rc;
+            done += 1;
+            continue;
+        }
+        if (done % 64 == 0 && t_end > 0.0) {
+            double t = 0.0;
+            HIP_TRY(hipMemcpyAsync(&t, s->t_dev, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+            HIP_TRY(hipStreamSynchronize(s->stream));
+            if (t >= t_end) break;
+        }
+    }
+    return 0;
+}
+
+extern "C" int crkfr_get_state(crkfr_solver* s, double* out, int on_device)
+{
+    if (!s || !out) return fail(CRKFR_EINVAL, "null argument");
+    if (!s->has_state) return fail(CRKFR_ESTATE, "no state set");
+    const size_t n = (size_t)s->M * s->ne * s->np;
+    double* dst = out;
+    double* tmp = nullptr;
+    if (!on_device) {
+        HIP_TRY(hipMalloc((void**)&tmp, n * sizeof(double)));
+        dst = tmp;
+    }
+    int rc = run_io(s, PH_EXPORT, nullptr, dst, nullptr);
+    if (!rc && tmp) HIP_TRY(hipMemcpyAsync(out, tmp, n * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    if (tmp) (void)hipFree(tmp);
+    return rc;
+}
+
+extern "C" int crkfr_get_means(crkfr_solver* s, double* out)
+{
+    if (!s || !out) return fail(CRKFR_EINVAL, "null argument");
+    if (!s->has_state) return fail(CRKFR_ESTATE, "no state set");
+    const size_t n = (size_t)s->M * s->ne;
+    double* tmp = nullptr;
+    HIP_TRY(hipMalloc((void**)&tmp, n * sizeof(double)));
+    int rc = run_io(s, PH_EXPORT, nullptr, nullptr, tmp);
+    if (!rc) HIP_TRY(hipMemcpyAsync(out, tmp, n * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    (void)hipFree(tmp);
+    return rc;
+}
+
+extern "C" int crkfr_get_alpha(crkfr_solver* s, double* out)
+{
+    if (!s || !out) return fail(CRKFR_EINVAL, "null argument");
+    HIP_TRY(hipMemcpyAsync(out, s->alpha_out, s->ne * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return 0;
+}
+
+extern "C" int crkfr_get_diag(crkfr_solver* s, crkfr_diag* out)
+{
+    if (!s || !out) return fail(CRKFR_EINVAL, "null argument");
+    unsigned long long d[D_NCOUNT];
+    double t = 0.0, dt = 0.0;
+    long long steps = 0;
+    HIP_TRY(hipMemcpyAsync(d, s->diag, sizeof(d), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipMemcpyAsync(&t, s->t_dev, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipMemcpyAsync(&dt, s->dt_dev, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipMemcpyAsync(&steps, s->steps, sizeof(long long), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    out->n_troubled = (long long)d[D_TROUBLED];
+    out->n_flux_limited = (long long)d[D_FLUXLIM];
+    out->n_lo_inadmissible = (long long)d[D_LOBAD];
+    out->n_slope_limited = (long long)d[D_SLOPELIM];
+    out->n_hancock_fallback = (long long)d[D_FALLBACK];
+    out->n_scaled = (long long)d[D_SCALED];
+    out->n_mean_inadmissible = (long long)d[D_MEANBAD];
+    std::memcpy(&out->min_theta_flux, &d[D_THFLUX], sizeof(double));
+    std::memcpy(&out->min_theta_scale, &d[D_THSCALE], sizeof(double));
+    out->t = t;
+    out->dt = dt;
+    out->steps = steps;
+    if (out->n_mean_inadmissible > 0)
+        return fail(CRKFR_EINADMISSIBLE_MEAN, "an element mean left the admissible set");
+    return 0;
+}
+
+extern "C" int crkfr_nvar(const crkfr_solver* s) { return s ? s->M : 0; }
+extern "C" int crkfr_nodes_per_element(const crkfr_solver* s) { return s ? s->np : 0; }
+extern "C" double crkfr_cfl_in_use(const crkfr_solver* s) { return s ? s->cfl : 0.0; }
+
+extern "C" int crkfr_set_timing(crkfr_solver* s, int on)
+{
+    if (!s) return fail(CRKFR_EINVAL, "null argument");
+    if (on && !s->ev[0])
+        for (int i = 0; i < 6; ++i) HIP_TRY(hipEventCreate(&s->ev[i]));
+    s->timing = on != 0;
+    return 0;
+}
+
+extern "C" int crkfr_get_kernel_times(crkfr_solver* s, float* ms4)
+{
+    if (!s || !ms4) return fail(CRKFR_EINVAL, "null argument");
+    if (!s->ev[0]) return fail(CRKFR_ESTATE, "timing not enabled");
+    HIP_TRY(hipEventSynchronize(s->ev[4]));
+    for (int i = 0; i < 4; ++i) HIP_TRY(hipEventElapsedTime(&ms4[i], s->ev[i], s->ev[i + 1]));
+    return 0;
+}
+
+extern "C" const char* crkfr_last_error(void) { return g_last_error.c_str(); }

@@ -1,0 +1,1310 @@
+// gfx950 kernels of one cRKFR step (Babbar & Chen, arXiv 2502.07517).
+//
+//   k_local   per element, one lane per solution point: the local cRK
+//             procedure (eqs. crkfr, crk22/33/44, disc.avg.flux, time.avg.sol,
+//             App. B source averages), EA face traces (eq. evaluate), the
+//             volume part of the FR update with the extrapolated averaged flux
+//             folded in (eq. crkfr.avg), and, with limiting, the smoothness
+//             indicator and the MUSCL-Hancock subcell predictor (Sec. 4).
+//   k_face    per face point: D2 time-averaged numerical flux (eqs.
+//             numflux.general, D2), boundary ghosts (Sec. 3.3), blend with the
+//             low-order face flux (eq. Fblend) and the flux limiter for
+//             admissibility in means (Sec. 4.3), admissibility roots in FP64.
+//   k_update  per element: correction-function part of the FR update, the
+//             low-order subcell update (eq. low.order.update), the blend (eq.
+//             blended.scheme), FP64 element means (eq. upmean), Zhang-Shu
+//             scaling in FP64 and the wave-speed rate for the next time step
+//             (eq. time.step.2d).
+//
+// Layouts (e = ey*nx + ex, k = q*(N+1) + p):
+//   state      u[var][e][k]                        (MP32: FP64 means ubar[var][e] + FP32 deviations)
+//   uHp        [var][e][k]   u^n + volume part of the FR update
+//   traces x   trx[side][comp][e][q], side 0 = left face, 1 = right face
+//   traces y   trY[side][comp][e][p], side 0 = bottom, 1 = top
+//              comps: F_EA (M), U (M), sigma of u^n trace (1)
+//                     + limiting: predicted subcell face value (M), adjacent interior subface flux (M)
+//   face flux  Fx[var][ey][i = 0..nx][q], Gy[var][j = 0..ny][ex][p]
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "crkfr_physics.hpp"
+
+namespace crkfr {
+
+constexpr int MAXND = 5;
+enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_FARFIELD = 2 };
+enum { BLEND_OFF = 0, BLEND_FO = 1, BLEND_MH = 2 };
+enum { IND_PAPER = 0, IND_CONST = 1, IND_GIVEN = 2, IND_LEARNED = 3 };
+enum { D_TROUBLED = 0, D_FLUXLIM, D_LOBAD, D_SLOPELIM, D_FALLBACK, D_SCALED, D_MEANBAD, D_THFLUX, D_THSCALE, D_NCOUNT };
+
+template <class real>
+struct RefTab {
+    real D[MAXND][MAXND];
+    real l0[MAXND], l1[MAXND], bR[MAXND], bL[MAXND], w[MAXND], xi[MAXND];
+    real sub[MAXND + 1];
+    real L[MAXND][MAXND];   // L[k][p] = orthonormal Legendre L_k(xi_p)
+};
+
+template <class real>
+struct StepArgs {
+    int nx, ny, ne;
+    double dx, dy, x0, y0;
+    int bc[4];
+    const double* ubar;    // MP32 element means of the input state
+    const real* u;         // FP64 nodal state / MP32 deviations
+    double* ubar_out;
+    real* u_out;
+    real* uHp;
+    real* trx;
+    real* trY;
+    real* Fx;
+    real* Gy;
+    real* dtS;             // dt * time-averaged source [var][e][k] (source runs)
+    double* alpha_raw;     // per element, before neighbour smoothing
+    double* alpha_out;     // per element, final
+    const double* alpha_given;
+    const real* ghost;     // far-field ghost states, xL [ny][nq][M] | xR | yB [nx][nd][M] | yT
+    const double* dt_dev;
+    int blend, indicator, smooth, flux_limiter, scaling, C;
+    double alpha_min, alpha_max, alpha_const;
+    Phys phys;
+    RefTab<real> R;
+    double w64[MAXND];
+    unsigned long long* diag;
+    unsigned long long* rate_bits;
+};
+
+template <int DIM, int N>
+struct Geo {
+    static constexpr int nd = N + 1, nq = DIM == 2 ? N + 1 : 1, np = nd * nq;
+    static constexpr int EB = 256 / np;          // elements per workgroup
+    static constexpr int BLOCK = EB * np;
+};
+
+// cRK tableaux of eqs. crk22, crk33, crk44: sub-diagonal a_{i+1,i} and weights b_i
+__host__ __device__ constexpr double tab_a(int S, int i)
+{
+    return S == 2 ? 0.5 : (S == 3 ? (i == 0 ? 1.0 / 3.0 : 2.0 / 3.0) : (i == 2 ? 1.0 : 0.5));
+}
+__host__ __device__ constexpr double tab_b(int S, int i)
+{
+    return S == 2 ? (i == 0 ? 0.0 : 1.0)
+         : S == 3 ? (i == 0 ? 0.25 : (i == 1 ? 0.0 : 0.75))
+                  : ((i == 0 || i == 3) ? 1.0 / 6.0 : 1.0 / 3.0);
+}
+
+template <class real>
+__device__ __forceinline__ constexpr bool is_mp() { return sizeof(real) == 4; }
+
+// ----------------------------------------------------------------------------
+// state access
+// ----------------------------------------------------------------------------
+template <class Eq, class real>
+__device__ __forceinline__ void load_node(const StepArgs<real>& a, int np, int e, int k, real* u)
+{
+#pragma unroll
+    for (int v = 0; v < Eq::M; ++v) {
+        size_t i = ((size_t)v * a.ne + e) * np + k;
+        if constexpr (is_mp<real>())
+            u[v] = (real)(a.ubar[(size_t)v * a.ne + e] + (double)a.u[i]);
+        else
+            u[v] = a.u[i];
+    }
+}
+
+// neighbour element across a face (dir 0: x, 1: y; side 0: low, 1: high), -1 at a non-periodic boundary
+template <class real>
+__device__ __forceinline__ int nbr(const StepArgs<real>& a, int ex, int ey, int dir, int side)
+{
+    if (dir == 0) {
+        int t = ex + (side ? 1 : -1);
+        if (t < 0) { if (a.bc[0] != BC_PERIODIC) return -1; t = a.nx - 1; }
+        if (t >= a.nx) { if (a.bc[1] != BC_PERIODIC) return -1; t = 0; }
+        return ey * a.nx + t;
+    }
+    int t = ey + (side ? 1 : -1);
+    if (t < 0) { if (a.bc[2] != BC_PERIODIC) return -1; t = a.ny - 1; }
+    if (t >= a.ny) { if (a.bc[3] != BC_PERIODIC) return -1; t = 0; }
+    return t * a.nx + ex;
+}
+
+// far-field ghost state at point t of the boundary face of element (ex, ey); null otherwise
+template <class real>
+__device__ __forceinline__ const real* ghost_at(const StepArgs<real>& a, int M, int nd, int nq,
+                                                int ex, int ey, int dir, int side, int t)
+{
+    if (a.bc[dir * 2 + side] != BC_FARFIELD) return nullptr;
+    size_t xsz = (size_t)a.ny * nq * M, ysz = (size_t)a.nx * nd * M;
+    if (dir == 0) return a.ghost + side * xsz + ((size_t)ey * nq + t) * M;
+    return a.ghost + 2 * xsz + side * ysz + ((size_t)ex * nd + t) * M;
+}
+
+// ----------------------------------------------------------------------------
+// admissibility helpers (FP64)
+// ----------------------------------------------------------------------------
+template <class Eq>
+__device__ double bisect_root(int k, const double* a, const double* b, double eps, const Phys& P)
+{
+    double lo = 0.0, hi = 1.0, z[Eq::M];
+    for (int it = 0; it < 60; ++it) {
+        double mid = 0.5 * (lo + hi);
+#pragma unroll
+        for (int v = 0; v < Eq::M; ++v) z[v] = a[v] + mid * (b[v] - a[v]);
+        if (Eq::adm(k, z, P) >= eps) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// fraction of the segment a -> b keeping P_k >= eps: concavity bound, else bisection
+template <class Eq>
+__device__ double segment_fraction(int k, const double* a, const double* b, double eps, const Phys& P)
+{
+    double Pa = Eq::adm(k, a, P), Pb = Eq::adm(k, b, P);
+    if (Pb >= eps) return 1.0;
+    if (Eq::concave(k)) {
+        double t = (Pa - eps) / (Pa - Pb);
+        return t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+    }
+    return bisect_root<Eq>(k, a, b, eps, P);
+}
+
+template <class Eq>
+__device__ bool admissible_eps(const double* u, const double* eps, const Phys& P)
+{
+#pragma unroll
+    for (int k = 0; k < Eq::K; ++k)
+        if (!(Eq::adm(k, u, P) >= eps[k])) return false;
+    return true;
+}
+
+template <class Eq, class real>
+__device__ __forceinline__ void flux_dir(int d, const real* u, real* f, const Phys& P)
+{
+    if (d == 0) Eq::fx(u, f, P); else Eq::gy(u, f, P);
+}
+
+template <class Eq, class real>
+__device__ __forceinline__ void rusanov(int d, const real* a, const real* b, real* out, const Phys& P)
+{
+    real fa[Eq::M], fb[Eq::M];
+    flux_dir<Eq>(d, a, fa, P);
+    flux_dir<Eq>(d, b, fb, P);
+    real la = d == 0 ? Eq::sx(a, P) : Eq::sy(a, P);
+    real lb = d == 0 ? Eq::sx(b, P) : Eq::sy(b, P);
+    real lam = fmax(la, lb);
+#pragma unroll
+    for (int v = 0; v < Eq::M; ++v) out[v] = (real)0.5 * (fa[v] + fb[v]) - (real)0.5 * lam * (b[v] - a[v]);
+}
+
+__device__ __forceinline__ void atomic_min_pos(unsigned long long* p, double v)
+{
+    atomicMin(p, (unsigned long long)__double_as_longlong(v));
+}
+__device__ __forceinline__ void atomic_max_pos(unsigned long long* p, double v)
+{
+    atomicMax(p, (unsigned long long)__double_as_longlong(v));
+}
+
+// ----------------------------------------------------------------------------
+// MUSCL-Hancock predictor of one subcell (Sec. 4.2; reading: minmod slopes
+// on the non-uniform subcell grid, slope scaled to keep the reconstructed
+// face values admissible, Hancock half step, zero slope when the predicted
+// values are not admissible).  The element's nodal values are in sh[v][k].
+// Outputs the predicted values at the x faces (xm, xp) and y faces (ym, yp).
+// ----------------------------------------------------------------------------
+template <class Eq, int N, class real>
+__device__ void mh_subcell(const StepArgs<real>& a, int e, int ex, int ey, int p, int q,
+                           const real* u, const real (*sh)[Geo<Eq::DIM, N>::np], double dt,
+                           real* xm, real* xp, real* ym, real* yp, int& nlim, int& nfb)
+{
+    using G = Geo<Eq::DIM, N>;
+    constexpr int M = Eq::M, nd = G::nd, nq = G::nq, np = G::np, K = Eq::K;
+    const Phys& P = a.phys;
+    const int k = q * nd + p;
+    real sx[M], sy[M];
+#pragma unroll
+    for (int v = 0; v < M; ++v) { sx[v] = 0; sy[v] = 0; }
+    double ud[M], eps[K > 0 ? K : 1];
+#pragma unroll
+    for (int v = 0; v < M; ++v) ud[v] = (double)u[v];
+    bool u_ok = true;
+#pragma unroll
+    for (int kk = 0; kk < K; ++kk) {
+        eps[kk] = 0.1 * Eq::adm(kk, ud, P);
+        if (!(eps[kk] > 0.0)) u_ok = false;
+    }
+    const bool mh = a.blend == BLEND_MH && u_ok;
+    if (mh) {
+#pragma unroll
+        for (int d = 0; d < Eq::DIM; ++d) {
+            const int pos = d == 0 ? p : q;
+            real um[M], up[M];
+            real x0 = a.R.xi[pos], xmn, xpn;
+            if (pos > 0) {
+                const int kn = d == 0 ? k - 1 : k - nd;
+#pragma unroll
+                for (int v = 0; v < M; ++v) um[v] = sh[v][kn];
+                xmn = a.R.xi[pos - 1];
+            } else {
+                int en = nbr(a, ex, ey, d, 0);
+                if (en >= 0) {
+                    load_node<Eq>(a, np, en, d == 0 ? q * nd + N : N * nd + p, um);
+                } else {
+                    const real* g = ghost_at(a, M, nd, nq, ex, ey, d, 0, d == 0 ? q : p);
+#pragma unroll
+                    for (int v = 0; v < M; ++v) um[v] = g ? g[v] : u[v];
+                }
+                xmn = a.R.xi[N] - (real)1;
+            }
+            if (pos < N) {
+                const int kn = d == 0 ? k + 1 : k + nd;
+#pragma unroll
+                for (int v = 0; v < M; ++v) up[v] = sh[v][kn];
+                xpn = a.R.xi[pos + 1];
+            } else {
+                int en = nbr(a, ex, ey, d, 1);
+                if (en >= 0) {
+                    load_node<Eq>(a, np, en, d == 0 ? q * nd + 0 : 0 * nd + p, up);
+                } else {
+                    const real* g = ghost_at(a, M, nd, nq, ex, ey, d, 1, d == 0 ? q : p);
+#pragma unroll
+                    for (int v = 0; v < M; ++v) up[v] = g ? g[v] : u[v];
+                }
+                xpn = (real)1 + a.R.xi[0];
+            }
+#pragma unroll
+            for (int v = 0; v < M; ++v) {
+                real s1 = (u[v] - um[v]) / (x0 - xmn), s2 = (up[v] - u[v]) / (xpn - x0);
+                real s = s1 * s2 <= 0 ? (real)0 : (fabs(s1) < fabs(s2) ? s1 : s2);
+                if (d == 0) sx[v] = s; else sy[v] = s;
+            }
+        }
+    }
+    const real hxm = a.R.sub[p] - a.R.xi[p], hxp = a.R.sub[p + 1] - a.R.xi[p];
+    const real hym = Eq::DIM == 2 ? a.R.sub[q] - a.R.xi[q] : (real)0;
+    const real hyp = Eq::DIM == 2 ? a.R.sub[q + 1] - a.R.xi[q] : (real)0;
+    constexpr int NF = Eq::DIM == 2 ? 4 : 2;
+    if (mh) {
+#pragma unroll
+        for (int kk = 0; kk < K; ++kk) {
+            double th = 1.0;
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                double fv[M];
+#pragma unroll
+                for (int v = 0; v < M; ++v) {
+                    real s = f < 2 ? sx[v] : sy[v];
+                    real h = f == 0 ? hxm : (f == 1 ? hxp : (f == 2 ? hym : hyp));
+                    fv[v] = (double)(u[v] + s * h);
+                }
+                double t = segment_fraction<Eq>(kk, ud, fv, eps[kk], P);
+                th = t < th ? t : th;
+            }
+            if (th < 1.0) {
+                ++nlim;
+#pragma unroll
+                for (int v = 0; v < M; ++v) { sx[v] = (real)(th * (double)sx[v]); sy[v] = (real)(th * (double)sy[v]); }
+            }
+        }
+    }
+    real fv0[M], fv1[M], fv2[M], fv3[M];
+#pragma unroll
+    for (int v = 0; v < M; ++v) {
+        fv0[v] = u[v] + sx[v] * hxm;
+        fv1[v] = u[v] + sx[v] * hxp;
+        fv2[v] = u[v] + sy[v] * hym;
+        fv3[v] = u[v] + sy[v] * hyp;
+    }
+    // Hancock half-step predictor
+    real fa[M], fb[M], delta[M];
+    Eq::fx(fv0, fa, P);
+    Eq::fx(fv1, fb, P);
+    const real hdt = (real)(0.5 * dt);
+    const real cx = hdt / (a.R.w[p] * (real)a.dx);
+#pragma unroll
+    for (int v = 0; v < M; ++v) delta[v] = -cx * (fb[v] - fa[v]);
+    if constexpr (Eq::DIM == 2) {
+        Eq::gy(fv2, fa, P);
+        Eq::gy(fv3, fb, P);
+        const real cy = hdt / (a.R.w[q] * (real)a.dy);
+#pragma unroll
+        for (int v = 0; v < M; ++v) delta[v] -= cy * (fb[v] - fa[v]);
+    }
+#pragma unroll
+    for (int v = 0; v < M; ++v) {
+        xm[v] = fv0[v] + delta[v];
+        xp[v] = fv1[v] + delta[v];
+        ym[v] = Eq::DIM == 2 ? fv2[v] + delta[v] : u[v];
+        yp[v] = Eq::DIM == 2 ? fv3[v] + delta[v] : u[v];
+    }
+    bool ok = true;
+    if constexpr (K > 0) {
+        double ev[M];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+#pragma unroll
+            for (int v = 0; v < M; ++v)
+                ev[v] = (double)(f == 0 ? xm[v] : (f == 1 ? xp[v] : (f == 2 ? ym[v] : yp[v])));
+            if (!admissible_eps<Eq>(ev, eps, P)) ok = false;
+        }
+    }
+    if (!ok) {
+        ++nfb;
+#pragma unroll
+        for (int v = 0; v < M; ++v) { xm[v] = u[v]; xp[v] = u[v]; ym[v] = u[v]; yp[v] = u[v]; }
+    }
+}
+
+// ----------------------------------------------------------------------------
+// k_local
+// ----------------------------------------------------------------------------
+template <class Eq, int N, class real, bool LIM>
+__global__ void __launch_bounds__(256) k_local(const StepArgs<real> a)
+{
+    using G = Geo<Eq::DIM, N>;
+    constexpr int M = Eq::M, DIM = Eq::DIM, nd = G::nd, nq = G::nq, np = G::np, EB = G::EB;
+    constexpr int S = N + 1 < 4 ? N + 1 : 4;
+    constexpr int MY = DIM == 2 ? M : 1;
+    __shared__ real sh_u[EB][M][np];
+    __shared__ real sh_f[EB][M][np];
+    __shared__ real sh_g[EB][MY][np];
+    __shared__ real sh_h[EB][M][4 * nd];
+
+    const Phys& P = a.phys;
+    const int le = threadIdx.x / np, k = threadIdx.x - le * np;
+    const int p = k % nd, q = k / nd;
+    const int e0 = blockIdx.x * EB + le;
+    const bool act = e0 < a.ne;
+    const int e = act ? e0 : a.ne - 1;
+    const int ex = e % a.nx, ey = e / a.nx;
+    const double dt = *a.dt_dev;
+    const real rdt = (real)dt, idx = (real)(1.0 / a.dx), idy = (real)(1.0 / a.dy);
+    const real xn = (real)(a.x0 + ((double)ex + (double)a.R.xi[p]) * a.dx);
+    const real yn = DIM == 2 ? (real)(a.y0 + ((double)ey + (double)a.R.xi[q]) * a.dy) : (real)0;
+    const bool src = Eq::ID == 3 && P.source;
+    const int C = a.C;
+    const size_t nes = (size_t)a.ne;
+
+    real un[M];
+    load_node<Eq>(a, np, e, k, un);
+
+    if constexpr (LIM) {
+        // ---- smoothness indicator (reading of the Hennemann indicator) ----
+#pragma unroll
+        for (int v = 0; v < M; ++v) sh_u[le][v][k] = un[v];
+        if (a.indicator == IND_PAPER) sh_f[le][0][k] = Eq::ind(un, P);
+        __syncthreads();
+        if (a.indicator == IND_PAPER) {
+            real m = 0;
+            if constexpr (DIM == 2) {
+#pragma unroll
+                for (int s2 = 0; s2 < nd; ++s2)
+#pragma unroll
+                    for (int r = 0; r < nd; ++r)
+                        m += a.R.w[r] * a.R.w[s2] * a.R.L[p][r] * a.R.L[q][s2] * sh_f[le][0][s2 * nd + r];
+            } else {
+#pragma unroll
+                for (int r = 0; r < nd; ++r) m += a.R.w[r] * a.R.L[p][r] * sh_f[le][0][r];
+            }
+            sh_g[le][0][k] = m * m;
+        }
+        __syncthreads();
+        if (k == 0 && act) {
+            if (a.indicator == IND_PAPER) {
+                double en[nd];
+#pragma unroll
+                for (int s2 = 0; s2 < nd; ++s2) en[s2] = 0.0;
+#pragma unroll
+                for (int kk = 0; kk < np; ++kk) {
+                    int pp = kk % nd, qq = kk / nd;
+                    en[pp > qq ? pp : qq] += (double)sh_g[le][0][kk];
+                }
+                double totN = 0.0, totNm1 = 0.0;
+#pragma unroll
+                for (int s2 = 0; s2 <= N; ++s2) totN += en[s2];
+#pragma unroll
+                for (int s2 = 0; s2 < N; ++s2) totNm1 += en[s2];
+                double E1 = totN > 0.0 ? en[N] / totN : 0.0;
+                double E2 = totNm1 > 0.0 ? en[N - 1] / totNm1 : 0.0;
+                double E = E1 > E2 ? E1 : E2;
+                const double T = 0.5 * pow(10.0, -1.8 * pow((double)(N + 1), 0.25));
+                const double sharp = log(9999.0);
+                double al_d = 1.0 / (1.0 + exp(-(sharp / T) * (E - T)));
+                if (al_d < a.alpha_min) al_d = 0.0;
+                if (al_d > a.alpha_max) al_d = a.alpha_max;
+                a.alpha_raw[e] = al_d;
+            } else if (a.indicator == IND_CONST) {
+                a.alpha_raw[e] = a.alpha_const;
+            } else if (a.indicator == IND_GIVEN) {
+                a.alpha_raw[e] = a.alpha_given[e];
+            }
+        }
+        // ---- MUSCL-Hancock predictor and interior subface fluxes ----
+        real xm[M], xp[M], ym[M], yp[M];
+        int nlim = 0, nfb = 0;
+        mh_subcell<Eq, N>(a, e, ex, ey, p, q, un, sh_u[le], dt, xm, xp, ym, yp, nlim, nfb);
+        __syncthreads();
+#pragma unroll
+        for (int v = 0; v < M; ++v) {
+            sh_f[le][v][k] = xm[v];
+            if constexpr (DIM == 2) sh_g[le][v][k] = ym[v];
+        }
+        __syncthreads();
+        if (act) {
+            if (p < N) {
+                real nb[M], fs[M];
+#pragma unroll
+                for (int v = 0; v < M; ++v) nb[v] = sh_f[le][v][k + 1];
+                rusanov<Eq>(0, xp, nb, fs, P);
+                if (p == N - 1)
+#pragma unroll
+                    for (int v = 0; v < M; ++v) a.trx[((size_t)(1 * C + 2 * M + 1 + M + v) * nes + e) * nq + q] = fs[v];
+                if (p == 0)
+#pragma unroll
+                    for (int v = 0; v < M; ++v) a.trx[((size_t)(0 * C + 2 * M + 1 + M + v) * nes + e) * nq + q] = fs[v];
+            }
+            if (p == N)
+#pragma unroll
+                for (int v = 0; v < M; ++v) a.trx[((size_t)(1 * C + 2 * M + 1 + v) * nes + e) * nq + q] = xp[v];
+            if (p == 0)
+#pragma unroll
+                for (int v = 0; v < M; ++v) a.trx[((size_t)(0 * C + 2 * M + 1 + v) * nes + e) * nq + q] = xm[v];
+            if constexpr (DIM == 2) {
+                if (q < N) {
+                    real nb[M], fs[M];
+#pragma unroll
+                    for (int v = 0; v < M; ++v) nb[v] = sh_g[le][v][k + nd];
+                    rusanov<Eq>(1, yp, nb, fs, P);
+                    if (q == N - 1)
+#pragma unroll
+                        for (int v = 0; v < M; ++v) a.trY[((size_t)(1 * C + 2 * M + 1 + M + v) * nes + e) * nd + p] = fs[v];
+                    if (q == 0)
+#pragma unroll
+                        for (int v = 0; v < M; ++v) a.trY[((size_t)(0 * C + 2 * M + 1 + M + v) * nes + e) * nd + p] = fs[v];
+                }
+                if (q == N)
+#pragma unroll
+                    for (int v = 0; v < M; ++v) a.trY[((size_t)(1 * C + 2 * M + 1 + v) * nes + e) * nd + p] = yp[v];
+                if (q == 0)
+#pragma unroll
+                    for (int v = 0; v < M; ++v) a.trY[((size_t)(0 * C + 2 * M + 1 + v) * nes + e) * nd + p] = ym[v];
+            }
+            if (nlim) atomicAdd(&a.diag[D_SLOPELIM], (unsigned long long)nlim);
+            if (nfb) atomicAdd(&a.diag[D_FALLBACK], (unsigned long long)nfb);
+        }
+        __syncthreads();
+    }
+
+    // ---- local cRK procedure ----
+    real ui[M], F[M], Gs[M], U[M], Sa[M], trX[M], trYv[M];
+    real sigX = 0, sigY = 0;
+#pragma unroll
+    for (int v = 0; v < M; ++v) { ui[v] = un[v]; F[v] = 0; Gs[v] = 0; U[v] = 0; Sa[v] = 0; trX[v] = 0; trYv[v] = 0; }
+
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+        real f[M], g[M], s[M];
+        Eq::fx(ui, f, P);
+        if constexpr (DIM == 2) Eq::gy(ui, g, P);
+        if (src) Eq::src(ui, xn, yn, s, P);
+        else {
+#pragma unroll
+            for (int v = 0; v < M; ++v) s[v] = 0;
+        }
+        const real bi = (real)tab_b(S, i);
+#pragma unroll
+        for (int v = 0; v < M; ++v) {
+            F[v] += bi * f[v];
+            if constexpr (DIM == 2) Gs[v] += bi * g[v];
+            U[v] += bi * ui[v];
+            Sa[v] += bi * s[v];
+            sh_u[le][v][k] = ui[v];
+            sh_f[le][v][k] = f[v];
+            if constexpr (DIM == 2) sh_g[le][v][k] = g[v];
+        }
+        __syncthreads();
+        // EA traces: flux of the interpolated stage value at the faces
+        if (p == 0 || p == N) {
+            const real* lw = p == 0 ? a.R.l0 : a.R.l1;
+            real uf[M], ff[M];
+#pragma unroll
+            for (int v = 0; v < M; ++v) {
+                real s2 = 0;
+#pragma unroll
+                for (int r = 0; r < nd; ++r) s2 += lw[r] * sh_u[le][v][q * nd + r];
+                uf[v] = s2;
+            }
+            Eq::fx(uf, ff, P);
+#pragma unroll
+            for (int v = 0; v < M; ++v) trX[v] += bi * ff[v];
+            if (i == 0) sigX = Eq::sig_trace(0, uf, un, P);
+        }
+        if constexpr (DIM == 2) {
+            if (q == 0 || q == N) {
+                const real* lw = q == 0 ? a.R.l0 : a.R.l1;
+                real uf[M], ff[M];
+#pragma unroll
+                for (int v = 0; v < M; ++v) {
+                    real s2 = 0;
+#pragma unroll
+                    for (int r = 0; r < nd; ++r) s2 += lw[r] * sh_u[le][v][r * nd + p];
+                    uf[v] = s2;
+                }
+                Eq::gy(uf, ff, P);
+#pragma unroll
+                for (int v = 0; v < M; ++v) trYv[v] += bi * ff[v];
+                if (i == 0) sigY = Eq::sig_trace(1, uf, un, P);
+            }
+        }
+        if (i < S - 1) {
+            const real ai = (real)tab_a(S, i);
+#pragma unroll
+            for (int v = 0; v < M; ++v) {
+                real df = 0, dg = 0;
+#pragma unroll
+                for (int r = 0; r < nd; ++r) df += a.R.D[p][r] * sh_f[le][v][q * nd + r];
+                if constexpr (DIM == 2) {
+#pragma unroll
+                    for (int r = 0; r < nd; ++r) dg += a.R.D[q][r] * sh_g[le][v][r * nd + p];
+                }
+                ui[v] = un[v] - rdt * ai * (df * idx + dg * idy - s[v]);
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---- volume part of the FR update, traces of U, extrapolated averaged flux ----
+#pragma unroll
+    for (int v = 0; v < M; ++v) {
+        sh_u[le][v][k] = U[v];
+        sh_f[le][v][k] = F[v];
+        if constexpr (DIM == 2) sh_g[le][v][k] = Gs[v];
+    }
+    __syncthreads();
+    real vol[M], Ux[M], Uy[M];
+#pragma unroll
+    for (int v = 0; v < M; ++v) {
+        real df = 0, dg = 0;
+#pragma unroll
+        for (int r = 0; r < nd; ++r) df += a.R.D[p][r] * sh_f[le][v][q * nd + r];
+        if constexpr (DIM == 2) {
+#pragma unroll
+            for (int r = 0; r < nd; ++r) dg += a.R.D[q][r] * sh_g[le][v][r * nd + p];
+        }
+        vol[v] = df * idx + dg * idy;
+    }
+    if (p == 0 || p == N) {
+        const real* lw = p == 0 ? a.R.l0 : a.R.l1;
+        const int side = p == 0 ? 0 : 1;
+#pragma unroll
+        for (int v = 0; v < M; ++v) {
+            real su = 0, sf = 0;
+#pragma unroll
+            for (int r = 0; r < nd; ++r) {
+                su += lw[r] * sh_u[le][v][q * nd + r];
+                sf += lw[r] * sh_f[le][v][q * nd + r];
+            }
+            Ux[v] = su;
+            sh_h[le][v][side * nd + q] = sf;
+        }
+    }
+    if constexpr (DIM == 2) {
+        if (q == 0 || q == N) {
+            const real* lw = q == 0 ? a.R.l0 : a.R.l1;
+            const int side = q == 0 ? 0 : 1;
+#pragma unroll
+            for (int v = 0; v < M; ++v) {
+                real su = 0, sg = 0;
+#pragma unroll
+                for (int r = 0; r < nd; ++r) {
+                    su += lw[r] * sh_u[le][v][r * nd + p];
+                    sg += lw[r] * sh_g[le][v][r * nd + p];
+                }
+                Uy[v] = su;
+                sh_h[le][v][(2 + side) * nd + p] = sg;
+            }
+        }
+    }
+    __syncthreads();
+    if (!act) return;
+    const size_t gi = (size_t)e * np + k;
+#pragma unroll
+    for (int v = 0; v < M; ++v) {
+        real corr = (sh_h[le][v][nd + q] * a.R.bR[p] - sh_h[le][v][q] * a.R.bL[p]) * idx;
+        if constexpr (DIM == 2)
+            corr += (sh_h[le][v][3 * nd + p] * a.R.bR[q] - sh_h[le][v][2 * nd + p] * a.R.bL[q]) * idy;
+        a.uHp[(size_t)v * nes * np + gi] = un[v] - rdt * (vol[v] - Sa[v]) + rdt * corr;
+        if (src && a.dtS) a.dtS[(size_t)v * nes * np + gi] = rdt * Sa[v];
+    }
+    if (p == 0 || p == N) {
+        const int side = p == 0 ? 0 : 1;
+#pragma unroll
+        for (int v = 0; v < M; ++v) {
+            a.trx[((size_t)(side * C + v) * nes + e) * nq + q] = trX[v];
+            a.trx[((size_t)(side * C + M + v) * nes + e) * nq + q] = Ux[v];
+        }
+        a.trx[((size_t)(side * C + 2 * M) * nes + e) * nq + q] = sigX;
+    }
+    if constexpr (DIM == 2) {
+        if (q == 0 || q == N) {
+            const int side = q == 0 ? 0 : 1;
+#pragma unroll
+            for (int v = 0; v < M; ++v) {
+                a.trY[((size_t)(side * C + v) * nes + e) * nd + p] = trYv[v];
+                a.trY[((size_t)(side * C + M + v) * nes + e) * nd + p] = Uy[v];
+            }
+            a.trY[((size_t)(side * C + 2 * M) * nes + e) * nd + p] = sigY;
+        }
+    }
+}
+
+// smoothed blending coefficient alpha_e <- max(alpha_e, max_nbr alpha / 2)
+template <class real>
+__device__ __forceinline__ double alpha_smoothed(const StepArgs<real>& a, int e, int dim)
+{
+    double al = a.alpha_raw[e];
+    if ((a.indicator == IND_PAPER || a.indicator == IND_LEARNED) && a.smooth) {
+        int ex = e % a.nx, ey = e / a.nx;
+        for (int d = 0; d < dim; ++d)
+            for (int s = 0; s < 2; ++s) {
+                int en = nbr(a, ex, ey, d, s);
+                if (en >= 0) {
+                    double h = 0.5 * a.alpha_raw[en];
+                    al = h > al ? h : al;
+                }
+            }
+    }
+    return al;
+}
+
+// Share of direction d in the low-order update of a face-adjacent subcell:
+// proportional to the subcell's own nodal rate sigma_d / (w h_d).
+template <class Eq, int N, class real>
+__device__ __forceinline__ double dir_share(const StepArgs<real>& a, int d, int t, const real* u)
+{
+    if constexpr (Eq::DIM == 1) return 1.0;
+    double ax = (double)Eq::sx(u, a.phys) / ((double)(d == 0 ? a.R.w[N] : a.R.w[t]) * a.dx);
+    double ay = (double)Eq::sy(u, a.phys) / ((double)(d == 0 ? a.R.w[t] : a.R.w[N]) * a.dy);
+    return (d == 0 ? ax : ay) / (ax + ay);
+}
+
+// ----------------------------------------------------------------------------
+// k_face: one lane per face point of direction D
+// ----------------------------------------------------------------------------
+template <class Eq, int N, class real, bool LIM, int D>
+__global__ void __launch_bounds__(256) k_face(const StepArgs<real> a)
+{
+    using G = Geo<Eq::DIM, N>;
+    constexpr int M = Eq::M, nd = G::nd, nq = G::nq, np = G::np, K = Eq::K;
+    const Phys& P = a.phys;
+    const int npt = D == 0 ? nq : nd;
+    const long long total = D == 0 ? (long long)a.ny * (a.nx + 1) * nq : (long long)(a.ny + 1) * a.nx * nd;
+    const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= total) return;
+    const int t = (int)(tid % npt);
+    int eL, eR, exL, eyL, exR, eyR;
+    const real* trb = D == 0 ? a.trx : a.trY;
+    const size_t nes = (size_t)a.ne;
+    const int C = a.C;
+    size_t outi;
+    if (D == 0) {
+        const int i = (int)((tid / npt) % (a.nx + 1));
+        const int ey = (int)(tid / ((long long)npt * (a.nx + 1)));
+        eL = i > 0 ? ey * a.nx + i - 1 : (a.bc[0] == BC_PERIODIC ? ey * a.nx + a.nx - 1 : -1);
+        eR = i < a.nx ? ey * a.nx + i : (a.bc[1] == BC_PERIODIC ? ey * a.nx : -1);
+        exL = i > 0 ? i - 1 : a.nx - 1; eyL = ey;
+        exR = i < a.nx ? i : 0; eyR = ey;
+        outi = ((size_t)ey * (a.nx + 1) + i) * nq + t;
+    } else {
+        const int ex = (int)((tid / npt) % a.nx);
+        const int j = (int)(tid / ((long long)npt * a.nx));
+        eL = j > 0 ? (j - 1) * a.nx + ex : (a.bc[2] == BC_PERIODIC ? (a.ny - 1) * a.nx + ex : -1);
+        eR = j < a.ny ? j * a.nx + ex : (a.bc[3] == BC_PERIODIC ? ex : -1);
+        exL = ex; eyL = j > 0 ? j - 1 : a.ny - 1;
+        exR = ex; eyR = j < a.ny ? j : 0;
+        outi = ((size_t)j * a.nx + ex) * nd + t;
+    }
+    const bool hA = eL >= 0, hB = eR >= 0;
+    // ghost states (far-field) for a missing side
+    const real* gA = hA ? nullptr : ghost_at(a, M, nd, nq, exR, eyR, D, 0, t);
+    const real* gB = hB ? nullptr : ghost_at(a, M, nd, nq, exL, eyL, D, 1, t);
+    const int kA = D == 0 ? t * nd + N : N * nd + t;
+    const int kB = D == 0 ? t * nd : t;
+    const size_t pA = hA ? (size_t)eL * npt + t : 0, pB = hB ? (size_t)eR * npt + t : 0;
+#define TRA(c) trb[(size_t)(1 * C + (c)) * nes * npt + pA]
+#define TRB(c) trb[(size_t)(0 * C + (c)) * nes * npt + pB]
+    real Fm[M], Fp[M], Um[M], Up[M], uA[M], uB[M];
+    real sm = 0, sp = 0;
+    if (hA) {
+#pragma unroll
+        for (int v = 0; v < M; ++v) { Fm[v] = TRA(v); Um[v] = TRA(M + v); }
+        sm = TRA(2 * M);
+        load_node<Eq>(a, np, eL, kA, uA);
+    }
+    if (hB) {
+#pragma unroll
+        for (int v = 0; v < M; ++v) { Fp[v] = TRB(v); Up[v] = TRB(M + v); }
+        sp = TRB(2 * M);
+        load_node<Eq>(a, np, eR, kB, uB);
+    }
+    if (!hA) {
+        if (gA) {
+            flux_dir<Eq>(D, gA, Fm, P);
+#pragma unroll
+            for (int v = 0; v < M; ++v) { Um[v] = gA[v]; uA[v] = gA[v]; }
+            sm = Eq::sig_trace(D, gA, gA, P);
+        } else {
+#pragma unroll
+            for (int v = 0; v < M; ++v) { Fm[v] = Fp[v]; Um[v] = Up[v]; uA[v] = uB[v]; }
+            sm = sp;
+        }
+    }
+    if (!hB) {
+        if (gB) {
+            flux_dir<Eq>(D, gB, Fp, P);
+#pragma unroll
+            for (int v = 0; v < M; ++v) { Up[v] = gB[v]; uB[v] = gB[v]; }
+            sp = Eq::sig_trace(D, gB, gB, P);
+        } else {
+#pragma unroll
+            for (int v = 0; v < M; ++v) { Fp[v] = Fm[v]; Up[v] = Um[v]; uB[v] = uA[v]; }
+            sp = sm;
+        }
+    }
+    const real lam = fmax(sm, sp);
+    real F[M];
+#pragma unroll
+    for (int v = 0; v < M; ++v) F[v] = (real)0.5 * (Fm[v] + Fp[v]) - (real)0.5 * lam * (Up[v] - Um[v]);
+
+    if constexpr (LIM) {
+        real sA[M], sB[M], fLO[M];
+        if (hA) {
+#pragma unroll
+            for (int v = 0; v < M; ++v) sA[v] = TRA(2 * M + 1 + v);
+        }
+        if (hB) {
+#pragma unroll
+            for (int v = 0; v < M; ++v) sB[v] = TRB(2 * M + 1 + v);
+        }
+        if (!hA) {
+#pragma unroll
+            for (int v = 0; v < M; ++v) sA[v] = gA ? gA[v] : sB[v];
+        }
+        if (!hB) {
+#pragma unroll
+            for (int v = 0; v < M; ++v) sB[v] = gB ? gB[v] : sA[v];
+        }
+        rusanov<Eq>(D, sA, sB, fLO, P);
+        double aA = hA ? alpha_smoothed(a, eL, Eq::DIM) : 0.0;
+        double aB = hB ? alpha_smoothed(a, eR, Eq::DIM) : 0.0;
+        const real af = (real)(hA && hB ? 0.5 * (aA + aB) : (hA ? aA : aB));
+#pragma unroll
+        for (int v = 0; v < M; ++v) F[v] = (1 - af) * F[v] + af * fLO[v];
+
+        if constexpr (K > 0) {
+            if (a.flux_limiter) {
+                const double dt = *a.dt_dev;
+                const double h = D == 0 ? a.dx : a.dy;
+                double kA2 = 0.0, kB2 = 0.0;
+                double adjA[M], adjB[M], SA[M], SB[M], cAlo[M], cBlo[M], uAd[M], uBd[M];
+                if (hA) {
+                    kA2 = dt / ((double)a.R.w[N] * h * dir_share<Eq, N>(a, D, t, uA));
+#pragma unroll
+                    for (int v = 0; v < M; ++v) {
+                        adjA[v] = (double)TRA(3 * M + 1 + v);
+                        SA[v] = a.dtS ? (double)a.dtS[((size_t)v * nes + eL) * np + kA] : 0.0;
+                        uAd[v] = (double)uA[v];
+                        cAlo[v] = uAd[v] - kA2 * ((double)fLO[v] - adjA[v]) + SA[v];
+                    }
+                }
+                if (hB) {
+                    kB2 = dt / ((double)a.R.w[0] * h * dir_share<Eq, N>(a, D, t, uB));
+#pragma unroll
+                    for (int v = 0; v < M; ++v) {
+                        adjB[v] = (double)TRB(3 * M + 1 + v);
+                        SB[v] = a.dtS ? (double)a.dtS[((size_t)v * nes + eR) * np + kB] : 0.0;
+                        uBd[v] = (double)uB[v];
+                        cBlo[v] = uBd[v] - kB2 * (adjB[v] - (double)fLO[v]) + SB[v];
+                    }
+                }
+                double Fd[M];
+#pragma unroll
+                for (int v = 0; v < M; ++v) Fd[v] = (double)F[v];
+                double theta_face = 1.0;
+                bool bad = false;
+#pragma unroll
+                for (int kk = 0; kk < K; ++kk) {
+                    double th = 1.0;
+#pragma unroll
+                    for (int side = 0; side < 2; ++side) {
+                        if ((side == 0 && !hA) || (side == 1 && !hB)) continue;
+                        double cF[M];
+#pragma unroll
+                        for (int v = 0; v < M; ++v)
+                            cF[v] = side == 0 ? uAd[v] - kA2 * (Fd[v] - adjA[v]) + SA[v]
+                                              : uBd[v] - kB2 * (adjB[v] - Fd[v]) + SB[v];
+                        const double* lo = side == 0 ? cAlo : cBlo;
+                        double Plo = Eq::adm(kk, lo, P);
+                        if (!(Plo > 0.0)) { bad = true; th = 0.0; continue; }
+                        double t2 = segment_fraction<Eq>(kk, lo, cF, 0.1 * Plo, P);
+                        th = t2 < th ? t2 : th;
+                    }
+                    if (th < 1.0) {
+#pragma unroll
+                        for (int v = 0; v < M; ++v) Fd[v] = th * Fd[v] + (1.0 - th) * (double)fLO[v];
+                    }
+                    theta_face = th < theta_face ? th : theta_face;
+                }
+#pragma unroll
+                for (int v = 0; v < M; ++v) F[v] = (real)Fd[v];
+                if (theta_face < 1.0) {
+                    atomicAdd(&a.diag[D_FLUXLIM], 1ull);
+                    atomic_min_pos(&a.diag[D_THFLUX], theta_face);
+                }
+                if (bad) atomicAdd(&a.diag[D_LOBAD], 1ull);
+            }
+        }
+    }
+#undef TRA
+#undef TRB
+    real* out = D == 0 ? a.Fx : a.Gy;
+    const size_t nf = D == 0 ? (size_t)a.ny * (a.nx + 1) * nq : (size_t)(a.ny + 1) * a.nx * nd;
+#pragma unroll
+    for (int v = 0; v < M; ++v) out[(size_t)v * nf + outi] = F[v];
+}
+
+// ----------------------------------------------------------------------------
+// k_update
+// ----------------------------------------------------------------------------
+template <class Eq, int N, class real, bool LIM>
+__global__ void __launch_bounds__(256) k_update(const StepArgs<real> a)
+{
+    using G = Geo<Eq::DIM, N>;
+    constexpr int M = Eq::M, DIM = Eq::DIM, nd = G::nd, nq = G::nq, np = G::np, EB = G::EB, K = Eq::K;
+    constexpr bool MP = is_mp<real>();
+    __shared__ real sh_u[EB][M][np];
+    __shared__ real sh_f[EB][M][np];
+    __shared__ real sh_g[EB][DIM == 2 ? M : 1][np];
+    __shared__ double sh_d[EB][np];
+    __shared__ double sh_m[EB][M];
+
+    const Phys& P = a.phys;
+    const int le = threadIdx.x / np, k = threadIdx.x - le * np;
+    const int p = k % nd, q = k / nd;
+    const int e0 = blockIdx.x * EB + le;
+    const bool act = e0 < a.ne;
+    const int e = act ? e0 : a.ne - 1;
+    const int ex = e % a.nx, ey = e / a.nx;
+    const double dt = *a.dt_dev;
+    const real rdt = (real)dt, idx = (real)(1.0 / a.dx), idy = (real)(1.0 / a.dy);
+    const size_t nes = (size_t)a.ne, gi = (size_t)e * np + k;
+    const size_t nfx = (size_t)a.ny * (a.nx + 1) * nq, nfy = (size_t)(a.ny + 1) * a.nx * nd;
+    const size_t iL = ((size_t)ey * (a.nx + 1) + ex) * nq + q, iR = iL + nq;
+    const size_t iB = ((size_t)ey * a.nx + ex) * nd + p, iT = iB + (size_t)a.nx * nd;
+
+    real uH[M];
+#pragma unroll
+    for (int v = 0; v < M; ++v) {
+        real FL = a.Fx[v * nfx + iL], FR = a.Fx[v * nfx + iR];
+        real val = a.uHp[v * nes * np + gi] - rdt * idx * (FR * a.R.bR[p] - FL * a.R.bL[p]);
+        if constexpr (DIM == 2) {
+            real GB = a.Gy[v * nfy + iB], GT = a.Gy[v * nfy + iT];
+            val -= rdt * idy * (GT * a.R.bR[q] - GB * a.R.bL[q]);
+        }
+        uH[v] = val;
+    }
+    real unew[M];
+#pragma unroll
+    for (int v = 0; v < M; ++v) unew[v] = uH[v];
+
+    if constexpr (LIM) {
+        const double al = alpha_smoothed(a, e, DIM);
+        if (k == 0 && act) {
+            a.alpha_out[e] = al;
+            if (al > 0.0) atomicAdd(&a.diag[D_TROUBLED], 1ull);
+        }
+        const bool any = __syncthreads_or(act && al > 0.0);
+        if (any) {
+            // recompute the subcell predictor and the low-order update (eq. low.order.update)
+            real un[M];
+            load_node<Eq>(a, np, e, k, un);
+#pragma unroll
+            for (int v = 0; v < M; ++v) sh_u[le][v][k] = un[v];
+            __syncthreads();
+            real xm[M], xp[M], ym[M], yp[M];
+            int nlim = 0, nfb = 0;
+            if (al > 0.0) mh_subcell<Eq, N>(a, e, ex, ey, p, q, un, sh_u[le], dt, xm, xp, ym, yp, nlim, nfb);
+            __syncthreads();
+#pragma unroll
+            for (int v = 0; v < M; ++v) {
+                sh_f[le][v][k] = xm[v];
+                if constexpr (DIM == 2) sh_g[le][v][k] = ym[v];
+            }
+            __syncthreads();
+            real fxp[M], gyp[M];
+#pragma unroll
+            for (int v = 0; v < M; ++v) { fxp[v] = 0; gyp[v] = 0; }
+            if (al > 0.0) {
+                if (p < N) {
+                    real nb[M];
+#pragma unroll
+                    for (int v = 0; v < M; ++v) nb[v] = sh_f[le][v][k + 1];
+                    rusanov<Eq>(0, xp, nb, fxp, P);
+                }
+                if constexpr (DIM == 2) {
+                    if (q < N) {
+                        real nb[M];
+#pragma unroll
+                        for (int v = 0; v < M; ++v) nb[v] = sh_g[le][v][k + nd];
+                        rusanov<Eq>(1, yp, nb, gyp, P);
+                    }
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int v = 0; v < M; ++v) {
+                sh_f[le][v][k] = fxp[v];
+                if constexpr (DIM == 2) sh_g[le][v][k] = gyp[v];
+            }
+            __syncthreads();
+            if (al > 0.0) {
+                const real ralpha = (real)al;
+#pragma unroll
+                for (int v = 0; v < M; ++v) {
+                    real fm = p == 0 ? a.Fx[v * nfx + iL] : sh_f[le][v][k - 1];
+                    real fp = p == N ? a.Fx[v * nfx + iR] : fxp[v];
+                    real uL = un[v] - rdt / (a.R.w[p] * (real)a.dx) * (fp - fm);
+                    if constexpr (DIM == 2) {
+                        real gm = q == 0 ? a.Gy[v * nfy + iB] : sh_g[le][v][k - nd];
+                        real gp = q == N ? a.Gy[v * nfy + iT] : gyp[v];
+                        uL -= rdt / (a.R.w[q] * (real)a.dy) * (gp - gm);
+                    }
+                    if (a.dtS) uL += a.dtS[(size_t)v * nes * np + gi];
+                    unew[v] = (1 - ralpha) * uH[v] + ralpha * uL;
+                }
+            }
+        }
+    }
+
+    // ---- FP64 element means ----
+    const double wk = a.w64[p] * (DIM == 2 ? a.w64[q] : 1.0);
+    double ubar[M];
+#pragma unroll
+    for (int v = 0; v < M; ++v) {
+        sh_d[le][k] = wk * (double)unew[v];
+        __syncthreads();
+        if (k == 0) {
+            double s2 = 0.0;
+#pragma unroll
+            for (int kk = 0; kk < np; ++kk) s2 += sh_d[le][kk];
+            sh_m[le][v] = s2;
+        }
+        __syncthreads();
+        ubar[v] = sh_m[le][v];
+    }
+    double um[M];   // mean the scaling acts around
+    if constexpr (MP) {
+        // FP64 mean update from the face fluxes (eq. upmean with App. B source)
+        __syncthreads();
+        if (k == 0) {
+#pragma unroll
+            for (int v = 0; v < M; ++v) {
+                double s2 = a.ubar[(size_t)v * nes + e];
+                const size_t iL0 = ((size_t)ey * (a.nx + 1) + ex) * nq;
+                for (int qq = 0; qq < nq; ++qq)
+                    s2 -= dt / a.dx * (DIM == 2 ? a.w64[qq] : 1.0)
+                          * ((double)a.Fx[v * nfx + iL0 + nq + qq] - (double)a.Fx[v * nfx + iL0 + qq]);
+                if constexpr (DIM == 2) {
+                    const size_t iB0 = ((size_t)ey * a.nx + ex) * nd;
+                    for (int pp = 0; pp < nd; ++pp)
+                        s2 -= dt / a.dy * a.w64[pp]
+                              * ((double)a.Gy[v * nfy + iB0 + (size_t)a.nx * nd + pp] - (double)a.Gy[v * nfy + iB0 + pp]);
+                }
+                if (a.dtS)
+                    for (int kk = 0; kk < np; ++kk)
+                        s2 += a.w64[kk % nd] * (DIM == 2 ? a.w64[kk / nd] : 1.0)
+                              * (double)a.dtS[(size_t)v * nes * np + (size_t)e * np + kk];
+                sh_m[le][v] = s2;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int v = 0; v < M; ++v) um[v] = sh_m[le][v];
+    } else {
+#pragma unroll
+        for (int v = 0; v < M; ++v) um[v] = ubar[v];
+    }
+    // nodal values in FP64 relative to the mean the state keeps
+    double ud[M];
+#pragma unroll
+    for (int v = 0; v < M; ++v) ud[v] = MP ? um[v] + ((double)unew[v] - ubar[v]) : (double)unew[v];
+
+    // ---- Zhang-Shu scaling (reading: eps_k = min(1e-13, P_k(mean)); linear
+    //      root for density, 60-step bisection otherwise) ----
+    if constexpr (K > 0) {
+        if (a.scaling) {
+            // every lane runs every barrier: the per-element early exit is a flag
+            bool mean_bad = false;
+            double th_all = 1.0;
+#pragma unroll
+            for (int kk = 0; kk < K; ++kk) {
+                double Pbar = Eq::adm(kk, um, P);
+                if (!(Pbar > 0.0)) mean_bad = true;
+                double t = 1.0;
+                if (!mean_bad) {
+                    double eps = Pbar < 1e-13 ? Pbar : 1e-13;
+                    if (!(Eq::adm(kk, ud, P) >= eps)) {
+                        if (kk == 0) t = (um[0] - eps) / (um[0] - ud[0]);
+                        else t = bisect_root<Eq>(kk, um, ud, eps, P);
+                    }
+                }
+                sh_d[le][k] = t;
+                __syncthreads();
+                double th = 1.0;
+#pragma unroll
+                for (int kk2 = 0; kk2 < np; ++kk2) th = sh_d[le][kk2] < th ? sh_d[le][kk2] : th;
+                __syncthreads();
+                if (!mean_bad) {
+                    if (th < 1.0) {
+#pragma unroll
+                        for (int v = 0; v < M; ++v) ud[v] = um[v] + th * (ud[v] - um[v]);
+                    }
+                    th_all = th < th_all ? th : th_all;
+                }
+            }
+            if (mean_bad) th_all = 0.0;
+            if (k == 0 && act) {
+                if (mean_bad) atomicAdd(&a.diag[D_MEANBAD], 1ull);
+                else if (th_all < 1.0) atomicAdd(&a.diag[D_SCALED], 1ull);
+                if (th_all < 1.0) atomic_min_pos(&a.diag[D_THSCALE], th_all);
+            }
+        } else if (k == 0 && act) {
+            bool bad = false;
+#pragma unroll
+            for (int kk = 0; kk < K; ++kk)
+                if (!bad && !(Eq::adm(kk, um, P) > 0.0)) bad = true;
+            if (bad) atomicAdd(&a.diag[D_MEANBAD], 1ull);
+        }
+    }
+
+    // ---- store, next-step rate ----
+    if (act) {
+#pragma unroll
+        for (int v = 0; v < M; ++v) {
+            if constexpr (MP) a.u_out[(size_t)v * nes * np + gi] = (real)(ud[v] - um[v]);
+            else a.u_out[(size_t)v * nes * np + gi] = (real)ud[v];
+        }
+        if (k == 0) {
+            if constexpr (MP) {
+#pragma unroll
+                for (int v = 0; v < M; ++v) a.ubar_out[(size_t)v * nes + e] = um[v];
+            }
+        }
+    }
+    double rate = 0.0;
+    if (k == 0 && act) {
+        real ur[M];
+#pragma unroll
+        for (int v = 0; v < M; ++v) ur[v] = (real)um[v];
+        rate = (double)Eq::sx(ur, P) / a.dx + (DIM == 2 ? (double)Eq::sy(ur, P) / a.dy : 0.0);
+        if (!(rate == rate)) rate = 1e300;
+    }
+    // block max of the rate
+    __syncthreads();
+    sh_d[le][k] = rate;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r = 0.0;
+        for (int l = 0; l < EB; ++l) r = sh_d[l][0] > r ? sh_d[l][0] : r;
+        atomic_max_pos(a.rate_bits, r);
+    }
+}
+
+// ----------------------------------------------------------------------------
+// small kernels
+// ----------------------------------------------------------------------------
+struct PrepArgs {
+    double* dt_dev;
+    double* t_dev;
+    double t_end;
+    double dt_fixed;
+    double cfl_cs;
+    unsigned long long* rate_bits;
+    unsigned long long* diag;
+    long long* steps;
+};
+
+// time step of eq. time.step.2d from the rate of the current means, last step clipped
+static __global__ void k_prep(PrepArgs a)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double rate = __longlong_as_double((long long)*a.rate_bits);
+    double dt = a.dt_fixed > 0.0 ? a.dt_fixed : a.cfl_cs / rate;
+    double t = *a.t_dev;
+    if (a.t_end > 0.0 && t + dt > a.t_end) dt = a.t_end - t;
+    if (dt < 0.0) dt = 0.0;
+    *a.dt_dev = dt;
+    *a.t_dev = t + dt;
+    *a.rate_bits = 0ull;
+    for (int i = 0; i < D_THFLUX; ++i) a.diag[i] = 0ull;
+    a.diag[D_THFLUX] = (unsigned long long)__double_as_longlong(1.0);
+    a.diag[D_THSCALE] = (unsigned long long)__double_as_longlong(1.0);
+    *a.steps += 1;
+}
+
+// ----------------------------------------------------------------------------
+// state import / export, ghost states
+// ----------------------------------------------------------------------------
+template <class real>
+struct IoArgs {
+    int nx, ny, ne;
+    double dx, dy;
+    int bc[4];
+    const double* uin;     // FP64 nodal input  [var][e][k]
+    double* uout;          // FP64 nodal output [var][e][k]
+    double* means_out;     // FP64 means [var][e]
+    double* ubar;          // MP32 means of the state
+    real* u;               // FP64 nodal state / MP32 deviations
+    real* ghost;
+    Phys phys;
+    RefTab<real> R;
+    double w64[MAXND];
+    double l0_64[MAXND], l1_64[MAXND];
+    unsigned long long* diag;
+    unsigned long long* rate_bits;
+};
+
+// import an FP64 nodal state: admissibility check, MP32 split into FP64
+// means + FP32 deviations, rate of eq. time.step.2d; one lane per node
+template <class Eq, int N, class real>
+__global__ void __launch_bounds__(256) k_import(const IoArgs<real> a)
+{
+    using G = Geo<Eq::DIM, N>;
+    constexpr int M = Eq::M, DIM = Eq::DIM, nd = G::nd, np = G::np, EB = G::EB;
+    __shared__ double sh[EB][np];
+    __shared__ double shm[EB][M];
+    const int le = threadIdx.x / np, k = threadIdx.x - le * np;
+    const int p = k % nd, q = k / nd;
+    const int e0 = blockIdx.x * EB + le;
+    const bool act = e0 < a.ne;
+    const int e = act ? e0 : a.ne - 1;
+    const size_t nes = (size_t)a.ne, gi = (size_t)e * np + k;
+    double u[M];
+#pragma unroll
+    for (int v = 0; v < M; ++v) u[v] = a.uin[(size_t)v * nes * np + gi];
+    bool bad = false;
+#pragma unroll
+    for (int kk = 0; kk < Eq::K; ++kk)
+        if (!bad && !(Eq::adm(kk, u, a.phys) > 0.0)) bad = true;
+    if (bad && act) atomicAdd(&a.diag[D_MEANBAD], 1ull);
+    const double wk = a.w64[p] * (DIM == 2 ? a.w64[q] : 1.0);
+    double m[M];
+#pragma unroll
+    for (int v = 0; v < M; ++v) {
+        sh[le][k] = wk * u[v];
+        __syncthreads();
+        if (k == 0) {
+            double s = 0.0;
+            for (int kk = 0; kk < np; ++kk) s += sh[le][kk];
+            shm[le][v] = s;
+        }
+        __syncthreads();
+        m[v] = shm[le][v];
+    }
+    if (act) {
+#pragma unroll
+        for (int v = 0; v < M; ++v) {
+            if constexpr (is_mp<real>()) a.u[(size_t)v * nes * np + gi] = (real)(u[v] - m[v]);
+            else a.u[(size_t)v * nes * np + gi] = (real)u[v];
+        }
+        if (k == 0) {
+            if constexpr (is_mp<real>()) {
+#pragma unroll
+                for (int v = 0; v < M; ++v) a.ubar[(size_t)v * nes + e] = m[v];
+            }
+            real ur[M];
+#pragma unroll
+            for (int v = 0; v < M; ++v) ur[v] = (real)m[v];
+            double rate = (double)Eq::sx(ur, a.phys) / a.dx + (DIM == 2 ? (double)Eq::sy(ur, a.phys) / a.dy : 0.0);
+            if (!(rate == rate)) rate = 1e300;
+            atomic_max_pos(a.rate_bits, rate);
+        }
+    }
+}
+
+// export the nodal state in FP64 and the FP64 element means
+template <class Eq, int N, class real>
+__global__ void __launch_bounds__(256) k_export(const IoArgs<real> a)
+{
+    using G = Geo<Eq::DIM, N>;
+    constexpr int M = Eq::M, DIM = Eq::DIM, nd = G::nd, np = G::np, EB = G::EB;
+    __shared__ double sh[EB][np];
+    const int le = threadIdx.x / np, k = threadIdx.x - le * np;
+    const int p = k % nd, q = k / nd;
+    const int e0 = blockIdx.x * EB + le;
+    const bool act = e0 < a.ne;
+    const int e = act ? e0 : a.ne - 1;
+    const size_t nes = (size_t)a.ne, gi = (size_t)e * np + k;
+    const double wk = a.w64[p] * (DIM == 2 ? a.w64[q] : 1.0);
+#pragma unroll
+    for (int v = 0; v < M; ++v) {
+        double val = (double)a.u[(size_t)v * nes * np + gi];
+        if constexpr (is_mp<real>()) val += a.ubar[(size_t)v * nes + e];
+        if (act && a.uout) a.uout[(size_t)v * nes * np + gi] = val;
+        if (a.means_out) {
+            if constexpr (is_mp<real>()) {
+                // MP32 state: the FP64 mean is held exactly, deviations have zero mean
+                if (k == 0 && act) a.means_out[(size_t)v * nes + e] = a.ubar[(size_t)v * nes + e];
+            } else {
+                sh[le][k] = wk * val;
+                __syncthreads();
+                if (k == 0 && act) {
+                    double s = 0.0;
+                    for (int kk = 0; kk < np; ++kk) s += sh[le][kk];
+                    a.means_out[(size_t)v * nes + e] = s;
+                }
+                __syncthreads();
+            }
+        }
+    }
+}
+
+// far-field ghost states: traces of the state at every boundary face point
+template <class Eq, int N, class real>
+__global__ void k_ghost(const IoArgs<real> a)
+{
+    using G = Geo<Eq::DIM, N>;
+    constexpr int M = Eq::M, nd = G::nd, nq = G::nq, np = G::np;
+    const int nx_pts = a.ny * nq, ny_pts = Eq::DIM == 2 ? a.nx * nd : 0;
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= 2 * nx_pts + 2 * ny_pts) return;
+    const size_t nes = (size_t)a.ne;
+    int e, dir, side, t;
+    if (tid < 2 * nx_pts) {
+        dir = 0; side = tid / nx_pts;
+        int r = tid % nx_pts, ey = r / nq;
+        t = r % nq;
+        e = ey * a.nx + (side ? a.nx - 1 : 0);
+    } else {
+        int r0 = tid - 2 * nx_pts;
+        dir = 1; side = r0 / ny_pts;
+        int r = r0 % ny_pts, ex = r / nd;
+        t = r % nd;
+        e = (side ? a.ny - 1 : 0) * a.nx + ex;
+    }
+    const double* lw = side ? a.l1_64 : a.l0_64;
+#pragma unroll
+    for (int v = 0; v < M; ++v) {
+        double s = 0.0;
+        for (int j = 0; j < nd; ++j) {
+            int k = dir == 0 ? t * nd + j : j * nd + t;
+            double val = (double)a.u[((size_t)v * nes + e) * np + k];
+            if constexpr (is_mp<real>()) val += a.ubar[(size_t)v * nes + e];
+            s += lw[j] * val;
+        }
+        a.ghost[(size_t)tid * M + v] = (real)s;
+    }
+}
+
+}  // namespace crkfr

@@ -1,0 +1,109 @@
+// Host-side launchers of the templated kernels for one equation.  Each
+// equation's translation unit instantiates these for N = 1..4, FP64 and MP32.
+#pragma once
+#include "crkfr_kernels.hpp"
+
+namespace crkfr {
+
+enum { PH_LOCAL = 0, PH_FACE_X = 1, PH_FACE_Y = 2, PH_UPDATE = 3, PH_IMPORT = 4, PH_EXPORT = 5, PH_GHOST = 6 };
+
+template <template <class> class EqT, int N, class real, bool LIM>
+static void launch_step_phase(int phase, const StepArgs<real>& a, hipStream_t st)
+{
+    using Eq = EqT<real>;
+    using G = Geo<Eq::DIM, N>;
+    const int nb = (a.ne + G::EB - 1) / G::EB;
+    switch (phase) {
+    case PH_LOCAL:
+        hipLaunchKernelGGL((k_local<Eq, N, real, LIM>), dim3(nb), dim3(G::BLOCK), 0, st, a);
+        break;
+    case PH_FACE_X: {
+        long long tot = (long long)a.ny * (a.nx + 1) * G::nq;
+        hipLaunchKernelGGL((k_face<Eq, N, real, LIM, 0>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, a);
+        break;
+    }
+    case PH_FACE_Y:
+        if constexpr (Eq::DIM == 2) {
+            long long tot = (long long)(a.ny + 1) * a.nx * G::nd;
+            hipLaunchKernelGGL((k_face<Eq, N, real, LIM, 1>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, a);
+        }
+        break;
+    case PH_UPDATE:
+        hipLaunchKernelGGL((k_update<Eq, N, real, LIM>), dim3(nb), dim3(G::BLOCK), 0, st, a);
+        break;
+    }
+}
+
+template <template <class> class EqT, int N, class real>
+static void launch_io_phase(int phase, const IoArgs<real>& a, hipStream_t st)
+{
+    using Eq = EqT<real>;
+    using G = Geo<Eq::DIM, N>;
+    const int nb = (a.ne + G::EB - 1) / G::EB;
+    switch (phase) {
+    case PH_IMPORT:
+        hipLaunchKernelGGL((k_import<Eq, N, real>), dim3(nb), dim3(G::BLOCK), 0, st, a);
+        break;
+    case PH_EXPORT:
+        hipLaunchKernelGGL((k_export<Eq, N, real>), dim3(nb), dim3(G::BLOCK), 0, st, a);
+        break;
+    case PH_GHOST: {
+        int tot = 2 * a.ny * G::nq + (Eq::DIM == 2 ? 2 * a.nx * G::nd : 0);
+        hipLaunchKernelGGL((k_ghost<Eq, N, real>), dim3((tot + 255) / 256), dim3(256), 0, st, a);
+        break;
+    }
+    }
+}
+
+template <template <class> class EqT, class real>
+static int launch_step(int N, bool lim, int phase, const StepArgs<real>& a, hipStream_t st)
+{
+#define CRKFR_CASE(NN)                                                            \
+    case NN:                                                                      \
+        if (lim) launch_step_phase<EqT, NN, real, true>(phase, a, st);            \
+        else launch_step_phase<EqT, NN, real, false>(phase, a, st);               \
+        return 0;
+    switch (N) {
+        CRKFR_CASE(1)
+        CRKFR_CASE(2)
+        CRKFR_CASE(3)
+        CRKFR_CASE(4)
+    }
+#undef CRKFR_CASE
+    return -1;
+}
+
+template <template <class> class EqT, class real>
+static int launch_io(int N, int phase, const IoArgs<real>& a, hipStream_t st)
+{
+    switch (N) {
+    case 1: launch_io_phase<EqT, 1, real>(phase, a, st); return 0;
+    case 2: launch_io_phase<EqT, 2, real>(phase, a, st); return 0;
+    case 3: launch_io_phase<EqT, 3, real>(phase, a, st); return 0;
+    case 4: launch_io_phase<EqT, 4, real>(phase, a, st); return 0;
+    }
+    return -1;
+}
+
+// type-erased entry points, one set per equation (defined in crkfr_eq_*.hip)
+#define CRKFR_DECLARE_EQ(name)                                                                      \
+    int name##_step_f64(int N, bool lim, int phase, const StepArgs<double>& a, hipStream_t st);    \
+    int name##_step_f32(int N, bool lim, int phase, const StepArgs<float>& a, hipStream_t st);     \
+    int name##_io_f64(int N, int phase, const IoArgs<double>& a, hipStream_t st);                  \
+    int name##_io_f32(int N, int phase, const IoArgs<float>& a, hipStream_t st);
+#define CRKFR_DEFINE_EQ(name, EqT)                                                                  \
+    int name##_step_f64(int N, bool lim, int phase, const StepArgs<double>& a, hipStream_t st)     \
+    { return launch_step<EqT, double>(N, lim, phase, a, st); }                                      \
+    int name##_step_f32(int N, bool lim, int phase, const StepArgs<float>& a, hipStream_t st)      \
+    { return launch_step<EqT, float>(N, lim, phase, a, st); }                                       \
+    int name##_io_f64(int N, int phase, const IoArgs<double>& a, hipStream_t st)                   \
+    { return launch_io<EqT, double>(N, phase, a, st); }                                             \
+    int name##_io_f32(int N, int phase, const IoArgs<float>& a, hipStream_t st)                    \
+    { return launch_io<EqT, float>(N, phase, a, st); }
+
+CRKFR_DECLARE_EQ(linadv1d)
+CRKFR_DECLARE_EQ(euler1d)
+CRKFR_DECLARE_EQ(euler2d)
+CRKFR_DECLARE_EQ(tenmom2d)
+
+}  // namespace crkfr

@@ -1,0 +1,202 @@
+// Physics of the cRKFR step for gfx950: fluxes, spectral radii, admissibility
+// functions, indicator quantity and the ten-moment source.
+//   linear advection            f = a u                         (Sec. 5.1.1)
+//   1D / 2D Euler               eqs. 1deuler, state, 2deuler, 2dstate
+//   ten-moment system           eq. tmp, source eq. tenmom.source
+// Bulk arithmetic is in `real` (double or float); admissibility functions
+// P_k (eq. uad.form) are always evaluated in double.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace crkfr {
+
+struct Phys {
+    double gamma, adv;
+    int source;
+    double amp, kappa, xc, yc, gx, gy;   // W = amp exp(-kappa r^2) + gx x + gy y
+};
+
+template <class real>
+__device__ __forceinline__ real rsq(real x) { return sqrt(x); }
+
+// ---------------------------------------------------------------- linear advection
+template <class real>
+struct LinAdv1D {
+    static constexpr int M = 1, DIM = 1, K = 0, ID = 0;
+    __device__ static inline void fx(const real* u, real* f, const Phys& P) { f[0] = (real)P.adv * u[0]; }
+    __device__ static inline void gy(const real*, real* g, const Phys&) { g[0] = 0; }
+    __device__ static inline real sx(const real*, const Phys& P) { return fabs((real)P.adv); }
+    __device__ static inline real sy(const real*, const Phys&) { return 0; }
+    __device__ static inline double adm(int, const double*, const Phys&) { return 1.0; }
+    __device__ static inline bool concave(int) { return true; }
+    __device__ static inline real ind(const real* u, const Phys&) { return u[0]; }
+    __device__ static inline real sig_trace(int, const real*, const real*, const Phys& P) { return fabs((real)P.adv); }
+    __device__ static inline void src(const real*, real, real, real* s, const Phys&) { s[0] = 0; }
+};
+
+// ---------------------------------------------------------------- Euler 1D
+template <class real>
+struct Euler1D {
+    static constexpr int M = 3, DIM = 1, K = 2, ID = 1;
+    __device__ static inline real pres(const real* u, const Phys& P)
+    {
+        return ((real)P.gamma - 1) * (u[2] - (real)0.5 * u[1] * u[1] / u[0]);
+    }
+    __device__ static inline void fx(const real* u, real* f, const Phys& P)
+    {
+        real v = u[1] / u[0], p = pres(u, P);
+        f[0] = u[1];
+        f[1] = u[1] * v + p;
+        f[2] = (u[2] + p) * v;
+    }
+    __device__ static inline void gy(const real*, real* g, const Phys&) { g[0] = g[1] = g[2] = 0; }
+    __device__ static inline real sx(const real* u, const Phys& P)
+    {
+        return fabs(u[1] / u[0]) + sqrt((real)P.gamma * pres(u, P) / u[0]);
+    }
+    __device__ static inline real sy(const real*, const Phys&) { return 0; }
+    __device__ static inline double adm(int k, const double* u, const Phys& P)
+    {
+        if (k == 0) return u[0];
+        return (P.gamma - 1.0) * (u[2] - 0.5 * u[1] * u[1] / u[0]);
+    }
+    __device__ static inline bool concave(int) { return true; }
+    __device__ static inline real ind(const real* u, const Phys& P) { return u[0] * pres(u, P); }
+    // trace wave speed: pressure clipped at zero; non-positive density -> node
+    __device__ static inline real sig_trace(int, const real* tr, const real* node, const Phys& P)
+    {
+        const real* u = tr[0] > 0 ? tr : node;
+        real p = pres(u, P);
+        return fabs(u[1] / u[0]) + sqrt((real)P.gamma * fmax(p, (real)0) / u[0]);
+    }
+    __device__ static inline void src(const real*, real, real, real* s, const Phys&) { s[0] = s[1] = s[2] = 0; }
+};
+
+// ---------------------------------------------------------------- Euler 2D
+template <class real>
+struct Euler2D {
+    static constexpr int M = 4, DIM = 2, K = 2, ID = 2;
+    __device__ static inline real pres(const real* u, const Phys& P)
+    {
+        return ((real)P.gamma - 1) * (u[3] - (real)0.5 * (u[1] * u[1] + u[2] * u[2]) / u[0]);
+    }
+    __device__ static inline void fx(const real* u, real* f, const Phys& P)
+    {
+        real v1 = u[1] / u[0], p = pres(u, P);
+        f[0] = u[1];
+        f[1] = u[1] * v1 + p;
+        f[2] = u[2] * v1;
+        f[3] = (u[3] + p) * v1;
+    }
+    __device__ static inline void gy(const real* u, real* g, const Phys& P)
+    {
+        real v2 = u[2] / u[0], p = pres(u, P);
+        g[0] = u[2];
+        g[1] = u[1] * v2;
+        g[2] = u[2] * v2 + p;
+        g[3] = (u[3] + p) * v2;
+    }
+    __device__ static inline real sx(const real* u, const Phys& P)
+    {
+        return fabs(u[1] / u[0]) + sqrt((real)P.gamma * pres(u, P) / u[0]);
+    }
+    __device__ static inline real sy(const real* u, const Phys& P)
+    {
+        return fabs(u[2] / u[0]) + sqrt((real)P.gamma * pres(u, P) / u[0]);
+    }
+    __device__ static inline double adm(int k, const double* u, const Phys& P)
+    {
+        if (k == 0) return u[0];
+        return (P.gamma - 1.0) * (u[3] - 0.5 * (u[1] * u[1] + u[2] * u[2]) / u[0]);
+    }
+    __device__ static inline bool concave(int) { return true; }
+    __device__ static inline real ind(const real* u, const Phys& P) { return u[0] * pres(u, P); }
+    __device__ static inline real sig_trace(int d, const real* tr, const real* node, const Phys& P)
+    {
+        const real* u = tr[0] > 0 ? tr : node;
+        real c = sqrt((real)P.gamma * fmax(pres(u, P), (real)0) / u[0]);
+        return fabs(u[1 + d] / u[0]) + c;
+    }
+    __device__ static inline void src(const real*, real, real, real* s, const Phys&) { s[0] = s[1] = s[2] = s[3] = 0; }
+};
+
+// ---------------------------------------------------------------- ten-moment 2D
+template <class real>
+struct TenMom2D {
+    static constexpr int M = 6, DIM = 2, K = 3, ID = 3;
+    __device__ static inline void fx(const real* u, real* f, const Phys&)
+    {
+        real r = u[0], v1 = u[1] / r, v2 = u[2] / r;
+        real P11 = 2 * u[3] - r * v1 * v1, P12 = 2 * u[4] - r * v1 * v2;
+        f[0] = r * v1;
+        f[1] = P11 + r * v1 * v1;
+        f[2] = P12 + r * v1 * v2;
+        f[3] = (u[3] + P11) * v1;
+        f[4] = u[4] * v1 + (real)0.5 * (P11 * v2 + P12 * v1);
+        f[5] = u[5] * v1 + P12 * v2;
+    }
+    __device__ static inline void gy(const real* u, real* g, const Phys&)
+    {
+        real r = u[0], v1 = u[1] / r, v2 = u[2] / r;
+        real P12 = 2 * u[4] - r * v1 * v2, P22 = 2 * u[5] - r * v2 * v2;
+        g[0] = r * v2;
+        g[1] = P12 + r * v1 * v2;
+        g[2] = P22 + r * v2 * v2;
+        g[3] = u[3] * v2 + P12 * v1;
+        g[4] = u[4] * v2 + (real)0.5 * (P12 * v2 + P22 * v1);
+        g[5] = (u[5] + P22) * v2;
+    }
+    __device__ static inline real sx(const real* u, const Phys&)
+    {
+        real r = u[0], v1 = u[1] / r;
+        return fabs(v1) + sqrt(3 * (2 * u[3] - r * v1 * v1) / r);
+    }
+    __device__ static inline real sy(const real* u, const Phys&)
+    {
+        real r = u[0], v2 = u[2] / r;
+        return fabs(v2) + sqrt(3 * (2 * u[5] - r * v2 * v2) / r);
+    }
+    __device__ static inline double adm(int k, const double* u, const Phys&)
+    {
+        if (k == 0) return u[0];
+        double r = u[0], v1 = u[1] / r, v2 = u[2] / r;
+        double P11 = 2.0 * u[3] - r * v1 * v1;
+        if (k == 1) return P11;
+        double P12 = 2.0 * u[4] - r * v1 * v2, P22 = 2.0 * u[5] - r * v2 * v2;
+        return P11 * P22 - P12 * P12;
+    }
+    __device__ static inline bool concave(int k) { return k != 2; }   // det P is not concave
+    __device__ static inline real ind(const real* u, const Phys&)
+    {
+        real r = u[0], v1 = u[1] / r, v2 = u[2] / r;
+        return r * (real)0.5 * ((2 * u[3] - r * v1 * v1) + (2 * u[5] - r * v2 * v2));
+    }
+    __device__ static inline real sig_trace(int d, const real* tr, const real* node, const Phys&)
+    {
+        const real* u = tr[0] > 0 ? tr : node;
+        real r = u[0];
+        if (d == 0) {
+            real v1 = u[1] / r;
+            return fabs(v1) + sqrt(3 * fmax(2 * u[3] - r * v1 * v1, (real)0) / r);
+        }
+        real v2 = u[2] / r;
+        return fabs(v2) + sqrt(3 * fmax(2 * u[5] - r * v2 * v2, (real)0) / r);
+    }
+    // s = s^x + s^y with grad W of W = amp exp(-kappa r^2) + gx x + gy y
+    __device__ static inline void src(const real* u, real x, real y, real* s, const Phys& P)
+    {
+        real dx = x - (real)P.xc, dy = y - (real)P.yc;
+        real W = (real)P.amp * exp(-(real)P.kappa * (dx * dx + dy * dy));
+        real Wx = -2 * (real)P.kappa * dx * W + (real)P.gx;
+        real Wy = -2 * (real)P.kappa * dy * W + (real)P.gy;
+        real r = u[0], v1 = u[1] / r, v2 = u[2] / r;
+        s[0] = 0;
+        s[1] = (real)-0.5 * r * Wx;
+        s[2] = (real)-0.5 * r * Wy;
+        s[3] = (real)-0.5 * r * v1 * Wx;
+        s[4] = (real)-0.25 * r * v2 * Wx - (real)0.25 * r * v1 * Wy;
+        s[5] = (real)-0.5 * r * v2 * Wy;
+    }
+};
+
+}  // namespace crkfr

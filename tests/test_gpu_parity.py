@@ -1,0 +1,242 @@
+"""GPU (HIP, gfx950) path against the FP64 oracle, element by element, on the
+same seeded inputs and the same fixed time step.
+
+Tolerances: FP64 smooth runs rel. L_inf <= 1e-11; FP64 runs with the limiter
+chain rel. L1 <= 1e-9 (branches of the limiters may flip on the last bit);
+MP32 (FP32 bulk, FP64 means and roots) rel. L1 <= 2e-6 smooth and <= 1e-3
+with limiters."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2502_07517_amd import crkfr as C
+from paper_2502_07517_amd import workloads as W
+from gpu_cases import make_pair, run_pair, rel_l1, rel_linf
+from oracle_runs import cfl_for
+
+pytestmark = pytest.mark.gpu
+
+FF = (C.FARFIELD,) * 4
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 4])
+@pytest.mark.parametrize("nx", [1, 37])
+def test_linadv1d_fp64(N, nx):
+    ref, gpu = make_pair(C.LINADV1D, N, nx)
+    uo, ug, _, _ = run_pair(ref, gpu, W.linadv_modes(0, nx, N), 12)
+    assert rel_linf(uo, ug) <= 1e-12
+
+
+@pytest.mark.parametrize("N", [2, 3, 4])
+def test_euler2d_vortex_fp64(N):
+    dom = (-5.0, 5.0, -5.0, 5.0)
+    nx, ny = 13, 11
+    ref, gpu = make_pair(C.EULER2D, N, nx, ny, domain=dom)
+    X, Y = W.node_coords_2d(nx, ny, N, dom)
+    u0 = W.euler2d_cons(*W.vortex_prim(X, Y, 0.0, dom))
+    uo, ug, _, _ = run_pair(ref, gpu, u0, 8)
+    assert rel_linf(uo, ug) <= 1e-11
+
+
+def test_euler2d_single_element_periodic():
+    ref, gpu = make_pair(C.EULER2D, 3, 1, 1)
+    u0 = W.euler2d_smooth_periodic(2, 1, 3, amp=0.05)
+    uo, ug, _, _ = run_pair(ref, gpu, u0, 5)
+    assert rel_linf(uo, ug) <= 1e-11
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 4])
+@pytest.mark.parametrize("blend", [C.BLEND_FO, C.BLEND_MH])
+def test_euler1d_riemann_limited_fp64(N, blend):
+    nx = 41
+    ref, gpu = make_pair(C.EULER1D, N, nx, bc=FF, blend=blend, flux_limiter=1, scaling=1)
+    uo, ug, diags, _ = run_pair(ref, gpu, W.euler1d_riemann(3, nx, N), 15)
+    assert rel_l1(uo, ug) <= 1e-9
+    do, dg = diags[-1]
+    assert do["n_troubled"] == dg["n_troubled"]
+    assert dg["n_mean_inadmissible"] == 0
+
+
+@pytest.mark.parametrize("N", [2, 3, 4])
+@pytest.mark.parametrize("seed", [0, 1])
+def test_euler2d_quadrants_limited_fp64(N, seed):
+    n = 12
+    ref, gpu = make_pair(C.EULER2D, N, n, n + 3, bc=FF, blend=C.BLEND_MH, flux_limiter=1, scaling=1)
+    X, Y = W.node_coords_2d(n, n + 3, N, (0, 1, 0, 1))
+    st = W.quadrant_states_euler(seed)
+    rho, v1, v2, p = W._quadrant_fill(X, Y, 0.5 + 0.37 / n, 0.5 + 0.37 / (n + 3), st)
+    u0 = W.euler2d_cons(rho, v1, v2, p)
+    uo, ug, diags, _ = run_pair(ref, gpu, u0, 10)
+    assert rel_l1(uo, ug) <= 1e-9
+    do, dg = diags[-1]
+    assert do["n_troubled"] == dg["n_troubled"]
+    assert dg["n_mean_inadmissible"] == 0
+
+
+def test_euler2d_hard_data_flux_limiter_and_scaling_act():
+    # hard quadrant data: the flux limiter and scaling act; results still agree
+    n, N = 10, 3
+    rng = np.random.default_rng(0)
+    st = [(rng.uniform(0.05, 2.0), rng.uniform(-3, 3), rng.uniform(-3, 3), 10 ** rng.uniform(-4, 1))
+          for _ in range(4)]
+    u0 = W.euler2d_quadrants(0, n, N, states=st)
+    ref, gpu = make_pair(C.EULER2D, N, n, n, bc=FF, blend=C.BLEND_MH, flux_limiter=1, scaling=1)
+    for fac in (0.5, 1.0):
+        dt = fac * O.compute_dt(ref, u0)
+        uo, ug, diags, _ = run_pair(ref, gpu, u0, 3, dt=dt)
+        assert rel_l1(uo, ug) <= 1e-8
+        for do, dg in diags:
+            for key in ("n_troubled", "n_flux_limited", "n_slope_limited", "n_hancock_fallback", "n_scaled",
+                        "n_mean_inadmissible", "n_lo_inadmissible"):
+                assert do[key] == dg[key], (fac, key, do[key], dg[key])
+            assert abs(do["min_theta_flux"] - dg["min_theta_flux"]) < 1e-9
+            assert abs(do["min_theta_scale"] - dg["min_theta_scale"]) < 1e-9
+        assert any(dg["n_flux_limited"] > 0 for _, dg in diags)
+        assert all(dg["n_mean_inadmissible"] == 0 for _, dg in diags)
+
+
+@pytest.mark.parametrize("blend", [C.BLEND_FO, C.BLEND_MH])
+def test_euler1d_blast_scaling_acts(blend):
+    # strong blast: without the positivity fixes the pressure goes negative;
+    # here the scaling limiter acts and GPU and oracle agree counter by counter
+    n, N = 40, 3
+    x = W.node_coords_1d(n, N, -1, 1)
+    u0 = W.euler1d_cons(np.ones_like(x), np.zeros_like(x), np.where(np.abs(x) < 0.05, 1e3, 1e-6))
+    ref, gpu = make_pair(C.EULER1D, N, n, bc=(C.OUTFLOW,) * 4, domain=(-1, 1, 0, 1), blend=blend,
+                         flux_limiter=1, scaling=1)
+    uo, ug, diags, _ = run_pair(ref, gpu, u0, 6)
+    assert rel_l1(uo, ug) <= 1e-9
+    assert any(dg["n_scaled"] > 0 for _, dg in diags)
+    for do, dg in diags:
+        for key in ("n_troubled", "n_flux_limited", "n_scaled", "n_mean_inadmissible"):
+            assert do[key] == dg[key], (key, do[key], dg[key])
+
+
+@pytest.mark.parametrize("N", [2, 4])
+def test_tenmom2d_source_limited_fp64(N):
+    nx, ny = 16, 6
+    dom = (-2.0, 2.0, -0.5, 0.5)
+    src = (25.0, 200.0, 1.0, 0.0, 0.0, 0.0)
+    ref, gpu = make_pair(C.TENMOM2D, N, nx, ny, bc=FF, domain=dom, blend=C.BLEND_MH, flux_limiter=1,
+                         scaling=1, source=src)
+    uo, ug, diags, _ = run_pair(ref, gpu, W.tenmom2d_quadrants(1, nx, ny, N, dom), 8)
+    assert rel_l1(uo, ug) <= 1e-9
+    assert diags[-1][1]["n_mean_inadmissible"] == 0
+
+
+def test_given_alpha_and_const_alpha_fp64():
+    n, N = 9, 3
+    u0 = W.euler2d_quadrants(4, n, N)
+    alpha = np.random.default_rng(3).uniform(0, 1, n * n)
+    ref, gpu = make_pair(C.EULER2D, N, n, n, bc=FF, blend=C.BLEND_FO, indicator=C.IND_GIVEN, flux_limiter=1,
+                         scaling=1)
+    uo, ug, _, _ = run_pair(ref, gpu, u0, 4, alpha=alpha)
+    assert rel_l1(uo, ug) <= 1e-9
+    ref, gpu = make_pair(C.EULER2D, N, n, n, bc=FF, blend=C.BLEND_MH, indicator=C.IND_CONST, alpha_const=1.0)
+    uo, ug, _, _ = run_pair(ref, gpu, u0, 4)
+    assert rel_l1(uo, ug) <= 1e-9
+
+
+def test_indicator_alpha_matches():
+    n, N = 16, 3
+    u0 = W.euler2d_quadrants(6, n, N)
+    ref, gpu = make_pair(C.EULER2D, N, n, n, bc=FF, blend=C.BLEND_MH, flux_limiter=1, scaling=1)
+    dt = O.compute_dt(ref, u0)
+    gpu.set_state(u0)
+    gpu.step(dt)
+    _, ao, _, _ = O.step(ref, u0, dt, ghost=O.boundary_traces(ref, u0))
+    ag = gpu.get_alpha()
+    assert np.abs(ao - ag).max() < 1e-6
+    assert (ao > 0).sum() > 0
+
+
+# ---------------------------------------------------------------- MP32
+def test_vortex_mp32_smooth():
+    dom = (-5.0, 5.0, -5.0, 5.0)
+    n, N = 16, 3
+    ref, gpu = make_pair(C.EULER2D, N, n, n, domain=dom, dtype=C.MP32)
+    uo, ug, _, _ = run_pair(ref, gpu, W.vortex2d(n, N, 0.0, dom), 10)
+    assert rel_l1(uo, ug) <= 2e-6
+    assert rel_linf(uo, ug) <= 2e-5
+
+
+def test_quadrants_mp32_limited():
+    n, N = 12, 3
+    ref, gpu = make_pair(C.EULER2D, N, n, n, bc=FF, dtype=C.MP32, blend=C.BLEND_MH, flux_limiter=1, scaling=1)
+    uo, ug, diags, _ = run_pair(ref, gpu, W.euler2d_quadrants(2, n, N), 10)
+    assert rel_l1(uo, ug) <= 1e-3
+    assert all(dg["n_mean_inadmissible"] == 0 for _, dg in diags)
+
+
+@pytest.mark.parametrize("dtype", [C.FP64, C.MP32])
+def test_conservation_on_gpu(dtype):
+    n, N = 10, 3
+    ref, gpu = make_pair(C.EULER2D, N, n, n, dtype=dtype, blend=C.BLEND_MH, flux_limiter=1, scaling=1)
+    u0 = W.euler2d_quadrants(7, n, N)
+    gpu.set_state(u0)
+    m0 = gpu.get_means().sum(axis=(1, 2))
+    for _ in range(20):
+        gpu.step(0.0)
+    m1 = gpu.get_means().sum(axis=(1, 2))
+    assert np.all(np.abs(m1 - m0) <= 2e-13 * np.abs(m0).max())
+
+
+# ---------------------------------------------------------------- time step, CFL, errors
+def test_dt_and_cfl_match_oracle():
+    n, N = 12, 3
+    ref, gpu = make_pair(C.EULER2D, N, n, n)
+    u0 = W.euler2d_smooth_periodic(1, n, N)
+    gpu.set_state(u0)
+    assert abs(gpu.compute_dt() - O.compute_dt(ref, u0)) <= 1e-12 * O.compute_dt(ref, u0)
+    for Nn in (1, 2, 3):
+        assert abs(C.fourier_cfl(Nn, 0, 1, 1e-10) - cfl_for(Nn)) < 1e-4 * cfl_for(Nn)
+        assert abs(C.fourier_cfl(Nn, 0, 0, 1e-10) - cfl_for(Nn, system=False)) < 1e-4 * cfl_for(Nn, system=False)
+
+
+def test_device_dt_steps_match_oracle_dt_rule():
+    n, N = 8, 2
+    ref, gpu = make_pair(C.EULER2D, N, n, n)
+    u = W.euler2d_smooth_periodic(5, n, N)
+    gpu.set_state(u)
+    for _ in range(5):
+        dt = O.compute_dt(ref, u)
+        u, _, _, _ = O.step(ref, u, dt)
+        gpu.step(0.0)
+    d, _ = gpu.get_diag()
+    assert rel_linf(u, gpu.get_state().reshape(u.shape)) <= 1e-11
+    assert d["steps"] == 5
+
+
+def test_graph_advance_matches_steps():
+    n, N = 10, 3
+    dom = (-5.0, 5.0, -5.0, 5.0)
+    u0 = W.vortex2d(n, N, 0.0, dom)
+    a = C.Solver(C.EULER2D, N, n, n, domain=dom, cfl=cfl_for(N))
+    b = C.Solver(C.EULER2D, N, n, n, domain=dom, cfl=cfl_for(N))
+    a.set_state(u0)
+    b.set_state(u0)
+    for _ in range(7):
+        a.step(0.0)
+    b.advance(10.0, 7)
+    assert np.array_equal(a.get_state(), b.get_state())
+    b.advance(10.0, 6)          # replay after eager work
+    for _ in range(6):
+        a.step(0.0)
+    assert np.array_equal(a.get_state(), b.get_state())
+
+
+def test_inadmissible_input_is_reported():
+    n, N = 4, 2
+    gpu = C.Solver(C.EULER2D, N, n, n, cfl=cfl_for(N))
+    X, Y = W.node_coords_2d(n, n, N, (0, 1, 0, 1))
+    u0 = W.euler2d_cons(np.ones_like(X), 0 * X, 0 * X, np.where(X > 0.5, -1.0, 1.0))
+    with pytest.raises(C.CrkfrError) as e:
+        gpu.set_state(u0)
+    assert e.value.code == -4
+
+
+def test_bad_config_rejected():
+    with pytest.raises(C.CrkfrError):
+        C.Solver(C.EULER2D, 5, 4, 4)
+    with pytest.raises(C.CrkfrError):
+        C.Solver(C.EULER2D, 3, 0, 4)
