@@ -133,6 +133,11 @@ static void fill_tab(const RefElem& r, RefTab<real>& t)
         t.xi[i] = (real)r.xi[i];
     }
     for (int i = 0; i <= r.N + 1; ++i) t.sub[i] = (real)r.sub[i];
+    const int S = std::min(r.N + 1, 4);
+    for (int i = 0; i < S; ++i) {
+        t.tb[i] = (real)tab_b(S, i);
+        t.ta[i] = i < S - 1 ? (real)tab_a(S, i) : (real)0;
+    }
 }
 
 // ----------------------------------------------------------------------------
@@ -526,7 +531,7 @@ extern "C" int crkfr_create(const crkfr_config* cfg, void* hip_stream, crkfr_sol
     ok &= alloc((void**)&s->alpha_given, ne * sizeof(double));
     ok &= alloc((void**)&s->dt_dev, sizeof(double));
     ok &= alloc((void**)&s->t_dev, sizeof(double));
-    ok &= alloc((void**)&s->rate_bits, sizeof(unsigned long long));
+    ok &= alloc((void**)&s->rate_bits, RATE_SLOTS * sizeof(unsigned long long));
     ok &= alloc((void**)&s->diag, D_NCOUNT * sizeof(unsigned long long));
     ok &= alloc((void**)&s->steps, sizeof(long long));
     if (!ok) {
@@ -599,7 +604,7 @@ extern "C" int crkfr_set_state(crkfr_solver* s, const double* u, int on_device)
     s->cur = 0;
     const double zero = 0.0;
     HIP_TRY(hipMemcpyAsync(s->t_dev, &zero, sizeof(double), hipMemcpyHostToDevice, s->stream));
-    HIP_TRY(hipMemsetAsync(s->rate_bits, 0, sizeof(unsigned long long), s->stream));
+    HIP_TRY(hipMemsetAsync(s->rate_bits, 0, RATE_SLOTS * sizeof(unsigned long long), s->stream));
     HIP_TRY(hipMemsetAsync(s->diag, 0, D_NCOUNT * sizeof(unsigned long long), s->stream));
     HIP_TRY(hipMemsetAsync(s->steps, 0, sizeof(long long), s->stream));
     int rc = run_io(s, PH_IMPORT, src, nullptr, nullptr);
@@ -632,11 +637,15 @@ extern "C" int crkfr_compute_dt(crkfr_solver* s, double* dt)
 {
     if (!s || !dt) return fail(CRKFR_EINVAL, "null argument");
     if (!s->has_state) return fail(CRKFR_ESTATE, "no state set");
-    unsigned long long bits = 0;
-    HIP_TRY(hipMemcpyAsync(&bits, s->rate_bits, sizeof(bits), hipMemcpyDeviceToHost, s->stream));
+    unsigned long long bits[RATE_SLOTS];
+    HIP_TRY(hipMemcpyAsync(bits, s->rate_bits, sizeof(bits), hipMemcpyDeviceToHost, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
-    double rate;
-    std::memcpy(&rate, &bits, sizeof(rate));
+    double rate = 0.0;
+    for (int i = 0; i < RATE_SLOTS; ++i) {
+        double r;
+        std::memcpy(&r, &bits[i], sizeof(r));
+        rate = r > rate ? r : rate;
+    }
     *dt = s->cfg.cs * s->cfl / rate;
     return 0;
 }
@@ -652,7 +661,7 @@ static int enqueue_step(crkfr_solver* s, double dt_fixed, double t_end)
     pa.rate_bits = s->rate_bits;
     pa.diag = s->diag;
     pa.steps = s->steps;
-    hipLaunchKernelGGL(k_prep, dim3(1), dim3(64), 0, s->stream, pa);
+    hipLaunchKernelGGL(k_prep, dim3(1), dim3(RATE_SLOTS), 0, s->stream, pa);
     const int in = s->cur, out = 1 - s->cur;
     const bool tm = s->timing;
     if (tm) (void)hipEventRecord(s->ev[0], s->stream);

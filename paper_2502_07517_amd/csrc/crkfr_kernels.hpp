@@ -37,6 +37,9 @@ enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_FARFIELD = 2 };
 enum { BLEND_OFF = 0, BLEND_FO = 1, BLEND_MH = 2 };
 enum { IND_PAPER = 0, IND_CONST = 1, IND_GIVEN = 2, IND_LEARNED = 3 };
 enum { D_TROUBLED = 0, D_FLUXLIM, D_LOBAD, D_SLOPELIM, D_FALLBACK, D_SCALED, D_MEANBAD, D_THFLUX, D_THSCALE, D_NCOUNT };
+// the wave-speed rate of eq. time.step.2d is max-reduced into RATE_SLOTS
+// addresses (slot = workgroup index mod RATE_SLOTS) to spread the atomics
+constexpr int RATE_SLOTS = 256;
 
 template <class real>
 struct RefTab {
@@ -44,6 +47,7 @@ struct RefTab {
     real l0[MAXND], l1[MAXND], bR[MAXND], bL[MAXND], w[MAXND], xi[MAXND];
     real sub[MAXND + 1];
     real L[MAXND][MAXND];   // L[k][p] = orthonormal Legendre L_k(xi_p)
+    real ta[4], tb[4];      // cRK tableau: a_{i+1,i}, b_i
 };
 
 template <class real>
@@ -79,6 +83,16 @@ template <int DIM, int N>
 struct Geo {
     static constexpr int nd = N + 1, nq = DIM == 2 ? N + 1 : 1, np = nd * nq;
     static constexpr int EB = 256 / np;          // elements per workgroup
+    static constexpr int BLOCK = EB * np;
+};
+
+// k_local: one-wavefront workgroups while an element has at most 16 points
+// (barriers then order a single wavefront), 256 lanes otherwise
+template <int DIM, int N>
+struct LGeo {
+    static constexpr int nd = N + 1, nq = DIM == 2 ? N + 1 : 1, np = nd * nq;
+    static constexpr int TPB = np <= 16 ? 64 : 256;
+    static constexpr int EB = TPB / np;
     static constexpr int BLOCK = EB * np;
 };
 
@@ -210,12 +224,12 @@ __device__ __forceinline__ void atomic_max_pos(unsigned long long* p, double v)
 // MUSCL-Hancock predictor of one subcell (Sec. 4.2; reading: minmod slopes
 // on the non-uniform subcell grid, slope scaled to keep the reconstructed
 // face values admissible, Hancock half step, zero slope when the predicted
-// values are not admissible).  The element's nodal values are in sh[v][k].
+// values are not admissible).  The element's nodal values are in sh[k][v].
 // Outputs the predicted values at the x faces (xm, xp) and y faces (ym, yp).
 // ----------------------------------------------------------------------------
 template <class Eq, int N, class real>
 __device__ void mh_subcell(const StepArgs<real>& a, int e, int ex, int ey, int p, int q,
-                           const real* u, const real (*sh)[Geo<Eq::DIM, N>::np], double dt,
+                           const real* u, const real (*sh)[Eq::M], double dt,
                            real* xm, real* xp, real* ym, real* yp, int& nlim, int& nfb)
 {
     using G = Geo<Eq::DIM, N>;
@@ -244,7 +258,7 @@ __device__ void mh_subcell(const StepArgs<real>& a, int e, int ex, int ey, int p
             if (pos > 0) {
                 const int kn = d == 0 ? k - 1 : k - nd;
 #pragma unroll
-                for (int v = 0; v < M; ++v) um[v] = sh[v][kn];
+                for (int v = 0; v < M; ++v) um[v] = sh[kn][v];
                 xmn = a.R.xi[pos - 1];
             } else {
                 int en = nbr(a, ex, ey, d, 0);
@@ -252,15 +266,20 @@ __device__ void mh_subcell(const StepArgs<real>& a, int e, int ex, int ey, int p
                     load_node<Eq>(a, np, en, d == 0 ? q * nd + N : N * nd + p, um);
                 } else {
                     const real* g = ghost_at(a, M, nd, nq, ex, ey, d, 0, d == 0 ? q : p);
+                    if (g) {
 #pragma unroll
-                    for (int v = 0; v < M; ++v) um[v] = g ? g[v] : u[v];
+                        for (int v = 0; v < M; ++v) um[v] = g[v];
+                    } else {
+#pragma unroll
+                        for (int v = 0; v < M; ++v) um[v] = u[v];
+                    }
                 }
                 xmn = a.R.xi[N] - (real)1;
             }
             if (pos < N) {
                 const int kn = d == 0 ? k + 1 : k + nd;
 #pragma unroll
-                for (int v = 0; v < M; ++v) up[v] = sh[v][kn];
+                for (int v = 0; v < M; ++v) up[v] = sh[kn][v];
                 xpn = a.R.xi[pos + 1];
             } else {
                 int en = nbr(a, ex, ey, d, 1);
@@ -268,8 +287,13 @@ __device__ void mh_subcell(const StepArgs<real>& a, int e, int ex, int ey, int p
                     load_node<Eq>(a, np, en, d == 0 ? q * nd + 0 : 0 * nd + p, up);
                 } else {
                     const real* g = ghost_at(a, M, nd, nq, ex, ey, d, 1, d == 0 ? q : p);
+                    if (g) {
 #pragma unroll
-                    for (int v = 0; v < M; ++v) up[v] = g ? g[v] : u[v];
+                        for (int v = 0; v < M; ++v) up[v] = g[v];
+                    } else {
+#pragma unroll
+                        for (int v = 0; v < M; ++v) up[v] = u[v];
+                    }
                 }
                 xpn = (real)1 + a.R.xi[0];
             }
@@ -362,13 +386,13 @@ __device__ void mh_subcell(const StepArgs<real>& a, int e, int ex, int ey, int p
 template <class Eq, int N, class real, bool LIM>
 __global__ void __launch_bounds__(256) k_local(const StepArgs<real> a)
 {
-    using G = Geo<Eq::DIM, N>;
+    using G = LGeo<Eq::DIM, N>;
     constexpr int M = Eq::M, DIM = Eq::DIM, nd = G::nd, nq = G::nq, np = G::np, EB = G::EB;
     constexpr int S = N + 1 < 4 ? N + 1 : 4;
     constexpr int MY = DIM == 2 ? M : 1;
-    __shared__ real sh_u[EB][M][np];
-    __shared__ real sh_f[EB][M][np];
-    __shared__ real sh_g[EB][MY][np];
+    __shared__ real sh_u[EB][np][M];
+    __shared__ real sh_f[EB][np][M];
+    __shared__ real sh_g[EB][np][MY];
     __shared__ real sh_h[EB][M][4 * nd];
 
     const Phys& P = a.phys;
@@ -392,8 +416,8 @@ __global__ void __launch_bounds__(256) k_local(const StepArgs<real> a)
     if constexpr (LIM) {
         // ---- smoothness indicator (reading of the Hennemann indicator) ----
 #pragma unroll
-        for (int v = 0; v < M; ++v) sh_u[le][v][k] = un[v];
-        if (a.indicator == IND_PAPER) sh_f[le][0][k] = Eq::ind(un, P);
+        for (int v = 0; v < M; ++v) sh_u[le][k][v] = un[v];
+        if (a.indicator == IND_PAPER) sh_f[le][k][0] = Eq::ind(un, P);
         __syncthreads();
         if (a.indicator == IND_PAPER) {
             real m = 0;
@@ -402,12 +426,12 @@ __global__ void __launch_bounds__(256) k_local(const StepArgs<real> a)
                 for (int s2 = 0; s2 < nd; ++s2)
 #pragma unroll
                     for (int r = 0; r < nd; ++r)
-                        m += a.R.w[r] * a.R.w[s2] * a.R.L[p][r] * a.R.L[q][s2] * sh_f[le][0][s2 * nd + r];
+                        m += a.R.w[r] * a.R.w[s2] * a.R.L[p][r] * a.R.L[q][s2] * sh_f[le][s2 * nd + r][0];
             } else {
 #pragma unroll
-                for (int r = 0; r < nd; ++r) m += a.R.w[r] * a.R.L[p][r] * sh_f[le][0][r];
+                for (int r = 0; r < nd; ++r) m += a.R.w[r] * a.R.L[p][r] * sh_f[le][r][0];
             }
-            sh_g[le][0][k] = m * m;
+            sh_g[le][k][0] = m * m;
         }
         __syncthreads();
         if (k == 0 && act) {
@@ -418,7 +442,7 @@ __global__ void __launch_bounds__(256) k_local(const StepArgs<real> a)
 #pragma unroll
                 for (int kk = 0; kk < np; ++kk) {
                     int pp = kk % nd, qq = kk / nd;
-                    en[pp > qq ? pp : qq] += (double)sh_g[le][0][kk];
+                    en[pp > qq ? pp : qq] += (double)sh_g[le][kk][0];
                 }
                 double totN = 0.0, totNm1 = 0.0;
 #pragma unroll
@@ -447,15 +471,15 @@ __global__ void __launch_bounds__(256) k_local(const StepArgs<real> a)
         __syncthreads();
 #pragma unroll
         for (int v = 0; v < M; ++v) {
-            sh_f[le][v][k] = xm[v];
-            if constexpr (DIM == 2) sh_g[le][v][k] = ym[v];
+            sh_f[le][k][v] = xm[v];
+            if constexpr (DIM == 2) sh_g[le][k][v] = ym[v];
         }
         __syncthreads();
         if (act) {
             if (p < N) {
                 real nb[M], fs[M];
 #pragma unroll
-                for (int v = 0; v < M; ++v) nb[v] = sh_f[le][v][k + 1];
+                for (int v = 0; v < M; ++v) nb[v] = sh_f[le][k + 1][v];
                 rusanov<Eq>(0, xp, nb, fs, P);
                 if (p == N - 1)
 #pragma unroll
@@ -474,7 +498,7 @@ __global__ void __launch_bounds__(256) k_local(const StepArgs<real> a)
                 if (q < N) {
                     real nb[M], fs[M];
 #pragma unroll
-                    for (int v = 0; v < M; ++v) nb[v] = sh_g[le][v][k + nd];
+                    for (int v = 0; v < M; ++v) nb[v] = sh_g[le][k + nd][v];
                     rusanov<Eq>(1, yp, nb, fs, P);
                     if (q == N - 1)
 #pragma unroll
@@ -497,76 +521,100 @@ __global__ void __launch_bounds__(256) k_local(const StepArgs<real> a)
     }
 
     // ---- local cRK procedure ----
-    real ui[M], F[M], Gs[M], U[M], Sa[M], trX[M], trYv[M];
-    real sigX = 0, sigY = 0;
+    // Face points are spread over the lanes: point fp = k + j*np (j < FPL)
+    // lies on side s (0 left, 1 right, 2 bottom, 3 top) at line position t.
+    constexpr int NFP = DIM == 2 ? 4 * nd : 2;
+    constexpr int FPL = (NFP + np - 1) / np;
+    real ui[M], F[M], Gs[M], U[M], Sa[M], tr[FPL][M], sig[FPL];
 #pragma unroll
-    for (int v = 0; v < M; ++v) { ui[v] = un[v]; F[v] = 0; Gs[v] = 0; U[v] = 0; Sa[v] = 0; trX[v] = 0; trYv[v] = 0; }
+    for (int v = 0; v < M; ++v) { ui[v] = un[v]; F[v] = 0; Gs[v] = 0; U[v] = 0; Sa[v] = 0; }
+#pragma unroll
+    for (int j = 0; j < FPL; ++j) {
+        sig[j] = 0;
+#pragma unroll
+        for (int v = 0; v < M; ++v) tr[j][v] = 0;
+    }
+    // node index of position r on the line of face point fp, and its side
+    auto fside = [&](int fp) { return DIM == 2 ? fp / nd : fp; };
+    auto fpos = [&](int fp) { return DIM == 2 ? fp % nd : 0; };
+    auto fnode = [&](int fp, int r) {
+        const int sd = fside(fp), t = fpos(fp);
+        return sd < 2 ? t * nd + r : r * nd + t;
+    };
+    // this lane's face lines: LDS node indices and interpolation weights
+    int fkn[FPL][nd];
+    real fw[FPL][nd];
+#pragma unroll
+    for (int j = 0; j < FPL; ++j) {
+        const int fp = k + j * np < NFP ? k + j * np : NFP - 1;
+        const bool hi = fside(fp) & 1;
+#pragma unroll
+        for (int r = 0; r < nd; ++r) {
+            fkn[j][r] = fnode(fp, r);
+            fw[j][r] = hi ? a.R.l1[r] : a.R.l0[r];
+        }
+    }
+    real Dx[nd], Dy[nd];
+#pragma unroll
+    for (int r = 0; r < nd; ++r) { Dx[r] = a.R.D[p][r]; Dy[r] = a.R.D[q][r]; }
 
-#pragma unroll
+#pragma unroll 1
     for (int i = 0; i < S; ++i) {
         real f[M], g[M], s[M];
-        Eq::fx(ui, f, P);
-        if constexpr (DIM == 2) Eq::gy(ui, g, P);
+        Eq::fxy(ui, f, g, P);
         if (src) Eq::src(ui, xn, yn, s, P);
         else {
 #pragma unroll
             for (int v = 0; v < M; ++v) s[v] = 0;
         }
-        const real bi = (real)tab_b(S, i);
+        const real bi = a.R.tb[i];
 #pragma unroll
         for (int v = 0; v < M; ++v) {
             F[v] += bi * f[v];
             if constexpr (DIM == 2) Gs[v] += bi * g[v];
             U[v] += bi * ui[v];
             Sa[v] += bi * s[v];
-            sh_u[le][v][k] = ui[v];
-            sh_f[le][v][k] = f[v];
-            if constexpr (DIM == 2) sh_g[le][v][k] = g[v];
+            sh_u[le][k][v] = ui[v];
+            sh_f[le][k][v] = f[v];
+            if constexpr (DIM == 2) sh_g[le][k][v] = g[v];
         }
         __syncthreads();
-        // EA traces: flux of the interpolated stage value at the faces
-        if (p == 0 || p == N) {
-            const real* lw = p == 0 ? a.R.l0 : a.R.l1;
-            real uf[M], ff[M];
+        // EA traces: normal flux of the interpolated stage value at the face points
 #pragma unroll
-            for (int v = 0; v < M; ++v) {
-                real s2 = 0;
+        for (int j = 0; j < FPL; ++j) {
+            const int fp = k + j * np;
+            if (j == FPL - 1 && fp >= NFP) break;
+            const int sd = fside(fp);
+            real uf[M], ff[M], gf[M];
 #pragma unroll
-                for (int r = 0; r < nd; ++r) s2 += lw[r] * sh_u[le][v][q * nd + r];
-                uf[v] = s2;
+            for (int v = 0; v < M; ++v) uf[v] = 0;
+#pragma unroll
+            for (int r = 0; r < nd; ++r) {
+                const int kn = fkn[j][r];
+#pragma unroll
+                for (int v = 0; v < M; ++v) uf[v] += fw[j][r] * sh_u[le][kn][v];
             }
-            Eq::fx(uf, ff, P);
+            Eq::fxy(uf, ff, gf, P);
 #pragma unroll
-            for (int v = 0; v < M; ++v) trX[v] += bi * ff[v];
-            if (i == 0) sigX = Eq::sig_trace(0, uf, un, P);
-        }
-        if constexpr (DIM == 2) {
-            if (q == 0 || q == N) {
-                const real* lw = q == 0 ? a.R.l0 : a.R.l1;
-                real uf[M], ff[M];
+            for (int v = 0; v < M; ++v) tr[j][v] += bi * (sd < 2 ? ff[v] : gf[v]);
+            if (i == 0) {
+                real nodev[M];
+                const int kadj = (sd & 1) ? fkn[j][N] : fkn[j][0];
 #pragma unroll
-                for (int v = 0; v < M; ++v) {
-                    real s2 = 0;
-#pragma unroll
-                    for (int r = 0; r < nd; ++r) s2 += lw[r] * sh_u[le][v][r * nd + p];
-                    uf[v] = s2;
-                }
-                Eq::gy(uf, ff, P);
-#pragma unroll
-                for (int v = 0; v < M; ++v) trYv[v] += bi * ff[v];
-                if (i == 0) sigY = Eq::sig_trace(1, uf, un, P);
+                for (int v = 0; v < M; ++v) nodev[v] = sh_u[le][kadj][v];
+                sig[j] = Eq::sig_trace(sd < 2 ? 0 : 1, uf, nodev, P);
             }
         }
         if (i < S - 1) {
-            const real ai = (real)tab_a(S, i);
+            const real ai = a.R.ta[i];
 #pragma unroll
             for (int v = 0; v < M; ++v) {
                 real df = 0, dg = 0;
 #pragma unroll
-                for (int r = 0; r < nd; ++r) df += a.R.D[p][r] * sh_f[le][v][q * nd + r];
+                for (int r = 0; r < nd; ++r) df += Dx[r] * sh_f[le][q * nd + r][v];
                 if constexpr (DIM == 2) {
 #pragma unroll
-                    for (int r = 0; r < nd; ++r) dg += a.R.D[q][r] * sh_g[le][v][r * nd + p];
+                    for (int r = 0; r < nd; ++r) dg += Dy[r] * sh_g[le][r * nd + p][v];
                 }
                 ui[v] = un[v] - rdt * ai * (df * idx + dg * idy - s[v]);
             }
@@ -577,54 +625,42 @@ __global__ void __launch_bounds__(256) k_local(const StepArgs<real> a)
     // ---- volume part of the FR update, traces of U, extrapolated averaged flux ----
 #pragma unroll
     for (int v = 0; v < M; ++v) {
-        sh_u[le][v][k] = U[v];
-        sh_f[le][v][k] = F[v];
-        if constexpr (DIM == 2) sh_g[le][v][k] = Gs[v];
+        sh_u[le][k][v] = U[v];
+        sh_f[le][k][v] = F[v];
+        if constexpr (DIM == 2) sh_g[le][k][v] = Gs[v];
     }
     __syncthreads();
-    real vol[M], Ux[M], Uy[M];
+    real vol[M], Ut[FPL][M];
 #pragma unroll
     for (int v = 0; v < M; ++v) {
         real df = 0, dg = 0;
 #pragma unroll
-        for (int r = 0; r < nd; ++r) df += a.R.D[p][r] * sh_f[le][v][q * nd + r];
+        for (int r = 0; r < nd; ++r) df += Dx[r] * sh_f[le][q * nd + r][v];
         if constexpr (DIM == 2) {
 #pragma unroll
-            for (int r = 0; r < nd; ++r) dg += a.R.D[q][r] * sh_g[le][v][r * nd + p];
+            for (int r = 0; r < nd; ++r) dg += Dy[r] * sh_g[le][r * nd + p][v];
         }
         vol[v] = df * idx + dg * idy;
     }
-    if (p == 0 || p == N) {
-        const real* lw = p == 0 ? a.R.l0 : a.R.l1;
-        const int side = p == 0 ? 0 : 1;
 #pragma unroll
-        for (int v = 0; v < M; ++v) {
-            real su = 0, sf = 0;
+    for (int j = 0; j < FPL; ++j) {
+        const int fp = k + j * np;
+        if (j == FPL - 1 && fp >= NFP) break;
+        const int sd = fside(fp), t = fpos(fp);
+        real hf[M];
 #pragma unroll
-            for (int r = 0; r < nd; ++r) {
-                su += lw[r] * sh_u[le][v][q * nd + r];
-                sf += lw[r] * sh_f[le][v][q * nd + r];
-            }
-            Ux[v] = su;
-            sh_h[le][v][side * nd + q] = sf;
-        }
-    }
-    if constexpr (DIM == 2) {
-        if (q == 0 || q == N) {
-            const real* lw = q == 0 ? a.R.l0 : a.R.l1;
-            const int side = q == 0 ? 0 : 1;
+        for (int v = 0; v < M; ++v) { Ut[j][v] = 0; hf[v] = 0; }
+#pragma unroll
+        for (int r = 0; r < nd; ++r) {
+            const int kn = fkn[j][r];
 #pragma unroll
             for (int v = 0; v < M; ++v) {
-                real su = 0, sg = 0;
-#pragma unroll
-                for (int r = 0; r < nd; ++r) {
-                    su += lw[r] * sh_u[le][v][r * nd + p];
-                    sg += lw[r] * sh_g[le][v][r * nd + p];
-                }
-                Uy[v] = su;
-                sh_h[le][v][(2 + side) * nd + p] = sg;
+                Ut[j][v] += fw[j][r] * sh_u[le][kn][v];
+                hf[v] += fw[j][r] * (sd < 2 ? sh_f[le][kn][v] : sh_g[le][kn][DIM == 2 ? v : 0]);
             }
         }
+#pragma unroll
+        for (int v = 0; v < M; ++v) sh_h[le][v][sd * nd + t] = hf[v];
     }
     __syncthreads();
     if (!act) return;
@@ -637,25 +673,19 @@ __global__ void __launch_bounds__(256) k_local(const StepArgs<real> a)
         a.uHp[(size_t)v * nes * np + gi] = un[v] - rdt * (vol[v] - Sa[v]) + rdt * corr;
         if (src && a.dtS) a.dtS[(size_t)v * nes * np + gi] = rdt * Sa[v];
     }
-    if (p == 0 || p == N) {
-        const int side = p == 0 ? 0 : 1;
+#pragma unroll
+    for (int j = 0; j < FPL; ++j) {
+        const int fp = k + j * np;
+        if (j == FPL - 1 && fp >= NFP) break;
+        const int sd = fside(fp), t = fpos(fp), side = sd & 1;
+        real* base = sd < 2 ? a.trx : a.trY;
+        const int npt = sd < 2 ? nq : nd;
 #pragma unroll
         for (int v = 0; v < M; ++v) {
-            a.trx[((size_t)(side * C + v) * nes + e) * nq + q] = trX[v];
-            a.trx[((size_t)(side * C + M + v) * nes + e) * nq + q] = Ux[v];
+            base[((size_t)(side * C + v) * nes + e) * npt + t] = tr[j][v];
+            base[((size_t)(side * C + M + v) * nes + e) * npt + t] = Ut[j][v];
         }
-        a.trx[((size_t)(side * C + 2 * M) * nes + e) * nq + q] = sigX;
-    }
-    if constexpr (DIM == 2) {
-        if (q == 0 || q == N) {
-            const int side = q == 0 ? 0 : 1;
-#pragma unroll
-            for (int v = 0; v < M; ++v) {
-                a.trY[((size_t)(side * C + v) * nes + e) * nd + p] = trYv[v];
-                a.trY[((size_t)(side * C + M + v) * nes + e) * nd + p] = Uy[v];
-            }
-            a.trY[((size_t)(side * C + 2 * M) * nes + e) * nd + p] = sigY;
-        }
+        base[((size_t)(side * C + 2 * M) * nes + e) * npt + t] = sig[j];
     }
 }
 
@@ -875,6 +905,85 @@ __global__ void __launch_bounds__(256) k_face(const StepArgs<real> a)
 }
 
 // ----------------------------------------------------------------------------
+// Sums over the np lanes of one element (lanes of an element are contiguous).
+// When np divides the wavefront the sum is a butterfly of wavefront shuffles;
+// otherwise the M sums go through LDS with two barriers.  Every lane gets
+// every total.
+// ----------------------------------------------------------------------------
+template <int np>
+__device__ __forceinline__ constexpr bool elem_in_wave()
+{
+    return np == 2 || np == 4 || np == 8 || np == 16 || np == 32 || np == 64;
+}
+
+template <int M, int np, int EB>
+__device__ __forceinline__ void elem_sums(const double* in, double* out, double (*sh)[M][np], double (*shm)[M],
+                                          int le, int k)
+{
+    if constexpr (elem_in_wave<np>()) {
+#pragma unroll
+        for (int v = 0; v < M; ++v) {
+            double x = in[v];
+#pragma unroll
+            for (int m = 1; m < np; m <<= 1) x += __shfl_xor(x, m, np);
+            out[v] = x;
+        }
+    } else {
+#pragma unroll
+        for (int v = 0; v < M; ++v) sh[le][v][k] = in[v];
+        __syncthreads();
+        for (int v = k; v < M; v += np) {
+            double x = 0.0;
+#pragma unroll
+            for (int kk = 0; kk < np; ++kk) x += sh[le][v][kk];
+            shm[le][v] = x;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int v = 0; v < M; ++v) out[v] = shm[le][v];
+    }
+}
+
+// minimum over the lanes of one element, one barrier pair when through LDS
+template <int np>
+__device__ __forceinline__ double elem_min(double x, double (*sh)[np], int le, int k)
+{
+    if constexpr (elem_in_wave<np>()) {
+#pragma unroll
+        for (int m = 1; m < np; m <<= 1) {
+            double y = __shfl_xor(x, m, np);
+            x = y < x ? y : x;
+        }
+        return x;
+    } else {
+        sh[le][k] = x;
+        __syncthreads();
+        double r = 1.0;
+#pragma unroll
+        for (int kk = 0; kk < np; ++kk) r = sh[le][kk] < r ? sh[le][kk] : r;
+        __syncthreads();
+        return r;
+    }
+}
+
+// workgroup max of the per-element rates (one value per element, lane k = 0
+// of each element holds it), one atomic per workgroup into slot
+// blockIdx % RATE_SLOTS; every lane must call it (it has a barrier)
+template <int EB>
+__device__ __forceinline__ void block_rate_max(double rate, int le, int k, unsigned long long* slots)
+{
+    __shared__ double sh_w[EB];
+    if (k == 0) sh_w[le] = rate;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r = 0.0;
+#pragma unroll
+        for (int l = 0; l < EB; ++l) r = sh_w[l] > r ? sh_w[l] : r;
+        atomic_max_pos(&slots[blockIdx.x % RATE_SLOTS], r);
+    }
+}
+
+// ----------------------------------------------------------------------------
 // k_update
 // ----------------------------------------------------------------------------
 template <class Eq, int N, class real, bool LIM>
@@ -883,11 +992,14 @@ __global__ void __launch_bounds__(256) k_update(const StepArgs<real> a)
     using G = Geo<Eq::DIM, N>;
     constexpr int M = Eq::M, DIM = Eq::DIM, nd = G::nd, nq = G::nq, np = G::np, EB = G::EB, K = Eq::K;
     constexpr bool MP = is_mp<real>();
-    __shared__ real sh_u[EB][M][np];
-    __shared__ real sh_f[EB][M][np];
-    __shared__ real sh_g[EB][DIM == 2 ? M : 1][np];
+    __shared__ real sh_u[EB][np][M];
+    __shared__ real sh_f[EB][np][M];
+    __shared__ real sh_g[EB][np][DIM == 2 ? M : 1];
     __shared__ double sh_d[EB][np];
-    __shared__ double sh_m[EB][M];
+    __shared__ double sh_r[elem_in_wave<np>() ? 1 : EB][M][np];
+    __shared__ double sh_m[elem_in_wave<np>() ? 1 : EB][M];
+    __shared__ double sh_r2[elem_in_wave<np>() || !MP ? 1 : EB][2 * M][np];
+    __shared__ double sh_m2[elem_in_wave<np>() || !MP ? 1 : EB][2 * M];
 
     const Phys& P = a.phys;
     const int le = threadIdx.x / np, k = threadIdx.x - le * np;
@@ -930,7 +1042,7 @@ __global__ void __launch_bounds__(256) k_update(const StepArgs<real> a)
             real un[M];
             load_node<Eq>(a, np, e, k, un);
 #pragma unroll
-            for (int v = 0; v < M; ++v) sh_u[le][v][k] = un[v];
+            for (int v = 0; v < M; ++v) sh_u[le][k][v] = un[v];
             __syncthreads();
             real xm[M], xp[M], ym[M], yp[M];
             int nlim = 0, nfb = 0;
@@ -938,8 +1050,8 @@ __global__ void __launch_bounds__(256) k_update(const StepArgs<real> a)
             __syncthreads();
 #pragma unroll
             for (int v = 0; v < M; ++v) {
-                sh_f[le][v][k] = xm[v];
-                if constexpr (DIM == 2) sh_g[le][v][k] = ym[v];
+                sh_f[le][k][v] = xm[v];
+                if constexpr (DIM == 2) sh_g[le][k][v] = ym[v];
             }
             __syncthreads();
             real fxp[M], gyp[M];
@@ -949,14 +1061,14 @@ __global__ void __launch_bounds__(256) k_update(const StepArgs<real> a)
                 if (p < N) {
                     real nb[M];
 #pragma unroll
-                    for (int v = 0; v < M; ++v) nb[v] = sh_f[le][v][k + 1];
+                    for (int v = 0; v < M; ++v) nb[v] = sh_f[le][k + 1][v];
                     rusanov<Eq>(0, xp, nb, fxp, P);
                 }
                 if constexpr (DIM == 2) {
                     if (q < N) {
                         real nb[M];
 #pragma unroll
-                        for (int v = 0; v < M; ++v) nb[v] = sh_g[le][v][k + nd];
+                        for (int v = 0; v < M; ++v) nb[v] = sh_g[le][k + nd][v];
                         rusanov<Eq>(1, yp, nb, gyp, P);
                     }
                 }
@@ -964,19 +1076,19 @@ __global__ void __launch_bounds__(256) k_update(const StepArgs<real> a)
             __syncthreads();
 #pragma unroll
             for (int v = 0; v < M; ++v) {
-                sh_f[le][v][k] = fxp[v];
-                if constexpr (DIM == 2) sh_g[le][v][k] = gyp[v];
+                sh_f[le][k][v] = fxp[v];
+                if constexpr (DIM == 2) sh_g[le][k][v] = gyp[v];
             }
             __syncthreads();
             if (al > 0.0) {
                 const real ralpha = (real)al;
 #pragma unroll
                 for (int v = 0; v < M; ++v) {
-                    real fm = p == 0 ? a.Fx[v * nfx + iL] : sh_f[le][v][k - 1];
+                    real fm = p == 0 ? a.Fx[v * nfx + iL] : sh_f[le][k - 1][v];
                     real fp = p == N ? a.Fx[v * nfx + iR] : fxp[v];
                     real uL = un[v] - rdt / (a.R.w[p] * (real)a.dx) * (fp - fm);
                     if constexpr (DIM == 2) {
-                        real gm = q == 0 ? a.Gy[v * nfy + iB] : sh_g[le][v][k - nd];
+                        real gm = q == 0 ? a.Gy[v * nfy + iB] : sh_g[le][k - nd][v];
                         real gp = q == N ? a.Gy[v * nfy + iT] : gyp[v];
                         uL -= rdt / (a.R.w[q] * (real)a.dy) * (gp - gm);
                     }
@@ -987,53 +1099,38 @@ __global__ void __launch_bounds__(256) k_update(const StepArgs<real> a)
         }
     }
 
-    // ---- FP64 element means ----
+    // ---- FP64 element means (MP32: FP64 mean update from the face fluxes,
+    //      eq. upmean with the source average of App. B) ----
     const double wk = a.w64[p] * (DIM == 2 ? a.w64[q] : 1.0);
-    double ubar[M];
+    double part[2 * M], sums[2 * M];
 #pragma unroll
     for (int v = 0; v < M; ++v) {
-        sh_d[le][k] = wk * (double)unew[v];
-        __syncthreads();
-        if (k == 0) {
-            double s2 = 0.0;
-#pragma unroll
-            for (int kk = 0; kk < np; ++kk) s2 += sh_d[le][kk];
-            sh_m[le][v] = s2;
-        }
-        __syncthreads();
-        ubar[v] = sh_m[le][v];
-    }
-    double um[M];   // mean the scaling acts around
-    if constexpr (MP) {
-        // FP64 mean update from the face fluxes (eq. upmean with App. B source)
-        __syncthreads();
-        if (k == 0) {
-#pragma unroll
-            for (int v = 0; v < M; ++v) {
-                double s2 = a.ubar[(size_t)v * nes + e];
-                const size_t iL0 = ((size_t)ey * (a.nx + 1) + ex) * nq;
-                for (int qq = 0; qq < nq; ++qq)
-                    s2 -= dt / a.dx * (DIM == 2 ? a.w64[qq] : 1.0)
-                          * ((double)a.Fx[v * nfx + iL0 + nq + qq] - (double)a.Fx[v * nfx + iL0 + qq]);
-                if constexpr (DIM == 2) {
-                    const size_t iB0 = ((size_t)ey * a.nx + ex) * nd;
-                    for (int pp = 0; pp < nd; ++pp)
-                        s2 -= dt / a.dy * a.w64[pp]
-                              * ((double)a.Gy[v * nfy + iB0 + (size_t)a.nx * nd + pp] - (double)a.Gy[v * nfy + iB0 + pp]);
-                }
-                if (a.dtS)
-                    for (int kk = 0; kk < np; ++kk)
-                        s2 += a.w64[kk % nd] * (DIM == 2 ? a.w64[kk / nd] : 1.0)
-                              * (double)a.dtS[(size_t)v * nes * np + (size_t)e * np + kk];
-                sh_m[le][v] = s2;
+        part[v] = wk * (double)unew[v];
+        double c = 0.0;
+        if constexpr (MP) {
+            if (p == 0)
+                c -= dt / a.dx * (DIM == 2 ? a.w64[q] : 1.0)
+                     * ((double)a.Fx[v * nfx + iR] - (double)a.Fx[v * nfx + iL]);
+            if constexpr (DIM == 2) {
+                if (q == 0)
+                    c -= dt / a.dy * a.w64[p] * ((double)a.Gy[v * nfy + iT] - (double)a.Gy[v * nfy + iB]);
             }
+            if (a.dtS) c += wk * (double)a.dtS[(size_t)v * nes * np + gi];
         }
-        __syncthreads();
+        part[M + v] = c;
+    }
+    double ubar[M], um[M];
+    if constexpr (MP) {
+        elem_sums<2 * M, np, EB>(part, sums, sh_r2, sh_m2, le, k);
 #pragma unroll
-        for (int v = 0; v < M; ++v) um[v] = sh_m[le][v];
+        for (int v = 0; v < M; ++v) {
+            ubar[v] = sums[v];
+            um[v] = a.ubar[(size_t)v * nes + e] + sums[M + v];
+        }
     } else {
+        elem_sums<M, np, EB>(part, sums, sh_r, sh_m, le, k);
 #pragma unroll
-        for (int v = 0; v < M; ++v) um[v] = ubar[v];
+        for (int v = 0; v < M; ++v) { ubar[v] = sums[v]; um[v] = sums[v]; }
     }
     // nodal values in FP64 relative to the mean the state keeps
     double ud[M];
@@ -1041,10 +1138,10 @@ __global__ void __launch_bounds__(256) k_update(const StepArgs<real> a)
     for (int v = 0; v < M; ++v) ud[v] = MP ? um[v] + ((double)unew[v] - ubar[v]) : (double)unew[v];
 
     // ---- Zhang-Shu scaling (reading: eps_k = min(1e-13, P_k(mean)); linear
-    //      root for density, 60-step bisection otherwise) ----
+    //      root for density, 60-step bisection otherwise); every lane runs
+    //      every barrier, the per-element early exit is a flag ----
     if constexpr (K > 0) {
         if (a.scaling) {
-            // every lane runs every barrier: the per-element early exit is a flag
             bool mean_bad = false;
             double th_all = 1.0;
 #pragma unroll
@@ -1059,12 +1156,7 @@ __global__ void __launch_bounds__(256) k_update(const StepArgs<real> a)
                         else t = bisect_root<Eq>(kk, um, ud, eps, P);
                     }
                 }
-                sh_d[le][k] = t;
-                __syncthreads();
-                double th = 1.0;
-#pragma unroll
-                for (int kk2 = 0; kk2 < np; ++kk2) th = sh_d[le][kk2] < th ? sh_d[le][kk2] : th;
-                __syncthreads();
+                const double th = elem_min<np>(t, sh_d, le, k);
                 if (!mean_bad) {
                     if (th < 1.0) {
 #pragma unroll
@@ -1095,8 +1187,8 @@ __global__ void __launch_bounds__(256) k_update(const StepArgs<real> a)
             if constexpr (MP) a.u_out[(size_t)v * nes * np + gi] = (real)(ud[v] - um[v]);
             else a.u_out[(size_t)v * nes * np + gi] = (real)ud[v];
         }
-        if (k == 0) {
-            if constexpr (MP) {
+        if constexpr (MP) {
+            if (k == 0) {
 #pragma unroll
                 for (int v = 0; v < M; ++v) a.ubar_out[(size_t)v * nes + e] = um[v];
             }
@@ -1110,15 +1202,7 @@ __global__ void __launch_bounds__(256) k_update(const StepArgs<real> a)
         rate = (double)Eq::sx(ur, P) / a.dx + (DIM == 2 ? (double)Eq::sy(ur, P) / a.dy : 0.0);
         if (!(rate == rate)) rate = 1e300;
     }
-    // block max of the rate
-    __syncthreads();
-    sh_d[le][k] = rate;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double r = 0.0;
-        for (int l = 0; l < EB; ++l) r = sh_d[l][0] > r ? sh_d[l][0] : r;
-        atomic_max_pos(a.rate_bits, r);
-    }
+    block_rate_max<EB>(rate, le, k, a.rate_bits);
 }
 
 // ----------------------------------------------------------------------------
@@ -1135,18 +1219,30 @@ struct PrepArgs {
     long long* steps;
 };
 
-// time step of eq. time.step.2d from the rate of the current means, last step clipped
-static __global__ void k_prep(PrepArgs a)
+// time step of eq. time.step.2d from the rate of the current means, last
+// step clipped; one workgroup of RATE_SLOTS lanes reduces and clears the slots
+static __global__ void __launch_bounds__(RATE_SLOTS) k_prep(PrepArgs a)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    double rate = __longlong_as_double((long long)*a.rate_bits);
+    __shared__ double sh[RATE_SLOTS / 64];
+    const int t = threadIdx.x;
+    double r = __longlong_as_double((long long)a.rate_bits[t]);
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) {
+        double y = __shfl_xor(r, m, 64);
+        r = y > r ? y : r;
+    }
+    if ((t & 63) == 0) sh[t / 64] = r;
+    __syncthreads();
+    a.rate_bits[t] = 0ull;
+    if (t != 0) return;
+    double rate = 0.0;
+    for (int w = 0; w < RATE_SLOTS / 64; ++w) rate = sh[w] > rate ? sh[w] : rate;
     double dt = a.dt_fixed > 0.0 ? a.dt_fixed : a.cfl_cs / rate;
-    double t = *a.t_dev;
-    if (a.t_end > 0.0 && t + dt > a.t_end) dt = a.t_end - t;
+    double tt = *a.t_dev;
+    if (a.t_end > 0.0 && tt + dt > a.t_end) dt = a.t_end - tt;
     if (dt < 0.0) dt = 0.0;
     *a.dt_dev = dt;
-    *a.t_dev = t + dt;
-    *a.rate_bits = 0ull;
+    *a.t_dev = tt + dt;
     for (int i = 0; i < D_THFLUX; ++i) a.diag[i] = 0ull;
     a.diag[D_THFLUX] = (unsigned long long)__double_as_longlong(1.0);
     a.diag[D_THSCALE] = (unsigned long long)__double_as_longlong(1.0);
@@ -1228,7 +1324,7 @@ __global__ void __launch_bounds__(256) k_import(const IoArgs<real> a)
             for (int v = 0; v < M; ++v) ur[v] = (real)m[v];
             double rate = (double)Eq::sx(ur, a.phys) / a.dx + (DIM == 2 ? (double)Eq::sy(ur, a.phys) / a.dy : 0.0);
             if (!(rate == rate)) rate = 1e300;
-            atomic_max_pos(a.rate_bits, rate);
+            atomic_max_pos(&a.rate_bits[e % RATE_SLOTS], rate);
         }
     }
 }
@@ -1276,9 +1372,9 @@ __global__ void k_ghost(const IoArgs<real> a)
 {
     using G = Geo<Eq::DIM, N>;
     constexpr int M = Eq::M, nd = G::nd, nq = G::nq, np = G::np;
-    const int nx_pts = a.ny * nq, ny_pts = Eq::DIM == 2 ? a.nx * nd : 0;
+    const int nx_pts = a.ny * nq, ny_pts = Eq::DIM == 2 ? a.nx * nd : 1;
     const int tid = blockIdx.x * blockDim.x + threadIdx.x;
-    if (tid >= 2 * nx_pts + 2 * ny_pts) return;
+    if (tid >= 2 * nx_pts + (Eq::DIM == 2 ? 2 * ny_pts : 0)) return;
     const size_t nes = (size_t)a.ne;
     int e, dir, side, t;
     if (tid < 2 * nx_pts) {

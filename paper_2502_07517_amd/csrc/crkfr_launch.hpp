@@ -14,9 +14,12 @@ static void launch_step_phase(int phase, const StepArgs<real>& a, hipStream_t st
     using G = Geo<Eq::DIM, N>;
     const int nb = (a.ne + G::EB - 1) / G::EB;
     switch (phase) {
-    case PH_LOCAL:
-        hipLaunchKernelGGL((k_local<Eq, N, real, LIM>), dim3(nb), dim3(G::BLOCK), 0, st, a);
+    case PH_LOCAL: {
+        using LG = LGeo<Eq::DIM, N>;
+        const int nbl = (a.ne + LG::EB - 1) / LG::EB;
+        hipLaunchKernelGGL((k_local<Eq, N, real, LIM>), dim3(nbl), dim3(LG::BLOCK), 0, st, a);
         break;
+    }
     case PH_FACE_X: {
         long long tot = (long long)a.ny * (a.nx + 1) * G::nq;
         hipLaunchKernelGGL((k_face<Eq, N, real, LIM, 0>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, a);

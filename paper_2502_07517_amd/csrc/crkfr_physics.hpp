@@ -16,8 +16,15 @@ struct Phys {
     double amp, kappa, xc, yc, gx, gy;   // W = amp exp(-kappa r^2) + gx x + gy y
 };
 
-template <class real>
-__device__ __forceinline__ real rsq(real x) { return sqrt(x); }
+// trace value, or the face-adjacent node where the trace density is not positive
+// (value selection keeps both arrays in registers)
+template <int M, class real>
+__device__ __forceinline__ void pick_trace(const real* tr, const real* node, real* u)
+{
+    const bool t = tr[0] > 0;
+#pragma unroll
+    for (int v = 0; v < M; ++v) u[v] = t ? tr[v] : node[v];
+}
 
 // ---------------------------------------------------------------- linear advection
 template <class real>
@@ -32,6 +39,7 @@ struct LinAdv1D {
     __device__ static inline real ind(const real* u, const Phys&) { return u[0]; }
     __device__ static inline real sig_trace(int, const real*, const real*, const Phys& P) { return fabs((real)P.adv); }
     __device__ static inline void src(const real*, real, real, real* s, const Phys&) { s[0] = 0; }
+    __device__ static inline void fxy(const real* u, real* f, real* g, const Phys& P) { fx(u, f, P); g[0] = 0; }
 };
 
 // ---------------------------------------------------------------- Euler 1D
@@ -65,11 +73,21 @@ struct Euler1D {
     // trace wave speed: pressure clipped at zero; non-positive density -> node
     __device__ static inline real sig_trace(int, const real* tr, const real* node, const Phys& P)
     {
-        const real* u = tr[0] > 0 ? tr : node;
+        real u[M];
+        pick_trace<M>(tr, node, u);
         real p = pres(u, P);
         return fabs(u[1] / u[0]) + sqrt((real)P.gamma * fmax(p, (real)0) / u[0]);
     }
     __device__ static inline void src(const real*, real, real, real* s, const Phys&) { s[0] = s[1] = s[2] = 0; }
+    __device__ static inline void fxy(const real* u, real* f, real* g, const Phys& P)
+    {
+        real ir = (real)1 / u[0], v = u[1] * ir;
+        real p = ((real)P.gamma - 1) * (u[2] - (real)0.5 * u[1] * v);
+        f[0] = u[1];
+        f[1] = u[1] * v + p;
+        f[2] = (u[2] + p) * v;
+        g[0] = g[1] = g[2] = 0;
+    }
 };
 
 // ---------------------------------------------------------------- Euler 2D
@@ -113,11 +131,27 @@ struct Euler2D {
     __device__ static inline real ind(const real* u, const Phys& P) { return u[0] * pres(u, P); }
     __device__ static inline real sig_trace(int d, const real* tr, const real* node, const Phys& P)
     {
-        const real* u = tr[0] > 0 ? tr : node;
+        real u[M];
+        pick_trace<M>(tr, node, u);
         real c = sqrt((real)P.gamma * fmax(pres(u, P), (real)0) / u[0]);
-        return fabs(u[1 + d] / u[0]) + c;
+        return fabs((d == 0 ? u[1] : u[2]) / u[0]) + c;
     }
     __device__ static inline void src(const real*, real, real, real* s, const Phys&) { s[0] = s[1] = s[2] = s[3] = 0; }
+    // both fluxes with one reciprocal of the density
+    __device__ static inline void fxy(const real* u, real* f, real* g, const Phys& P)
+    {
+        real ir = (real)1 / u[0], v1 = u[1] * ir, v2 = u[2] * ir;
+        real p = ((real)P.gamma - 1) * (u[3] - (real)0.5 * (u[1] * v1 + u[2] * v2));
+        real ep = u[3] + p;
+        f[0] = u[1];
+        f[1] = u[1] * v1 + p;
+        f[2] = u[2] * v1;
+        f[3] = ep * v1;
+        g[0] = u[2];
+        g[1] = u[1] * v2;
+        g[2] = u[2] * v2 + p;
+        g[3] = ep * v2;
+    }
 };
 
 // ---------------------------------------------------------------- ten-moment 2D
@@ -173,7 +207,8 @@ struct TenMom2D {
     }
     __device__ static inline real sig_trace(int d, const real* tr, const real* node, const Phys&)
     {
-        const real* u = tr[0] > 0 ? tr : node;
+        real u[M];
+        pick_trace<M>(tr, node, u);
         real r = u[0];
         if (d == 0) {
             real v1 = u[1] / r;
@@ -181,6 +216,23 @@ struct TenMom2D {
         }
         real v2 = u[2] / r;
         return fabs(v2) + sqrt(3 * fmax(2 * u[5] - r * v2 * v2, (real)0) / r);
+    }
+    __device__ static inline void fxy(const real* u, real* f, real* g, const Phys& P)
+    {
+        real r = u[0], ir = (real)1 / r, v1 = u[1] * ir, v2 = u[2] * ir;
+        real P11 = 2 * u[3] - r * v1 * v1, P12 = 2 * u[4] - r * v1 * v2, P22 = 2 * u[5] - r * v2 * v2;
+        f[0] = u[1];
+        f[1] = P11 + r * v1 * v1;
+        f[2] = P12 + r * v1 * v2;
+        f[3] = (u[3] + P11) * v1;
+        f[4] = u[4] * v1 + (real)0.5 * (P11 * v2 + P12 * v1);
+        f[5] = u[5] * v1 + P12 * v2;
+        g[0] = u[2];
+        g[1] = f[2];
+        g[2] = P22 + r * v2 * v2;
+        g[3] = u[3] * v2 + P12 * v1;
+        g[4] = u[4] * v2 + (real)0.5 * (P12 * v2 + P22 * v1);
+        g[5] = (u[5] + P22) * v2;
     }
     // s = s^x + s^y with grad W of W = amp exp(-kappa r^2) + gx x + gy y
     __device__ static inline void src(const real* u, real x, real y, real* s, const Phys& P)
