@@ -105,9 +105,9 @@ typedef struct {
 typedef struct crkfr_solver crkfr_solver;
 
 /* Create a solver on the current HIP device, ordered on hip_stream (a
- * hipStream_t; NULL = the null stream).  Allocates every device buffer the
- * step needs.  Errors: EINVAL (N outside 1..4, sizes < 1, bad enums),
- * ENOMEM, EHIP. */
+ * hipStream_t; NULL: the solver creates a stream of its own, default
+ * priority, destroyed with it).  Allocates every device buffer the step
+ * needs.  Errors: EINVAL (N outside 1..4, sizes < 1, bad enums), ENOMEM, EHIP. */
 int crkfr_create(const crkfr_config* cfg, void* hip_stream, crkfr_solver** out);
 void crkfr_destroy(crkfr_solver* s);
 
@@ -161,6 +161,30 @@ double crkfr_fourier_cfl(int N, int stages, int system, double tol);
  * [0] local cRK, [1] x faces, [2] y faces, [3] update; needs timing = 1. */
 int crkfr_set_timing(crkfr_solver* s, int on);
 int crkfr_get_kernel_times(crkfr_solver* s, float* ms4);
+
+/* ---- batches --------------------------------------------------------------
+ * Many solvers advanced together: each step is one batched time-step kernel
+ * (one workgroup per instance) and, per phase of the step and per group of
+ * members with equal equation, degree, arithmetic and limiting, one launch of
+ * persistent workgroups walking a table of (instance, block) work items.  The
+ * solvers stay owned by the caller, must have a state, and must not be used
+ * on their own while the batch runs; call crkfr_batch_sync before reading
+ * their state.  Each member keeps its own time step (eq. time.step.2d). */
+typedef struct crkfr_batch crkfr_batch;
+int crkfr_batch_create(crkfr_solver* const* solvers, int count, void* hip_stream, crkfr_batch** out);
+void crkfr_batch_destroy(crkfr_batch* b);
+/* one step of every member (enqueue only) */
+int crkfr_batch_step(crkfr_batch* b);
+/* steps, replaying a captured two-step HIP graph */
+int crkfr_batch_advance(crkfr_batch* b, int steps);
+int crkfr_batch_sync(crkfr_batch* b);
+int crkfr_batch_num_groups(const crkfr_batch* b);
+/* persistent workgroups of (group, phase 0..3: local, x faces, y faces,
+ * update); set_to >= 0 sets it (0: one workgroup per work item); returns it */
+int crkfr_batch_grid(crkfr_batch* b, int group, int phase, int set_to);
+/* time each phase of each group for persistent grids of 0, 1, 2, 4, 8, 16
+ * workgroups per compute unit and keep the fastest (state not advanced) */
+int crkfr_batch_autotune(crkfr_batch* b, int reps);
 
 const char* crkfr_last_error(void);
 

@@ -55,7 +55,9 @@ SYMBOLS = ["crkfr_create", "crkfr_destroy", "crkfr_set_limiter", "crkfr_set_sour
            "crkfr_set_alpha", "crkfr_compute_dt", "crkfr_step", "crkfr_advance", "crkfr_get_state",
            "crkfr_get_means", "crkfr_get_alpha", "crkfr_get_diag", "crkfr_nvar", "crkfr_nodes_per_element",
            "crkfr_cfl_in_use", "crkfr_fourier_cfl", "crkfr_set_timing", "crkfr_get_kernel_times",
-           "crkfr_last_error"]
+           "crkfr_last_error", "crkfr_batch_create", "crkfr_batch_destroy", "crkfr_batch_step",
+           "crkfr_batch_advance", "crkfr_batch_sync", "crkfr_batch_num_groups", "crkfr_batch_grid",
+           "crkfr_batch_autotune"]
 
 _lib = None
 
@@ -99,6 +101,15 @@ def lib():
         L.crkfr_set_timing.argtypes = [vp, ip]
         L.crkfr_get_kernel_times.argtypes = [vp, ctypes.POINTER(ctypes.c_float)]
         L.crkfr_last_error.restype = ctypes.c_char_p
+        L.crkfr_batch_create.argtypes = [ctypes.POINTER(vp), ip, vp, ctypes.POINTER(vp)]
+        L.crkfr_batch_destroy.argtypes = [vp]
+        L.crkfr_batch_destroy.restype = None
+        L.crkfr_batch_step.argtypes = [vp]
+        L.crkfr_batch_advance.argtypes = [vp, ip]
+        L.crkfr_batch_sync.argtypes = [vp]
+        L.crkfr_batch_num_groups.argtypes = [vp]
+        L.crkfr_batch_grid.argtypes = [vp, ip, ip, ip]
+        L.crkfr_batch_autotune.argtypes = [vp, ip]
         _lib = L
     return _lib
 
@@ -244,3 +255,51 @@ class Solver:
         ms = (ctypes.c_float * 4)()
         _check(lib().crkfr_get_kernel_times(self.h, ms))
         return list(ms)
+
+
+class Batch:
+    """Many solvers advanced together (see the batch calls of include/crkfr.h)."""
+
+    def __init__(self, solvers, stream=None):
+        self.solvers = list(solvers)
+        arr = (ctypes.c_void_p * len(self.solvers))(*[s.h.value for s in self.solvers])
+        h = ctypes.c_void_p()
+        st = ctypes.c_void_p(stream) if stream is not None else None
+        _check(lib().crkfr_batch_create(arr, len(self.solvers), st, ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().crkfr_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self):
+        _check(lib().crkfr_batch_step(self.h))
+
+    def advance(self, steps):
+        _check(lib().crkfr_batch_advance(self.h, int(steps)))
+
+    def sync(self):
+        _check(lib().crkfr_batch_sync(self.h))
+
+    def num_groups(self):
+        return lib().crkfr_batch_num_groups(self.h)
+
+    def grid(self, group, phase, set_to=-1):
+        r = lib().crkfr_batch_grid(self.h, group, phase, set_to)
+        if r < 0:
+            _check(r)
+        return r
+
+    def grids(self):
+        return [[self.grid(g, ph) for ph in range(4)] for g in range(self.num_groups())]
+
+    def autotune(self, reps=3):
+        _check(lib().crkfr_batch_autotune(self.h, int(reps)))
+        return self.grids()

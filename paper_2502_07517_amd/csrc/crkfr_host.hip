@@ -836,3 +836,353 @@ extern "C" int crkfr_get_kernel_times(crkfr_solver* s, float* ms4)
 }
 
 extern "C" const char* crkfr_last_error(void) { return g_last_error.c_str(); }
+
+// ----------------------------------------------------------------------------
+// batches: many instances advanced together, one launch per phase and degree
+// group (persistent workgroups over a table of work items), the steps
+// captured as one HIP graph
+// ----------------------------------------------------------------------------
+struct BatchGroup {
+    int eq, N, lim;
+    bool mp;
+    std::vector<int> members;
+    void* d_args[2];          // StepArgs<real>[members] for state parity 0 / 1
+    int2* d_work[4];
+    int nwork[4];
+    int grid[4];              // persistent workgroups per phase (0: one per work item)
+};
+
+struct crkfr_batch {
+    std::vector<crkfr_solver*> s;
+    std::vector<int> cur0;
+    hipStream_t stream;
+    bool own_stream;
+    std::vector<BatchGroup> groups;
+    PrepArgs* d_prep;
+    int parity;
+    hipGraphExec_t graph;
+    int graph_parity;
+    hipEvent_t ev0, ev1;
+};
+
+static int eq_geometry(int eq, int N, int* el, int* eu, int* nq)
+{
+    switch (eq) {
+    case CRKFR_LINADV1D: return linadv1d_geometry(N, el, eu, nq);
+    case CRKFR_EULER1D: return euler1d_geometry(N, el, eu, nq);
+    case CRKFR_EULER2D: return euler2d_geometry(N, el, eu, nq);
+    case CRKFR_TENMOM2D: return tenmom2d_geometry(N, el, eu, nq);
+    }
+    return -1;
+}
+
+static int launch_group_phase(const crkfr_batch* b, const BatchGroup& g, int phase, int grid)
+{
+    if (g.nwork[phase] == 0) return 0;
+    int rc = -1;
+    const int2* w = g.d_work[phase];
+    const int nw = g.nwork[phase];
+    if (g.mp) {
+        const StepArgs<float>* args = (const StepArgs<float>*)g.d_args[b->parity];
+        switch (g.eq) {
+        case CRKFR_LINADV1D: rc = linadv1d_batch_f32(g.N, g.lim, phase, args, w, nw, grid, b->stream); break;
+        case CRKFR_EULER1D: rc = euler1d_batch_f32(g.N, g.lim, phase, args, w, nw, grid, b->stream); break;
+        case CRKFR_EULER2D: rc = euler2d_batch_f32(g.N, g.lim, phase, args, w, nw, grid, b->stream); break;
+        case CRKFR_TENMOM2D: rc = tenmom2d_batch_f32(g.N, g.lim, phase, args, w, nw, grid, b->stream); break;
+        }
+    } else {
+        const StepArgs<double>* args = (const StepArgs<double>*)g.d_args[b->parity];
+        switch (g.eq) {
+        case CRKFR_LINADV1D: rc = linadv1d_batch_f64(g.N, g.lim, phase, args, w, nw, grid, b->stream); break;
+        case CRKFR_EULER1D: rc = euler1d_batch_f64(g.N, g.lim, phase, args, w, nw, grid, b->stream); break;
+        case CRKFR_EULER2D: rc = euler2d_batch_f64(g.N, g.lim, phase, args, w, nw, grid, b->stream); break;
+        case CRKFR_TENMOM2D: rc = tenmom2d_batch_f64(g.N, g.lim, phase, args, w, nw, grid, b->stream); break;
+        }
+    }
+    if (rc) return fail(CRKFR_EINVAL, "no batched kernel for this group");
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(CRKFR_EHIP, std::string("batched launch: ") + hipGetErrorString(e));
+    return 0;
+}
+
+static int enqueue_batch_step(crkfr_batch* b)
+{
+    hipLaunchKernelGGL(k_prep_batch, dim3((unsigned)b->s.size()), dim3(RATE_SLOTS), 0, b->stream, b->d_prep);
+    for (int ph = 0; ph < 4; ++ph)
+        for (const BatchGroup& g : b->groups) {
+            int rc = launch_group_phase(b, g, ph, g.grid[ph]);
+            if (rc) return rc;
+        }
+    b->parity ^= 1;
+    for (size_t i = 0; i < b->s.size(); ++i) b->s[i]->cur = b->parity ? 1 - b->cur0[i] : b->cur0[i];
+    return 0;
+}
+
+static void free_batch(crkfr_batch* b)
+{
+    for (BatchGroup& g : b->groups) {
+        for (int i = 0; i < 2; ++i)
+            if (g.d_args[i]) (void)hipFree(g.d_args[i]);
+        for (int i = 0; i < 4; ++i)
+            if (g.d_work[i]) (void)hipFree(g.d_work[i]);
+    }
+    if (b->d_prep) (void)hipFree(b->d_prep);
+    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    if (b->ev0) (void)hipEventDestroy(b->ev0);
+    if (b->ev1) (void)hipEventDestroy(b->ev1);
+    if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+}
+
+template <class real>
+static int upload_group_args(crkfr_batch* b, BatchGroup& g)
+{
+    for (int par = 0; par < 2; ++par) {
+        std::vector<StepArgs<real>> h;
+        for (int m : g.members) {
+            crkfr_solver* s = b->s[m];
+            const int in = par ? 1 - b->cur0[m] : b->cur0[m];
+            h.push_back(step_args<real>(s, in, 1 - in));
+        }
+        HIP_TRY(hipMalloc(&g.d_args[par], h.size() * sizeof(StepArgs<real>)));
+        HIP_TRY(hipMemcpy(g.d_args[par], h.data(), h.size() * sizeof(StepArgs<real>), hipMemcpyHostToDevice));
+    }
+    return 0;
+}
+
+extern "C" int crkfr_batch_create(crkfr_solver* const* solvers, int count, void* hip_stream, crkfr_batch** out)
+{
+    if (!solvers || count < 1 || !out) return fail(CRKFR_EINVAL, "null argument or empty batch");
+    *out = nullptr;
+    crkfr_batch* b = new crkfr_batch();
+    b->stream = (hipStream_t)hip_stream;
+    if (!b->stream) {
+        hipError_t e = hipStreamCreate(&b->stream);
+        if (e != hipSuccess) {
+            delete b;
+            return fail(CRKFR_EHIP, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+        }
+        b->own_stream = true;
+    }
+    for (int i = 0; i < count; ++i) {
+        crkfr_solver* s = solvers[i];
+        if (!s || !s->has_state) {
+            free_batch(b);
+            delete b;
+            return fail(CRKFR_ESTATE, "every batch member needs a state");
+        }
+        (void)hipStreamSynchronize(s->stream);
+        b->s.push_back(s);
+        b->cur0.push_back(s->cur);
+    }
+    // group members by equation, degree, arithmetic and limiting
+    for (int i = 0; i < count; ++i) {
+        crkfr_solver* s = b->s[i];
+        const int lim = s->lim.blend != CRKFR_BLEND_OFF;
+        BatchGroup* g = nullptr;
+        for (BatchGroup& gg : b->groups)
+            if (gg.eq == s->cfg.equation && gg.N == s->cfg.N && gg.mp == s->mp && gg.lim == lim) g = &gg;
+        if (!g) {
+            BatchGroup ng;
+            std::memset(ng.d_args, 0, sizeof(ng.d_args));
+            std::memset(ng.d_work, 0, sizeof(ng.d_work));
+            std::memset(ng.nwork, 0, sizeof(ng.nwork));
+            std::memset(ng.grid, 0, sizeof(ng.grid));
+            ng.eq = s->cfg.equation;
+            ng.N = s->cfg.N;
+            ng.mp = s->mp;
+            ng.lim = lim;
+            b->groups.push_back(ng);
+            g = &b->groups.back();
+        }
+        g->members.push_back(i);
+    }
+    for (BatchGroup& g : b->groups) {
+        int rc = g.mp ? upload_group_args<float>(b, g) : upload_group_args<double>(b, g);
+        if (rc) { free_batch(b); delete b; return rc; }
+        int el = 0, eu = 0, nq = 0;
+        eq_geometry(g.eq, g.N, &el, &eu, &nq);
+        std::vector<int2> work[4];
+        for (size_t j = 0; j < g.members.size(); ++j) {
+            crkfr_solver* s = b->s[g.members[j]];
+            const int nx = s->cfg.nx, ny = s->cfg.ny, nd = s->nd;
+            const long long cnt[4] = {
+                (s->ne + el - 1) / el,
+                ((long long)ny * (nx + 1) * nq + 255) / 256,
+                s->dim == 2 ? ((long long)(ny + 1) * nx * nd + 255) / 256 : 0,
+                (s->ne + eu - 1) / eu};
+            for (int ph = 0; ph < 4; ++ph)
+                for (long long w = 0; w < cnt[ph]; ++w) work[ph].push_back(make_int2((int)j, (int)w));
+        }
+        for (int ph = 0; ph < 4; ++ph) {
+            g.nwork[ph] = (int)work[ph].size();
+            if (g.nwork[ph] == 0) continue;
+            if (hipMalloc((void**)&g.d_work[ph], work[ph].size() * sizeof(int2)) != hipSuccess ||
+                hipMemcpy(g.d_work[ph], work[ph].data(), work[ph].size() * sizeof(int2), hipMemcpyHostToDevice)
+                    != hipSuccess) {
+                free_batch(b);
+                delete b;
+                return fail(CRKFR_ENOMEM, "batch work tables");
+            }
+        }
+    }
+    std::vector<PrepArgs> prep;
+    for (crkfr_solver* s : b->s) {
+        PrepArgs pa;
+        pa.dt_dev = s->dt_dev;
+        pa.t_dev = s->t_dev;
+        pa.t_end = 0.0;
+        pa.dt_fixed = 0.0;
+        pa.cfl_cs = s->cfg.cs * s->cfl;
+        pa.rate_bits = s->rate_bits;
+        pa.diag = s->diag;
+        pa.steps = s->steps;
+        prep.push_back(pa);
+    }
+    if (hipMalloc((void**)&b->d_prep, prep.size() * sizeof(PrepArgs)) != hipSuccess ||
+        hipMemcpy(b->d_prep, prep.data(), prep.size() * sizeof(PrepArgs), hipMemcpyHostToDevice) != hipSuccess) {
+        free_batch(b);
+        delete b;
+        return fail(CRKFR_ENOMEM, "batch time-step table");
+    }
+    (void)hipEventCreate(&b->ev0);
+    (void)hipEventCreate(&b->ev1);
+    *out = b;
+    return 0;
+}
+
+extern "C" void crkfr_batch_destroy(crkfr_batch* b)
+{
+    if (!b) return;
+    (void)hipStreamSynchronize(b->stream);
+    free_batch(b);
+    delete b;
+}
+
+extern "C" int crkfr_batch_step(crkfr_batch* b)
+{
+    if (!b) return fail(CRKFR_EINVAL, "null argument");
+    return enqueue_batch_step(b);
+}
+
+extern "C" int crkfr_batch_advance(crkfr_batch* b, int steps)
+{
+    if (!b || steps < 0) return fail(CRKFR_EINVAL, "bad argument");
+    if (!b->graph || b->graph_parity != b->parity) {
+        if (b->graph) {
+            (void)hipGraphExecDestroy(b->graph);
+            b->graph = nullptr;
+        }
+        hipGraph_t g;
+        const int par0 = b->parity;
+        hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return fail(CRKFR_EHIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
+        int rc = enqueue_batch_step(b);
+        if (!rc) rc = enqueue_batch_step(b);
+        e = hipStreamEndCapture(b->stream, &g);
+        b->parity = par0;
+        for (size_t i = 0; i < b->s.size(); ++i) b->s[i]->cur = b->parity ? 1 - b->cur0[i] : b->cur0[i];
+        if (rc) {
+            if (e == hipSuccess) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return fail(CRKFR_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+        e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return fail(CRKFR_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+        b->graph_parity = par0;
+    }
+    int done = 0;
+    for (; done + 2 <= steps; done += 2) HIP_TRY(hipGraphLaunch(b->graph, b->stream));
+    if (done < steps) return enqueue_batch_step(b);
+    return 0;
+}
+
+extern "C" int crkfr_batch_sync(crkfr_batch* b)
+{
+    if (!b) return fail(CRKFR_EINVAL, "null argument");
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    return 0;
+}
+
+extern "C" int crkfr_batch_num_groups(const crkfr_batch* b) { return b ? (int)b->groups.size() : 0; }
+
+extern "C" int crkfr_batch_grid(crkfr_batch* b, int group, int phase, int set_to)
+{
+    if (!b || group < 0 || group >= (int)b->groups.size() || phase < 0 || phase > 3)
+        return fail(CRKFR_EINVAL, "bad group or phase");
+    if (set_to >= 0) {
+        b->groups[group].grid[phase] = set_to;
+        if (b->graph) {
+            (void)hipGraphExecDestroy(b->graph);
+            b->graph = nullptr;
+        }
+    }
+    return b->groups[group].grid[phase];
+}
+
+// time each phase of each group for a set of persistent grid sizes and keep
+// the fastest; phases are re-run on the current state (their outputs are
+// recomputed by the next step), so the state is not advanced
+extern "C" int crkfr_batch_autotune(crkfr_batch* b, int reps)
+{
+    if (!b || reps < 1) return fail(CRKFR_EINVAL, "bad argument");
+    int dev = 0, ncu = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    // the trial runs touch each member's time-step slots, clock and counters:
+    // keep them and put them back afterwards
+    struct Saved {
+        unsigned long long rate[RATE_SLOTS], diag[D_NCOUNT];
+        double t, dt;
+        long long steps;
+    };
+    std::vector<Saved> saved(b->s.size());
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    for (size_t i = 0; i < b->s.size(); ++i) {
+        crkfr_solver* s = b->s[i];
+        HIP_TRY(hipMemcpy(saved[i].rate, s->rate_bits, sizeof(saved[i].rate), hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(saved[i].diag, s->diag, sizeof(saved[i].diag), hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(&saved[i].t, s->t_dev, sizeof(double), hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(&saved[i].dt, s->dt_dev, sizeof(double), hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(&saved[i].steps, s->steps, sizeof(long long), hipMemcpyDeviceToHost));
+    }
+    // the step's inputs must exist: one k_prep so every dt is set
+    hipLaunchKernelGGL(k_prep_batch, dim3((unsigned)b->s.size()), dim3(RATE_SLOTS), 0, b->stream, b->d_prep);
+    for (BatchGroup& g : b->groups)
+        for (int ph = 0; ph < 4; ++ph) {
+            if (g.nwork[ph] == 0) continue;
+            const int cands[] = {0, ncu, 2 * ncu, 4 * ncu, 8 * ncu, 16 * ncu};
+            float best = 1e30f;
+            int best_grid = 0;
+            for (int c : cands) {
+                if (c >= g.nwork[ph]) continue;
+                int rc = launch_group_phase(b, g, ph, c);   // warm-up
+                if (rc) return rc;
+                HIP_TRY(hipEventRecord(b->ev0, b->stream));
+                for (int r = 0; r < reps; ++r) {
+                    rc = launch_group_phase(b, g, ph, c);
+                    if (rc) return rc;
+                }
+                HIP_TRY(hipEventRecord(b->ev1, b->stream));
+                HIP_TRY(hipEventSynchronize(b->ev1));
+                float ms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&ms, b->ev0, b->ev1));
+                if (ms < best) { best = ms; best_grid = c; }
+            }
+            g.grid[ph] = best_grid;
+        }
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    for (size_t i = 0; i < b->s.size(); ++i) {
+        crkfr_solver* s = b->s[i];
+        HIP_TRY(hipMemcpy(s->rate_bits, saved[i].rate, sizeof(saved[i].rate), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(s->diag, saved[i].diag, sizeof(saved[i].diag), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(s->t_dev, &saved[i].t, sizeof(double), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(s->dt_dev, &saved[i].dt, sizeof(double), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(s->steps, &saved[i].steps, sizeof(long long), hipMemcpyHostToDevice));
+    }
+    if (b->graph) {
+        (void)hipGraphExecDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    return 0;
+}

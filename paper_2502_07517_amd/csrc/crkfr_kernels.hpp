@@ -384,7 +384,7 @@ __device__ void mh_subcell(const StepArgs<real>& a, int e, int ex, int ey, int p
 // k_local
 // ----------------------------------------------------------------------------
 template <class Eq, int N, class real, bool LIM>
-__global__ void __launch_bounds__(256) k_local(const StepArgs<real> a)
+__device__ void local_body(const StepArgs<real>& a, int vblock)
 {
     using G = LGeo<Eq::DIM, N>;
     constexpr int M = Eq::M, DIM = Eq::DIM, nd = G::nd, nq = G::nq, np = G::np, EB = G::EB;
@@ -398,7 +398,7 @@ __global__ void __launch_bounds__(256) k_local(const StepArgs<real> a)
     const Phys& P = a.phys;
     const int le = threadIdx.x / np, k = threadIdx.x - le * np;
     const int p = k % nd, q = k / nd;
-    const int e0 = blockIdx.x * EB + le;
+    const int e0 = vblock * EB + le;
     const bool act = e0 < a.ne;
     const int e = act ? e0 : a.ne - 1;
     const int ex = e % a.nx, ey = e / a.nx;
@@ -723,14 +723,14 @@ __device__ __forceinline__ double dir_share(const StepArgs<real>& a, int d, int 
 // k_face: one lane per face point of direction D
 // ----------------------------------------------------------------------------
 template <class Eq, int N, class real, bool LIM, int D>
-__global__ void __launch_bounds__(256) k_face(const StepArgs<real> a)
+__device__ void face_body(const StepArgs<real>& a, int vblock)
 {
     using G = Geo<Eq::DIM, N>;
     constexpr int M = Eq::M, nd = G::nd, nq = G::nq, np = G::np, K = Eq::K;
     const Phys& P = a.phys;
     const int npt = D == 0 ? nq : nd;
     const long long total = D == 0 ? (long long)a.ny * (a.nx + 1) * nq : (long long)(a.ny + 1) * a.nx * nd;
-    const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long tid = (long long)vblock * blockDim.x + threadIdx.x;
     if (tid >= total) return;
     const int t = (int)(tid % npt);
     int eL, eR, exL, eyL, exR, eyR;
@@ -970,7 +970,7 @@ __device__ __forceinline__ double elem_min(double x, double (*sh)[np], int le, i
 // of each element holds it), one atomic per workgroup into slot
 // blockIdx % RATE_SLOTS; every lane must call it (it has a barrier)
 template <int EB>
-__device__ __forceinline__ void block_rate_max(double rate, int le, int k, unsigned long long* slots)
+__device__ __forceinline__ void block_rate_max(double rate, int le, int k, int vblock, unsigned long long* slots)
 {
     __shared__ double sh_w[EB];
     if (k == 0) sh_w[le] = rate;
@@ -979,7 +979,7 @@ __device__ __forceinline__ void block_rate_max(double rate, int le, int k, unsig
         double r = 0.0;
 #pragma unroll
         for (int l = 0; l < EB; ++l) r = sh_w[l] > r ? sh_w[l] : r;
-        atomic_max_pos(&slots[blockIdx.x % RATE_SLOTS], r);
+        atomic_max_pos(&slots[vblock % RATE_SLOTS], r);
     }
 }
 
@@ -987,7 +987,7 @@ __device__ __forceinline__ void block_rate_max(double rate, int le, int k, unsig
 // k_update
 // ----------------------------------------------------------------------------
 template <class Eq, int N, class real, bool LIM>
-__global__ void __launch_bounds__(256) k_update(const StepArgs<real> a)
+__device__ void update_body(const StepArgs<real>& a, int vblock)
 {
     using G = Geo<Eq::DIM, N>;
     constexpr int M = Eq::M, DIM = Eq::DIM, nd = G::nd, nq = G::nq, np = G::np, EB = G::EB, K = Eq::K;
@@ -1004,7 +1004,7 @@ __global__ void __launch_bounds__(256) k_update(const StepArgs<real> a)
     const Phys& P = a.phys;
     const int le = threadIdx.x / np, k = threadIdx.x - le * np;
     const int p = k % nd, q = k / nd;
-    const int e0 = blockIdx.x * EB + le;
+    const int e0 = vblock * EB + le;
     const bool act = e0 < a.ne;
     const int e = act ? e0 : a.ne - 1;
     const int ex = e % a.nx, ey = e / a.nx;
@@ -1202,7 +1202,41 @@ __global__ void __launch_bounds__(256) k_update(const StepArgs<real> a)
         rate = (double)Eq::sx(ur, P) / a.dx + (DIM == 2 ? (double)Eq::sy(ur, P) / a.dy : 0.0);
         if (!(rate == rate)) rate = 1e300;
     }
-    block_rate_max<EB>(rate, le, k, a.rate_bits);
+    block_rate_max<EB>(rate, le, k, vblock, a.rate_bits);
+}
+
+// ----------------------------------------------------------------------------
+// single-instance kernels
+// ----------------------------------------------------------------------------
+template <class Eq, int N, class real, bool LIM>
+__global__ void __launch_bounds__(256) k_local(const StepArgs<real> a) { local_body<Eq, N, real, LIM>(a, blockIdx.x); }
+
+template <class Eq, int N, class real, bool LIM, int D>
+__global__ void __launch_bounds__(256) k_face(const StepArgs<real> a) { face_body<Eq, N, real, LIM, D>(a, blockIdx.x); }
+
+template <class Eq, int N, class real, bool LIM>
+__global__ void __launch_bounds__(256) k_update(const StepArgs<real> a) { update_body<Eq, N, real, LIM>(a, blockIdx.x); }
+
+// ----------------------------------------------------------------------------
+// batched kernels: persistent workgroups walk a table of (instance, block)
+// work items of one phase over every instance of one degree; each instance's
+// arguments are read from device memory (block-uniform, scalar loads)
+// ----------------------------------------------------------------------------
+enum { BPH_LOCAL = 0, BPH_FACE_X = 1, BPH_FACE_Y = 2, BPH_UPDATE = 3 };
+
+template <class Eq, int N, class real, bool LIM, int PH>
+__global__ void __launch_bounds__(256) k_batch(const StepArgs<real>* __restrict__ args,
+                                                const int2* __restrict__ work, int nwork)
+{
+    for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
+        const int2 it = work[w];
+        const StepArgs<real>& a = args[it.x];
+        if constexpr (PH == BPH_LOCAL) local_body<Eq, N, real, LIM>(a, it.y);
+        else if constexpr (PH == BPH_FACE_X) face_body<Eq, N, real, LIM, 0>(a, it.y);
+        else if constexpr (PH == BPH_FACE_Y) face_body<Eq, N, real, LIM, 1>(a, it.y);
+        else update_body<Eq, N, real, LIM>(a, it.y);
+        __syncthreads();   // LDS of this work item is reused by the next
+    }
 }
 
 // ----------------------------------------------------------------------------
@@ -1221,7 +1255,7 @@ struct PrepArgs {
 
 // time step of eq. time.step.2d from the rate of the current means, last
 // step clipped; one workgroup of RATE_SLOTS lanes reduces and clears the slots
-static __global__ void __launch_bounds__(RATE_SLOTS) k_prep(PrepArgs a)
+__device__ __forceinline__ void prep_body(const PrepArgs& a)
 {
     __shared__ double sh[RATE_SLOTS / 64];
     const int t = threadIdx.x;
@@ -1247,6 +1281,14 @@ static __global__ void __launch_bounds__(RATE_SLOTS) k_prep(PrepArgs a)
     a.diag[D_THFLUX] = (unsigned long long)__double_as_longlong(1.0);
     a.diag[D_THSCALE] = (unsigned long long)__double_as_longlong(1.0);
     *a.steps += 1;
+}
+
+static __global__ void __launch_bounds__(RATE_SLOTS) k_prep(PrepArgs a) { prep_body(a); }
+
+// one workgroup per instance of a batch
+static __global__ void __launch_bounds__(RATE_SLOTS) k_prep_batch(const PrepArgs* __restrict__ arr)
+{
+    prep_body(arr[blockIdx.x]);
 }
 
 // ----------------------------------------------------------------------------

@@ -58,6 +58,72 @@ static void launch_io_phase(int phase, const IoArgs<real>& a, hipStream_t st)
     }
 }
 
+// work-item block sizes of each phase (host side)
+template <template <class> class EqT, int N, class real>
+static void batch_geometry(int* elems_local, int* elems_update, int* nq)
+{
+    using Eq = EqT<real>;
+    *elems_local = LGeo<Eq::DIM, N>::EB;
+    *elems_update = Geo<Eq::DIM, N>::EB;
+    *nq = Geo<Eq::DIM, N>::nq;
+}
+
+template <template <class> class EqT, int N, class real, bool LIM>
+static void launch_batch_phase(int phase, const StepArgs<real>* args, const int2* work, int nwork, int grid,
+                               hipStream_t st)
+{
+    using Eq = EqT<real>;
+    const dim3 g(grid > 0 ? grid : nwork);
+    switch (phase) {
+    case BPH_LOCAL:
+        hipLaunchKernelGGL((k_batch<Eq, N, real, LIM, BPH_LOCAL>), g, dim3(LGeo<Eq::DIM, N>::BLOCK), 0, st, args,
+                           work, nwork);
+        break;
+    case BPH_FACE_X:
+        hipLaunchKernelGGL((k_batch<Eq, N, real, LIM, BPH_FACE_X>), g, dim3(256), 0, st, args, work, nwork);
+        break;
+    case BPH_FACE_Y:
+        if constexpr (Eq::DIM == 2)
+            hipLaunchKernelGGL((k_batch<Eq, N, real, LIM, BPH_FACE_Y>), g, dim3(256), 0, st, args, work, nwork);
+        break;
+    case BPH_UPDATE:
+        hipLaunchKernelGGL((k_batch<Eq, N, real, LIM, BPH_UPDATE>), g, dim3(Geo<Eq::DIM, N>::BLOCK), 0, st, args,
+                           work, nwork);
+        break;
+    }
+}
+
+template <template <class> class EqT, class real>
+static int launch_batch(int N, bool lim, int phase, const StepArgs<real>* args, const int2* work, int nwork,
+                        int grid, hipStream_t st)
+{
+#define CRKFR_BCASE(NN)                                                                           \
+    case NN:                                                                                      \
+        if (lim) launch_batch_phase<EqT, NN, real, true>(phase, args, work, nwork, grid, st);     \
+        else launch_batch_phase<EqT, NN, real, false>(phase, args, work, nwork, grid, st);        \
+        return 0;
+    switch (N) {
+        CRKFR_BCASE(1)
+        CRKFR_BCASE(2)
+        CRKFR_BCASE(3)
+        CRKFR_BCASE(4)
+    }
+#undef CRKFR_BCASE
+    return -1;
+}
+
+template <template <class> class EqT, class real>
+static int geometry(int N, int* el, int* eu, int* nq)
+{
+    switch (N) {
+    case 1: batch_geometry<EqT, 1, real>(el, eu, nq); return 0;
+    case 2: batch_geometry<EqT, 2, real>(el, eu, nq); return 0;
+    case 3: batch_geometry<EqT, 3, real>(el, eu, nq); return 0;
+    case 4: batch_geometry<EqT, 4, real>(el, eu, nq); return 0;
+    }
+    return -1;
+}
+
 template <template <class> class EqT, class real>
 static int launch_step(int N, bool lim, int phase, const StepArgs<real>& a, hipStream_t st)
 {
@@ -93,7 +159,12 @@ static int launch_io(int N, int phase, const IoArgs<real>& a, hipStream_t st)
     int name##_step_f64(int N, bool lim, int phase, const StepArgs<double>& a, hipStream_t st);    \
     int name##_step_f32(int N, bool lim, int phase, const StepArgs<float>& a, hipStream_t st);     \
     int name##_io_f64(int N, int phase, const IoArgs<double>& a, hipStream_t st);                  \
-    int name##_io_f32(int N, int phase, const IoArgs<float>& a, hipStream_t st);
+    int name##_io_f32(int N, int phase, const IoArgs<float>& a, hipStream_t st);                   \
+    int name##_batch_f64(int N, bool lim, int phase, const StepArgs<double>* args, const int2* work, \
+                         int nwork, int grid, hipStream_t st);                                     \
+    int name##_batch_f32(int N, bool lim, int phase, const StepArgs<float>* args, const int2* work,  \
+                         int nwork, int grid, hipStream_t st);                                     \
+    int name##_geometry(int N, int* elems_local, int* elems_update, int* nq);
 #define CRKFR_DEFINE_EQ(name, EqT)                                                                  \
     int name##_step_f64(int N, bool lim, int phase, const StepArgs<double>& a, hipStream_t st)     \
     { return launch_step<EqT, double>(N, lim, phase, a, st); }                                      \
@@ -102,7 +173,14 @@ static int launch_io(int N, int phase, const IoArgs<real>& a, hipStream_t st)
     int name##_io_f64(int N, int phase, const IoArgs<double>& a, hipStream_t st)                   \
     { return launch_io<EqT, double>(N, phase, a, st); }                                             \
     int name##_io_f32(int N, int phase, const IoArgs<float>& a, hipStream_t st)                    \
-    { return launch_io<EqT, float>(N, phase, a, st); }
+    { return launch_io<EqT, float>(N, phase, a, st); }                                              \
+    int name##_batch_f64(int N, bool lim, int phase, const StepArgs<double>* args, const int2* work, \
+                         int nwork, int grid, hipStream_t st)                                      \
+    { return launch_batch<EqT, double>(N, lim, phase, args, work, nwork, grid, st); }               \
+    int name##_batch_f32(int N, bool lim, int phase, const StepArgs<float>* args, const int2* work,  \
+                         int nwork, int grid, hipStream_t st)                                      \
+    { return launch_batch<EqT, float>(N, lim, phase, args, work, nwork, grid, st); }                \
+    int name##_geometry(int N, int* el, int* eu, int* nq) { return geometry<EqT, double>(N, el, eu, nq); }
 
 CRKFR_DECLARE_EQ(linadv1d)
 CRKFR_DECLARE_EQ(euler1d)
