@@ -7,9 +7,9 @@ marshalling plus the Fourier stability analysis in ``cfl.py``.
 """
 from .oracle import (  # noqa: F401
     LINADV1D, EULER1D, EULER2D, TENMOM2D, PERIODIC, OUTFLOW, FARFIELD,
-    BLEND_OFF, BLEND_FO, BLEND_MH, IND_PAPER, IND_CONST, IND_GIVEN,
+    BLEND_OFF, BLEND_FO, BLEND_MH, IND_PAPER, IND_CONST, IND_GIVEN, IND_LEARNED,
     RefConfig, lib, build, gl, diff_matrix, lagrange_at, legendre_orthonormal,
-    tableau, flux, sigma, adm, nvar, nadm, local_crk, indicator_raw,
+    tableau, flux, sigma, adm, nvar, nadm, local_crk, indicator_raw, indicator_features, learned_alpha,
     scale_element, compute_dt, step, means, mlp_forward, mlp_loss_grad,
     boundary_traces, has_farfield,
 )

@@ -577,6 +577,58 @@ double ref_indicator_raw(const ref_config* c, const double* ue, double* energy_o
 }
 
 /* ------------------------------------------------------------------ */
+/* Learned troubled-cell indicator: a small network maps the element's
+ * modal energies (the quantities the indicator above compares) to the
+ * blending coefficient; outside the box of features it was trained on,
+ * the indicator above is used instead.                                 */
+/* ------------------------------------------------------------------ */
+
+static void features_from_energies(int N, const double* en, double* feat)
+{
+    double cum = en[0];
+    for (int k = 1; k <= N; ++k) {
+        cum += en[k];
+        double r = cum > 0.0 ? en[k] / cum : 0.0;
+        if (r < 1e-12) r = 1e-12;
+        feat[k - 1] = log10(r) / 6.0 + 1.0;
+    }
+}
+
+void ref_indicator_features(const ref_config* c, const double* ue, double* feat)
+{
+    refel r;
+    refel_init(&r, c->N);
+    double en[ND];
+    indicator_raw(c, &r, ue, en);
+    features_from_energies(c->N, en, feat);
+}
+
+static double learned_alpha(const ref_config* c, const refel* r, const double* ue, int* fallback)
+{
+    double en[ND], feat[ND];
+    double a_ind = indicator_raw(c, r, ue, en);
+    features_from_energies(c->N, en, feat);
+    *fallback = 0;
+    for (int k = 0; k < c->N; ++k)
+        if (!(feat[k] >= c->mlp_lo[k] && feat[k] <= c->mlp_hi[k])) { *fallback = 1; return a_ind; }
+    double y;
+    ref_mlp_forward(c->mlp_nl, c->mlp_dims, c->mlp_params, 1, feat, &y, NULL);
+    if (y < c->alpha_min) y = 0.0;
+    if (y > c->alpha_max) y = c->alpha_max;
+    return y;
+}
+
+double ref_learned_alpha(const ref_config* c, const double* ue, int* fallback)
+{
+    refel r;
+    refel_init(&r, c->N);
+    int fb = 0;
+    double a = learned_alpha(c, &r, ue, &fb);
+    if (fallback) *fallback = fb;
+    return a;
+}
+
+/* ------------------------------------------------------------------ */
 /* Zhang-Shu scaling limiter of one element (Sec. 3.2; reading: eps_k =
  * min(1e-13, P_k(mean)); linear root for density, 60-step bisection for
  * the other constraints).                                               */
@@ -938,7 +990,10 @@ int ref_step(const ref_config* c, const double* u_in, double* u_out, double dt,
             alpha_raw[e] = c->alpha_const;
         else if (c->indicator == REF_IND_GIVEN && blend != REF_BLEND_OFF)
             alpha_raw[e] = alpha_given[e];
-        else
+        else if (c->indicator == REF_IND_LEARNED && blend != REF_BLEND_OFF) {
+            int fb;
+            alpha_raw[e] = learned_alpha(c, &r, ue, &fb);
+        } else
             alpha_raw[e] = 0.0;
         if (mh) {
             mh_element(&g, ex, ey, dt, blend, &mh[e]);
@@ -962,7 +1017,8 @@ int ref_step(const ref_config* c, const double* u_in, double* u_out, double dt,
     for (int e = 0; e < ne; ++e) {
         int ex = e % nx, ey = e / nx;
         double a = alpha_raw[e];
-        if (c->indicator == REF_IND_PAPER && c->smooth_nbr && blend != REF_BLEND_OFF) {
+        if ((c->indicator == REF_IND_PAPER || c->indicator == REF_IND_LEARNED) && c->smooth_nbr &&
+            blend != REF_BLEND_OFF) {
             for (int d = 0; d < dim; ++d)
                 for (int s = 0; s < 2; ++s) {
                     int en = nbr_elem(&g, ex, ey, d, s);

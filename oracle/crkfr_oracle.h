@@ -25,7 +25,7 @@ extern "C" {
 enum { REF_LINADV1D = 0, REF_EULER1D = 1, REF_EULER2D = 2, REF_TENMOM2D = 3 };
 enum { REF_BC_PERIODIC = 0, REF_BC_OUTFLOW = 1, REF_BC_FARFIELD = 2 };
 enum { REF_BLEND_OFF = 0, REF_BLEND_FO = 1, REF_BLEND_MH = 2 };
-enum { REF_IND_PAPER = 0, REF_IND_CONST = 1, REF_IND_GIVEN = 2 };
+enum { REF_IND_PAPER = 0, REF_IND_CONST = 1, REF_IND_GIVEN = 2, REF_IND_LEARNED = 3 };
 
 typedef struct {
     int eq, N, nx, ny, stages;
@@ -36,6 +36,15 @@ typedef struct {
     double alpha_min, alpha_max, alpha_const;
     double src_amp, src_kappa, src_xc, src_yc;   /* W = A exp(-kappa r^2) + gx x + gy y */
     double src_gx, src_gy;
+    /* learned indicator (indicator == REF_IND_LEARNED): an MLP with layer
+     * sizes mlp_dims[0..mlp_nl] (mlp_dims[0] = N inputs, one output), tanh
+     * hidden layers and a sigmoid output, parameters per layer W[out][in]
+     * then b[out]; feature box [mlp_lo, mlp_hi] per input */
+    int mlp_nl;
+    const int* mlp_dims;
+    const double* mlp_params;
+    const double* mlp_lo;
+    const double* mlp_hi;
 } ref_config;
 
 typedef struct {
@@ -70,6 +79,15 @@ void ref_local_crk(const ref_config* c, const double* ue /*[var][q][p]*/, double
 
 /* smoothness indicator of one element (raw, before neighbour smoothing) */
 double ref_indicator_raw(const ref_config* c, const double* ue, double* energy_out);
+
+/* features of the learned indicator for one element, feat[k-1], k = 1..N:
+ * log10(max(r_k, 1e-12)) / 6 + 1 with r_k the share of the degree-k shell in
+ * the energy of the shells 0..k (0 when that energy is 0) */
+void ref_indicator_features(const ref_config* c, const double* ue, double* feat);
+
+/* learned blending coefficient of one element (before neighbour smoothing);
+ * *fallback = 1 when a feature left the box and the indicator was used */
+double ref_learned_alpha(const ref_config* c, const double* ue, int* fallback);
 
 /* Zhang-Shu scaling of one element in place; returns theta (min over constraints) */
 double ref_scale_element(const ref_config* c, double* ue, int* mean_bad);

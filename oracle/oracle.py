@@ -8,7 +8,7 @@ import numpy as np
 LINADV1D, EULER1D, EULER2D, TENMOM2D = 0, 1, 2, 3
 PERIODIC, OUTFLOW, FARFIELD = 0, 1, 2
 BLEND_OFF, BLEND_FO, BLEND_MH = 0, 1, 2
-IND_PAPER, IND_CONST, IND_GIVEN = 0, 1, 2
+IND_PAPER, IND_CONST, IND_GIVEN, IND_LEARNED = 0, 1, 2, 3
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "crkfr_oracle.c")
@@ -36,6 +36,9 @@ class RefConfig(ctypes.Structure):
         ("src_amp", ctypes.c_double), ("src_kappa", ctypes.c_double),
         ("src_xc", ctypes.c_double), ("src_yc", ctypes.c_double),
         ("src_gx", ctypes.c_double), ("src_gy", ctypes.c_double),
+        ("mlp_nl", ctypes.c_int), ("mlp_dims", ctypes.POINTER(ctypes.c_int)),
+        ("mlp_params", ctypes.POINTER(ctypes.c_double)),
+        ("mlp_lo", ctypes.POINTER(ctypes.c_double)), ("mlp_hi", ctypes.POINTER(ctypes.c_double)),
     ]
 
     @staticmethod
@@ -43,7 +46,8 @@ class RefConfig(ctypes.Structure):
              indicator=IND_PAPER, smooth_nbr=1, flux_limiter=0, scaling=0, source=0,
              domain=(0.0, 1.0, 0.0, 1.0), gamma=1.4, adv=1.0, cfl=0.0, cs=0.98,
              alpha_min=1e-3, alpha_max=1.0, alpha_const=0.0,
-             src=(0.0, 0.0, 0.0, 0.0), src_lin=(0.0, 0.0)):
+             src=(0.0, 0.0, 0.0, 0.0), src_lin=(0.0, 0.0), mlp=None):
+        """mlp: (dims, params, lo, hi) of the learned indicator (dims[0] = N)."""
         c = RefConfig()
         c.eq, c.N, c.nx, c.ny = eq, N, nx, ny
         c.stages = stages if stages is not None else min(N + 1, 4)
@@ -56,7 +60,19 @@ class RefConfig(ctypes.Structure):
         c.alpha_min, c.alpha_max, c.alpha_const = alpha_min, alpha_max, alpha_const
         c.src_amp, c.src_kappa, c.src_xc, c.src_yc = src
         c.src_gx, c.src_gy = src_lin
+        if mlp is not None:
+            c.set_mlp(*mlp)
         return c
+
+    def set_mlp(self, dims, params, lo, hi):
+        keep = (np.ascontiguousarray(dims, dtype=np.int32), _f64(params), _f64(lo), _f64(hi))
+        assert keep[0][0] == self.N and keep[2].size == self.N and keep[3].size == self.N
+        self._mlp_keep = keep   # the C side only borrows these arrays
+        self.mlp_nl = keep[0].size - 1
+        self.mlp_dims = keep[0].ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+        self.mlp_params = keep[1].ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        self.mlp_lo = keep[2].ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        self.mlp_hi = keep[3].ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
 class RefDiag(ctypes.Structure):
@@ -105,6 +121,9 @@ def lib():
         L.ref_boundary_traces.argtypes = [cp, dp, dp]
         L.ref_means.argtypes = [cp, dp, dp]
         ip = ctypes.POINTER(ctypes.c_int)
+        L.ref_indicator_features.argtypes = [cp, dp, dp]
+        L.ref_learned_alpha.argtypes = [cp, dp, ctypes.POINTER(ctypes.c_int)]
+        L.ref_learned_alpha.restype = ctypes.c_double
         L.ref_mlp_forward.argtypes = [ctypes.c_int, ip, dp, ctypes.c_int, dp, dp, dp]
         L.ref_mlp_loss_grad.argtypes = [ctypes.c_int, ip, dp, ctypes.c_int, dp, dp, dp]
         L.ref_mlp_loss_grad.restype = ctypes.c_double
@@ -193,6 +212,22 @@ def indicator_raw(cfg, ue):
     e = np.zeros(cfg.N + 1)
     a = lib().ref_indicator_raw(ctypes.byref(cfg), _p(_f64(ue)), _p(e))
     return a, e
+
+
+def indicator_features(cfg, ue):
+    """Features of the learned indicator of one element (N values)."""
+    ue = _f64(ue)
+    f = np.zeros(cfg.N)
+    lib().ref_indicator_features(ctypes.byref(cfg), _p(ue), _p(f))
+    return f
+
+
+def learned_alpha(cfg, ue):
+    """(alpha, fallback) of the learned indicator for one element."""
+    ue = _f64(ue)
+    fb = ctypes.c_int(0)
+    a = lib().ref_learned_alpha(ctypes.byref(cfg), _p(ue), ctypes.byref(fb))
+    return a, bool(fb.value)
 
 
 def scale_element(cfg, ue):
