@@ -100,9 +100,14 @@ typedef struct {
     double min_theta_flux, min_theta_scale;
     double t, dt;                  /* time reached and last step size */
     long long steps;
+    /* learned indicator, judged by the smoothness indicator on the same state: */
+    long long n_learned_fallback;  /* elements whose features left the network's box (indicator used) */
+    long long n_learned_disagree;  /* elements troubled (alpha > 0) by one indicator but not the other */
+    double max_alpha_dev;          /* max over elements of |alpha_learned - alpha_indicator| (raw) */
 } crkfr_diag;
 
 typedef struct crkfr_solver crkfr_solver;
+typedef struct crkfr_mlp crkfr_mlp;
 
 /* Create a solver on the current HIP device, ordered on hip_stream (a
  * hipStream_t; NULL: the solver creates a stream of its own, default
@@ -125,6 +130,17 @@ int crkfr_set_state(crkfr_solver* s, const double* u, int on_device);
 
 /* Per-element blending coefficients for CRKFR_IND_GIVEN, [ey][ex] doubles. */
 int crkfr_set_alpha(crkfr_solver* s, const double* alpha, int on_device);
+
+/* Network of the learned indicator (CRKFR_IND_LEARNED), borrowed: it must
+ * have N inputs and outlive its use by this solver; NULL detaches it.  Steps
+ * with the learned indicator and no network fail with ESTATE. */
+int crkfr_set_mlp(crkfr_solver* s, const crkfr_mlp* m);
+
+/* Features of the learned indicator for the current state, [e][N] floats
+ * (see crkfr_mlp_create), and the smoothness indicator's alpha before
+ * neighbour smoothing, [e] doubles: the training pairs of the network.
+ * Either output may be NULL; on_device = 1: device pointers.  Synchronises. */
+int crkfr_features(crkfr_solver* s, float* feat, double* alpha_ind, int on_device);
 
 /* Time step of eq. time.step.2d from the current element means (synchronises). */
 int crkfr_compute_dt(crkfr_solver* s, double* dt);
@@ -185,6 +201,47 @@ int crkfr_batch_grid(crkfr_batch* b, int group, int phase, int set_to);
 /* time each phase of each group for persistent grids of 0, 1, 2, 4, 8, 16
  * workgroups per compute unit and keep the fastest (state not advanced) */
 int crkfr_batch_autotune(crkfr_batch* b, int reps);
+
+/* ---- learned troubled-cell indicator ---------------------------------------
+ * A network n_inputs -> hidden -> hidden -> 1 with tanh hidden layers and a
+ * sigmoid output maps an element's features to its blending coefficient.
+ * Features (n_inputs = N): with e_s the energy of the orthonormal Legendre
+ * modes of the indicator quantity (rho p; ten-moment: rho (p11 + p22) / 2)
+ * whose highest degree is s -- the energies the smoothness indicator of
+ * Sec. 4 compares -- and r_s = e_s / (e_0 + ... + e_s) (0 if that sum is 0),
+ * feature s - 1 = max(log10(max(r_s, 1e-12)) / 6 + 1, -1), in [-1, 1], s = 1..N.
+ * In a step the output y gives alpha = 0 if y < alpha_min, else
+ * min(y, alpha_max), followed by the same neighbour smoothing; an element
+ * whose features leave the network's box [lo, hi] takes the smoothness
+ * indicator's alpha instead (a fallback, counted in the diagnostics).
+ * The network is trained on pairs (features, indicator alpha) that the
+ * method produces (crkfr_features) by minimising the mean squared error with
+ * Adam; training runs on the GPU.  Parameters, per layer: W[out][in]
+ * row-major then b[out] (floats).  Calls are ordered on the network's stream
+ * (NULL: a stream of its own); the data pointers x (rows x n_inputs floats),
+ * t and y (rows floats) are device pointers owned by the caller. */
+int crkfr_mlp_create(int n_inputs, int hidden, unsigned long long seed, void* hip_stream, crkfr_mlp** out);
+void crkfr_mlp_destroy(crkfr_mlp* m);
+/* number of network parameters (hidden 8, 16 or 32; n_inputs 1..4) */
+int crkfr_mlp_num_params(const crkfr_mlp* m);
+/* set / read the parameters (host or device buffer); setting resets Adam's moments */
+int crkfr_mlp_set_params(crkfr_mlp* m, const float* params, int on_device);
+int crkfr_mlp_get_params(crkfr_mlp* m, float* params, int on_device);
+/* feature box (host arrays of n_inputs); default [-1, 1], i.e. no fallback */
+int crkfr_mlp_set_box(crkfr_mlp* m, const float* lo, const float* hi);
+int crkfr_mlp_get_box(crkfr_mlp* m, float* lo, float* hi);
+/* box = [min - margin, max + margin] of the rows of x, per feature (synchronises) */
+int crkfr_mlp_fit_box(crkfr_mlp* m, const float* x, int n, float margin);
+/* y[r] = network(x[r]) for n rows (enqueue only) */
+int crkfr_mlp_forward(crkfr_mlp* m, const float* x, int n, float* y);
+/* mean squared error over n rows and its gradient w.r.t. the parameters
+ * (host arrays; grad may be NULL); synchronises */
+int crkfr_mlp_loss_grad(crkfr_mlp* m, const float* x, const float* t, int n, double* loss, float* grad);
+/* Adam (beta1 0.9, beta2 0.999, eps 1e-8) over consecutive minibatches of
+ * `batch` rows (shuffle the rows beforehand), `epochs` passes; writes the
+ * mean loss seen in each epoch to loss_per_epoch (host, may be NULL) */
+int crkfr_mlp_train(crkfr_mlp* m, const float* x, const float* t, int n, int epochs, int batch, float lr,
+                    float* loss_per_epoch);
 
 const char* crkfr_last_error(void);
 

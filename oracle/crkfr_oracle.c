@@ -590,7 +590,8 @@ static void features_from_energies(int N, const double* en, double* feat)
         cum += en[k];
         double r = cum > 0.0 ? en[k] / cum : 0.0;
         if (r < 1e-12) r = 1e-12;
-        feat[k - 1] = log10(r) / 6.0 + 1.0;
+        double v = log10(r) / 6.0 + 1.0;
+        feat[k - 1] = v < -1.0 ? -1.0 : v;   /* the floor is exactly -1 */
     }
 }
 

@@ -81,8 +81,8 @@ void ref_local_crk(const ref_config* c, const double* ue /*[var][q][p]*/, double
 double ref_indicator_raw(const ref_config* c, const double* ue, double* energy_out);
 
 /* features of the learned indicator for one element, feat[k-1], k = 1..N:
- * log10(max(r_k, 1e-12)) / 6 + 1 with r_k the share of the degree-k shell in
- * the energy of the shells 0..k (0 when that energy is 0) */
+ * log10(max(r_k, 1e-12)) / 6 + 1, at least -1, with r_k the share of the
+ * degree-k shell in the energy of the shells 0..k (0 when that energy is 0) */
 void ref_indicator_features(const ref_config* c, const double* ue, double* feat);
 
 /* learned blending coefficient of one element (before neighbour smoothing);

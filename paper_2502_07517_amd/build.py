@@ -10,7 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libcrkfr.so")
 SOURCES = ["crkfr_eq_linadv1d.hip", "crkfr_eq_euler1d.hip", "crkfr_eq_euler2d.hip",
-           "crkfr_eq_tenmom2d.hip", "crkfr_host.hip"]
+           "crkfr_eq_tenmom2d.hip", "crkfr_host.hip", "crkfr_mlp.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

@@ -45,7 +45,9 @@ class Diag(ctypes.Structure):
                 ("n_hancock_fallback", ctypes.c_longlong), ("n_scaled", ctypes.c_longlong),
                 ("n_mean_inadmissible", ctypes.c_longlong),
                 ("min_theta_flux", ctypes.c_double), ("min_theta_scale", ctypes.c_double),
-                ("t", ctypes.c_double), ("dt", ctypes.c_double), ("steps", ctypes.c_longlong)]
+                ("t", ctypes.c_double), ("dt", ctypes.c_double), ("steps", ctypes.c_longlong),
+                ("n_learned_fallback", ctypes.c_longlong), ("n_learned_disagree", ctypes.c_longlong),
+                ("max_alpha_dev", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -57,7 +59,10 @@ SYMBOLS = ["crkfr_create", "crkfr_destroy", "crkfr_set_limiter", "crkfr_set_sour
            "crkfr_cfl_in_use", "crkfr_fourier_cfl", "crkfr_set_timing", "crkfr_get_kernel_times",
            "crkfr_last_error", "crkfr_batch_create", "crkfr_batch_destroy", "crkfr_batch_step",
            "crkfr_batch_advance", "crkfr_batch_sync", "crkfr_batch_num_groups", "crkfr_batch_grid",
-           "crkfr_batch_autotune"]
+           "crkfr_batch_autotune", "crkfr_set_mlp", "crkfr_features", "crkfr_mlp_create", "crkfr_mlp_destroy",
+           "crkfr_mlp_num_params", "crkfr_mlp_set_params", "crkfr_mlp_get_params", "crkfr_mlp_set_box",
+           "crkfr_mlp_get_box", "crkfr_mlp_fit_box", "crkfr_mlp_forward", "crkfr_mlp_loss_grad",
+           "crkfr_mlp_train"]
 
 _lib = None
 
@@ -110,6 +115,21 @@ def lib():
         L.crkfr_batch_num_groups.argtypes = [vp]
         L.crkfr_batch_grid.argtypes = [vp, ip, ip, ip]
         L.crkfr_batch_autotune.argtypes = [vp, ip]
+        fp = ctypes.POINTER(ctypes.c_float)
+        L.crkfr_set_mlp.argtypes = [vp, vp]
+        L.crkfr_features.argtypes = [vp, vp, vp, ip]
+        L.crkfr_mlp_create.argtypes = [ip, ip, ctypes.c_ulonglong, vp, ctypes.POINTER(vp)]
+        L.crkfr_mlp_destroy.argtypes = [vp]
+        L.crkfr_mlp_destroy.restype = None
+        L.crkfr_mlp_num_params.argtypes = [vp]
+        L.crkfr_mlp_set_params.argtypes = [vp, vp, ip]
+        L.crkfr_mlp_get_params.argtypes = [vp, vp, ip]
+        L.crkfr_mlp_set_box.argtypes = [vp, fp, fp]
+        L.crkfr_mlp_get_box.argtypes = [vp, fp, fp]
+        L.crkfr_mlp_fit_box.argtypes = [vp, vp, ip, ctypes.c_float]
+        L.crkfr_mlp_forward.argtypes = [vp, vp, ip, vp]
+        L.crkfr_mlp_loss_grad.argtypes = [vp, vp, vp, ip, dp, fp]
+        L.crkfr_mlp_train.argtypes = [vp, vp, vp, ip, ip, ip, ctypes.c_float, fp]
         _lib = L
     return _lib
 
@@ -255,6 +275,120 @@ class Solver:
         ms = (ctypes.c_float * 4)()
         _check(lib().crkfr_get_kernel_times(self.h, ms))
         return list(ms)
+
+    def set_mlp(self, mlp):
+        """Borrow a network for the learned indicator (None detaches)."""
+        self._mlp = mlp
+        _check(lib().crkfr_set_mlp(self.h, mlp.h if mlp is not None else None))
+
+    def features(self, device=False):
+        """(features [ne][N] float32, indicator alpha [ne] float64) of the
+        current state; torch CUDA tensors when device=True."""
+        N = self.cfg.N
+        if device:
+            import torch
+            f = torch.empty((self.ne, N), dtype=torch.float32, device="cuda")
+            a = torch.empty(self.ne, dtype=torch.float64, device="cuda")
+            _check(lib().crkfr_features(self.h, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(a.data_ptr()), 1))
+            return f, a
+        f = np.empty((self.ne, N), dtype=np.float32)
+        a = np.empty(self.ne, dtype=np.float64)
+        _check(lib().crkfr_features(self.h, ctypes.c_void_p(f.ctypes.data), ctypes.c_void_p(a.ctypes.data), 0))
+        return f, a
+
+
+def _dev_f32(x, cols=None):
+    """A contiguous float32 CUDA tensor (device data of the network calls)."""
+    import torch
+    t = torch.as_tensor(x)
+    if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+        t = t.to(device="cuda", dtype=torch.float32).contiguous()
+    if cols is not None and (t.dim() != 2 or t.shape[1] != cols):
+        raise ValueError(f"expected rows of {cols} features")
+    return t
+
+
+class Mlp:
+    """Network of the learned troubled-cell indicator (see include/crkfr.h)."""
+
+    def __init__(self, n_inputs, hidden=16, seed=0, stream=None):
+        h = ctypes.c_void_p()
+        st = ctypes.c_void_p(stream) if stream is not None else None
+        _check(lib().crkfr_mlp_create(int(n_inputs), int(hidden), int(seed), st, ctypes.byref(h)))
+        self.h = h
+        self.n_inputs, self.hidden = int(n_inputs), int(hidden)
+        self.dims = [self.n_inputs, self.hidden, self.hidden, 1]
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().crkfr_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def num_params(self):
+        return lib().crkfr_mlp_num_params(self.h)
+
+    def get_params(self):
+        out = np.empty(self.num_params(), dtype=np.float32)
+        _check(lib().crkfr_mlp_get_params(self.h, ctypes.c_void_p(out.ctypes.data), 0))
+        return out
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        if p.size != self.num_params():
+            raise ValueError("wrong number of parameters")
+        _check(lib().crkfr_mlp_set_params(self.h, ctypes.c_void_p(p.ctypes.data), 0))
+
+    def get_box(self):
+        lo = (ctypes.c_float * self.n_inputs)()
+        hi = (ctypes.c_float * self.n_inputs)()
+        _check(lib().crkfr_mlp_get_box(self.h, lo, hi))
+        return np.array(lo, dtype=np.float32), np.array(hi, dtype=np.float32)
+
+    def set_box(self, lo, hi):
+        lo = (ctypes.c_float * self.n_inputs)(*[float(v) for v in lo])
+        hi = (ctypes.c_float * self.n_inputs)(*[float(v) for v in hi])
+        _check(lib().crkfr_mlp_set_box(self.h, lo, hi))
+
+    def fit_box(self, x, margin=0.02):
+        x = _dev_f32(x, self.n_inputs)
+        _check(lib().crkfr_mlp_fit_box(self.h, ctypes.c_void_p(x.data_ptr()), x.shape[0], float(margin)))
+        return self.get_box()
+
+    def forward(self, x):
+        import torch
+        x = _dev_f32(x, self.n_inputs)
+        y = torch.empty(x.shape[0], dtype=torch.float32, device="cuda")
+        _check(lib().crkfr_mlp_forward(self.h, ctypes.c_void_p(x.data_ptr()), x.shape[0],
+                                       ctypes.c_void_p(y.data_ptr())))
+        torch.cuda.synchronize()
+        return y
+
+    def loss_grad(self, x, t):
+        x = _dev_f32(x, self.n_inputs)
+        t = _dev_f32(t).reshape(-1)
+        g = np.empty(self.num_params(), dtype=np.float32)
+        loss = ctypes.c_double()
+        _check(lib().crkfr_mlp_loss_grad(self.h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(t.data_ptr()),
+                                         x.shape[0], ctypes.byref(loss),
+                                         g.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return loss.value, g
+
+    def train(self, x, t, epochs=20, batch=4096, lr=3e-3):
+        x = _dev_f32(x, self.n_inputs)
+        t = _dev_f32(t).reshape(-1)
+        if t.shape[0] != x.shape[0]:
+            raise ValueError("x and t need the same number of rows")
+        hist = np.empty(int(epochs), dtype=np.float32)
+        _check(lib().crkfr_mlp_train(self.h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(t.data_ptr()),
+                                     x.shape[0], int(epochs), int(batch), float(lr),
+                                     hist.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return hist
 
 
 class Batch:

@@ -20,6 +20,7 @@
 #include <vector>
 
 #include "../../include/crkfr.h"
+#include "crkfr_internal.hpp"
 #include "crkfr_launch.hpp"
 
 using namespace crkfr;
@@ -31,6 +32,8 @@ static int fail(int code, const std::string& msg)
     g_last_error = msg;
     return code;
 }
+
+int crkfr::set_error(int code, const std::string& msg) { return fail(code, msg); }
 
 #define HIP_TRY(call)                                                                        \
     do {                                                                                     \
@@ -269,6 +272,9 @@ struct crkfr_solver {
     double* ubar[2];
     void *uHp, *trx, *trY, *Fx, *Gy, *dtS, *ghost;
     double *alpha_raw, *alpha_out, *alpha_given;
+    double* alpha_judge;     // the smoothness indicator's alpha (learned-indicator runs, features)
+    float* feat;             // learned-indicator features [e][N]
+    const crkfr_mlp* mlp;    // borrowed network of the learned indicator
     double *dt_dev, *t_dev;
     unsigned long long *rate_bits, *diag;
     long long* steps;
@@ -351,6 +357,10 @@ static StepArgs<real> step_args(const crkfr_solver* s, int in, int out)
     for (int i = 0; i < MAXND; ++i) a.w64[i] = i <= s->cfg.N ? s->ref.w[i] : 0.0;
     a.diag = s->diag;
     a.rate_bits = s->rate_bits;
+    a.mlp = s->mlp ? mlp_device_params(s->mlp) : nullptr;
+    a.mlp_hidden = s->mlp ? mlp_hidden(s->mlp) : 0;
+    a.alpha_judge = s->alpha_judge;
+    a.feat_out = s->feat;
     return a;
 }
 
@@ -451,7 +461,8 @@ static int run_io(const crkfr_solver* s, int phase, const double* uin, double* u
 static void free_all(crkfr_solver* s)
 {
     void* ptrs[] = {s->u[0], s->u[1], s->ubar[0], s->ubar[1], s->uHp, s->trx, s->trY, s->Fx, s->Gy, s->dtS,
-                    s->ghost, s->alpha_raw, s->alpha_out, s->alpha_given, s->dt_dev, s->t_dev,
+                    s->ghost, s->alpha_raw, s->alpha_out, s->alpha_given, s->alpha_judge, s->feat,
+                    s->dt_dev, s->t_dev,
                     s->rate_bits, s->diag, s->steps};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -529,6 +540,8 @@ extern "C" int crkfr_create(const crkfr_config* cfg, void* hip_stream, crkfr_sol
     ok &= alloc((void**)&s->alpha_raw, ne * sizeof(double));
     ok &= alloc((void**)&s->alpha_out, ne * sizeof(double));
     ok &= alloc((void**)&s->alpha_given, ne * sizeof(double));
+    ok &= alloc((void**)&s->alpha_judge, ne * sizeof(double));
+    ok &= alloc((void**)&s->feat, ne * (size_t)cfg->N * sizeof(float));
     ok &= alloc((void**)&s->dt_dev, sizeof(double));
     ok &= alloc((void**)&s->t_dev, sizeof(double));
     ok &= alloc((void**)&s->rate_bits, RATE_SLOTS * sizeof(unsigned long long));
@@ -542,6 +555,7 @@ extern "C" int crkfr_create(const crkfr_config* cfg, void* hip_stream, crkfr_sol
     (void)hipMemsetAsync(s->alpha_raw, 0, ne * sizeof(double), s->stream);
     (void)hipMemsetAsync(s->alpha_out, 0, ne * sizeof(double), s->stream);
     (void)hipMemsetAsync(s->alpha_given, 0, ne * sizeof(double), s->stream);
+    (void)hipMemsetAsync(s->alpha_judge, 0, ne * sizeof(double), s->stream);
     (void)hipMemsetAsync(s->diag, 0, D_NCOUNT * sizeof(unsigned long long), s->stream);
     if (hipStreamSynchronize(s->stream) != hipSuccess) {
         free_all(s);
@@ -633,6 +647,28 @@ extern "C" int crkfr_set_alpha(crkfr_solver* s, const double* alpha, int on_devi
     return 0;
 }
 
+extern "C" int crkfr_set_mlp(crkfr_solver* s, const crkfr_mlp* m)
+{
+    if (!s) return fail(CRKFR_EINVAL, "null argument");
+    if (m && mlp_inputs(m) != s->cfg.N) return fail(CRKFR_EINVAL, "the network's inputs must equal N");
+    s->mlp = m;
+    invalidate_graph(s);
+    return 0;
+}
+
+extern "C" int crkfr_features(crkfr_solver* s, float* feat, double* alpha_ind, int on_device)
+{
+    if (!s) return fail(CRKFR_EINVAL, "null argument");
+    if (!s->has_state) return fail(CRKFR_ESTATE, "no state set");
+    int rc = dispatch_step(s, PH_FEATURES, s->cur, 1 - s->cur);
+    if (rc) return rc;
+    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (feat) HIP_TRY(hipMemcpyAsync(feat, s->feat, (size_t)s->ne * s->cfg.N * sizeof(float), kind, s->stream));
+    if (alpha_ind) HIP_TRY(hipMemcpyAsync(alpha_ind, s->alpha_judge, s->ne * sizeof(double), kind, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return 0;
+}
+
 extern "C" int crkfr_compute_dt(crkfr_solver* s, double* dt)
 {
     if (!s || !dt) return fail(CRKFR_EINVAL, "null argument");
@@ -650,8 +686,19 @@ extern "C" int crkfr_compute_dt(crkfr_solver* s, double* dt)
     return 0;
 }
 
+// the learned indicator needs a network whose inputs match the degree
+static int check_learned(const crkfr_solver* s)
+{
+    if (s->lim.blend == CRKFR_BLEND_OFF || s->lim.indicator != CRKFR_IND_LEARNED) return 0;
+    if (!s->mlp) return fail(CRKFR_ESTATE, "the learned indicator needs a network (crkfr_set_mlp)");
+    if (mlp_inputs(s->mlp) != s->cfg.N) return fail(CRKFR_EINVAL, "the network's inputs must equal N");
+    return 0;
+}
+
 static int enqueue_step(crkfr_solver* s, double dt_fixed, double t_end)
 {
+    int lrc = check_learned(s);
+    if (lrc) return lrc;
     PrepArgs pa;
     pa.dt_dev = s->dt_dev;
     pa.t_dev = s->t_dev;
@@ -808,6 +855,21 @@ extern "C" int crkfr_get_diag(crkfr_solver* s, crkfr_diag* out)
     out->t = t;
     out->dt = dt;
     out->steps = steps;
+    out->n_learned_fallback = (long long)d[D_LFALLBACK];
+    out->n_learned_disagree = 0;
+    out->max_alpha_dev = 0.0;
+    if (s->lim.indicator == CRKFR_IND_LEARNED && s->lim.blend != CRKFR_BLEND_OFF) {
+        // judge: the learned alpha against the smoothness indicator's, per element
+        std::vector<double> al(s->ne), ai(s->ne);
+        HIP_TRY(hipMemcpyAsync(al.data(), s->alpha_raw, s->ne * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+        HIP_TRY(hipMemcpyAsync(ai.data(), s->alpha_judge, s->ne * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+        HIP_TRY(hipStreamSynchronize(s->stream));
+        for (int e = 0; e < s->ne; ++e) {
+            if ((al[e] > 0.0) != (ai[e] > 0.0)) ++out->n_learned_disagree;
+            double dv = std::fabs(al[e] - ai[e]);
+            if (dv > out->max_alpha_dev) out->max_alpha_dev = dv;
+        }
+    }
     if (out->n_mean_inadmissible > 0)
         return fail(CRKFR_EINADMISSIBLE_MEAN, "an element mean left the admissible set");
     return 0;
@@ -969,6 +1031,12 @@ extern "C" int crkfr_batch_create(crkfr_solver* const* solvers, int count, void*
             free_batch(b);
             delete b;
             return fail(CRKFR_ESTATE, "every batch member needs a state");
+        }
+        int lrc = check_learned(s);
+        if (lrc) {
+            free_batch(b);
+            delete b;
+            return lrc;
         }
         (void)hipStreamSynchronize(s->stream);
         b->s.push_back(s);

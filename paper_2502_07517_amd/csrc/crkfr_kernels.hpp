@@ -36,7 +36,12 @@ constexpr int MAXND = 5;
 enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_FARFIELD = 2 };
 enum { BLEND_OFF = 0, BLEND_FO = 1, BLEND_MH = 2 };
 enum { IND_PAPER = 0, IND_CONST = 1, IND_GIVEN = 2, IND_LEARNED = 3 };
-enum { D_TROUBLED = 0, D_FLUXLIM, D_LOBAD, D_SLOPELIM, D_FALLBACK, D_SCALED, D_MEANBAD, D_THFLUX, D_THSCALE, D_NCOUNT };
+enum { D_TROUBLED = 0, D_FLUXLIM, D_LOBAD, D_SLOPELIM, D_FALLBACK, D_SCALED, D_MEANBAD, D_LFALLBACK,
+       D_THFLUX, D_THSCALE, D_NCOUNT };
+
+// learned indicator: network N -> H -> H -> 1 (tanh, tanh, sigmoid), H <= MLP_HMAX
+constexpr int MLP_HMAX = 32;
+__host__ __device__ constexpr int mlp_nparams(int nin, int H) { return H * nin + H + H * H + H + H + 1; }
 // the wave-speed rate of eq. time.step.2d is max-reduced into RATE_SLOTS
 // addresses (slot = workgroup index mod RATE_SLOTS) to spread the atomics
 constexpr int RATE_SLOTS = 256;
@@ -77,6 +82,10 @@ struct StepArgs {
     double w64[MAXND];
     unsigned long long* diag;
     unsigned long long* rate_bits;
+    const float* mlp;      // learned indicator: parameters, then the feature box lo[N], hi[N]
+    int mlp_hidden;
+    double* alpha_judge;   // learned indicator: the smoothness indicator's alpha per element
+    float* feat_out;       // k_features: learned-indicator features [e][N]
 };
 
 template <int DIM, int N>
@@ -381,6 +390,81 @@ __device__ void mh_subcell(const StepArgs<real>& a, int e, int ex, int ey, int p
 }
 
 // ----------------------------------------------------------------------------
+// smoothness indicator (reading of the Hennemann indicator, Sec. 4) and the
+// learned indicator's features
+// ----------------------------------------------------------------------------
+// orthonormal Legendre coefficient (p, q) of the element's indicator quantity
+// eps[k * stride], by Gauss-Legendre quadrature (exact for degree <= N)
+template <int DIM, int N, class real>
+__device__ __forceinline__ real modal_coeff(const RefTab<real>& R, int p, int q, const real* eps, int stride)
+{
+    constexpr int nd = N + 1;
+    real m = 0;
+    if constexpr (DIM == 2) {
+#pragma unroll
+        for (int s2 = 0; s2 < nd; ++s2)
+#pragma unroll
+            for (int r = 0; r < nd; ++r)
+                m += R.w[r] * R.w[s2] * R.L[p][r] * R.L[q][s2] * eps[(s2 * nd + r) * stride];
+    } else {
+#pragma unroll
+        for (int r = 0; r < nd; ++r) m += R.w[r] * R.L[p][r] * eps[r * stride];
+    }
+    return m;
+}
+
+// shell energies en[s] = sum of squared coefficients whose highest degree is s
+template <int DIM, int N, class real>
+__device__ __forceinline__ void shell_energies(const real* m2, int stride, double* en)
+{
+    constexpr int nd = N + 1, np = DIM == 2 ? nd * nd : nd;
+#pragma unroll
+    for (int s2 = 0; s2 < nd; ++s2) en[s2] = 0.0;
+#pragma unroll
+    for (int kk = 0; kk < np; ++kk) {
+        int pp = kk % nd, qq = kk / nd;
+        en[pp > qq ? pp : qq] += (double)m2[kk * stride];
+    }
+}
+
+// alpha of the smoothness indicator: logistic of the energy ratio around the
+// threshold T(N), clipped to [alpha_min, alpha_max] (0 below alpha_min)
+template <int N>
+__device__ __forceinline__ double indicator_alpha(const double* en, double amin, double amax)
+{
+    double totN = 0.0, totNm1 = 0.0;
+#pragma unroll
+    for (int s2 = 0; s2 <= N; ++s2) totN += en[s2];
+#pragma unroll
+    for (int s2 = 0; s2 < N; ++s2) totNm1 += en[s2];
+    double E1 = totN > 0.0 ? en[N] / totN : 0.0;
+    double E2 = totNm1 > 0.0 ? en[N - 1] / totNm1 : 0.0;
+    double E = E1 > E2 ? E1 : E2;
+    const double T = 0.5 * pow(10.0, -1.8 * pow((double)(N + 1), 0.25));
+    const double sharp = log(9999.0);
+    double al = 1.0 / (1.0 + exp(-(sharp / T) * (E - T)));
+    if (al < amin) al = 0.0;
+    if (al > amax) al = amax;
+    return al;
+}
+
+// features of the learned indicator: for shells s = 1..N the share r_s of
+// shell s in the energy of shells 0..s, as log10(max(r_s, 1e-12)) / 6 + 1
+// (at least -1)
+template <int N>
+__device__ __forceinline__ void learned_features(const double* en, double* ft)
+{
+    double cum = en[0];
+#pragma unroll
+    for (int s2 = 1; s2 <= N; ++s2) {
+        cum += en[s2];
+        const double r = cum > 0.0 ? en[s2] / cum : 0.0;
+        // floor exactly -1, so a box edge at -1 is decided the same everywhere
+        ft[s2 - 1] = r > 1e-12 ? fmax(log10(r) / 6.0 + 1.0, -1.0) : -1.0;
+    }
+}
+
+// ----------------------------------------------------------------------------
 // k_local
 // ----------------------------------------------------------------------------
 template <class Eq, int N, class real, bool LIM>
@@ -414,54 +498,75 @@ __device__ void local_body(const StepArgs<real>& a, int vblock)
     load_node<Eq>(a, np, e, k, un);
 
     if constexpr (LIM) {
-        // ---- smoothness indicator (reading of the Hennemann indicator) ----
+        // ---- smoothness indicator (reading of the Hennemann indicator) or
+        //      the learned indicator over the same modal energies ----
+        __shared__ real sh_m[EB][2][MLP_HMAX];
 #pragma unroll
         for (int v = 0; v < M; ++v) sh_u[le][k][v] = un[v];
-        if (a.indicator == IND_PAPER) sh_f[le][k][0] = Eq::ind(un, P);
+        const bool modal = a.indicator == IND_PAPER || a.indicator == IND_LEARNED;
+        if (modal) sh_f[le][k][0] = Eq::ind(un, P);
         __syncthreads();
-        if (a.indicator == IND_PAPER) {
-            real m = 0;
-            if constexpr (DIM == 2) {
-#pragma unroll
-                for (int s2 = 0; s2 < nd; ++s2)
-#pragma unroll
-                    for (int r = 0; r < nd; ++r)
-                        m += a.R.w[r] * a.R.w[s2] * a.R.L[p][r] * a.R.L[q][s2] * sh_f[le][s2 * nd + r][0];
-            } else {
-#pragma unroll
-                for (int r = 0; r < nd; ++r) m += a.R.w[r] * a.R.L[p][r] * sh_f[le][r][0];
-            }
+        if (modal) {
+            real m = modal_coeff<DIM, N>(a.R, p, q, &sh_f[le][0][0], M);
             sh_g[le][k][0] = m * m;
         }
         __syncthreads();
+        double al_ind = 0.0;
+        bool inbox = true;
         if (k == 0 && act) {
-            if (a.indicator == IND_PAPER) {
+            if (modal) {
                 double en[nd];
+                shell_energies<DIM, N>(&sh_g[le][0][0], MY, en);
+                al_ind = indicator_alpha<N>(en, a.alpha_min, a.alpha_max);
+                if (a.indicator == IND_PAPER) {
+                    a.alpha_raw[e] = al_ind;
+                } else {
+                    double ft[N];
+                    learned_features<N>(en, ft);
+                    const float* box = a.mlp + mlp_nparams(N, a.mlp_hidden);
 #pragma unroll
-                for (int s2 = 0; s2 < nd; ++s2) en[s2] = 0.0;
-#pragma unroll
-                for (int kk = 0; kk < np; ++kk) {
-                    int pp = kk % nd, qq = kk / nd;
-                    en[pp > qq ? pp : qq] += (double)sh_g[le][kk][0];
+                    for (int j = 0; j < N; ++j) {
+                        if (!(ft[j] >= (double)box[j] && ft[j] <= (double)box[N + j])) inbox = false;
+                        sh_f[le][j][0] = (real)ft[j];
+                    }
+                    a.alpha_judge[e] = al_ind;
+                    if (!inbox) atomicAdd(&a.diag[D_LFALLBACK], 1ull);
                 }
-                double totN = 0.0, totNm1 = 0.0;
-#pragma unroll
-                for (int s2 = 0; s2 <= N; ++s2) totN += en[s2];
-#pragma unroll
-                for (int s2 = 0; s2 < N; ++s2) totNm1 += en[s2];
-                double E1 = totN > 0.0 ? en[N] / totN : 0.0;
-                double E2 = totNm1 > 0.0 ? en[N - 1] / totNm1 : 0.0;
-                double E = E1 > E2 ? E1 : E2;
-                const double T = 0.5 * pow(10.0, -1.8 * pow((double)(N + 1), 0.25));
-                const double sharp = log(9999.0);
-                double al_d = 1.0 / (1.0 + exp(-(sharp / T) * (E - T)));
-                if (al_d < a.alpha_min) al_d = 0.0;
-                if (al_d > a.alpha_max) al_d = a.alpha_max;
-                a.alpha_raw[e] = al_d;
             } else if (a.indicator == IND_CONST) {
                 a.alpha_raw[e] = a.alpha_const;
             } else if (a.indicator == IND_GIVEN) {
                 a.alpha_raw[e] = a.alpha_given[e];
+            }
+        }
+        if (a.indicator == IND_LEARNED) {
+            // the network: hidden units spread over the element's lanes
+            __syncthreads();
+            const int H = a.mlp_hidden;
+            const float* W1 = a.mlp;
+            const float* b1 = W1 + H * N;
+            const float* W2 = b1 + H;
+            const float* b2 = W2 + H * H;
+            const float* w3 = b2 + H;
+            for (int j = k; j < H; j += np) {
+                real s = (real)b1[j];
+#pragma unroll
+                for (int i = 0; i < N; ++i) s += (real)W1[j * N + i] * sh_f[le][i][0];
+                sh_m[le][0][j] = tanh(s);
+            }
+            __syncthreads();
+            for (int j = k; j < H; j += np) {
+                real s = (real)b2[j];
+                for (int i = 0; i < H; ++i) s += (real)W2[j * H + i] * sh_m[le][0][i];
+                sh_m[le][1][j] = tanh(s);
+            }
+            __syncthreads();
+            if (k == 0 && act) {
+                real s = (real)w3[H];
+                for (int j = 0; j < H; ++j) s += (real)w3[j] * sh_m[le][1][j];
+                double y = 1.0 / (1.0 + exp(-(double)s));
+                if (y < a.alpha_min) y = 0.0;
+                if (y > a.alpha_max) y = a.alpha_max;
+                a.alpha_raw[e] = inbox ? y : al_ind;
             }
         }
         // ---- MUSCL-Hancock predictor and interior subface fluxes ----
@@ -1442,6 +1547,38 @@ __global__ void k_ghost(const IoArgs<real> a)
             s += lw[j] * val;
         }
         a.ghost[(size_t)tid * M + v] = (real)s;
+    }
+}
+
+// features of the learned indicator and the smoothness indicator's alpha
+// for the current state (the quantities the next step's indicator uses);
+// one lane per node: feat_out[e][N] and alpha_judge[e]
+template <class Eq, int N, class real>
+__global__ void __launch_bounds__(256) k_features(const StepArgs<real> a)
+{
+    using G = Geo<Eq::DIM, N>;
+    constexpr int DIM = Eq::DIM, nd = G::nd, np = G::np, EB = G::EB;
+    __shared__ real sh_e[EB][np];
+    __shared__ real sh_m2[EB][np];
+    const int le = threadIdx.x / np, k = threadIdx.x - le * np;
+    const int p = k % nd, q = k / nd;
+    const int e0 = blockIdx.x * EB + le;
+    const bool act = e0 < a.ne;
+    const int e = act ? e0 : a.ne - 1;
+    real un[Eq::M];
+    load_node<Eq>(a, np, e, k, un);
+    sh_e[le][k] = Eq::ind(un, a.phys);
+    __syncthreads();
+    real m = modal_coeff<DIM, N>(a.R, p, q, &sh_e[le][0], 1);
+    sh_m2[le][k] = m * m;
+    __syncthreads();
+    if (k == 0 && act) {
+        double en[nd], ft[N];
+        shell_energies<DIM, N>(&sh_m2[le][0], 1, en);
+        a.alpha_judge[e] = indicator_alpha<N>(en, a.alpha_min, a.alpha_max);
+        learned_features<N>(en, ft);
+#pragma unroll
+        for (int j = 0; j < N; ++j) a.feat_out[(size_t)e * N + j] = (float)ft[j];
     }
 }
 

@@ -5,7 +5,8 @@
 
 namespace crkfr {
 
-enum { PH_LOCAL = 0, PH_FACE_X = 1, PH_FACE_Y = 2, PH_UPDATE = 3, PH_IMPORT = 4, PH_EXPORT = 5, PH_GHOST = 6 };
+enum { PH_LOCAL = 0, PH_FACE_X = 1, PH_FACE_Y = 2, PH_UPDATE = 3, PH_IMPORT = 4, PH_EXPORT = 5, PH_GHOST = 6,
+       PH_FEATURES = 7 };
 
 template <template <class> class EqT, int N, class real, bool LIM>
 static void launch_step_phase(int phase, const StepArgs<real>& a, hipStream_t st)
@@ -33,6 +34,9 @@ static void launch_step_phase(int phase, const StepArgs<real>& a, hipStream_t st
         break;
     case PH_UPDATE:
         hipLaunchKernelGGL((k_update<Eq, N, real, LIM>), dim3(nb), dim3(G::BLOCK), 0, st, a);
+        break;
+    case PH_FEATURES:
+        hipLaunchKernelGGL((k_features<Eq, N, real>), dim3(nb), dim3(G::BLOCK), 0, st, a);
         break;
     }
 }

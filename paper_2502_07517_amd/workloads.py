@@ -173,6 +173,56 @@ def euler2d_smooth_periodic(seed, n, N, dom=(0.0, 1.0, 0.0, 1.0), amp=0.2, gamma
     return euler2d_cons(rho, v1, v2, p, gamma)
 
 
+# ---------------------------------------------------------------- single-element patterns
+def _rand_prim(rng, n):
+    return (rng.uniform(0.1, 2.0, n), rng.uniform(-1.0, 1.0, n), rng.uniform(-1.0, 1.0, n), rng.uniform(0.1, 2.0, n))
+
+
+def element_patterns_1d(seed, nx, N, gamma=GAMMA):
+    """1D Euler states built element by element: a jump at a uniformly random
+    position inside the element (60 %), a smooth profile (20 %) or a constant
+    (20 %), between seeded random states; elements are independent."""
+    rng = np.random.default_rng(seed)
+    xi = gl_nodes(N)[None, :]
+    kind = rng.uniform(size=(nx, 1))
+    pos = rng.uniform(0.0, 1.0, (nx, 1))
+    A, B = _rand_prim(rng, nx), _rand_prim(rng, nx)
+    amp, k, ph = rng.uniform(0.0, 0.5, (nx, 1)), rng.uniform(0.5, 3.0, (nx, 1)), rng.uniform(0, 2 * np.pi, (nx, 1))
+    cols = []
+    for c in (0, 1, 3):
+        a, b = A[c][:, None], B[c][:, None]
+        jump = np.where(xi < pos, a, b)
+        smooth = a * (1.0 + amp * np.sin(2 * np.pi * k * xi + ph))
+        cols.append(np.where(kind < 0.6, jump, np.where(kind < 0.8, smooth, a + 0.0 * xi)))
+    rho, v, p = cols
+    return np.stack([rho, rho * v, p / (gamma - 1.0) + 0.5 * rho * v * v])
+
+
+def element_patterns_2d(seed, nx, ny, N, gamma=GAMMA):
+    """2D Euler states built element by element: a straight discontinuity
+    through a random point of the element at a random angle (60 %), a smooth
+    profile (20 %) or a constant (20 %), between seeded random states."""
+    rng = np.random.default_rng(seed)
+    ne = nx * ny
+    xi = gl_nodes(N)
+    XI, ETA = np.meshgrid(xi, xi)                        # [q][p]
+    XI, ETA = XI[None], ETA[None]
+    kind = rng.uniform(size=(ne, 1, 1))
+    px, py = rng.uniform(0, 1, (ne, 1, 1)), rng.uniform(0, 1, (ne, 1, 1))
+    th = rng.uniform(0, 2 * np.pi, (ne, 1, 1))
+    side = (XI - px) * np.cos(th) + (ETA - py) * np.sin(th) < 0
+    A, B = _rand_prim(rng, ne), _rand_prim(rng, ne)
+    amp, k, ph = rng.uniform(0.0, 0.5, (ne, 1, 1)), rng.uniform(0.5, 3.0, (ne, 1, 1)), rng.uniform(0, 2 * np.pi, (ne, 1, 1))
+    cols = []
+    for c in range(4):
+        a, b = A[c][:, None, None], B[c][:, None, None]
+        jump = np.where(side, a, b)
+        smooth = a * (1.0 + amp * np.sin(2 * np.pi * k * (XI * np.cos(th) + ETA * np.sin(th)) + ph))
+        cols.append(np.where(kind < 0.6, jump, np.where(kind < 0.8, smooth, a + 0.0 * XI)).reshape(ny, nx, N + 1, N + 1))
+    rho, v1, v2, p = cols
+    return euler2d_cons(rho, v1, v2, p, gamma)
+
+
 # ---------------------------------------------------------------- ten-moment
 def tenmom_quadrant_states(seed):
     """rho ~ U[0.5,2], v_i ~ U[-1,1], p11, p22 ~ U[0.5,2], p12 = r sqrt(p11 p22), r ~ U[-0.8,0.8]."""

@@ -1,0 +1,265 @@
+"""GPU tests of the learned troubled-cell indicator: the network kernels
+against the oracle's FP64 forward and back-propagation, the features and the
+learned step against the oracle, GPU training, and what the trained network
+gains over the method without an indicator."""
+import numpy as np
+import pytest
+
+import oracle as O
+import riemann_exact
+from gpu_cases import make_pair, rel_l1, run_pair
+from oracle_runs import cfl_for
+from paper_2502_07517_amd import crkfr as C
+from paper_2502_07517_amd import learned as LI
+from paper_2502_07517_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+FF = (C.FARFIELD,) * 4
+
+
+def _rand_net(nin, hidden, seed, scale=1.0):
+    net = C.Mlp(nin, hidden, seed=seed)
+    p = (scale * np.random.default_rng(seed).standard_normal(net.num_params())).astype(np.float32)
+    net.set_params(p)
+    return net, p
+
+
+# ------------------------------------------------------------------ network kernels
+@pytest.mark.parametrize("nin,hidden", [(1, 8), (2, 16), (3, 16), (4, 32)])
+def test_forward_matches_oracle(nin, hidden):
+    net, p = _rand_net(nin, hidden, 1, 0.7)
+    x = np.random.default_rng(2).uniform(-1, 1, (1000, nin)).astype(np.float32)
+    y = net.forward(x).cpu().numpy()
+    ref = O.mlp_forward(net.dims, p.astype(np.float64), x.astype(np.float64))
+    assert np.max(np.abs(y - ref)) < 2e-6
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 5000, 200003])
+@pytest.mark.parametrize("nin,hidden", [(3, 16), (2, 8), (4, 32)])
+def test_loss_grad_matches_oracle_backprop(n, nin, hidden):
+    """Mean squared error and its gradient against the oracle's FP64 reverse
+    pass on the same FP32 parameters and data (tiles of 64 rows, a ragged
+    tail, and more tiles than workgroups)."""
+    if n > 5000 and hidden != 16:
+        pytest.skip("large case once")
+    net, p = _rand_net(nin, hidden, 3, 0.5)
+    rng = np.random.default_rng(n)
+    x = rng.uniform(-1, 1, (n, nin)).astype(np.float32)
+    t = rng.uniform(0, 1, n).astype(np.float32)
+    loss, g = net.loss_grad(x, t)
+    lref, gref = O.mlp_loss_grad(net.dims, p.astype(np.float64), x.astype(np.float64), t.astype(np.float64))
+    # FP32 forward: |dy| <= 2e-6 per row (the forward test's bound), so the
+    # mean of r^2 moves by at most 2 |dy| mean|r| <= 2 |dy| sqrt(loss) + |dy|^2
+    assert abs(loss - lref) <= 4e-6 * np.sqrt(lref) + 4e-12
+    assert np.max(np.abs(g - gref)) <= 2e-5 * np.max(np.abs(gref)) + 1e-8
+
+
+def test_gradient_is_deterministic():
+    net, _ = _rand_net(3, 16, 4)
+    x = np.random.default_rng(0).uniform(-1, 1, (70001, 3)).astype(np.float32)
+    t = np.random.default_rng(1).uniform(0, 1, 70001).astype(np.float32)
+    a = net.loss_grad(x, t)
+    b = net.loss_grad(x, t)
+    assert a[0] == b[0] and np.array_equal(a[1], b[1])
+
+
+def test_training_fits_a_known_map_and_is_reproducible():
+    rng = np.random.default_rng(5)
+    x = rng.uniform(-1, 1, (40000, 3)).astype(np.float32)
+    t = (1 / (1 + np.exp(-(6 * x[:, 2] - 3 * x[:, 0] + 1)))).astype(np.float32)
+    hists, params = [], []
+    for _ in range(2):
+        net = C.Mlp(3, 16, seed=11)
+        hists.append(net.train(x, t, epochs=25, batch=2048, lr=3e-3))
+        params.append(net.get_params())
+    h = hists[0]
+    assert h[-1] < 0.02 * h[0] and h[-1] < 2e-4, h
+    assert np.array_equal(params[0], params[1]) and np.array_equal(hists[0], hists[1])
+
+
+def test_fit_box():
+    x = np.random.default_rng(6).uniform(-0.8, 0.6, (3001, 3)).astype(np.float32)
+    net = C.Mlp(3, 16)
+    lo, hi = net.fit_box(x, 0.05)
+    assert np.allclose(lo, x.min(0) - 0.05) and np.allclose(hi, x.max(0) + 0.05)
+
+
+# ------------------------------------------------------------------ features and the learned step
+def _quadrants(N, n, m, seed):
+    X, Y = W.node_coords_2d(n, m, N, (0, 1, 0, 1))
+    st = W.quadrant_states_euler(seed)
+    rho, v1, v2, p = W._quadrant_fill(X, Y, 0.5 + 0.37 / n, 0.5 + 0.37 / m, st)
+    return W.euler2d_cons(rho, v1, v2, p)
+
+
+@pytest.mark.parametrize("dtype", [C.FP64, C.MP32])
+@pytest.mark.parametrize("N", [2, 3, 4])
+def test_features_match_oracle(N, dtype):
+    n, m = 12, 15
+    u0 = _quadrants(N, n, m, 1)
+    s = C.Solver(C.EULER2D, N, n, m, bc=FF, dtype=dtype)
+    s.set_state(u0.copy())
+    f, a = s.features()
+    cfg = O.RefConfig.make(O.EULER2D, N, n, m)
+    M, npn = 4, (N + 1) ** 2
+    ue_all = u0.reshape(M, n * m, npn)
+    fr = np.array([O.indicator_features(cfg, ue_all[:, e]) for e in range(n * m)])
+    ar = np.array([O.indicator_raw(cfg, ue_all[:, e])[0] for e in range(n * m)])
+    tol = 2e-6 if dtype == C.FP64 else 5e-4
+    assert np.max(np.abs(f - fr)) < tol
+    if dtype == C.FP64:
+        assert np.max(np.abs(a - ar)) < 1e-9
+    else:
+        assert np.mean((a > 0) == (ar > 0)) > 0.97
+
+
+def _learned_pair(N, n, m, dtype, params, lo, hi, hidden):
+    ref, gpu = make_pair(C.EULER2D, N, n, m, bc=FF, blend=C.BLEND_MH, flux_limiter=1, scaling=1,
+                         indicator=C.IND_LEARNED, dtype=dtype)
+    ref.set_mlp([N, hidden, hidden, 1], params.astype(np.float64), lo.astype(np.float64), hi.astype(np.float64))
+    net = C.Mlp(N, hidden)
+    net.set_params(params)
+    net.set_box(lo, hi)
+    gpu.set_mlp(net)
+    return ref, gpu, net
+
+
+@pytest.mark.parametrize("N", [2, 3, 4])
+@pytest.mark.parametrize("box", ["full", "partial"])
+def test_learned_step_matches_oracle_fp64(N, box):
+    """A network with outputs across (0, 1) and, with the partial box, some
+    elements falling back to the indicator: same result as the oracle."""
+    n, m = 12, 15
+    hidden = 16
+    u0 = _quadrants(N, n, m, 2)
+    p = (0.8 * np.random.default_rng(N).standard_normal(C.Mlp(N, hidden).num_params())).astype(np.float32)
+    lo, hi = -np.ones(N, np.float32), np.ones(N, np.float32)
+    if box == "partial":
+        lo[-1] = np.float32(-0.6)
+    ref, gpu, net = _learned_pair(N, n, m, C.FP64, p, lo, hi, hidden)
+    uo, ug, diags, _ = run_pair(ref, gpu, u0, 8)
+    assert rel_l1(uo, ug) <= 1e-9
+    do, dg = diags[-1]
+    assert do["n_troubled"] == dg["n_troubled"]
+    assert dg["n_mean_inadmissible"] == 0
+    # the judge: learned alpha against the indicator's alpha on the last step's input state
+    gpu2 = C.Solver(C.EULER2D, N, n, m, bc=FF, cfl=cfl_for(N))
+    gpu2.set_limiter(blend=C.BLEND_MH, indicator=C.IND_LEARNED, flux_limiter=1, scaling=1)
+    gpu2.set_mlp(net)
+    gpu2.set_state(u0.copy())
+    gpu2.step(O.compute_dt(ref, u0))
+    d, _ = gpu2.get_diag()
+    M, npn = 4, (N + 1) ** 2
+    ue_all = u0.reshape(M, n * m, npn)
+    fb, dis, dev = 0, 0, 0.0
+    for e in range(n * m):
+        al, f = O.learned_alpha(ref, ue_all[:, e])
+        ai = O.indicator_raw(ref, ue_all[:, e])[0]
+        fb += f
+        dis += (al > 0) != (ai > 0)
+        dev = max(dev, abs(al - ai))
+    assert d["n_learned_fallback"] == fb
+    assert d["n_learned_disagree"] == dis
+    assert abs(d["max_alpha_dev"] - dev) < 1e-9
+    if box == "partial":
+        assert fb > 0
+
+
+def test_learned_step_matches_oracle_mp32():
+    N, n, m, hidden = 3, 12, 15, 16
+    u0 = _quadrants(N, n, m, 2)
+    p = (0.8 * np.random.default_rng(7).standard_normal(C.Mlp(N, hidden).num_params())).astype(np.float32)
+    lo, hi = -np.ones(N, np.float32), np.ones(N, np.float32)
+    ref, gpu, _ = _learned_pair(N, n, m, C.MP32, p, lo, hi, hidden)
+    uo, ug, _, _ = run_pair(ref, gpu, u0, 8)
+    assert rel_l1(uo, ug) <= 1e-3
+
+
+def test_learned_without_network_is_an_error():
+    s = C.Solver(C.EULER2D, 3, 8, 8, bc=FF)
+    s.set_limiter(blend=C.BLEND_MH, indicator=C.IND_LEARNED)
+    s.set_state(_quadrants(3, 8, 8, 0))
+    with pytest.raises(C.CrkfrError) as e:
+        s.step(0.0)
+    assert e.value.code == -6
+    with pytest.raises(C.CrkfrError):
+        s.set_mlp(C.Mlp(2, 16))
+
+
+# ------------------------------------------------------------------ training on the method's own alphas
+def _riemann_solvers(seeds, nx, N, indicator, net=None, dtype=C.FP64, alpha_const=0.0):
+    out = []
+    for sd in seeds:
+        s = C.Solver(C.EULER1D, N, nx, bc=FF, cfl=cfl_for(N), dtype=dtype)
+        s.set_limiter(blend=C.BLEND_MH, indicator=indicator, flux_limiter=1, scaling=1, alpha_const=alpha_const)
+        if net is not None:
+            s.set_mlp(net)
+        s.set_state(W.euler1d_riemann(sd, nx, N))
+        out.append(s)
+    return out
+
+
+def _density_l1(s, seed, nx, N, t_end):
+    u = s.get_state()
+    L, R = W.riemann_states_1d(seed)
+    x = W.node_coords_1d(nx, N, 0, 1)
+    rex = riemann_exact.density_profile(L, R, x, t_end, x0=0.5 + W.OFF_FACE / nx)
+    _, w = O.gl(N)
+    return float((np.abs(u[0] - rex) * w).sum() / nx)
+
+
+@pytest.fixture(scope="module")
+def riemann_net():
+    """Trained on the method's own alphas: snapshots of eight Riemann runs
+    (every other step of 320) and 32 states of single-element patterns
+    (jumps at random positions, smooth profiles, constants)."""
+    import torch
+    N, nx = 3, 200
+    X1, y1 = LI.collect_pairs(_riemann_solvers(range(8), nx, N, C.IND_PAPER), steps=320, every=2)
+    ps = C.Solver(C.EULER1D, N, 4096, bc=FF)
+    X2, y2 = LI.pairs_of_states(ps, [W.element_patterns_1d(1000 + i, 4096, N) for i in range(32)])
+    X, y = torch.cat([X1, X2]), torch.cat([y1, y2])
+    net, hist = LI.train_indicator(X, y, epochs=100, batch=2048, lr=3e-3, seed=0)
+    return net, hist, X, y
+
+
+def test_trained_network_reproduces_the_indicator(riemann_net):
+    net, hist, X, y = riemann_net
+    assert hist[-1] < 0.01 * hist[0]
+    # held-out Riemann runs and held-out pattern states
+    Xh, yh = LI.collect_pairs(_riemann_solvers(range(100, 104), 200, 3, C.IND_PAPER), steps=300, every=3)
+    ps = C.Solver(C.EULER1D, 3, 4096, bc=FF)
+    Xp, yp = LI.pairs_of_states(ps, [W.element_patterns_1d(5000 + i, 4096, 3) for i in range(4)])
+    for name, (Xe, ye) in (("runs", (Xh, yh)), ("patterns", (Xp, yp))):
+        agree, mad = LI.agreement(net, Xe, ye)
+        print(f"held-out {name}: agreement {agree:.4f}, mean |alpha diff| {mad:.2e}, final loss {hist[-1]:.2e}")
+        assert agree > 0.99 and mad < 0.005
+
+
+def test_trained_network_gain_over_no_indicator(riemann_net):
+    """Held-out Riemann problems run to t = 0.05: density L1 error against
+    the exact solution with the learned indicator, the smoothness indicator,
+    and without an indicator (alpha = 0: the high-order scheme kept admissible
+    by the flux limiter and the scaling limiter alone).  A run whose element
+    means leave the admissible set counts as failed (error = inf)."""
+    net = riemann_net[0]
+    N, nx, t_end = 3, 200, 0.05
+    seeds = list(range(100, 106))
+    res, fails = {}, {}
+    for name, ind in (("learned", C.IND_LEARNED), ("indicator", C.IND_PAPER), ("none", C.IND_CONST)):
+        errs, nf = [], 0
+        for sd, s in zip(seeds, _riemann_solvers(seeds, nx, N, ind, net=net if ind == C.IND_LEARNED else None)):
+            s.advance(t_end, 100000)
+            d, rc = s.get_diag()
+            ok = rc == 0 and d["n_mean_inadmissible"] == 0 and abs(d["t"] - t_end) < 1e-12
+            e = _density_l1(s, sd, nx, N, t_end) if ok else np.inf
+            if not np.isfinite(e):
+                nf += 1
+            errs.append(e)
+        res[name], fails[name] = np.array(errs), nf
+    print({k: v.round(6).tolist() for k, v in res.items()}, "failed runs:", fails)
+    gain = res["none"] / res["learned"]
+    print("L1(no indicator) / L1(learned):", gain.round(3).tolist())
+    assert fails["learned"] == 0 and fails["indicator"] == 0
+    assert np.all(res["learned"] <= 1.1 * res["indicator"])
+    assert np.mean(np.minimum(gain, 10.0)) > 1.2
