@@ -194,6 +194,14 @@ int crkfr_batch_step(crkfr_batch* b);
 /* steps, replaying a captured two-step HIP graph */
 int crkfr_batch_advance(crkfr_batch* b, int steps);
 int crkfr_batch_sync(crkfr_batch* b);
+/* end time of every member: each member's last step is clipped to reach
+ * t_end and later steps have dt = 0 (t_end <= 0: no end time, the default) */
+int crkfr_batch_set_t_end(crkfr_batch* b, double t_end);
+/* per-phase device times (ms) of the last batched step, all groups of a phase
+ * together: [0] local, [1] x faces, [2] y faces, [3] update.  With timing on,
+ * crkfr_batch_advance enqueues the steps one by one instead of the graph. */
+int crkfr_batch_set_timing(crkfr_batch* b, int on);
+int crkfr_batch_phase_times(crkfr_batch* b, float* ms4);
 int crkfr_batch_num_groups(const crkfr_batch* b);
 /* persistent workgroups of (group, phase 0..3: local, x faces, y faces,
  * update); set_to >= 0 sets it (0: one workgroup per work item); returns it */

@@ -62,7 +62,7 @@ SYMBOLS = ["crkfr_create", "crkfr_destroy", "crkfr_set_limiter", "crkfr_set_sour
            "crkfr_batch_autotune", "crkfr_set_mlp", "crkfr_features", "crkfr_mlp_create", "crkfr_mlp_destroy",
            "crkfr_mlp_num_params", "crkfr_mlp_set_params", "crkfr_mlp_get_params", "crkfr_mlp_set_box",
            "crkfr_mlp_get_box", "crkfr_mlp_fit_box", "crkfr_mlp_forward", "crkfr_mlp_loss_grad",
-           "crkfr_mlp_train"]
+           "crkfr_mlp_train", "crkfr_batch_set_t_end", "crkfr_batch_set_timing", "crkfr_batch_phase_times"]
 
 _lib = None
 
@@ -115,6 +115,9 @@ def lib():
         L.crkfr_batch_num_groups.argtypes = [vp]
         L.crkfr_batch_grid.argtypes = [vp, ip, ip, ip]
         L.crkfr_batch_autotune.argtypes = [vp, ip]
+        L.crkfr_batch_set_t_end.argtypes = [vp, ctypes.c_double]
+        L.crkfr_batch_set_timing.argtypes = [vp, ip]
+        L.crkfr_batch_phase_times.argtypes = [vp, ctypes.POINTER(ctypes.c_float)]
         fp = ctypes.POINTER(ctypes.c_float)
         L.crkfr_set_mlp.argtypes = [vp, vp]
         L.crkfr_features.argtypes = [vp, vp, vp, ip]
@@ -421,6 +424,17 @@ class Batch:
 
     def sync(self):
         _check(lib().crkfr_batch_sync(self.h))
+
+    def set_t_end(self, t_end):
+        _check(lib().crkfr_batch_set_t_end(self.h, float(t_end)))
+
+    def set_timing(self, on=True):
+        _check(lib().crkfr_batch_set_timing(self.h, int(on)))
+
+    def phase_times(self):
+        ms = (ctypes.c_float * 4)()
+        _check(lib().crkfr_batch_phase_times(self.h, ms))
+        return list(ms)
 
     def num_groups(self):
         return lib().crkfr_batch_num_groups(self.h)

@@ -925,6 +925,9 @@ struct crkfr_batch {
     hipGraphExec_t graph;
     int graph_parity;
     hipEvent_t ev0, ev1;
+    bool timing;              // per-phase events, steps not replayed from the graph
+    hipEvent_t pev[5];
+    float phase_ms[4];
 };
 
 static int eq_geometry(int eq, int N, int* el, int* eu, int* nq)
@@ -970,11 +973,14 @@ static int launch_group_phase(const crkfr_batch* b, const BatchGroup& g, int pha
 static int enqueue_batch_step(crkfr_batch* b)
 {
     hipLaunchKernelGGL(k_prep_batch, dim3((unsigned)b->s.size()), dim3(RATE_SLOTS), 0, b->stream, b->d_prep);
-    for (int ph = 0; ph < 4; ++ph)
+    if (b->timing) (void)hipEventRecord(b->pev[0], b->stream);
+    for (int ph = 0; ph < 4; ++ph) {
         for (const BatchGroup& g : b->groups) {
             int rc = launch_group_phase(b, g, ph, g.grid[ph]);
             if (rc) return rc;
         }
+        if (b->timing) (void)hipEventRecord(b->pev[ph + 1], b->stream);
+    }
     b->parity ^= 1;
     for (size_t i = 0; i < b->s.size(); ++i) b->s[i]->cur = b->parity ? 1 - b->cur0[i] : b->cur0[i];
     return 0;
@@ -992,6 +998,8 @@ static void free_batch(crkfr_batch* b)
     if (b->graph) (void)hipGraphExecDestroy(b->graph);
     if (b->ev0) (void)hipEventDestroy(b->ev0);
     if (b->ev1) (void)hipEventDestroy(b->ev1);
+    for (int i = 0; i < 5; ++i)
+        if (b->pev[i]) (void)hipEventDestroy(b->pev[i]);
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
 }
 
@@ -1135,6 +1143,13 @@ extern "C" int crkfr_batch_step(crkfr_batch* b)
 extern "C" int crkfr_batch_advance(crkfr_batch* b, int steps)
 {
     if (!b || steps < 0) return fail(CRKFR_EINVAL, "bad argument");
+    if (b->timing) {
+        for (int k = 0; k < steps; ++k) {
+            int rc = enqueue_batch_step(b);
+            if (rc) return rc;
+        }
+        return 0;
+    }
     if (!b->graph || b->graph_parity != b->parity) {
         if (b->graph) {
             (void)hipGraphExecDestroy(b->graph);
@@ -1169,6 +1184,35 @@ extern "C" int crkfr_batch_sync(crkfr_batch* b)
 {
     if (!b) return fail(CRKFR_EINVAL, "null argument");
     HIP_TRY(hipStreamSynchronize(b->stream));
+    return 0;
+}
+
+extern "C" int crkfr_batch_set_t_end(crkfr_batch* b, double t_end)
+{
+    if (!b) return fail(CRKFR_EINVAL, "null argument");
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    std::vector<PrepArgs> prep(b->s.size());
+    HIP_TRY(hipMemcpy(prep.data(), b->d_prep, prep.size() * sizeof(PrepArgs), hipMemcpyDeviceToHost));
+    for (PrepArgs& p : prep) p.t_end = t_end > 0.0 ? t_end : 0.0;
+    HIP_TRY(hipMemcpy(b->d_prep, prep.data(), prep.size() * sizeof(PrepArgs), hipMemcpyHostToDevice));
+    return 0;
+}
+
+extern "C" int crkfr_batch_set_timing(crkfr_batch* b, int on)
+{
+    if (!b) return fail(CRKFR_EINVAL, "null argument");
+    if (on && !b->pev[0])
+        for (int i = 0; i < 5; ++i) HIP_TRY(hipEventCreate(&b->pev[i]));
+    b->timing = on != 0;
+    return 0;
+}
+
+extern "C" int crkfr_batch_phase_times(crkfr_batch* b, float* ms4)
+{
+    if (!b || !ms4) return fail(CRKFR_EINVAL, "null argument");
+    if (!b->pev[0]) return fail(CRKFR_ESTATE, "timing is off");
+    HIP_TRY(hipEventSynchronize(b->pev[4]));
+    for (int i = 0; i < 4; ++i) HIP_TRY(hipEventElapsedTime(&ms4[i], b->pev[i], b->pev[i + 1]));
     return 0;
 }
 

@@ -1330,16 +1330,33 @@ __global__ void __launch_bounds__(256) k_update(const StepArgs<real> a) { update
 enum { BPH_LOCAL = 0, BPH_FACE_X = 1, BPH_FACE_Y = 2, BPH_UPDATE = 3 };
 
 template <class Eq, int N, class real, bool LIM, int PH>
+__device__ __forceinline__ void batch_item(const StepArgs<real>& a, int block)
+{
+    if constexpr (PH == BPH_LOCAL) local_body<Eq, N, real, LIM>(a, block);
+    else if constexpr (PH == BPH_FACE_X) face_body<Eq, N, real, LIM, 0>(a, block);
+    else if constexpr (PH == BPH_FACE_Y) face_body<Eq, N, real, LIM, 1>(a, block);
+    else update_body<Eq, N, real, LIM>(a, block);
+}
+
+// one workgroup per (instance, block) work item
+template <class Eq, int N, class real, bool LIM, int PH>
 __global__ void __launch_bounds__(256) k_batch(const StepArgs<real>* __restrict__ args,
                                                 const int2* __restrict__ work, int nwork)
 {
+    if ((int)blockIdx.x >= nwork) return;
+    const int2 it = work[blockIdx.x];
+    batch_item<Eq, N, real, LIM, PH>(args[it.x], it.y);
+}
+
+// persistent workgroups walking the work table (the loop keeps more values
+// live than one item per workgroup does, so the autotuner weighs both)
+template <class Eq, int N, class real, bool LIM, int PH>
+__global__ void __launch_bounds__(256) k_batch_persistent(const StepArgs<real>* __restrict__ args,
+                                                           const int2* __restrict__ work, int nwork)
+{
     for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
         const int2 it = work[w];
-        const StepArgs<real>& a = args[it.x];
-        if constexpr (PH == BPH_LOCAL) local_body<Eq, N, real, LIM>(a, it.y);
-        else if constexpr (PH == BPH_FACE_X) face_body<Eq, N, real, LIM, 0>(a, it.y);
-        else if constexpr (PH == BPH_FACE_Y) face_body<Eq, N, real, LIM, 1>(a, it.y);
-        else update_body<Eq, N, real, LIM>(a, it.y);
+        batch_item<Eq, N, real, LIM, PH>(args[it.x], it.y);
         __syncthreads();   // LDS of this work item is reused by the next
     }
 }

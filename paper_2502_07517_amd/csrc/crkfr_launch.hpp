@@ -78,23 +78,21 @@ static void launch_batch_phase(int phase, const StepArgs<real>* args, const int2
 {
     using Eq = EqT<real>;
     const dim3 g(grid > 0 ? grid : nwork);
+    const int bl = phase == BPH_LOCAL ? LGeo<Eq::DIM, N>::BLOCK : (phase == BPH_UPDATE ? Geo<Eq::DIM, N>::BLOCK : 256);
+#define CRKFR_BATCH_LAUNCH(PH)                                                                        \
+    if (grid > 0)                                                                                     \
+        hipLaunchKernelGGL((k_batch_persistent<Eq, N, real, LIM, PH>), g, dim3(bl), 0, st, args, work, nwork); \
+    else                                                                                              \
+        hipLaunchKernelGGL((k_batch<Eq, N, real, LIM, PH>), g, dim3(bl), 0, st, args, work, nwork);
     switch (phase) {
-    case BPH_LOCAL:
-        hipLaunchKernelGGL((k_batch<Eq, N, real, LIM, BPH_LOCAL>), g, dim3(LGeo<Eq::DIM, N>::BLOCK), 0, st, args,
-                           work, nwork);
-        break;
-    case BPH_FACE_X:
-        hipLaunchKernelGGL((k_batch<Eq, N, real, LIM, BPH_FACE_X>), g, dim3(256), 0, st, args, work, nwork);
-        break;
+    case BPH_LOCAL: CRKFR_BATCH_LAUNCH(BPH_LOCAL) break;
+    case BPH_FACE_X: CRKFR_BATCH_LAUNCH(BPH_FACE_X) break;
     case BPH_FACE_Y:
-        if constexpr (Eq::DIM == 2)
-            hipLaunchKernelGGL((k_batch<Eq, N, real, LIM, BPH_FACE_Y>), g, dim3(256), 0, st, args, work, nwork);
+        if constexpr (Eq::DIM == 2) { CRKFR_BATCH_LAUNCH(BPH_FACE_Y) }
         break;
-    case BPH_UPDATE:
-        hipLaunchKernelGGL((k_batch<Eq, N, real, LIM, BPH_UPDATE>), g, dim3(Geo<Eq::DIM, N>::BLOCK), 0, st, args,
-                           work, nwork);
-        break;
+    case BPH_UPDATE: CRKFR_BATCH_LAUNCH(BPH_UPDATE) break;
     }
+#undef CRKFR_BATCH_LAUNCH
 }
 
 template <template <class> class EqT, class real>
