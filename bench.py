@@ -184,7 +184,9 @@ def run_plain(n, t_end, steps, warmup):
             "l1": l1, "steps_to_t_end": int(d["steps"]), "n_troubled_last": int(d["n_troubled"])}
 
 
-def run_optimized(n, t_end, steps, warmup, net, fill_dof, phase_timing=True):
+def run_optimized(n, t_end, steps, warmup, net, fill_dof, phase_timing=True, dtype=None, indicator=None):
+    """Batched copies of the n^2 vortex; by default FP32 bulk + the learned
+    indicator (other arithmetic / indicator for the speed-up decomposition)."""
     import torch
     from paper_2502_07517_amd import crkfr as C
     from paper_2502_07517_amd import workloads as W
@@ -194,8 +196,10 @@ def run_optimized(n, t_end, steps, warmup, net, fill_dof, phase_timing=True):
     u0 = torch.from_numpy(np.ascontiguousarray(W.vortex2d(n, N_DEG, 0.0, DOM))).to("cuda")
     solvers = []
     for _ in range(copies):
-        s = C.Solver(C.EULER2D, N_DEG, n, n, domain=DOM, dtype=C.MP32, cfl=CFL3, stream=st)
-        _limited(s, C, C.IND_LEARNED, net)
+        dt_ = C.MP32 if dtype is None else dtype
+        ind = C.IND_LEARNED if indicator is None else indicator
+        s = C.Solver(C.EULER2D, N_DEG, n, n, domain=DOM, dtype=dt_, cfl=CFL3, stream=st)
+        _limited(s, C, ind, net if ind == C.IND_LEARNED else None)
         s.set_state(u0)
         solvers.append(s)
     b = C.Batch(solvers, stream=st)
@@ -275,7 +279,7 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--t-end", type=float, default=2.0)
-    ap.add_argument("--sweep", default="32,48,64,96,128,192,256")
+    ap.add_argument("--sweep", default="8,12,16,24,32,48,64,96,128,192,256")
     ap.add_argument("--fill-dof", type=float, default=4.2e6)
     ap.add_argument("--cpu-steps", type=int, default=400)
     ap.add_argument("--no-cpu", action="store_true")
@@ -332,6 +336,26 @@ def main():
                                                   for k, v in c3.items()}, "optimized": opt}), flush=True)
         return
 
+    # decomposition of the speed-up on the headline grid: batching alone
+    # (FP64, smoothness indicator), then FP32 bulk (smoothness indicator)
+    decomposition = None
+    ro0 = matched(opt, HEADLINE_TARGET)
+    if ro0 is not None and plain:
+        rb64 = run_optimized(ro0["n"], args.t_end, args.steps, args.warmup, None, args.fill_dof,
+                             phase_timing=False, dtype=C.FP64, indicator=C.IND_PAPER)
+        rb32 = run_optimized(ro0["n"], args.t_end, args.steps, args.warmup, None, args.fill_dof,
+                             phase_timing=False, dtype=C.MP32, indicator=C.IND_PAPER)
+        rp0 = [r for r in plain if r["n"] == ro0["n"]][0]
+        decomposition = {
+            "grid": ro0["n"],
+            "plain_fp64_single": rp0["dofsteps_per_s"],
+            "fp64_batched_indicator": rb64["dofsteps_per_s"],
+            "fp32_bulk_batched_indicator": rb32["dofsteps_per_s"],
+            "fp32_bulk_batched_learned": ro0["dofsteps_per_s"],
+            "l1": {"plain_fp64_single": rp0["l1"], "fp64_batched_indicator": rb64["l1"],
+                   "fp32_bulk_batched_indicator": rb32["l1"], "fp32_bulk_batched_learned": ro0["l1"]}}
+        print(f"# decomposition n={ro0['n']}: {decomposition}", flush=True)
+
     dof512 = 512 * 512 * (N_DEG + 1) ** 2
     per_target = {}
     for tau in TARGETS:
@@ -368,6 +392,7 @@ def main():
         "plain_fp64_at_target": None if rp is None else {"n": rp["n"], "dofsteps_per_s": rp["dofsteps_per_s"],
                                                           "ms_per_step": rp["ms_per_step"], "l1": rp["l1"]},
         "speedup_vs_plain_fp64": head["speedup"],
+        "speedup_decomposition": decomposition,
         "matched_l1": per_target,
         "roofline": {"bound": "hbm", "kernel": "k_batch local phase (MP32, limiter chain)",
                      "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",

@@ -99,7 +99,7 @@ typedef struct {
     long long n_mean_inadmissible; /* elements whose mean left the admissible set */
     double min_theta_flux, min_theta_scale;
     double t, dt;                  /* time reached and last step size */
-    long long steps;
+    long long steps;               /* steps taken with dt > 0 */
     /* learned indicator, judged by the smoothness indicator on the same state: */
     long long n_learned_fallback;  /* elements whose features left the network's box (indicator used) */
     long long n_learned_disagree;  /* elements troubled (alpha > 0) by one indicator but not the other */

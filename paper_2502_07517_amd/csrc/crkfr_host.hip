@@ -136,6 +136,12 @@ static void fill_tab(const RefElem& r, RefTab<real>& t)
         t.xi[i] = (real)r.xi[i];
     }
     for (int i = 0; i <= r.N + 1; ++i) t.sub[i] = (real)r.sub[i];
+    for (int i = 0; i <= r.N; ++i) {
+        const double xm = i > 0 ? r.xi[i - 1] : r.xi[r.N] - 1.0;
+        const double xp = i < r.N ? r.xi[i + 1] : 1.0 + r.xi[0];
+        t.rdm[i] = (real)(1.0 / (r.xi[i] - xm));
+        t.rdp[i] = (real)(1.0 / (xp - r.xi[i]));
+    }
     const int S = std::min(r.N + 1, 4);
     for (int i = 0; i < S; ++i) {
         t.tb[i] = (real)tab_b(S, i);
@@ -361,6 +367,8 @@ static StepArgs<real> step_args(const crkfr_solver* s, int in, int out)
     a.mlp_hidden = s->mlp ? mlp_hidden(s->mlp) : 0;
     a.alpha_judge = s->alpha_judge;
     a.feat_out = s->feat;
+    a.ind_T = 0.5 * std::pow(10.0, -1.8 * std::pow((double)(s->cfg.N + 1), 0.25));
+    a.ind_kT = std::log(9999.0) / a.ind_T;
     return a;
 }
 

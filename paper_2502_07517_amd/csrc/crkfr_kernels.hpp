@@ -52,6 +52,7 @@ struct RefTab {
     real l0[MAXND], l1[MAXND], bR[MAXND], bL[MAXND], w[MAXND], xi[MAXND];
     real sub[MAXND + 1];
     real L[MAXND][MAXND];   // L[k][p] = orthonormal Legendre L_k(xi_p)
+    real rdm[MAXND], rdp[MAXND];   // 1 / distance to the previous / next solution point (across faces too)
     real ta[4], tb[4];      // cRK tableau: a_{i+1,i}, b_i
 };
 
@@ -86,6 +87,7 @@ struct StepArgs {
     int mlp_hidden;
     double* alpha_judge;   // learned indicator: the smoothness indicator's alpha per element
     float* feat_out;       // k_features: learned-indicator features [e][N]
+    double ind_T, ind_kT;  // indicator threshold T(N) = 0.5 10^(-1.8 (N+1)^(1/4)) and ln(9999) / T
 };
 
 template <int DIM, int N>
@@ -179,11 +181,13 @@ __device__ double bisect_root(int k, const double* a, const double* b, double ep
     return lo;
 }
 
-// fraction of the segment a -> b keeping P_k >= eps: concavity bound, else bisection
+// fraction of the segment a -> b keeping P_k >= eps, given Pa = P_k(a):
+// concavity bound, else bisection
 template <class Eq>
-__device__ double segment_fraction(int k, const double* a, const double* b, double eps, const Phys& P)
+__device__ double segment_fraction(int k, const double* a, double Pa, const double* b, double eps, const Phys& P)
 {
-    double Pa = Eq::adm(k, a, P), Pb = Eq::adm(k, b, P);
+    if (Eq::adm_ge(k, b, eps, P)) return 1.0;
+    const double Pb = Eq::adm(k, b, P);
     if (Pb >= eps) return 1.0;
     if (Eq::concave(k)) {
         double t = (Pa - eps) / (Pa - Pb);
@@ -197,7 +201,7 @@ __device__ bool admissible_eps(const double* u, const double* eps, const Phys& P
 {
 #pragma unroll
     for (int k = 0; k < Eq::K; ++k)
-        if (!(Eq::adm(k, u, P) >= eps[k])) return false;
+        if (!Eq::adm_ge(k, u, eps[k], P)) return false;
     return true;
 }
 
@@ -248,13 +252,14 @@ __device__ void mh_subcell(const StepArgs<real>& a, int e, int ex, int ey, int p
     real sx[M], sy[M];
 #pragma unroll
     for (int v = 0; v < M; ++v) { sx[v] = 0; sy[v] = 0; }
-    double ud[M], eps[K > 0 ? K : 1];
+    double ud[M], eps[K > 0 ? K : 1], Pu[K > 0 ? K : 1];
 #pragma unroll
     for (int v = 0; v < M; ++v) ud[v] = (double)u[v];
     bool u_ok = true;
 #pragma unroll
     for (int kk = 0; kk < K; ++kk) {
-        eps[kk] = 0.1 * Eq::adm(kk, ud, P);
+        Pu[kk] = Eq::adm(kk, ud, P);
+        eps[kk] = 0.1 * Pu[kk];
         if (!(eps[kk] > 0.0)) u_ok = false;
     }
     const bool mh = a.blend == BLEND_MH && u_ok;
@@ -263,12 +268,10 @@ __device__ void mh_subcell(const StepArgs<real>& a, int e, int ex, int ey, int p
         for (int d = 0; d < Eq::DIM; ++d) {
             const int pos = d == 0 ? p : q;
             real um[M], up[M];
-            real x0 = a.R.xi[pos], xmn, xpn;
             if (pos > 0) {
                 const int kn = d == 0 ? k - 1 : k - nd;
 #pragma unroll
                 for (int v = 0; v < M; ++v) um[v] = sh[kn][v];
-                xmn = a.R.xi[pos - 1];
             } else {
                 int en = nbr(a, ex, ey, d, 0);
                 if (en >= 0) {
@@ -283,13 +286,11 @@ __device__ void mh_subcell(const StepArgs<real>& a, int e, int ex, int ey, int p
                         for (int v = 0; v < M; ++v) um[v] = u[v];
                     }
                 }
-                xmn = a.R.xi[N] - (real)1;
             }
             if (pos < N) {
                 const int kn = d == 0 ? k + 1 : k + nd;
 #pragma unroll
                 for (int v = 0; v < M; ++v) up[v] = sh[kn][v];
-                xpn = a.R.xi[pos + 1];
             } else {
                 int en = nbr(a, ex, ey, d, 1);
                 if (en >= 0) {
@@ -304,11 +305,10 @@ __device__ void mh_subcell(const StepArgs<real>& a, int e, int ex, int ey, int p
                         for (int v = 0; v < M; ++v) up[v] = u[v];
                     }
                 }
-                xpn = (real)1 + a.R.xi[0];
             }
 #pragma unroll
             for (int v = 0; v < M; ++v) {
-                real s1 = (u[v] - um[v]) / (x0 - xmn), s2 = (up[v] - u[v]) / (xpn - x0);
+                real s1 = (u[v] - um[v]) * a.R.rdm[pos], s2 = (up[v] - u[v]) * a.R.rdp[pos];
                 real s = s1 * s2 <= 0 ? (real)0 : (fabs(s1) < fabs(s2) ? s1 : s2);
                 if (d == 0) sx[v] = s; else sy[v] = s;
             }
@@ -331,7 +331,7 @@ __device__ void mh_subcell(const StepArgs<real>& a, int e, int ex, int ey, int p
                     real h = f == 0 ? hxm : (f == 1 ? hxp : (f == 2 ? hym : hyp));
                     fv[v] = (double)(u[v] + s * h);
                 }
-                double t = segment_fraction<Eq>(kk, ud, fv, eps[kk], P);
+                double t = segment_fraction<Eq>(kk, ud, Pu[kk], fv, eps[kk], P);
                 th = t < th ? t : th;
             }
             if (th < 1.0) {
@@ -414,35 +414,35 @@ __device__ __forceinline__ real modal_coeff(const RefTab<real>& R, int p, int q,
 }
 
 // shell energies en[s] = sum of squared coefficients whose highest degree is s
+// (the indicator's arithmetic runs in the step's precision)
 template <int DIM, int N, class real>
-__device__ __forceinline__ void shell_energies(const real* m2, int stride, double* en)
+__device__ __forceinline__ void shell_energies(const real* m2, int stride, real* en)
 {
     constexpr int nd = N + 1, np = DIM == 2 ? nd * nd : nd;
 #pragma unroll
-    for (int s2 = 0; s2 < nd; ++s2) en[s2] = 0.0;
+    for (int s2 = 0; s2 < nd; ++s2) en[s2] = 0;
 #pragma unroll
     for (int kk = 0; kk < np; ++kk) {
         int pp = kk % nd, qq = kk / nd;
-        en[pp > qq ? pp : qq] += (double)m2[kk * stride];
+        en[pp > qq ? pp : qq] += m2[kk * stride];
     }
 }
 
-// alpha of the smoothness indicator: logistic of the energy ratio around the
-// threshold T(N), clipped to [alpha_min, alpha_max] (0 below alpha_min)
-template <int N>
-__device__ __forceinline__ double indicator_alpha(const double* en, double amin, double amax)
+// alpha of the smoothness indicator: logistic of the energy ratio E around
+// the threshold T(N) with slope kT = ln(9999) / T, clipped to
+// [alpha_min, alpha_max] (0 below alpha_min)
+template <int N, class real>
+__device__ __forceinline__ double indicator_alpha(const real* en, double amin, double amax, double T, double kT)
 {
-    double totN = 0.0, totNm1 = 0.0;
+    real totN = 0, totNm1 = 0;
 #pragma unroll
     for (int s2 = 0; s2 <= N; ++s2) totN += en[s2];
 #pragma unroll
     for (int s2 = 0; s2 < N; ++s2) totNm1 += en[s2];
-    double E1 = totN > 0.0 ? en[N] / totN : 0.0;
-    double E2 = totNm1 > 0.0 ? en[N - 1] / totNm1 : 0.0;
-    double E = E1 > E2 ? E1 : E2;
-    const double T = 0.5 * pow(10.0, -1.8 * pow((double)(N + 1), 0.25));
-    const double sharp = log(9999.0);
-    double al = 1.0 / (1.0 + exp(-(sharp / T) * (E - T)));
+    const real E1 = totN > 0 ? en[N] / totN : (real)0;
+    const real E2 = totNm1 > 0 ? en[N - 1] / totNm1 : (real)0;
+    const real E = E1 > E2 ? E1 : E2;
+    double al = (double)((real)1 / ((real)1 + exp(-(real)kT * (E - (real)T))));
     if (al < amin) al = 0.0;
     if (al > amax) al = amax;
     return al;
@@ -451,16 +451,16 @@ __device__ __forceinline__ double indicator_alpha(const double* en, double amin,
 // features of the learned indicator: for shells s = 1..N the share r_s of
 // shell s in the energy of shells 0..s, as log10(max(r_s, 1e-12)) / 6 + 1
 // (at least -1)
-template <int N>
-__device__ __forceinline__ void learned_features(const double* en, double* ft)
+template <int N, class real>
+__device__ __forceinline__ void learned_features(const real* en, real* ft)
 {
-    double cum = en[0];
+    real cum = en[0];
 #pragma unroll
     for (int s2 = 1; s2 <= N; ++s2) {
         cum += en[s2];
-        const double r = cum > 0.0 ? en[s2] / cum : 0.0;
+        const real r = cum > 0 ? en[s2] / cum : (real)0;
         // floor exactly -1, so a box edge at -1 is decided the same everywhere
-        ft[s2 - 1] = r > 1e-12 ? fmax(log10(r) / 6.0 + 1.0, -1.0) : -1.0;
+        ft[s2 - 1] = r > (real)1e-12 ? fmax(log10(r) / (real)6 + (real)1, (real)-1) : (real)-1;
     }
 }
 
@@ -515,13 +515,13 @@ __device__ void local_body(const StepArgs<real>& a, int vblock)
         bool inbox = true;
         if (k == 0 && act) {
             if (modal) {
-                double en[nd];
+                real en[nd];
                 shell_energies<DIM, N>(&sh_g[le][0][0], MY, en);
-                al_ind = indicator_alpha<N>(en, a.alpha_min, a.alpha_max);
+                al_ind = indicator_alpha<N>(en, a.alpha_min, a.alpha_max, a.ind_T, a.ind_kT);
                 if (a.indicator == IND_PAPER) {
                     a.alpha_raw[e] = al_ind;
                 } else {
-                    double ft[N];
+                    real ft[N];
                     learned_features<N>(en, ft);
                     const float* box = a.mlp + mlp_nparams(N, a.mlp_hidden);
 #pragma unroll
@@ -563,7 +563,7 @@ __device__ void local_body(const StepArgs<real>& a, int vblock)
             if (k == 0 && act) {
                 real s = (real)w3[H];
                 for (int j = 0; j < H; ++j) s += (real)w3[j] * sh_m[le][1][j];
-                double y = 1.0 / (1.0 + exp(-(double)s));
+                double y = (double)((real)1 / ((real)1 + exp(-s)));
                 if (y < a.alpha_min) y = 0.0;
                 if (y > a.alpha_max) y = a.alpha_max;
                 a.alpha_raw[e] = inbox ? y : al_ind;
@@ -982,7 +982,7 @@ __device__ void face_body(const StepArgs<real>& a, int vblock)
                         const double* lo = side == 0 ? cAlo : cBlo;
                         double Plo = Eq::adm(kk, lo, P);
                         if (!(Plo > 0.0)) { bad = true; th = 0.0; continue; }
-                        double t2 = segment_fraction<Eq>(kk, lo, cF, 0.1 * Plo, P);
+                        double t2 = segment_fraction<Eq>(kk, lo, Plo, cF, 0.1 * Plo, P);
                         th = t2 < th ? t2 : th;
                     }
                     if (th < 1.0) {
@@ -1256,7 +1256,7 @@ __device__ void update_body(const StepArgs<real>& a, int vblock)
                 double t = 1.0;
                 if (!mean_bad) {
                     double eps = Pbar < 1e-13 ? Pbar : 1e-13;
-                    if (!(Eq::adm(kk, ud, P) >= eps)) {
+                    if (!Eq::adm_ge(kk, ud, eps, P)) {
                         if (kk == 0) t = (um[0] - eps) / (um[0] - ud[0]);
                         else t = bisect_root<Eq>(kk, um, ud, eps, P);
                     }
@@ -1402,7 +1402,7 @@ __device__ __forceinline__ void prep_body(const PrepArgs& a)
     for (int i = 0; i < D_THFLUX; ++i) a.diag[i] = 0ull;
     a.diag[D_THFLUX] = (unsigned long long)__double_as_longlong(1.0);
     a.diag[D_THSCALE] = (unsigned long long)__double_as_longlong(1.0);
-    *a.steps += 1;
+    if (dt > 0.0) *a.steps += 1;   // steps past the end time (dt = 0) do not count
 }
 
 static __global__ void __launch_bounds__(RATE_SLOTS) k_prep(PrepArgs a) { prep_body(a); }
@@ -1590,9 +1590,9 @@ __global__ void __launch_bounds__(256) k_features(const StepArgs<real> a)
     sh_m2[le][k] = m * m;
     __syncthreads();
     if (k == 0 && act) {
-        double en[nd], ft[N];
+        real en[nd], ft[N];
         shell_energies<DIM, N>(&sh_m2[le][0], 1, en);
-        a.alpha_judge[e] = indicator_alpha<N>(en, a.alpha_min, a.alpha_max);
+        a.alpha_judge[e] = indicator_alpha<N>(en, a.alpha_min, a.alpha_max, a.ind_T, a.ind_kT);
         learned_features<N>(en, ft);
 #pragma unroll
         for (int j = 0; j < N; ++j) a.feat_out[(size_t)e * N + j] = (float)ft[j];

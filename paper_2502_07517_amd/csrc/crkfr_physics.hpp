@@ -35,6 +35,7 @@ struct LinAdv1D {
     __device__ static inline real sx(const real*, const Phys& P) { return fabs((real)P.adv); }
     __device__ static inline real sy(const real*, const Phys&) { return 0; }
     __device__ static inline double adm(int, const double*, const Phys&) { return 1.0; }
+    __device__ static inline bool adm_ge(int, const double*, double eps, const Phys&) { return 1.0 >= eps; }
     __device__ static inline bool concave(int) { return true; }
     __device__ static inline real ind(const real* u, const Phys&) { return u[0]; }
     __device__ static inline real sig_trace(int, const real*, const real*, const Phys& P) { return fabs((real)P.adv); }
@@ -67,6 +68,13 @@ struct Euler1D {
     {
         if (k == 0) return u[0];
         return (P.gamma - 1.0) * (u[2] - 0.5 * u[1] * u[1] / u[0]);
+    }
+    // adm(k, u) >= eps, for positive density without the division (times rho)
+    __device__ static inline bool adm_ge(int k, const double* u, double eps, const Phys& P)
+    {
+        if (k == 0) return u[0] >= eps;
+        if (!(u[0] > 0.0)) return adm(k, u, P) >= eps;
+        return (P.gamma - 1.0) * (u[2] * u[0] - 0.5 * u[1] * u[1]) >= eps * u[0];
     }
     __device__ static inline bool concave(int) { return true; }
     __device__ static inline real ind(const real* u, const Phys& P) { return u[0] * pres(u, P); }
@@ -126,6 +134,13 @@ struct Euler2D {
     {
         if (k == 0) return u[0];
         return (P.gamma - 1.0) * (u[3] - 0.5 * (u[1] * u[1] + u[2] * u[2]) / u[0]);
+    }
+    // adm(k, u) >= eps, for positive density without the division (times rho)
+    __device__ static inline bool adm_ge(int k, const double* u, double eps, const Phys& P)
+    {
+        if (k == 0) return u[0] >= eps;
+        if (!(u[0] > 0.0)) return adm(k, u, P) >= eps;
+        return (P.gamma - 1.0) * (u[3] * u[0] - 0.5 * (u[1] * u[1] + u[2] * u[2])) >= eps * u[0];
     }
     __device__ static inline bool concave(int) { return true; }
     __device__ static inline real ind(const real* u, const Phys& P) { return u[0] * pres(u, P); }
@@ -198,6 +213,17 @@ struct TenMom2D {
         if (k == 1) return P11;
         double P12 = 2.0 * u[4] - r * v1 * v2, P22 = 2.0 * u[5] - r * v2 * v2;
         return P11 * P22 - P12 * P12;
+    }
+    // adm(k, u) >= eps, for positive density without the divisions (times rho, rho^2)
+    __device__ static inline bool adm_ge(int k, const double* u, double eps, const Phys& P)
+    {
+        if (k == 0) return u[0] >= eps;
+        const double r = u[0];
+        if (!(r > 0.0)) return adm(k, u, P) >= eps;
+        const double a11 = 2.0 * u[3] * r - u[1] * u[1];   // rho P11
+        if (k == 1) return a11 >= eps * r;
+        const double a12 = 2.0 * u[4] * r - u[1] * u[2], a22 = 2.0 * u[5] * r - u[2] * u[2];
+        return a11 * a22 - a12 * a12 >= eps * r * r;
     }
     __device__ static inline bool concave(int k) { return k != 2; }   // det P is not concave
     __device__ static inline real ind(const real* u, const Phys&)
