@@ -62,6 +62,40 @@ def local_bytes_per_node(M, N, real_bytes, lim, mp, dim=2):
     return b
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_batch_local_mp32_limited_vortex_32sq_x256_hbm_traffic.md")
+
+
+def kernel_sources_digest():
+    """SHA-256 over the HIP sources (file names and contents, sorted)."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2502_07517_amd", "csrc")
+    for fn in sorted(os.listdir(d)):
+        h.update(fn.encode())
+        with open(os.path.join(d, fn), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(grid, copies):
+    """HBM bytes per launch of the batched local phase from the committed
+    counter summary, if it was taken on the current kernel sources and the
+    same batch (else None)."""
+    import re
+    try:
+        txt = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    m = re.search(r"sources_sha256: (\w+)", txt)
+    t = re.search(r"traffic_bytes_per_launch: (\d+)", txt)
+    w = re.search(r"batch: (\d+) x (\d+)\^2", txt)
+    if not (m and t and w) or m.group(1) != kernel_sources_digest():
+        return None
+    if int(w.group(1)) != copies or int(w.group(2)) != grid:
+        return None
+    return int(t.group(1))
+
+
 def gl_weights(N):
     _, w = np.polynomial.legendre.leggauss(N + 1)
     return 0.5 * w
@@ -83,13 +117,15 @@ def _events():
 
 
 # ---------------------------------------------------------------- the 512^2 single-instance step
-def run_c3(dtype, steps, warmup):
+def run_c3(dtype, steps, warmup, limited=False):
     import torch
     from paper_2502_07517_amd import crkfr as C
     from paper_2502_07517_amd import workloads as W
     n = 512
     s = C.Solver(C.EULER2D, N_DEG, n, n, domain=DOM, dtype=dtype, cfl=CFL3,
                  stream=torch.cuda.current_stream().cuda_stream)
+    if limited:
+        _limited(s, C, C.IND_PAPER)
     s.set_state(torch.from_numpy(np.ascontiguousarray(W.vortex2d(n, N_DEG, 0.0, DOM))).to("cuda"))
     for _ in range(warmup):
         s.step(0.0)
@@ -263,7 +299,7 @@ def cpu_baseline(n, t_end, max_steps):
     while k < max_steps:
         u, _, _, _ = O.step(cfg, u, dt)
         k += 1
-        if time.perf_counter() - t0 > 20.0:
+        if time.perf_counter() - t0 > 15.0:
             break
     el = time.perf_counter() - t0
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -281,11 +317,14 @@ def main():
     ap.add_argument("--t-end", type=float, default=2.0)
     ap.add_argument("--sweep", default="8,12,16,24,32,48,64,96,128,192,256")
     ap.add_argument("--fill-dof", type=float, default=4.2e6)
-    ap.add_argument("--cpu-steps", type=int, default=400)
+    ap.add_argument("--cpu-steps", type=int, default=1000000,
+                    help="cap on the oracle's steps (the CPU leg also stops after 15 s)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--part", choices=["all", "sweep", "c3", "optimized"], default="all",
                     help="c3: only the 512^2 single-instance step; optimized: only the optimized path "
                          "on the --sweep grids (profiling)")
+    ap.add_argument("--c3-limiter", action="store_true",
+                    help="also run the 512^2 step with the limiter chain (smoothness indicator)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy (scale for the HBM byte counters)")
     args = ap.parse_args()
@@ -313,6 +352,8 @@ def main():
     if args.part in ("all", "c3"):
         for key, dt in (("fp64", C.FP64), ("mp32", C.MP32)):
             c3[key] = run_c3(dt, args.steps, args.warmup)
+            if args.c3_limiter:
+                c3[key + "_limited"] = run_c3(dt, args.steps, args.warmup, limited=True)
             print(f"# c3 512^2 {key}: {c3[key]['ms_per_step']:.4f} ms/step kernels "
                   f"{np.round(c3[key]['kernel_ms'], 4).tolist()}", flush=True)
 
@@ -396,7 +437,7 @@ def main():
         "matched_l1": per_target,
         "roofline": {"bound": "hbm", "kernel": "k_batch local phase (MP32, limiter chain)",
                      "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK, "traffic": None,
+                     "frac": achieved / HBM_PEAK, "traffic": recorded_traffic(ro["n"], ro["copies"]),
                      "algorithmic_bytes_per_launch": lb, "avg_ms": lms},
         "learned_indicator": train,
         "sweep": {"plain": plain, "optimized": opt},
@@ -416,6 +457,10 @@ def main():
                                       "frac": kb / (k_ms * 1e-3) / HBM_PEAK, "algorithmic_bytes_per_launch": kb,
                                       "avg_ms": k_ms},
             "limiter": "off"}
+        for key in ("fp64_limited", "mp32_limited"):
+            if key in c3:
+                line["c3_512"][key] = {"dofsteps_per_s": dof512 / (c3[key]["ms_per_step"] * 1e-3),
+                                       "ms_per_step": c3[key]["ms_per_step"], "kernel_ms": c3[key]["kernel_ms"]}
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(rp["n"] if rp else 64, args.t_end, args.cpu_steps)
     print(json.dumps(line), flush=True)
