@@ -56,11 +56,15 @@ def train_indicator(X, y, *, hidden=16, epochs=30, batch=4096, lr=3e-3, seed=0, 
     return net, hist
 
 
-def agreement(net, X, y, alpha_min=1e-3, alpha_max=1.0):
+def agreement(net, X, y, alpha_min=1e-3, alpha_max=1.0, within=None):
     """Share of rows on which the network and the labels agree about
     'troubled' (alpha > 0 after the indicator's clipping), and the mean
-    absolute difference of the clipped coefficients."""
+    absolute difference of the clipped coefficients; with `within`, also the
+    share of rows whose coefficients differ by at most that much."""
     out = net.forward(X).double().cpu().numpy()
     a = np.where(out < alpha_min, 0.0, np.minimum(out, alpha_max))
     t = y.double().cpu().numpy()
-    return float(np.mean((a > 0) == (t > 0))), float(np.mean(np.abs(a - t)))
+    res = (float(np.mean((a > 0) == (t > 0))), float(np.mean(np.abs(a - t))))
+    if within is not None:
+        res += (float(np.mean(np.abs(a - t) <= within)),)
+    return res
