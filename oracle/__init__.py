@@ -6,7 +6,7 @@ HIP library.  ``crkfr_oracle.c`` holds the arithmetic; this module is ctypes
 marshalling plus the Fourier stability analysis in ``cfl.py``.
 """
 from .oracle import (  # noqa: F401
-    LINADV1D, EULER1D, EULER2D, TENMOM2D, PERIODIC, OUTFLOW, FARFIELD,
+    LINADV1D, EULER1D, EULER2D, TENMOM2D, PERIODIC, OUTFLOW, FARFIELD, REFLECT,
     BLEND_OFF, BLEND_FO, BLEND_MH, IND_PAPER, IND_CONST, IND_GIVEN, IND_LEARNED,
     RefConfig, lib, build, gl, diff_matrix, lagrange_at, legendre_orthonormal,
     tableau, flux, sigma, adm, nvar, nadm, local_crk, indicator_raw, indicator_features, learned_alpha,

@@ -757,6 +757,22 @@ static const double* ghost_at(const grid_ctx* g, int ex, int ey, int dir, int si
     return g->ghost + 2 * xsz + side * ysz + ((size_t)ex * nd + t) * M;
 }
 
+/* solid wall normal to direction d (Sec. 3.3, eq. reflect.time.avg): the
+ * ghost state mirrors the interior one, flipping the normal momentum (and,
+ * for the ten-moment system, the off-diagonal energy E12); the mirrored
+ * normal flux is then -(mirror of F) */
+static int wall(const ref_config* c, int dir, int side)
+{
+    return c->bc[dir * 2 + side] == REF_BC_REFLECT;
+}
+
+static double mirror_sign(int eq, int d, int v)
+{
+    if (v == 1 + d) return -1.0;
+    if (eq == REF_TENMOM2D && v == 4) return -1.0;
+    return 1.0;
+}
+
 static size_t gidx(const grid_ctx* g, int v, int e, int k)
 {
     return (size_t)v * g->ne * g->np + (size_t)e * g->np + k;
@@ -809,8 +825,10 @@ static void mh_element(const grid_ctx* g, int ex, int ey, double dt, int blend, 
                         int en = nbr_elem(g, ex, ey, d, 0);
                         int kn = d == 0 ? q * nd + N : N * nd + p;
                         const double* gh = en < 0 ? ghost_at(g, ex, ey, d, 0, d == 0 ? q : p) : NULL;
+                        const int wl = en < 0 && wall(c, d, 0);
                         for (int v = 0; v < M; ++v)
-                            um[v] = en >= 0 ? g->u[gidx(g, v, en, kn)] : (gh ? gh[v] : u[v]);
+                            um[v] = en >= 0 ? g->u[gidx(g, v, en, kn)]
+                                  : (gh ? gh[v] : (wl ? mirror_sign(c->eq, d, v) * u[v] : u[v]));
                         xm = r->xi[N] - 1.0;
                     }
                     if (pos < N) {
@@ -821,8 +839,10 @@ static void mh_element(const grid_ctx* g, int ex, int ey, double dt, int blend, 
                         int en = nbr_elem(g, ex, ey, d, 1);
                         int kn = d == 0 ? q * nd + 0 : 0 * nd + p;
                         const double* gh = en < 0 ? ghost_at(g, ex, ey, d, 1, d == 0 ? q : p) : NULL;
+                        const int wl = en < 0 && wall(c, d, 1);
                         for (int v = 0; v < M; ++v)
-                            up[v] = en >= 0 ? g->u[gidx(g, v, en, kn)] : (gh ? gh[v] : u[v]);
+                            up[v] = en >= 0 ? g->u[gidx(g, v, en, kn)]
+                                  : (gh ? gh[v] : (wl ? mirror_sign(c->eq, d, v) * u[v] : u[v]));
                         xp = 1.0 + r->xi[0];
                     }
                     for (int v = 0; v < M; ++v) {
@@ -1065,13 +1085,20 @@ int ref_step(const ref_config* c, const double* u_in, double* u_out, double dt,
                 }
                 /* boundary ghost values (Sec. 3.3): outflow copies the interior
                  * side, so F = F^+ (F^-); far-field takes a time-constant state g,
-                 * u^- = U^- = g and F^- = f(g) */
+                 * u^- = U^- = g and F^- = f(g); a solid wall mirrors the interior
+                 * side (eq. reflect.time.avg) */
+                const int wA = !A && wall(c, d, 0), wB = !B && wall(c, d, 1);
                 const double* gA = !A ? ghost_at(&g, ex, ey, d, 0, t) : NULL;
                 const double* gB = !B ? ghost_at(&g, d == 0 ? ex - 1 : ex, d == 0 ? ey : ey - 1, d, 1, t) : NULL;
                 if (!A) {
                     if (gA) {
                         phys_flux(c, d, gA, Fm);
                         for (int v = 0; v < M; ++v) { Um[v] = gA[v]; unm[v] = gA[v]; }
+                    } else if (wA) {
+                        for (int v = 0; v < M; ++v) {
+                            double s = mirror_sign(c->eq, d, v);
+                            Fm[v] = -s * Fp[v]; Um[v] = s * Up[v]; unm[v] = s * unp[v];
+                        }
                     } else {
                         for (int v = 0; v < M; ++v) { Fm[v] = Fp[v]; Um[v] = Up[v]; unm[v] = unp[v]; }
                     }
@@ -1080,6 +1107,11 @@ int ref_step(const ref_config* c, const double* u_in, double* u_out, double dt,
                     if (gB) {
                         phys_flux(c, d, gB, Fp);
                         for (int v = 0; v < M; ++v) { Up[v] = gB[v]; unp[v] = gB[v]; }
+                    } else if (wB) {
+                        for (int v = 0; v < M; ++v) {
+                            double s = mirror_sign(c->eq, d, v);
+                            Fp[v] = -s * Fm[v]; Up[v] = s * Um[v]; unp[v] = s * unm[v];
+                        }
                     } else {
                         for (int v = 0; v < M; ++v) { Fp[v] = Fm[v]; Up[v] = Um[v]; unp[v] = unm[v]; }
                     }
@@ -1092,8 +1124,8 @@ int ref_step(const ref_config* c, const double* u_in, double* u_out, double dt,
                     if (A) uA[v] = u_in[gidx(&g, v, eL, kA)];
                     if (B) uB[v] = u_in[gidx(&g, v, eR, kB)];
                 }
-                if (!A) for (int v = 0; v < M; ++v) uA[v] = gA ? gA[v] : uB[v];
-                if (!B) for (int v = 0; v < M; ++v) uB[v] = gB ? gB[v] : uA[v];
+                if (!A) for (int v = 0; v < M; ++v) uA[v] = gA ? gA[v] : (wA ? mirror_sign(c->eq, d, v) : 1.0) * uB[v];
+                if (!B) for (int v = 0; v < M; ++v) uB[v] = gB ? gB[v] : (wB ? mirror_sign(c->eq, d, v) : 1.0) * uA[v];
                 double lam = fmax(sigma_trace(c, d, unm, uA), sigma_trace(c, d, unp, uB));
                 double F[MM];
                 for (int v = 0; v < M; ++v) F[v] = 0.5 * (Fm[v] + Fp[v]) - 0.5 * lam * (Up[v] - Um[v]);
@@ -1105,8 +1137,8 @@ int ref_step(const ref_config* c, const double* u_in, double* u_out, double dt,
                         if (A) sA[v] = d == 0 ? mh[eL].xp[kA][v] : mh[eL].yp[kA][v];
                         if (B) sB[v] = d == 0 ? mh[eR].xm[kB][v] : mh[eR].ym[kB][v];
                     }
-                    if (!A) for (int v = 0; v < M; ++v) sA[v] = gA ? gA[v] : sB[v];
-                    if (!B) for (int v = 0; v < M; ++v) sB[v] = gB ? gB[v] : sA[v];
+                    if (!A) for (int v = 0; v < M; ++v) sA[v] = gA ? gA[v] : (wA ? mirror_sign(c->eq, d, v) : 1.0) * sB[v];
+                    if (!B) for (int v = 0; v < M; ++v) sB[v] = gB ? gB[v] : (wB ? mirror_sign(c->eq, d, v) : 1.0) * sA[v];
                     rusanov(c, d, sA, sB, fLO);   /* eq. mh.at.face (fo.at.face when FO) */
                     double af = A && B ? 0.5 * (alpha[eL] + alpha[eR]) : alpha[A ? eL : eR];
                     for (int v = 0; v < M; ++v) F[v] = (1.0 - af) * F[v] + af * fLO[v];   /* eq. Fblend */

@@ -23,7 +23,7 @@ extern "C" {
 #define REF_MAXM 6
 
 enum { REF_LINADV1D = 0, REF_EULER1D = 1, REF_EULER2D = 2, REF_TENMOM2D = 3 };
-enum { REF_BC_PERIODIC = 0, REF_BC_OUTFLOW = 1, REF_BC_FARFIELD = 2 };
+enum { REF_BC_PERIODIC = 0, REF_BC_OUTFLOW = 1, REF_BC_FARFIELD = 2, REF_BC_REFLECT = 3 };
 enum { REF_BLEND_OFF = 0, REF_BLEND_FO = 1, REF_BLEND_MH = 2 };
 enum { REF_IND_PAPER = 0, REF_IND_CONST = 1, REF_IND_GIVEN = 2, REF_IND_LEARNED = 3 };
 
