@@ -46,8 +46,12 @@ enum { CRKFR_LINADV1D = 0, CRKFR_EULER1D = 1, CRKFR_EULER2D = 2, CRKFR_TENMOM2D 
  * interior side, so the boundary flux is the interior time-averaged flux, the
  * paper's rule for fully outflow boundaries); far-field (ghost state fixed to
  * the boundary traces of the state given to crkfr_set_state, used through the
- * D2 numerical flux, the paper's inflow rule with a time-constant state) */
-enum { CRKFR_BC_PERIODIC = 0, CRKFR_BC_OUTFLOW = 1, CRKFR_BC_FARFIELD = 2 };
+ * D2 numerical flux, the paper's inflow rule with a time-constant state);
+ * solid wall (eq. reflect.time.avg: the ghost traces mirror the interior
+ * ones — normal momentum, and the ten-moment E12, change sign in u and U,
+ * the other components in F — and the subcell ghosts mirror the boundary
+ * subcell; Euler and ten-moment only) */
+enum { CRKFR_BC_PERIODIC = 0, CRKFR_BC_OUTFLOW = 1, CRKFR_BC_FARFIELD = 2, CRKFR_BC_REFLECT = 3 };
 
 /* arithmetic: FP64 throughout, or FP32 bulk with FP64 element means and
  * FP64 admissibility roots (the state is held as FP64 means plus FP32

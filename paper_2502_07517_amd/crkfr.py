@@ -10,7 +10,7 @@ import os
 import numpy as np
 
 LINADV1D, EULER1D, EULER2D, TENMOM2D = 0, 1, 2, 3
-PERIODIC, OUTFLOW, FARFIELD = 0, 1, 2
+PERIODIC, OUTFLOW, FARFIELD, REFLECT = 0, 1, 2, 3
 FP64, MP32 = 0, 1
 BLEND_OFF, BLEND_FO, BLEND_MH = 0, 1, 2
 IND_PAPER, IND_CONST, IND_GIVEN, IND_LEARNED = 0, 1, 2, 3

@@ -490,7 +490,10 @@ extern "C" int crkfr_create(const crkfr_config* cfg, void* hip_stream, crkfr_sol
     if (cfg->nx < 1 || cfg->ny < 1 || (dim == 1 && cfg->ny != 1)) return fail(CRKFR_EINVAL, "bad grid size");
     if (cfg->dtype != CRKFR_FP64 && cfg->dtype != CRKFR_MP32) return fail(CRKFR_EINVAL, "bad dtype");
     for (int i = 0; i < (dim == 2 ? 4 : 2); ++i)
-        if (cfg->bc[i] < 0 || cfg->bc[i] > 2) return fail(CRKFR_EINVAL, "bad boundary kind");
+        if (cfg->bc[i] < 0 || cfg->bc[i] > 3) return fail(CRKFR_EINVAL, "bad boundary kind");
+    for (int i = 0; i < (dim == 2 ? 4 : 2); ++i)
+        if (cfg->bc[i] == CRKFR_BC_REFLECT && cfg->equation == CRKFR_LINADV1D)
+            return fail(CRKFR_EINVAL, "solid walls are defined for the Euler and ten-moment systems");
     if ((cfg->bc[0] == CRKFR_BC_PERIODIC) != (cfg->bc[1] == CRKFR_BC_PERIODIC) ||
         (dim == 2 && (cfg->bc[2] == CRKFR_BC_PERIODIC) != (cfg->bc[3] == CRKFR_BC_PERIODIC)))
         return fail(CRKFR_EINVAL, "periodic boundaries come in pairs");

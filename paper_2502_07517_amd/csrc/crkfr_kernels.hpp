@@ -33,7 +33,7 @@
 namespace crkfr {
 
 constexpr int MAXND = 5;
-enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_FARFIELD = 2 };
+enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_FARFIELD = 2, BC_REFLECT = 3 };
 enum { BLEND_OFF = 0, BLEND_FO = 1, BLEND_MH = 2 };
 enum { IND_PAPER = 0, IND_CONST = 1, IND_GIVEN = 2, IND_LEARNED = 3 };
 enum { D_TROUBLED = 0, D_FLUXLIM, D_LOBAD, D_SLOPELIM, D_FALLBACK, D_SCALED, D_MEANBAD, D_LFALLBACK,
@@ -165,6 +165,21 @@ __device__ __forceinline__ const real* ghost_at(const StepArgs<real>& a, int M, 
     return a.ghost + 2 * xsz + side * ysz + ((size_t)ex * nd + t) * M;
 }
 
+// solid wall normal to direction dir (Sec. 3.3, eq. reflect.time.avg): the
+// ghost mirrors the interior state, flipping the normal momentum (and the
+// ten-moment E12); the mirrored normal flux is -(mirror of the flux)
+template <class real>
+__device__ __forceinline__ bool is_wall(const StepArgs<real>& a, int dir, int side)
+{
+    return a.bc[dir * 2 + side] == BC_REFLECT;
+}
+
+template <class Eq>
+__device__ __forceinline__ constexpr bool mirror_flips(int dir, int v)
+{
+    return v == 1 + dir || (Eq::ID == 3 && v == 4);
+}
+
 // ----------------------------------------------------------------------------
 // admissibility helpers (FP64)
 // ----------------------------------------------------------------------------
@@ -281,6 +296,9 @@ __device__ void mh_subcell(const StepArgs<real>& a, int e, int ex, int ey, int p
                     if (g) {
 #pragma unroll
                         for (int v = 0; v < M; ++v) um[v] = g[v];
+                    } else if (is_wall(a, d, 0)) {
+#pragma unroll
+                        for (int v = 0; v < M; ++v) um[v] = mirror_flips<Eq>(d, v) ? -u[v] : u[v];
                     } else {
 #pragma unroll
                         for (int v = 0; v < M; ++v) um[v] = u[v];
@@ -300,6 +318,9 @@ __device__ void mh_subcell(const StepArgs<real>& a, int e, int ex, int ey, int p
                     if (g) {
 #pragma unroll
                         for (int v = 0; v < M; ++v) up[v] = g[v];
+                    } else if (is_wall(a, d, 1)) {
+#pragma unroll
+                        for (int v = 0; v < M; ++v) up[v] = mirror_flips<Eq>(d, v) ? -u[v] : u[v];
                     } else {
 #pragma unroll
                         for (int v = 0; v < M; ++v) up[v] = u[v];
@@ -883,12 +904,22 @@ __device__ void face_body(const StepArgs<real>& a, int vblock)
         sp = TRB(2 * M);
         load_node<Eq>(a, np, eR, kB, uB);
     }
+    const bool wA = !hA && is_wall(a, D, 0), wB = !hB && is_wall(a, D, 1);
     if (!hA) {
         if (gA) {
             flux_dir<Eq>(D, gA, Fm, P);
 #pragma unroll
             for (int v = 0; v < M; ++v) { Um[v] = gA[v]; uA[v] = gA[v]; }
             sm = Eq::sig_trace(D, gA, gA, P);
+        } else if (wA) {
+#pragma unroll
+            for (int v = 0; v < M; ++v) {
+                const bool fl = mirror_flips<Eq>(D, v);
+                Fm[v] = fl ? Fp[v] : -Fp[v];
+                Um[v] = fl ? -Up[v] : Up[v];
+                uA[v] = fl ? -uB[v] : uB[v];
+            }
+            sm = sp;
         } else {
 #pragma unroll
             for (int v = 0; v < M; ++v) { Fm[v] = Fp[v]; Um[v] = Up[v]; uA[v] = uB[v]; }
@@ -901,6 +932,15 @@ __device__ void face_body(const StepArgs<real>& a, int vblock)
 #pragma unroll
             for (int v = 0; v < M; ++v) { Up[v] = gB[v]; uB[v] = gB[v]; }
             sp = Eq::sig_trace(D, gB, gB, P);
+        } else if (wB) {
+#pragma unroll
+            for (int v = 0; v < M; ++v) {
+                const bool fl = mirror_flips<Eq>(D, v);
+                Fp[v] = fl ? Fm[v] : -Fm[v];
+                Up[v] = fl ? -Um[v] : Um[v];
+                uB[v] = fl ? -uA[v] : uA[v];
+            }
+            sp = sm;
         } else {
 #pragma unroll
             for (int v = 0; v < M; ++v) { Fp[v] = Fm[v]; Up[v] = Um[v]; uB[v] = uA[v]; }
@@ -924,11 +964,11 @@ __device__ void face_body(const StepArgs<real>& a, int vblock)
         }
         if (!hA) {
 #pragma unroll
-            for (int v = 0; v < M; ++v) sA[v] = gA ? gA[v] : sB[v];
+            for (int v = 0; v < M; ++v) sA[v] = gA ? gA[v] : (wA && mirror_flips<Eq>(D, v) ? -sB[v] : sB[v]);
         }
         if (!hB) {
 #pragma unroll
-            for (int v = 0; v < M; ++v) sB[v] = gB ? gB[v] : sA[v];
+            for (int v = 0; v < M; ++v) sB[v] = gB ? gB[v] : (wB && mirror_flips<Eq>(D, v) ? -sA[v] : sA[v]);
         }
         rusanov<Eq>(D, sA, sB, fLO, P);
         double aA = hA ? alpha_smoothed(a, eL, Eq::DIM) : 0.0;

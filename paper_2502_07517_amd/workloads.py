@@ -93,6 +93,27 @@ def euler1d_riemann(seed, nx, N, x0=0.0, x1=1.0, xs=None, gamma=GAMMA):
     return euler1d_cons(rho, v, p, gamma)
 
 
+def euler1d_cons(rho, v, p, gamma=GAMMA):
+    return np.stack([rho, rho * v, p / (gamma - 1.0) + 0.5 * rho * v * v])
+
+
+def blast1d(nx, N):
+    """Woodward-Colella blast wave on [0, 1] (Sec. 5.2): p = 1000, 0.01, 100
+    left of 0.1, between, right of 0.9; rho = 1, v = 0."""
+    x = node_coords_1d(nx, N, 0.0, 1.0)
+    p = np.where(x < 0.1, 1000.0, np.where(x > 0.9, 100.0, 0.01))
+    return euler1d_cons(np.ones_like(x), np.zeros_like(x), p)
+
+
+def sedov1d(nx, N, gamma=GAMMA):
+    """1D Sedov blast on [-1, 1] (Sec. 5.2): rho = 1, v = 0, E = 3.2e6/dx in
+    the element around x = 0 and 1e-12 elsewhere (nx odd)."""
+    x = node_coords_1d(nx, N, -1.0, 1.0)
+    dx = 2.0 / nx
+    E = np.where(np.abs(x) <= dx / 2, 3.2e6 / dx, 1e-12)
+    return np.stack([np.ones_like(x), np.zeros_like(x), E])
+
+
 # ---------------------------------------------------------------- 2D Euler
 def vortex_prim(X, Y, t=0.0, dom=(-5.0, 5.0, -5.0, 5.0), beta=5.0, mach=0.5,
                 angle_deg=45.0, gamma=GAMMA):
@@ -116,6 +137,19 @@ def vortex2d(n, N, t=0.0, dom=(-5.0, 5.0, -5.0, 5.0), gamma=GAMMA):
     X, Y = node_coords_2d(n, n, N, dom)
     rho, v1, v2, p = vortex_prim(X, Y, t, dom, gamma=gamma)
     return euler2d_cons(rho, v1, v2, p, gamma)
+
+
+def sedov2d(n, N, dom=(-1.5, 1.5, -1.5, 1.5), gamma=GAMMA):
+    """2D Sedov test of Sec. 5.3 on a periodic square: gas at rest, Gaussian
+    density and pressure bumps (sigma_rho 0.25, sigma_p 0.15) over rho0 = 1,
+    p0 = 1e-5."""
+    X, Y = node_coords_2d(n, n, N, dom)
+    r2 = X * X + Y * Y
+    sr, sp = 0.25, 0.15
+    rho = 1.0 + np.exp(-r2 / (2 * sr * sr)) / (4 * np.pi * sr * sr)
+    p = 1e-5 + (gamma - 1.0) * np.exp(-r2 / (2 * sp * sp)) / (4 * np.pi * sp * sp)
+    z = np.zeros_like(X)
+    return euler2d_cons(rho, z, z, p, gamma)
 
 
 def quadrant_states_euler(seed, rho_rng=(0.1, 2.0), v_rng=(-1.0, 1.0), p_rng=(0.1, 2.0)):
