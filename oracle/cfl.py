@@ -17,13 +17,18 @@ radius <= 1 + tol for every wavenumber and every speed ratio a/lambda in the
 given set.  With the ratio 1 (upwind, a scalar linear flux) this is the table
 the paper refers to; for systems, where the Rusanov speed exceeds the speed of
 all but the fastest field, the ratios span [0, 1].
+
+With the D1 dissipation (eq. D1) the dissipative part acts on the solution
+at the current time instead of the time average: the face operators split
+into a central part applied to U = P u and a dissipative part applied to u.
+D-CSX (eq. dcsx) equals D2 for a linear flux.
 """
 import numpy as np
 
 from .oracle import gl, diff_matrix, lagrange_at, tableau
 
 
-def amplification_matrix(N, s, nu, kappa, ratio=1.0):
+def amplification_matrix(N, s, nu, kappa, ratio=1.0, d1=False):
     xi, w = gl(N)
     D = diff_matrix(N, xi)
     l0 = lagrange_at(N, xi, 0.0)
@@ -39,31 +44,34 @@ def amplification_matrix(N, s, nu, kappa, ratio=1.0):
         R.append(Ri)
     P = sum(b[i] * R[i] for i in range(s))
     E = np.exp(1j * kappa)
-    FR = 0.5 * nu_a * (l1 + E * l0) - 0.5 * nu * (E * l0 - l1)
-    FL = 0.5 * nu_a * (np.conj(E) * l1 + l0) - 0.5 * nu * (l0 - np.conj(E) * l1)
-    op = nu_a * D + np.outer(l1 / w, FR - nu_a * l1) - np.outer(l0 / w, FL - nu_a * l0)
-    return I - op @ P
+    FRc = 0.5 * nu_a * (l1 + E * l0)
+    FLc = 0.5 * nu_a * (np.conj(E) * l1 + l0)
+    FRd = -0.5 * nu * (E * l0 - l1)
+    FLd = -0.5 * nu * (l0 - np.conj(E) * l1)
+    central = nu_a * D + np.outer(l1 / w, FRc - nu_a * l1) - np.outer(l0 / w, FLc - nu_a * l0)
+    diss = np.outer(l1 / w, FRd) - np.outer(l0 / w, FLd)
+    return I - central @ P - diss @ (I if d1 else P)
 
 
-def max_growth(N, s, nu, nk=4096, ratios=(1.0,)):
+def max_growth(N, s, nu, nk=4096, ratios=(1.0,), d1=False):
     ks = np.linspace(0.0, 2.0 * np.pi, nk)
-    return max(np.max(np.abs(np.linalg.eigvals(amplification_matrix(N, s, nu, k, r))))
+    return max(np.max(np.abs(np.linalg.eigvals(amplification_matrix(N, s, nu, k, r, d1))))
                for r in ratios for k in ks)
 
 
 SYSTEM_RATIOS = tuple(np.linspace(0.0, 1.0, 21))
 
 
-def cfl_number(N, s=None, tol=1e-12, nk=4096, iters=50, ratios=(1.0,)):
+def cfl_number(N, s=None, tol=1e-12, nk=4096, iters=50, ratios=(1.0,), d1=False):
     """Largest stable nu by bisection on max_{k, ratio} rho(G) <= 1 + tol."""
     if s is None:
         s = min(N + 1, 4)
     lo, hi = 0.0, 1.0
-    while max_growth(N, s, hi, nk, ratios) <= 1.0 + tol:
+    while max_growth(N, s, hi, nk, ratios, d1) <= 1.0 + tol:
         hi *= 2.0
     for _ in range(iters):
         mid = 0.5 * (lo + hi)
-        if max_growth(N, s, mid, nk, ratios) <= 1.0 + tol:
+        if max_growth(N, s, mid, nk, ratios, d1) <= 1.0 + tol:
             lo = mid
         else:
             hi = mid

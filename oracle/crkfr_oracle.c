@@ -163,6 +163,8 @@ int ref_nvar(int eq)
     case REF_EULER1D: return 3;
     case REF_EULER2D: return 4;
     case REF_TENMOM2D: return 6;
+    case REF_BURGERS1D: return 1;
+    case REF_TENMOM1D: return 6;
     }
     return 0;
 }
@@ -174,11 +176,12 @@ int ref_nadm(int eq)
     case REF_EULER1D: return 2;
     case REF_EULER2D: return 2;
     case REF_TENMOM2D: return 3;
+    case REF_TENMOM1D: return 3;
     }
     return 0;
 }
 
-static int eq_dim(int eq) { return eq >= REF_EULER2D ? 2 : 1; }
+static int eq_dim(int eq) { return eq == REF_EULER2D || eq == REF_TENMOM2D ? 2 : 1; }
 
 static double euler_p(int eq, double gamma, const double* u)
 {
@@ -190,6 +193,8 @@ void ref_flux(int eq, double gamma, double adv, const double* u, double* f, doub
 {
     if (eq == REF_LINADV1D) {
         f[0] = adv * u[0];
+    } else if (eq == REF_BURGERS1D) {
+        f[0] = 0.5 * u[0] * u[0];
     } else if (eq == REF_EULER1D) {
         double v = u[1] / u[0], p = euler_p(eq, gamma, u);
         f[0] = u[1];
@@ -236,6 +241,8 @@ void ref_sigma(int eq, double gamma, double adv, const double* u, double* sx, do
 {
     if (eq == REF_LINADV1D) {
         *sx = fabs(adv); *sy = 0.0;
+    } else if (eq == REF_BURGERS1D) {
+        *sx = fabs(u[0]); *sy = 0.0;
     } else if (eq == REF_EULER1D) {
         double p = euler_p(eq, gamma, u);
         *sx = fabs(u[1] / u[0]) + sqrt(gamma * p / u[0]);
@@ -267,7 +274,8 @@ double ref_adm(int eq, int k, double gamma, const double* u)
 }
 
 /* P_k concave once P_j > 0 for j < k: true for all but the determinant */
-static int adm_concave(int eq, int k) { return !(eq == REF_TENMOM2D && k == 2); }
+static int is_tenmom(int eq) { return eq == REF_TENMOM2D || eq == REF_TENMOM1D; }
+static int adm_concave(int eq, int k) { return !(is_tenmom(eq) && k == 2); }
 
 /* ten-moment source s^x + s^y (eq. tenmom.source) with the potential
  * W = A exp(-kappa ((x-xc)^2 + (y-yc)^2)) + gx x + gy y */
@@ -275,8 +283,9 @@ static void source_at(const ref_config* c, double x, double y, const double* u, 
 {
     int M = ref_nvar(c->eq);
     for (int v = 0; v < M; ++v) s[v] = 0.0;
-    if (!c->source || c->eq != REF_TENMOM2D) return;
-    double dx = x - c->src_xc, dy = y - c->src_yc;
+    if (!c->source || !is_tenmom(c->eq)) return;
+    /* the 1D system: W depends on x only */
+    double dx = x - c->src_xc, dy = c->eq == REF_TENMOM2D ? y - c->src_yc : 0.0;
     double W = c->src_amp * exp(-c->src_kappa * (dx * dx + dy * dy));
     double Wx = -2.0 * c->src_kappa * dx * W + c->src_gx;
     double Wy = -2.0 * c->src_kappa * dy * W + c->src_gy;
@@ -295,8 +304,9 @@ static void source_at(const ref_config* c, double x, double y, const double* u, 
 static double sigma_trace(const ref_config* c, int dir, const double* tr, const double* node)
 {
     int eq = c->eq;
-    const double* u = tr[0] > 0.0 || eq == REF_LINADV1D ? tr : node;
+    const double* u = tr[0] > 0.0 || eq == REF_LINADV1D || eq == REF_BURGERS1D ? tr : node;
     if (eq == REF_LINADV1D) return fabs(c->adv);
+    if (eq == REF_BURGERS1D) return fabs(u[0]);
     double r = u[0], v1 = u[1] / r;
     if (eq == REF_EULER1D || eq == REF_EULER2D) {
         double p = euler_p(eq, c->gamma, u);
@@ -384,6 +394,8 @@ typedef struct {
     double unxL[ND][MM], unxR[ND][MM], unyB[ND][MM], unyT[ND][MM];
     /* extrapolated discontinuous time-averaged flux F^delta(0), F^delta(1) */
     double FhL[ND][MM], FhR[ND][MM], GhB[ND][MM], GhT[ND][MM];
+    /* stage values at the faces, u^(i)(x^+-) (D-CSX dissipation, eq. dcsx) */
+    double uixL[4][ND][MM], uixR[4][ND][MM], uiyB[4][ND][MM], uiyT[4][ND][MM];
 } local_out;
 
 static void local_crk(const ref_config* c, const refel* r, const double* ue, double dt,
@@ -449,6 +461,8 @@ static void local_crk(const ref_config* c, const refel* r, const double* ue, dou
             for (int v = 0; v < M; ++v) {
                 o->FxL[q][v] += b[i] * fL[v];
                 o->FxR[q][v] += b[i] * fR[v];
+                o->uixL[i][q][v] = uL[v];
+                o->uixR[i][q][v] = uR[v];
                 if (i == 0) { o->unxL[q][v] = uL[v]; o->unxR[q][v] = uR[v]; }
             }
         }
@@ -467,6 +481,8 @@ static void local_crk(const ref_config* c, const refel* r, const double* ue, dou
                 for (int v = 0; v < M; ++v) {
                     o->GyB[p][v] += b[i] * gB[v];
                     o->GyT[p][v] += b[i] * gT[v];
+                    o->uiyB[i][p][v] = uB[v];
+                    o->uiyT[i][p][v] = uT[v];
                     if (i == 0) { o->unyB[p][v] = uB[v]; o->unyT[p][v] = uT[v]; }
                 }
             }
@@ -517,7 +533,7 @@ void ref_local_crk(const ref_config* c, const double* ue, double dt, double xe0,
 
 static double indicator_quantity(const ref_config* c, const double* u)
 {
-    if (c->eq == REF_LINADV1D) return u[0];
+    if (c->eq == REF_LINADV1D || c->eq == REF_BURGERS1D) return u[0];
     if (c->eq == REF_EULER1D || c->eq == REF_EULER2D) return u[0] * euler_p(c->eq, c->gamma, u);
     double r = u[0], v1 = u[1] / r, v2 = u[2] / r;
     double P11 = 2.0 * u[3] - r * v1 * v1;
@@ -683,6 +699,110 @@ double ref_scale_element(const ref_config* c, double* ue, int* mean_bad)
 /* Means and time step (eqs. upmean, time.step.2d)                      */
 /* ------------------------------------------------------------------ */
 
+/* ------------------------------------------------------------------ */
+/* The scheme in its stage form (eq. crkfr): the inner stages are the local
+ * evolutions, the final stage applies the FR derivative (with a Rusanov
+ * flux per stage at every face, eq. num.flux.fr) to each stage's flux and
+ * combines them with b_i.  Periodic boundaries, no limiter, no source.    */
+/* ------------------------------------------------------------------ */
+
+static size_t sidx(int M, int np, int e, int k, int v) { return ((size_t)e * np + k) * M + v; }
+
+void ref_step_crkfr_form(const ref_config* c, const double* u_in, double* u_out, double dt)
+{
+    refel r;
+    refel_init(&r, c->N);
+    const int M = ref_nvar(c->eq), nd = r.nd, dim = eq_dim(c->eq), N = c->N;
+    const int nq = dim == 2 ? nd : 1, np = nd * nq, nx = c->nx, ny = c->ny, ne = nx * ny;
+    const double dx = (c->x1 - c->x0) / nx, dy = dim == 2 ? (c->y1 - c->y0) / ny : 1.0;
+    const int S = c->stages;
+    double ta[16], tb[4], tc[4];
+    ref_tableau(S, ta, tb, tc);
+    const size_t tot = (size_t)ne * np * M;
+    double* st = (double*)calloc((size_t)S * tot, sizeof(double));    /* stage values [i][e][k][v] */
+    double* loc = (double*)calloc((size_t)S * tot, sizeof(double));   /* local derivative [i][e][k][v] */
+    double* un = (double*)malloc(tot * sizeof(double));
+    for (int e = 0; e < ne; ++e)
+        for (int k = 0; k < np; ++k)
+            for (int v = 0; v < M; ++v) un[sidx(M, np, e, k, v)] = u_in[((size_t)v * ne + e) * np + k];
+    for (int i = 0; i < S; ++i) {
+        double* si = st + (size_t)i * tot;
+        for (size_t z = 0; z < tot; ++z) {
+            double val = un[z];
+            for (int j = 0; j < i; ++j) val -= dt * ta[i * 4 + j] * loc[(size_t)j * tot + z];
+            si[z] = val;
+        }
+        double* li = loc + (size_t)i * tot;
+        for (int e = 0; e < ne; ++e)
+            for (int q = 0; q < nq; ++q)
+                for (int p = 0; p < nd; ++p) {
+                    double dfx[MM] = {0}, dgy[MM] = {0}, f[MM], g[MM];
+                    for (int m = 0; m < nd; ++m) {
+                        ref_flux(c->eq, c->gamma, c->adv, &si[sidx(M, np, e, q * nd + m, 0)], f, g);
+                        for (int v = 0; v < M; ++v) dfx[v] += r.D[p * nd + m] * f[v];
+                        if (dim == 2) {
+                            ref_flux(c->eq, c->gamma, c->adv, &si[sidx(M, np, e, m * nd + p, 0)], f, g);
+                            for (int v = 0; v < M; ++v) dgy[v] += r.D[q * nd + m] * g[v];
+                        }
+                    }
+                    for (int v = 0; v < M; ++v)
+                        li[sidx(M, np, e, q * nd + p, v)] = dfx[v] / dx + (dim == 2 ? dgy[v] / dy : 0.0);
+                }
+    }
+    /* final stage: u^{n+1} = u^n - dt sum_i b_i D_FR f(u^(i)) */
+    for (size_t z = 0; z < tot; ++z) u_out[z] = 0.0;
+    double* res = (double*)calloc(tot, sizeof(double));
+    for (int i = 0; i < S; ++i) {
+        const double* si = st + (size_t)i * tot;
+        for (size_t z = 0; z < tot; ++z) res[z] += tb[i] * loc[(size_t)i * tot + z];
+        for (int d = 0; d < dim; ++d) {
+            const int nlines = d == 0 ? nq : nd;
+            const double h = d == 0 ? dx : dy;
+            for (int e = 0; e < ne; ++e) {
+                const int ex = e % nx, ey = e / nx;
+                const int en = d == 0 ? ey * nx + (ex + 1) % nx : ((ey + 1) % ny) * nx + ex;   /* high-side neighbour */
+                for (int t = 0; t < nlines; ++t) {
+                    /* face between e (left/bottom) and en: traces, nodal-flux extrapolations */
+                    double um[MM] = {0}, up[MM] = {0}, fhm[MM] = {0}, fhp[MM] = {0}, f[MM], g[MM], fm[MM], fp[MM];
+                    for (int m = 0; m < nd; ++m) {
+                        const int km = d == 0 ? t * nd + m : m * nd + t;
+                        ref_flux(c->eq, c->gamma, c->adv, &si[sidx(M, np, e, km, 0)], f, g);
+                        for (int v = 0; v < M; ++v) {
+                            um[v] += r.l1[m] * si[sidx(M, np, e, km, v)];
+                            fhm[v] += r.l1[m] * (d == 0 ? f[v] : g[v]);
+                        }
+                        ref_flux(c->eq, c->gamma, c->adv, &si[sidx(M, np, en, km, 0)], f, g);
+                        for (int v = 0; v < M; ++v) {
+                            up[v] += r.l0[m] * si[sidx(M, np, en, km, v)];
+                            fhp[v] += r.l0[m] * (d == 0 ? f[v] : g[v]);
+                        }
+                    }
+                    phys_flux(c, d, um, fm);
+                    phys_flux(c, d, up, fp);
+                    const int kA = d == 0 ? t * nd + N : N * nd + t, kB = d == 0 ? t * nd : t;
+                    const double lam = fmax(sigma_trace(c, d, um, &un[sidx(M, np, e, kA, 0)]),
+                                            sigma_trace(c, d, up, &un[sidx(M, np, en, kB, 0)]));
+                    double Fs[MM];
+                    for (int v = 0; v < M; ++v) Fs[v] = 0.5 * (fm[v] + fp[v]) - 0.5 * lam * (up[v] - um[v]);
+                    /* correction of e at its high face and of en at its low face */
+                    for (int m = 0; m < nd; ++m) {
+                        const int km = d == 0 ? t * nd + m : m * nd + t;
+                        for (int v = 0; v < M; ++v) {
+                            res[sidx(M, np, e, km, v)] += tb[i] * (Fs[v] - fhm[v]) * (r.l1[m] / r.w[m]) / h;
+                            res[sidx(M, np, en, km, v)] -= tb[i] * (Fs[v] - fhp[v]) * (r.l0[m] / r.w[m]) / h;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    for (int e = 0; e < ne; ++e)
+        for (int k = 0; k < np; ++k)
+            for (int v = 0; v < M; ++v)
+                u_out[((size_t)v * ne + e) * np + k] = un[sidx(M, np, e, k, v)] - dt * res[sidx(M, np, e, k, v)];
+    free(st); free(loc); free(un); free(res);
+}
+
 void ref_means(const ref_config* c, const double* u, double* ubar)
 {
     refel r;
@@ -769,7 +889,7 @@ static int wall(const ref_config* c, int dir, int side)
 static double mirror_sign(int eq, int d, int v)
 {
     if (v == 1 + d) return -1.0;
-    if (eq == REF_TENMOM2D && v == 4) return -1.0;
+    if (is_tenmom(eq) && v == 4) return -1.0;
     return 1.0;
 }
 
@@ -1074,13 +1194,16 @@ int ref_step(const ref_config* c, const double* u_in, double* u_out, double dt,
                 double Fm[MM], Fp[MM], Um[MM], Up[MM], unm[MM], unp[MM];
                 const local_out* A = eL >= 0 ? &lo[eL] : NULL;
                 const local_out* B = eR >= 0 ? &lo[eR] : NULL;
+                /* central part: EA traces (eq. evaluate) or the extrapolated
+                 * averaged flux (eq. extrapolate) */
+                const int ae = c->central == REF_CENTRAL_AE;
                 for (int v = 0; v < M; ++v) {
                     if (d == 0) {
-                        if (A) { Fm[v] = A->FxR[t][v]; Um[v] = A->UxR[t][v]; unm[v] = A->unxR[t][v]; }
-                        if (B) { Fp[v] = B->FxL[t][v]; Up[v] = B->UxL[t][v]; unp[v] = B->unxL[t][v]; }
+                        if (A) { Fm[v] = ae ? A->FhR[t][v] : A->FxR[t][v]; Um[v] = A->UxR[t][v]; unm[v] = A->unxR[t][v]; }
+                        if (B) { Fp[v] = ae ? B->FhL[t][v] : B->FxL[t][v]; Up[v] = B->UxL[t][v]; unp[v] = B->unxL[t][v]; }
                     } else {
-                        if (A) { Fm[v] = A->GyT[t][v]; Um[v] = A->UyT[t][v]; unm[v] = A->unyT[t][v]; }
-                        if (B) { Fp[v] = B->GyB[t][v]; Up[v] = B->UyB[t][v]; unp[v] = B->unyB[t][v]; }
+                        if (A) { Fm[v] = ae ? A->GhT[t][v] : A->GyT[t][v]; Um[v] = A->UyT[t][v]; unm[v] = A->unyT[t][v]; }
+                        if (B) { Fp[v] = ae ? B->GhB[t][v] : B->GyB[t][v]; Up[v] = B->UyB[t][v]; unp[v] = B->unyB[t][v]; }
                     }
                 }
                 /* boundary ghost values (Sec. 3.3): outflow copies the interior
@@ -1127,8 +1250,31 @@ int ref_step(const ref_config* c, const double* u_in, double* u_out, double dt,
                 if (!A) for (int v = 0; v < M; ++v) uA[v] = gA ? gA[v] : (wA ? mirror_sign(c->eq, d, v) : 1.0) * uB[v];
                 if (!B) for (int v = 0; v < M; ++v) uB[v] = gB ? gB[v] : (wB ? mirror_sign(c->eq, d, v) : 1.0) * uA[v];
                 double lam = fmax(sigma_trace(c, d, unm, uA), sigma_trace(c, d, unp, uB));
+                /* dissipative part: D2 (eq. D2), D1 (eq. D1) or D-CSX (eq. dcsx,
+                 * one wave speed per stage from that stage's face values) */
+                double Dis[MM];
+                if (c->dissipation == REF_DISS_DCSX) {
+                    double ta[16], tb[4], tc[4];
+                    ref_tableau(c->stages, ta, tb, tc);
+                    for (int v = 0; v < M; ++v) Dis[v] = 0.0;
+                    for (int i = 0; i < c->stages; ++i) {
+                        double um[MM], up[MM];
+                        for (int v = 0; v < M; ++v) {
+                            if (A) um[v] = d == 0 ? A->uixR[i][t][v] : A->uiyT[i][t][v];
+                            if (B) up[v] = d == 0 ? B->uixL[i][t][v] : B->uiyB[i][t][v];
+                        }
+                        if (!A) for (int v = 0; v < M; ++v) um[v] = gA ? gA[v] : (wA ? mirror_sign(c->eq, d, v) : 1.0) * up[v];
+                        if (!B) for (int v = 0; v < M; ++v) up[v] = gB ? gB[v] : (wB ? mirror_sign(c->eq, d, v) : 1.0) * um[v];
+                        double li = fmax(sigma_trace(c, d, um, uA), sigma_trace(c, d, up, uB));
+                        for (int v = 0; v < M; ++v) Dis[v] += tb[i] * 0.5 * li * (up[v] - um[v]);
+                    }
+                } else if (c->dissipation == REF_DISS_D1) {
+                    for (int v = 0; v < M; ++v) Dis[v] = 0.5 * lam * (unp[v] - unm[v]);
+                } else {
+                    for (int v = 0; v < M; ++v) Dis[v] = 0.5 * lam * (Up[v] - Um[v]);
+                }
                 double F[MM];
-                for (int v = 0; v < M; ++v) F[v] = 0.5 * (Fm[v] + Fp[v]) - 0.5 * lam * (Up[v] - Um[v]);
+                for (int v = 0; v < M; ++v) F[v] = 0.5 * (Fm[v] + Fp[v]) - Dis[v];
 
                 if (blend != REF_BLEND_OFF) {
                     /* predicted values at the face-adjacent subcells */

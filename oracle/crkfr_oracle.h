@@ -22,7 +22,12 @@ extern "C" {
 #define REF_MAXNP (REF_MAXND * REF_MAXND)
 #define REF_MAXM 6
 
-enum { REF_LINADV1D = 0, REF_EULER1D = 1, REF_EULER2D = 2, REF_TENMOM2D = 3 };
+enum { REF_LINADV1D = 0, REF_EULER1D = 1, REF_EULER2D = 2, REF_TENMOM2D = 3, REF_BURGERS1D = 4,
+       REF_TENMOM1D = 5 };
+/* dissipative part of the numerical flux (Sec. 3.1.1): eqs. D2, D1, dcsx */
+enum { REF_DISS_D2 = 0, REF_DISS_D1 = 1, REF_DISS_DCSX = 2 };
+/* central part (Sec. 3.1.2): eq. evaluate (EA) or eq. extrapolate (AE) */
+enum { REF_CENTRAL_EA = 0, REF_CENTRAL_AE = 1 };
 enum { REF_BC_PERIODIC = 0, REF_BC_OUTFLOW = 1, REF_BC_FARFIELD = 2, REF_BC_REFLECT = 3 };
 enum { REF_BLEND_OFF = 0, REF_BLEND_FO = 1, REF_BLEND_MH = 2 };
 enum { REF_IND_PAPER = 0, REF_IND_CONST = 1, REF_IND_GIVEN = 2, REF_IND_LEARNED = 3 };
@@ -45,6 +50,8 @@ typedef struct {
     const double* mlp_params;
     const double* mlp_lo;
     const double* mlp_hi;
+    int dissipation;      /* REF_DISS_* */
+    int central;          /* REF_CENTRAL_* */
 } ref_config;
 
 typedef struct {
@@ -105,6 +112,13 @@ void ref_boundary_traces(const ref_config* c, const double* u, double* ghost);
  * boundaries only) as written by ref_boundary_traces. */
 int ref_step(const ref_config* c, const double* u_in, double* u_out, double dt,
              const double* alpha_given, double* alpha_out, ref_diag* diag, const double* ghost);
+
+/* one step of the scheme in its stage form (eq. crkfr): every stage's flux
+ * goes through the FR derivative with its own Rusanov numerical flux at the
+ * faces, and the update combines the stages with the weights b_i; periodic
+ * boundaries, no limiter, no source.  Independent of ref_step; with the
+ * D-CSX dissipation and EA central part ref_step computes the same update. */
+void ref_step_crkfr_form(const ref_config* c, const double* u_in, double* u_out, double dt);
 
 /* element means [var][ey][ex] */
 void ref_means(const ref_config* c, const double* u, double* ubar);

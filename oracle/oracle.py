@@ -5,7 +5,9 @@ import subprocess
 
 import numpy as np
 
-LINADV1D, EULER1D, EULER2D, TENMOM2D = 0, 1, 2, 3
+LINADV1D, EULER1D, EULER2D, TENMOM2D, BURGERS1D, TENMOM1D = 0, 1, 2, 3, 4, 5
+DISS_D2, DISS_D1, DISS_DCSX = 0, 1, 2
+CENTRAL_EA, CENTRAL_AE = 0, 1
 PERIODIC, OUTFLOW, FARFIELD, REFLECT = 0, 1, 2, 3
 BLEND_OFF, BLEND_FO, BLEND_MH = 0, 1, 2
 IND_PAPER, IND_CONST, IND_GIVEN, IND_LEARNED = 0, 1, 2, 3
@@ -39,6 +41,7 @@ class RefConfig(ctypes.Structure):
         ("mlp_nl", ctypes.c_int), ("mlp_dims", ctypes.POINTER(ctypes.c_int)),
         ("mlp_params", ctypes.POINTER(ctypes.c_double)),
         ("mlp_lo", ctypes.POINTER(ctypes.c_double)), ("mlp_hi", ctypes.POINTER(ctypes.c_double)),
+        ("dissipation", ctypes.c_int), ("central", ctypes.c_int),
     ]
 
     @staticmethod
@@ -46,7 +49,8 @@ class RefConfig(ctypes.Structure):
              indicator=IND_PAPER, smooth_nbr=1, flux_limiter=0, scaling=0, source=0,
              domain=(0.0, 1.0, 0.0, 1.0), gamma=1.4, adv=1.0, cfl=0.0, cs=0.98,
              alpha_min=1e-3, alpha_max=1.0, alpha_const=0.0,
-             src=(0.0, 0.0, 0.0, 0.0), src_lin=(0.0, 0.0), mlp=None):
+             src=(0.0, 0.0, 0.0, 0.0), src_lin=(0.0, 0.0), mlp=None, dissipation=DISS_D2,
+             central=CENTRAL_EA):
         """mlp: (dims, params, lo, hi) of the learned indicator (dims[0] = N)."""
         c = RefConfig()
         c.eq, c.N, c.nx, c.ny = eq, N, nx, ny
@@ -60,6 +64,7 @@ class RefConfig(ctypes.Structure):
         c.alpha_min, c.alpha_max, c.alpha_const = alpha_min, alpha_max, alpha_const
         c.src_amp, c.src_kappa, c.src_xc, c.src_yc = src
         c.src_gx, c.src_gy = src_lin
+        c.dissipation, c.central = dissipation, central
         if mlp is not None:
             c.set_mlp(*mlp)
         return c
@@ -120,6 +125,7 @@ def lib():
         L.ref_step.argtypes = [cp, dp, dp, ctypes.c_double, dp, dp, ctypes.POINTER(RefDiag), dp]
         L.ref_boundary_traces.argtypes = [cp, dp, dp]
         L.ref_means.argtypes = [cp, dp, dp]
+        L.ref_step_crkfr_form.argtypes = [cp, dp, dp, ctypes.c_double]
         ip = ctypes.POINTER(ctypes.c_int)
         L.ref_indicator_features.argtypes = [cp, dp, dp]
         L.ref_learned_alpha.argtypes = [cp, dp, ctypes.POINTER(ctypes.c_int)]
@@ -195,9 +201,13 @@ def adm(eq, k, u, gamma=1.4):
     return lib().ref_adm(eq, k, gamma, _p(_f64(u)))
 
 
+def _is2d(eq):
+    return eq in (EULER2D, TENMOM2D)
+
+
 def _np(cfg):
     nd = cfg.N + 1
-    return nd * nd if cfg.eq >= EULER2D else nd
+    return nd * nd if _is2d(cfg.eq) else nd
 
 
 def local_crk(cfg, ue, dt, xe0=0.0, ye0=0.0):
@@ -251,8 +261,8 @@ def means(cfg, u):
 def boundary_traces(cfg, u):
     """Ghost states of far-field boundaries: the boundary traces of u."""
     M, nd = nvar(cfg.eq), cfg.N + 1
-    nq = nd if cfg.eq >= EULER2D else 1
-    n = 2 * cfg.ny * nq * M + (2 * cfg.nx * nd * M if cfg.eq >= EULER2D else 0)
+    nq = nd if _is2d(cfg.eq) else 1
+    n = 2 * cfg.ny * nq * M + (2 * cfg.nx * nd * M if _is2d(cfg.eq) else 0)
     g = np.zeros(n)
     lib().ref_boundary_traces(ctypes.byref(cfg), _p(_f64(u)), _p(g))
     return g
@@ -275,6 +285,14 @@ def step(cfg, u, dt, alpha_given=None, ghost=None):
     d = RefDiag()
     st = lib().ref_step(ctypes.byref(cfg), _p(u), _p(out), float(dt), _p(ag), _p(alpha), ctypes.byref(d), gp)
     return out, alpha, d.as_dict(), st
+
+
+def step_crkfr_form(cfg, u, dt):
+    """One step of the stage form (eq. crkfr); periodic, no limiter."""
+    u = _f64(u)
+    out = np.empty_like(u)
+    lib().ref_step_crkfr_form(ctypes.byref(cfg), _p(u), _p(out), float(dt))
+    return out
 
 
 def mlp_forward(dims, params, x):

@@ -93,8 +93,20 @@ def euler1d_riemann(seed, nx, N, x0=0.0, x1=1.0, xs=None, gamma=GAMMA):
     return euler1d_cons(rho, v, p, gamma)
 
 
-def euler1d_cons(rho, v, p, gamma=GAMMA):
-    return np.stack([rho, rho * v, p / (gamma - 1.0) + 0.5 * rho * v * v])
+def euler1d_smooth(seed, nx, N, x0=0.0, x1=1.0, amp=0.3, gamma=GAMMA):
+    """Periodic smooth Euler data: one sine mode with a seeded phase per field."""
+    ph = np.random.default_rng(seed).uniform(0.0, 1.0, 3)
+    x = (node_coords_1d(nx, N, x0, x1) - x0) / (x1 - x0)
+    rho = 1.0 + amp * np.sin(2 * np.pi * (x + ph[0]))
+    v = 0.5 + amp * np.sin(2 * np.pi * (x + ph[1]))
+    p = 1.0 + amp * np.cos(2 * np.pi * (x + ph[2]))
+    return euler1d_cons(rho, v, p, gamma)
+
+
+def burgers_sine(nx, N, amp=0.2, x0=0.0, x1=2 * np.pi, shift=0.0):
+    """Burgers data u0 = shift + amp sin(x) (the smooth Burgers test uses amp
+    0.2 on [0, 2 pi]: smooth until t = 1/amp = 5)."""
+    return (shift + amp * np.sin(node_coords_1d(nx, N, x0, x1)))[None].copy()
 
 
 def blast1d(nx, N):
@@ -294,6 +306,35 @@ def tenmom2d_smooth(seed, nx, ny, N, dom=(-2.0, 2.0, -0.5, 0.5), amp=0.1):
     rho, v1, v2 = field(1.0), field(0.2), field(-0.1)
     p11, p22, p12 = field(1.0), field(0.8), field(0.1)
     return tenmom_cons(rho, v1, v2, p11, p12, p22)
+
+
+# Two-rarefaction problem of the ten-moment system with the source (the 1D
+# system): (rho, v1, v2, P11, P12, P22) = (1, -4, 0, 9, 7, 9) left of the jump,
+# (1, 4, 0, 9, 7, 9) right of it; potential W = 25 exp(-200 (x - 2)^2).  The
+# domain [0, 4] with the jump at the potential's centre x = 2 (OFF_FACE of an
+# element to the right) is a reading: the paper gives no domain.
+TWO_RARE_SOURCE = (25.0, 200.0, 2.0, 0.0, 0.0, 0.0)   # amp, kappa, xc, yc, gx, gy
+
+
+def tenmom1d_two_rarefaction(nx, N, dom=(0.0, 4.0), xs=None):
+    x0, x1 = dom
+    if xs is None:
+        xs = 0.5 * (x0 + x1) + OFF_FACE * (x1 - x0) / nx
+    x = node_coords_1d(nx, N, x0, x1)
+    one = np.ones_like(x)
+    v1 = np.where(x < xs, -4.0, 4.0)
+    return tenmom_cons(one, v1, 0.0 * one, 9.0 * one, 7.0 * one, 9.0 * one)
+
+
+def tenmom1d_equilibrium(nx, N, dom=(0.0, 4.0), T=10.0, amp=25.0, kappa=200.0, xc=2.0):
+    """Rest state in the potential W = amp exp(-kappa (x - xc)^2): rho =
+    exp(-W / (2 T)), v = 0, P11 = P22 = rho T, P12 = 0, for which the x
+    momentum balance dP11/dx = -rho W_x / 2 of eq. tenmom.source holds."""
+    x = node_coords_1d(nx, N, dom[0], dom[1])
+    W = amp * np.exp(-kappa * (x - xc) ** 2)
+    rho = np.exp(-W / (2.0 * T))
+    z = 0.0 * rho
+    return tenmom_cons(rho, z, z, rho * T, z, rho * T)
 
 
 def batch_instances(seed, count, sides=(64, 512), degrees=(2, 3, 4)):

@@ -3,6 +3,11 @@ import sys
 
 import pytest
 
+# The oracle's OpenMP loops are tiny; under parallel test workers one thread
+# each avoids oversubscribing the cores (spinning threads slow every worker).
+if os.environ.get("PYTEST_XDIST_WORKER"):
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)

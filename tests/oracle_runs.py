@@ -12,7 +12,7 @@ _GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 def cfl_table(kind="cfl"):
     with open(os.path.join(_GOLD, "cfl.json")) as f:
         d = json.load(f)
-    return {(v["N"], v["stages"]): v[kind] for v in d.values()}
+    return {(v["N"], v["stages"]): v[kind] for v in d.values() if kind in v}
 
 
 def cfl_for(N, s=None, system=True):
