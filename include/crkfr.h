@@ -39,8 +39,21 @@ extern "C" {
 #define CRKFR_ESTATE (-6)              /* call order (e.g. step before set_state) */
 
 /* equations: scalar linear advection u_t + a u_x = 0 (Sec. 5.1.1), 1D Euler
- * (eq. 1deuler), 2D Euler (eq. 2deuler), ten-moment system (eq. tmp) */
-enum { CRKFR_LINADV1D = 0, CRKFR_EULER1D = 1, CRKFR_EULER2D = 2, CRKFR_TENMOM2D = 3 };
+ * (eq. 1deuler), 2D Euler (eq. 2deuler), ten-moment system (eq. tmp),
+ * Burgers' equation u_t + (u^2/2)_x = 0 (Sec. 5.1.3), and the ten-moment
+ * system in one dimension (the same six variables with x dependence only,
+ * as in the two-rarefaction test of Sec. 5.4.2) */
+enum { CRKFR_LINADV1D = 0, CRKFR_EULER1D = 1, CRKFR_EULER2D = 2, CRKFR_TENMOM2D = 3, CRKFR_BURGERS1D = 4,
+       CRKFR_TENMOM1D = 5 };
+
+/* dissipative part of the time-averaged numerical flux (Sec. 3.1.1): D2
+ * lambda/2 (U+ - U-) (eq. D2, the default), D1 lambda/2 (u+ - u-) with the
+ * current solution (eq. D1), D-CSX sum_i b_i lambda_i/2 (u(i)+ - u(i)-) with a
+ * wave speed per stage (eq. dcsx); central part (Sec. 3.1.2): EA traces
+ * sum_i b_i f(u(i)+-) (eq. evaluate, the default) or the extrapolated
+ * time-averaged flux (eq. extrapolate) */
+enum { CRKFR_DISS_D2 = 0, CRKFR_DISS_D1 = 1, CRKFR_DISS_DCSX = 2 };
+enum { CRKFR_CENTRAL_EA = 0, CRKFR_CENTRAL_AE = 1 };
 
 /* boundary kinds (Sec. 3.3): periodic; outflow (ghost values copy the
  * interior side, so the boundary flux is the interior time-averaged flux, the
@@ -120,6 +133,20 @@ typedef struct crkfr_mlp crkfr_mlp;
 int crkfr_create(const crkfr_config* cfg, void* hip_stream, crkfr_solver** out);
 void crkfr_destroy(crkfr_solver* s);
 
+/* Scheme options: number of cRK stages (0: min(N+1, 4), the paper's pairing;
+ * 2, 3, 4: cRK22, cRK33, cRK44 of eqs. crk22-crk44), dissipation and central
+ * part of the numerical flux.  When the configuration's cfl is <= 0 the CFL
+ * number is recomputed for the new options by the library's Fourier
+ * analysis.  Errors: EINVAL (bad option), ENOMEM (D-CSX keeps every stage's
+ * face values and may enlarge the trace buffers), ESTATE (the solver is a
+ * member of a live batch, which holds its buffers and options). */
+typedef struct {
+    int stages;
+    int dissipation;    /* CRKFR_DISS_* */
+    int central;        /* CRKFR_CENTRAL_* */
+} crkfr_scheme;
+int crkfr_set_scheme(crkfr_solver* s, const crkfr_scheme* opts);
+
 /* Limiter options (Sec. 4).  Default: blending off, no limiters. */
 int crkfr_set_limiter(crkfr_solver* s, const crkfr_limiter_opts* opts);
 
@@ -174,8 +201,10 @@ double crkfr_cfl_in_use(const crkfr_solver* s);
 /* CFL(N) by the library's Fourier analysis of the linear scheme (host only):
  * the largest lambda dt/dx with spectral radius <= 1 + tol for all wave
  * numbers; system = 0: wave speed equal to the dissipation speed (scalar
- * linear flux), system = 1: every ratio of wave to dissipation speed in [0,1]. */
-double crkfr_fourier_cfl(int N, int stages, int system, double tol);
+ * linear flux), system = 1: every ratio of wave to dissipation speed in [0,1];
+ * stages 0 = min(N+1, 4); dissipation CRKFR_DISS_* (D-CSX equals D2 for a
+ * linear flux).  Returns -1 for bad arguments. */
+double crkfr_fourier_cfl(int N, int stages, int system, int dissipation, double tol);
 
 /* Device time per kernel of the last step measured with HIP events (ms):
  * [0] local cRK, [1] x faces, [2] y faces, [3] update; needs timing = 1. */
@@ -189,7 +218,9 @@ int crkfr_get_kernel_times(crkfr_solver* s, float* ms4);
  * persistent workgroups walking a table of (instance, block) work items.  The
  * solvers stay owned by the caller, must have a state, and must not be used
  * on their own while the batch runs; call crkfr_batch_sync before reading
- * their state.  Each member keeps its own time step (eq. time.step.2d). */
+ * their state.  Members must outlive the batch; the batch keeps the options
+ * each member had at creation.  Each member keeps its own time step (eq.
+ * time.step.2d). */
 typedef struct crkfr_batch crkfr_batch;
 int crkfr_batch_create(crkfr_solver* const* solvers, int count, void* hip_stream, crkfr_batch** out);
 void crkfr_batch_destroy(crkfr_batch* b);

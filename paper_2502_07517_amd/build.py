@@ -10,7 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libcrkfr.so")
 SOURCES = ["crkfr_eq_linadv1d.hip", "crkfr_eq_euler1d.hip", "crkfr_eq_euler2d.hip",
-           "crkfr_eq_tenmom2d.hip", "crkfr_host.hip", "crkfr_mlp.hip"]
+           "crkfr_eq_tenmom2d.hip", "crkfr_eq_burgers1d.hip", "crkfr_eq_tenmom1d.hip", "crkfr_host.hip", "crkfr_mlp.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # FP32 division and square root at 1 ulp-level accuracy (v_rcp / v_sqrt)
 # instead of the correctly rounded sequences: only the FP32-bulk path and the

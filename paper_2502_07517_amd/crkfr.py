@@ -9,12 +9,14 @@ import os
 
 import numpy as np
 
-LINADV1D, EULER1D, EULER2D, TENMOM2D = 0, 1, 2, 3
+LINADV1D, EULER1D, EULER2D, TENMOM2D, BURGERS1D, TENMOM1D = 0, 1, 2, 3, 4, 5
+DISS_D2, DISS_D1, DISS_DCSX = 0, 1, 2
+CENTRAL_EA, CENTRAL_AE = 0, 1
 PERIODIC, OUTFLOW, FARFIELD, REFLECT = 0, 1, 2, 3
 FP64, MP32 = 0, 1
 BLEND_OFF, BLEND_FO, BLEND_MH = 0, 1, 2
 IND_PAPER, IND_CONST, IND_GIVEN, IND_LEARNED = 0, 1, 2, 3
-NVAR = {LINADV1D: 1, EULER1D: 3, EULER2D: 4, TENMOM2D: 6}
+NVAR = {LINADV1D: 1, EULER1D: 3, EULER2D: 4, TENMOM2D: 6, BURGERS1D: 1, TENMOM1D: 6}
 EINADMISSIBLE_MEAN = -5
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -32,6 +34,10 @@ class LimiterOpts(ctypes.Structure):
     _fields_ = [("blend", ctypes.c_int), ("indicator", ctypes.c_int), ("smooth_nbr", ctypes.c_int),
                 ("flux_limiter", ctypes.c_int), ("scaling", ctypes.c_int),
                 ("alpha_min", ctypes.c_double), ("alpha_max", ctypes.c_double), ("alpha_const", ctypes.c_double)]
+
+
+class Scheme(ctypes.Structure):
+    _fields_ = [("stages", ctypes.c_int), ("dissipation", ctypes.c_int), ("central", ctypes.c_int)]
 
 
 class Source(ctypes.Structure):
@@ -62,7 +68,8 @@ SYMBOLS = ["crkfr_create", "crkfr_destroy", "crkfr_set_limiter", "crkfr_set_sour
            "crkfr_batch_autotune", "crkfr_set_mlp", "crkfr_features", "crkfr_mlp_create", "crkfr_mlp_destroy",
            "crkfr_mlp_num_params", "crkfr_mlp_set_params", "crkfr_mlp_get_params", "crkfr_mlp_set_box",
            "crkfr_mlp_get_box", "crkfr_mlp_fit_box", "crkfr_mlp_forward", "crkfr_mlp_loss_grad",
-           "crkfr_mlp_train", "crkfr_batch_set_t_end", "crkfr_batch_set_timing", "crkfr_batch_phase_times"]
+           "crkfr_mlp_train", "crkfr_batch_set_t_end", "crkfr_batch_set_timing", "crkfr_batch_phase_times",
+           "crkfr_set_scheme"]
 
 _lib = None
 
@@ -101,7 +108,8 @@ def lib():
         L.crkfr_nodes_per_element.argtypes = [vp]
         L.crkfr_cfl_in_use.argtypes = [vp]
         L.crkfr_cfl_in_use.restype = ctypes.c_double
-        L.crkfr_fourier_cfl.argtypes = [ip, ip, ip, ctypes.c_double]
+        L.crkfr_fourier_cfl.argtypes = [ip, ip, ip, ip, ctypes.c_double]
+        L.crkfr_set_scheme.argtypes = [vp, ctypes.POINTER(Scheme)]
         L.crkfr_fourier_cfl.restype = ctypes.c_double
         L.crkfr_set_timing.argtypes = [vp, ip]
         L.crkfr_get_kernel_times.argtypes = [vp, ctypes.POINTER(ctypes.c_float)]
@@ -156,8 +164,8 @@ def _ptr(a):
     return ctypes.c_void_p(a.ctypes.data), 0
 
 
-def fourier_cfl(N, stages=0, system=1, tol=1e-10):
-    return lib().crkfr_fourier_cfl(N, stages, system, tol)
+def fourier_cfl(N, stages=0, system=1, tol=1e-10, dissipation=DISS_D2):
+    return lib().crkfr_fourier_cfl(N, stages, system, dissipation, tol)
 
 
 class Solver:
@@ -174,7 +182,7 @@ class Solver:
         c.gamma, c.adv, c.cfl, c.cs = gamma, adv, cfl, cs
         self.cfg = c
         self.M = NVAR[equation]
-        self.dim = 2 if equation >= EULER2D else 1
+        self.dim = 2 if equation in (EULER2D, TENMOM2D) else 1
         self.np = (N + 1) ** self.dim
         self.ne = nx * ny
         h = ctypes.c_void_p()
@@ -203,6 +211,10 @@ class Solver:
                     alpha_min=1e-3, alpha_max=1.0, alpha_const=0.0):
         o = LimiterOpts(blend, indicator, smooth_nbr, flux_limiter, scaling, alpha_min, alpha_max, alpha_const)
         _check(lib().crkfr_set_limiter(self.h, ctypes.byref(o)))
+
+    def set_scheme(self, stages=0, dissipation=DISS_D2, central=CENTRAL_EA):
+        o = Scheme(stages, dissipation, central)
+        _check(lib().crkfr_set_scheme(self.h, ctypes.byref(o)))
 
     def set_source(self, enabled=1, amp=0.0, kappa=0.0, xc=0.0, yc=0.0, gx=0.0, gy=0.0):
         s = Source(enabled, amp, kappa, xc, yc, gx, gy)

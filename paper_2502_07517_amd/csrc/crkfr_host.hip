@@ -120,7 +120,7 @@ static void make_ref(int N, RefElem& r)
 }
 
 template <class real>
-static void fill_tab(const RefElem& r, RefTab<real>& t)
+static void fill_tab(const RefElem& r, int S, RefTab<real>& t)
 {
     std::memset(&t, 0, sizeof(t));
     for (int i = 0; i <= r.N; ++i) {
@@ -142,7 +142,6 @@ static void fill_tab(const RefElem& r, RefTab<real>& t)
         t.rdm[i] = (real)(1.0 / (r.xi[i] - xm));
         t.rdp[i] = (real)(1.0 / (xp - r.xi[i]));
     }
-    const int S = std::min(r.N + 1, 4);
     for (int i = 0; i < S; ++i) {
         t.tb[i] = (real)tab_b(S, i);
         t.ta[i] = i < S - 1 ? (real)tab_a(S, i) : (real)0;
@@ -154,6 +153,8 @@ static void fill_tab(const RefElem& r, RefTab<real>& t)
 //   U = P u, P = sum_i b_i R_i, R_1 = I, R_{i+1} = I - nu_a a_{i+1,i} D R_i
 //   D2 flux with dissipation speed lambda, wave speed a = ratio * lambda
 //   G = I - (nu_a D + b_R (F_R - nu_a l1^T) - b_L (F_L - nu_a l0^T)) P
+//   (D1: the dissipative part of F_R, F_L acts on u instead of U = P u;
+//   D-CSX equals D2 for a linear flux)
 // spectral radius from the growth of ||G^(2^j)|| under repeated squaring.
 // ----------------------------------------------------------------------------
 typedef std::complex<double> cplx;
@@ -182,7 +183,7 @@ static double spectral_radius(int n, const cplx* G)
     return std::exp(logsum);
 }
 
-static double max_growth(const RefElem& r, int S, double nu, double ratio, int nk)
+static double max_growth(const RefElem& r, int S, double nu, double ratio, int nk, bool d1)
 {
     const int n = r.N + 1;
     const double nua = ratio * nu;
@@ -208,19 +209,21 @@ static double max_growth(const RefElem& r, int S, double nu, double ratio, int n
     for (int ik = 0; ik < nk; ++ik) {
         const double kap = 2.0 * M_PI * ik / (nk - 1);
         const cplx E = std::polar(1.0, kap), Ec = std::conj(E);
-        cplx op[MAXND * MAXND], G[MAXND * MAXND];
+        cplx op[MAXND * MAXND], dis[MAXND * MAXND], G[MAXND * MAXND];
         for (int i = 0; i < n; ++i)
             for (int j = 0; j < n; ++j) {
-                cplx FR = 0.5 * nua * (r.l1[j] + E * r.l0[j]) - 0.5 * nu * (E * r.l0[j] - r.l1[j]);
-                cplx FL = 0.5 * nua * (Ec * r.l1[j] + r.l0[j]) - 0.5 * nu * (r.l0[j] - Ec * r.l1[j]);
-                op[i * n + j] = nua * r.D[i][j] + (r.l1[i] / r.w[i]) * (FR - nua * r.l1[j])
-                                - (r.l0[i] / r.w[i]) * (FL - nua * r.l0[j]);
+                cplx FRc = 0.5 * nua * (r.l1[j] + E * r.l0[j]), FRd = -0.5 * nu * (E * r.l0[j] - r.l1[j]);
+                cplx FLc = 0.5 * nua * (Ec * r.l1[j] + r.l0[j]), FLd = -0.5 * nu * (r.l0[j] - Ec * r.l1[j]);
+                op[i * n + j] = nua * r.D[i][j] + (r.l1[i] / r.w[i]) * (FRc - nua * r.l1[j])
+                                - (r.l0[i] / r.w[i]) * (FLc - nua * r.l0[j]);
+                dis[i * n + j] = (r.l1[i] / r.w[i]) * FRd - (r.l0[i] / r.w[i]) * FLd;
+                if (!d1) op[i * n + j] += dis[i * n + j];
             }
         for (int i = 0; i < n; ++i)
             for (int j = 0; j < n; ++j) {
                 cplx s = 0.0;
                 for (int k = 0; k < n; ++k) s += op[i * n + k] * P[k][j];
-                G[i * n + j] = (i == j ? 1.0 : 0.0) - s;
+                G[i * n + j] = (i == j ? 1.0 : 0.0) - s - (d1 ? dis[i * n + j] : 0.0);
             }
         double rho = spectral_radius(n, G);
         worst = rho > worst ? rho : worst;
@@ -228,9 +231,10 @@ static double max_growth(const RefElem& r, int S, double nu, double ratio, int n
     return worst;
 }
 
-extern "C" double crkfr_fourier_cfl(int N, int stages, int system, double tol)
+extern "C" double crkfr_fourier_cfl(int N, int stages, int system, int dissipation, double tol)
 {
-    if (N < 1 || N > 4) return -1.0;
+    if (N < 1 || N > 4 || stages == 1 || stages < 0 || stages > 4 || dissipation < 0 || dissipation > 2) return -1.0;
+    const bool d1 = dissipation == CRKFR_DISS_D1;
     RefElem r;
     make_ref(N, r);
     const int S = stages > 0 ? stages : std::min(N + 1, 4);
@@ -238,7 +242,7 @@ extern "C" double crkfr_fourier_cfl(int N, int stages, int system, double tol)
     auto stable = [&](double nu) {
         for (int ir = 0; ir < nr; ++ir) {
             double ratio = system ? (double)ir / (nr - 1) : 1.0;
-            if (max_growth(r, S, nu, ratio, nk) > 1.0 + tol) return false;
+            if (max_growth(r, S, nu, ratio, nk, d1) > 1.0 + tol) return false;
         }
         return true;
     };
@@ -250,14 +254,18 @@ extern "C" double crkfr_fourier_cfl(int N, int stages, int system, double tol)
     return lo;
 }
 
-static double cached_cfl(int eq, int N)
+// CFL(N) for (equation kind, stages, D1 or not); the tolerance is 1e-10 except
+// for the 4-stage tableau at N = 4 (weak growth below 5e-6 per step)
+static double cached_cfl(int eq, int N, int stages, int dissipation)
 {
     static std::mutex mu;
-    static double cache[2][5] = {{0}};
+    static double cache[2][5][5][2] = {};
     const int sys = eq == CRKFR_LINADV1D ? 0 : 1;
+    const int d1 = dissipation == CRKFR_DISS_D1 ? 1 : 0;
     std::lock_guard<std::mutex> lk(mu);
-    if (cache[sys][N] == 0.0) cache[sys][N] = crkfr_fourier_cfl(N, 0, sys, N == 4 ? 1e-5 : 1e-10);
-    return cache[sys][N];
+    double& v = cache[sys][N][stages][d1];
+    if (v == 0.0) v = crkfr_fourier_cfl(N, stages, sys, dissipation, N == 4 && stages == 4 ? 1e-5 : 1e-10);
+    return v;
 }
 
 // ----------------------------------------------------------------------------
@@ -270,6 +278,8 @@ struct crkfr_solver {
     hipStream_t stream;
     bool own_stream;
     int M, dim, nd, nq, np, ne, C_max;
+    int stages, dissipation, central;   // scheme options (crkfr_set_scheme)
+    int batch_refs;                     // batches holding this solver's buffers
     double cfl;
     bool mp, has_state;
     int cur;   // which state buffer is current
@@ -294,6 +304,8 @@ struct crkfr_solver {
 
 static size_t real_size(const crkfr_solver* s) { return s->mp ? sizeof(float) : sizeof(double); }
 
+static bool is_tenmom(int eq) { return eq == CRKFR_TENMOM2D || eq == CRKFR_TENMOM1D; }
+
 static int eq_nvar(int eq)
 {
     switch (eq) {
@@ -301,6 +313,8 @@ static int eq_nvar(int eq)
     case CRKFR_EULER1D: return 3;
     case CRKFR_EULER2D: return 4;
     case CRKFR_TENMOM2D: return 6;
+    case CRKFR_BURGERS1D: return 1;
+    case CRKFR_TENMOM1D: return 6;
     }
     return 0;
 }
@@ -310,7 +324,7 @@ static Phys make_phys(const crkfr_solver* s)
     Phys P;
     P.gamma = s->cfg.gamma;
     P.adv = s->cfg.adv;
-    P.source = s->src.enabled && s->cfg.equation == CRKFR_TENMOM2D;
+    P.source = s->src.enabled && is_tenmom(s->cfg.equation);
     P.amp = s->src.amp;
     P.kappa = s->src.kappa;
     P.xc = s->src.xc;
@@ -343,7 +357,7 @@ static StepArgs<real> step_args(const crkfr_solver* s, int in, int out)
     a.trY = (real*)s->trY;
     a.Fx = (real*)s->Fx;
     a.Gy = (real*)s->Gy;
-    a.dtS = (s->src.enabled && s->cfg.equation == CRKFR_TENMOM2D) ? (real*)s->dtS : nullptr;
+    a.dtS = (s->src.enabled && is_tenmom(s->cfg.equation)) ? (real*)s->dtS : nullptr;
     a.alpha_raw = s->alpha_raw;
     a.alpha_out = s->alpha_out;
     a.alpha_given = s->alpha_given;
@@ -355,11 +369,14 @@ static StepArgs<real> step_args(const crkfr_solver* s, int in, int out)
     a.flux_limiter = s->lim.flux_limiter;
     a.scaling = s->lim.scaling;
     a.C = s->C_max;
+    a.stages = s->stages;
+    a.dissipation = s->dissipation;
+    a.central = s->central;
     a.alpha_min = s->lim.alpha_min;
     a.alpha_max = s->lim.alpha_max;
     a.alpha_const = s->lim.alpha_const;
     a.phys = make_phys(s);
-    fill_tab(s->ref, a.R);
+    fill_tab(s->ref, s->stages, a.R);
     for (int i = 0; i < MAXND; ++i) a.w64[i] = i <= s->cfg.N ? s->ref.w[i] : 0.0;
     a.diag = s->diag;
     a.rate_bits = s->rate_bits;
@@ -387,7 +404,7 @@ static IoArgs<real> io_args(const crkfr_solver* s)
     a.u = (real*)s->u[s->cur];
     a.ghost = (real*)s->ghost;
     a.phys = make_phys(s);
-    fill_tab(s->ref, a.R);
+    fill_tab(s->ref, s->stages, a.R);
     for (int i = 0; i < MAXND; ++i) {
         a.w64[i] = i <= s->cfg.N ? s->ref.w[i] : 0.0;
         a.l0_64[i] = i <= s->cfg.N ? s->ref.l0[i] : 0.0;
@@ -408,6 +425,8 @@ static int dispatch_step(const crkfr_solver* s, int phase, int in, int out)
         StepArgs<float> a = step_args<float>(s, in, out);
         switch (s->cfg.equation) {
         case CRKFR_LINADV1D: rc = linadv1d_step_f32(N, lim, phase, a, st); break;
+        case CRKFR_BURGERS1D: rc = burgers1d_step_f32(N, lim, phase, a, st); break;
+        case CRKFR_TENMOM1D: rc = tenmom1d_step_f32(N, lim, phase, a, st); break;
         case CRKFR_EULER1D: rc = euler1d_step_f32(N, lim, phase, a, st); break;
         case CRKFR_EULER2D: rc = euler2d_step_f32(N, lim, phase, a, st); break;
         case CRKFR_TENMOM2D: rc = tenmom2d_step_f32(N, lim, phase, a, st); break;
@@ -416,6 +435,8 @@ static int dispatch_step(const crkfr_solver* s, int phase, int in, int out)
         StepArgs<double> a = step_args<double>(s, in, out);
         switch (s->cfg.equation) {
         case CRKFR_LINADV1D: rc = linadv1d_step_f64(N, lim, phase, a, st); break;
+        case CRKFR_BURGERS1D: rc = burgers1d_step_f64(N, lim, phase, a, st); break;
+        case CRKFR_TENMOM1D: rc = tenmom1d_step_f64(N, lim, phase, a, st); break;
         case CRKFR_EULER1D: rc = euler1d_step_f64(N, lim, phase, a, st); break;
         case CRKFR_EULER2D: rc = euler2d_step_f64(N, lim, phase, a, st); break;
         case CRKFR_TENMOM2D: rc = tenmom2d_step_f64(N, lim, phase, a, st); break;
@@ -436,6 +457,8 @@ static int dispatch_io_t(const crkfr_solver* s, int phase, IoArgs<real>& a)
     if constexpr (sizeof(real) == 4) {
         switch (s->cfg.equation) {
         case CRKFR_LINADV1D: rc = linadv1d_io_f32(N, phase, a, st); break;
+        case CRKFR_BURGERS1D: rc = burgers1d_io_f32(N, phase, a, st); break;
+        case CRKFR_TENMOM1D: rc = tenmom1d_io_f32(N, phase, a, st); break;
         case CRKFR_EULER1D: rc = euler1d_io_f32(N, phase, a, st); break;
         case CRKFR_EULER2D: rc = euler2d_io_f32(N, phase, a, st); break;
         case CRKFR_TENMOM2D: rc = tenmom2d_io_f32(N, phase, a, st); break;
@@ -443,6 +466,8 @@ static int dispatch_io_t(const crkfr_solver* s, int phase, IoArgs<real>& a)
     } else {
         switch (s->cfg.equation) {
         case CRKFR_LINADV1D: rc = linadv1d_io_f64(N, phase, a, st); break;
+        case CRKFR_BURGERS1D: rc = burgers1d_io_f64(N, phase, a, st); break;
+        case CRKFR_TENMOM1D: rc = tenmom1d_io_f64(N, phase, a, st); break;
         case CRKFR_EULER1D: rc = euler1d_io_f64(N, phase, a, st); break;
         case CRKFR_EULER2D: rc = euler2d_io_f64(N, phase, a, st); break;
         case CRKFR_TENMOM2D: rc = tenmom2d_io_f64(N, phase, a, st); break;
@@ -484,15 +509,15 @@ extern "C" int crkfr_create(const crkfr_config* cfg, void* hip_stream, crkfr_sol
 {
     if (!cfg || !out) return fail(CRKFR_EINVAL, "null argument");
     *out = nullptr;
-    if (cfg->equation < 0 || cfg->equation > 3) return fail(CRKFR_EINVAL, "unknown equation");
+    if (cfg->equation < 0 || cfg->equation > 5) return fail(CRKFR_EINVAL, "unknown equation");
     if (cfg->N < 1 || cfg->N > 4) return fail(CRKFR_EINVAL, "N must be in 1..4");
-    const int dim = cfg->equation >= CRKFR_EULER2D ? 2 : 1;
+    const int dim = cfg->equation == CRKFR_EULER2D || cfg->equation == CRKFR_TENMOM2D ? 2 : 1;
     if (cfg->nx < 1 || cfg->ny < 1 || (dim == 1 && cfg->ny != 1)) return fail(CRKFR_EINVAL, "bad grid size");
     if (cfg->dtype != CRKFR_FP64 && cfg->dtype != CRKFR_MP32) return fail(CRKFR_EINVAL, "bad dtype");
     for (int i = 0; i < (dim == 2 ? 4 : 2); ++i)
         if (cfg->bc[i] < 0 || cfg->bc[i] > 3) return fail(CRKFR_EINVAL, "bad boundary kind");
     for (int i = 0; i < (dim == 2 ? 4 : 2); ++i)
-        if (cfg->bc[i] == CRKFR_BC_REFLECT && cfg->equation == CRKFR_LINADV1D)
+        if (cfg->bc[i] == CRKFR_BC_REFLECT && (cfg->equation == CRKFR_LINADV1D || cfg->equation == CRKFR_BURGERS1D))
             return fail(CRKFR_EINVAL, "solid walls are defined for the Euler and ten-moment systems");
     if ((cfg->bc[0] == CRKFR_BC_PERIODIC) != (cfg->bc[1] == CRKFR_BC_PERIODIC) ||
         (dim == 2 && (cfg->bc[2] == CRKFR_BC_PERIODIC) != (cfg->bc[3] == CRKFR_BC_PERIODIC)))
@@ -519,8 +544,11 @@ extern "C" int crkfr_create(const crkfr_config* cfg, void* hip_stream, crkfr_sol
     s->np = s->nd * s->nq;
     s->ne = cfg->nx * cfg->ny;
     s->C_max = 4 * s->M + 1;
+    s->stages = std::min(cfg->N + 1, 4);
+    s->dissipation = CRKFR_DISS_D2;
+    s->central = CRKFR_CENTRAL_EA;
     s->mp = cfg->dtype == CRKFR_MP32;
-    s->cfl = cfg->cfl > 0.0 ? cfg->cfl : cached_cfl(cfg->equation, cfg->N);
+    s->cfl = cfg->cfl > 0.0 ? cfg->cfl : cached_cfl(cfg->equation, cfg->N, s->stages, s->dissipation);
     if (s->cfg.cs <= 0.0) s->cfg.cs = 0.98;
     s->lim.blend = CRKFR_BLEND_OFF;
     s->lim.alpha_min = 1e-3;
@@ -546,7 +574,7 @@ extern "C" int crkfr_create(const crkfr_config* cfg, void* hip_stream, crkfr_sol
     if (dim == 2) ok &= alloc(&s->trY, 2 * (size_t)s->C_max * ne * s->nd * rs);
     ok &= alloc(&s->Fx, M * (size_t)cfg->ny * (cfg->nx + 1) * s->nq * rs);
     if (dim == 2) ok &= alloc(&s->Gy, M * (size_t)(cfg->ny + 1) * cfg->nx * s->nd * rs);
-    if (cfg->equation == CRKFR_TENMOM2D) ok &= alloc(&s->dtS, nstate * rs);
+    if (is_tenmom(cfg->equation)) ok &= alloc(&s->dtS, nstate * rs);
     ok &= alloc(&s->ghost, (2 * (size_t)cfg->ny * s->nq + (dim == 2 ? 2 * (size_t)cfg->nx * s->nd : 0)) * M * rs);
     ok &= alloc((void**)&s->alpha_raw, ne * sizeof(double));
     ok &= alloc((void**)&s->alpha_out, ne * sizeof(double));
@@ -608,9 +636,43 @@ extern "C" int crkfr_set_limiter(crkfr_solver* s, const crkfr_limiter_opts* o)
 extern "C" int crkfr_set_source(crkfr_solver* s, const crkfr_source* src)
 {
     if (!s || !src) return fail(CRKFR_EINVAL, "null argument");
-    if (src->enabled && s->cfg.equation != CRKFR_TENMOM2D)
+    if (src->enabled && !is_tenmom(s->cfg.equation))
         return fail(CRKFR_EINVAL, "sources are implemented for the ten-moment system");
     s->src = *src;
+    invalidate_graph(s);
+    return 0;
+}
+
+extern "C" int crkfr_set_scheme(crkfr_solver* s, const crkfr_scheme* o)
+{
+    if (!s || !o) return fail(CRKFR_EINVAL, "null argument");
+    if (s->batch_refs > 0) return fail(CRKFR_ESTATE, "solver is a batch member: destroy the batch first");
+    const int S = o->stages > 0 ? o->stages : std::min(s->cfg.N + 1, 4);
+    if (S < 2 || S > 4) return fail(CRKFR_EINVAL, "stages must be 0 (N+1 up to 4) or 2..4");
+    if (o->dissipation < 0 || o->dissipation > 2 || o->central < 0 || o->central > 1)
+        return fail(CRKFR_EINVAL, "bad dissipation or central option");
+    const int need = 4 * s->M + 1 + (o->dissipation == CRKFR_DISS_DCSX ? S * s->M : 0);
+    if (need > s->C_max) {
+        // the D-CSX dissipation keeps every stage's face values: larger trace buffers
+        const size_t rs = real_size(s), ne = s->ne;
+        void *trx = nullptr, *trY = nullptr;
+        HIP_TRY(hipStreamSynchronize(s->stream));
+        if (hipMalloc(&trx, 2 * (size_t)need * ne * s->nq * rs) != hipSuccess)
+            return fail(CRKFR_ENOMEM, "device allocation failed");
+        if (s->dim == 2 && hipMalloc(&trY, 2 * (size_t)need * ne * s->nd * rs) != hipSuccess) {
+            (void)hipFree(trx);
+            return fail(CRKFR_ENOMEM, "device allocation failed");
+        }
+        (void)hipFree(s->trx);
+        if (s->trY) (void)hipFree(s->trY);
+        s->trx = trx;
+        s->trY = trY;
+        s->C_max = need;
+    }
+    s->stages = S;
+    s->dissipation = o->dissipation;
+    s->central = o->central;
+    if (s->cfg.cfl <= 0.0) s->cfl = cached_cfl(s->cfg.equation, s->cfg.N, S, o->dissipation);
     invalidate_graph(s);
     return 0;
 }
@@ -945,6 +1007,8 @@ static int eq_geometry(int eq, int N, int* el, int* eu, int* nq)
 {
     switch (eq) {
     case CRKFR_LINADV1D: return linadv1d_geometry(N, el, eu, nq);
+    case CRKFR_BURGERS1D: return burgers1d_geometry(N, el, eu, nq);
+    case CRKFR_TENMOM1D: return tenmom1d_geometry(N, el, eu, nq);
     case CRKFR_EULER1D: return euler1d_geometry(N, el, eu, nq);
     case CRKFR_EULER2D: return euler2d_geometry(N, el, eu, nq);
     case CRKFR_TENMOM2D: return tenmom2d_geometry(N, el, eu, nq);
@@ -962,6 +1026,8 @@ static int launch_group_phase(const crkfr_batch* b, const BatchGroup& g, int pha
         const StepArgs<float>* args = (const StepArgs<float>*)g.d_args[b->parity];
         switch (g.eq) {
         case CRKFR_LINADV1D: rc = linadv1d_batch_f32(g.N, g.lim, phase, args, w, nw, grid, b->stream); break;
+        case CRKFR_BURGERS1D: rc = burgers1d_batch_f32(g.N, g.lim, phase, args, w, nw, grid, b->stream); break;
+        case CRKFR_TENMOM1D: rc = tenmom1d_batch_f32(g.N, g.lim, phase, args, w, nw, grid, b->stream); break;
         case CRKFR_EULER1D: rc = euler1d_batch_f32(g.N, g.lim, phase, args, w, nw, grid, b->stream); break;
         case CRKFR_EULER2D: rc = euler2d_batch_f32(g.N, g.lim, phase, args, w, nw, grid, b->stream); break;
         case CRKFR_TENMOM2D: rc = tenmom2d_batch_f32(g.N, g.lim, phase, args, w, nw, grid, b->stream); break;
@@ -970,6 +1036,8 @@ static int launch_group_phase(const crkfr_batch* b, const BatchGroup& g, int pha
         const StepArgs<double>* args = (const StepArgs<double>*)g.d_args[b->parity];
         switch (g.eq) {
         case CRKFR_LINADV1D: rc = linadv1d_batch_f64(g.N, g.lim, phase, args, w, nw, grid, b->stream); break;
+        case CRKFR_BURGERS1D: rc = burgers1d_batch_f64(g.N, g.lim, phase, args, w, nw, grid, b->stream); break;
+        case CRKFR_TENMOM1D: rc = tenmom1d_batch_f64(g.N, g.lim, phase, args, w, nw, grid, b->stream); break;
         case CRKFR_EULER1D: rc = euler1d_batch_f64(g.N, g.lim, phase, args, w, nw, grid, b->stream); break;
         case CRKFR_EULER2D: rc = euler2d_batch_f64(g.N, g.lim, phase, args, w, nw, grid, b->stream); break;
         case CRKFR_TENMOM2D: rc = tenmom2d_batch_f64(g.N, g.lim, phase, args, w, nw, grid, b->stream); break;
@@ -1133,6 +1201,7 @@ extern "C" int crkfr_batch_create(crkfr_solver* const* solvers, int count, void*
     }
     (void)hipEventCreate(&b->ev0);
     (void)hipEventCreate(&b->ev1);
+    for (crkfr_solver* s : b->s) ++s->batch_refs;
     *out = b;
     return 0;
 }
@@ -1141,6 +1210,7 @@ extern "C" void crkfr_batch_destroy(crkfr_batch* b)
 {
     if (!b) return;
     (void)hipStreamSynchronize(b->stream);
+    for (crkfr_solver* s : b->s) --s->batch_refs;
     free_batch(b);
     delete b;
 }

@@ -36,6 +36,8 @@ constexpr int MAXND = 5;
 enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_FARFIELD = 2, BC_REFLECT = 3 };
 enum { BLEND_OFF = 0, BLEND_FO = 1, BLEND_MH = 2 };
 enum { IND_PAPER = 0, IND_CONST = 1, IND_GIVEN = 2, IND_LEARNED = 3 };
+enum { DISS_D2 = 0, DISS_D1 = 1, DISS_DCSX = 2 };
+enum { CENTRAL_EA = 0, CENTRAL_AE = 1 };
 enum { D_TROUBLED = 0, D_FLUXLIM, D_LOBAD, D_SLOPELIM, D_FALLBACK, D_SCALED, D_MEANBAD, D_LFALLBACK,
        D_THFLUX, D_THSCALE, D_NCOUNT };
 
@@ -88,7 +90,16 @@ struct StepArgs {
     double* alpha_judge;   // learned indicator: the smoothness indicator's alpha per element
     float* feat_out;       // k_features: learned-indicator features [e][N]
     double ind_T, ind_kT;  // indicator threshold T(N) = 0.5 10^(-1.8 (N+1)^(1/4)) and ln(9999) / T
+    int stages;            // cRK stages (tableau in R.ta, R.tb)
+    int dissipation;       // DISS_*: D2 (eq. D2), D1 (eq. D1), D-CSX (eq. dcsx)
+    int central;           // CENTRAL_*: EA traces (eq. evaluate) or extrapolation (eq. extrapolate)
 };
+
+// trace components per face point: F (M), U (M; u^n for D1), sigma (1),
+// limiting: predicted subcell value (M), adjacent subface flux (M),
+// D-CSX: the stage values u^(i) (stages x M) from TRACE_STAGES on
+template <int M>
+__host__ __device__ constexpr int trace_stage_offset() { return 4 * M + 1; }
 
 template <int DIM, int N>
 struct Geo {
@@ -177,7 +188,7 @@ __device__ __forceinline__ bool is_wall(const StepArgs<real>& a, int dir, int si
 template <class Eq>
 __device__ __forceinline__ constexpr bool mirror_flips(int dir, int v)
 {
-    return v == 1 + dir || (Eq::ID == 3 && v == 4);
+    return v == 1 + dir || (Eq::K == 3 && v == 4);   // ten-moment: E12 flips too
 }
 
 // ----------------------------------------------------------------------------
@@ -493,7 +504,7 @@ __device__ void local_body(const StepArgs<real>& a, int vblock)
 {
     using G = LGeo<Eq::DIM, N>;
     constexpr int M = Eq::M, DIM = Eq::DIM, nd = G::nd, nq = G::nq, np = G::np, EB = G::EB;
-    constexpr int S = N + 1 < 4 ? N + 1 : 4;
+    const int S = a.stages;
     constexpr int MY = DIM == 2 ? M : 1;
     __shared__ real sh_u[EB][np][M];
     __shared__ real sh_f[EB][np][M];
@@ -511,7 +522,7 @@ __device__ void local_body(const StepArgs<real>& a, int vblock)
     const real rdt = (real)dt, idx = (real)(1.0 / a.dx), idy = (real)(1.0 / a.dy);
     const real xn = (real)(a.x0 + ((double)ex + (double)a.R.xi[p]) * a.dx);
     const real yn = DIM == 2 ? (real)(a.y0 + ((double)ey + (double)a.R.xi[q]) * a.dy) : (real)0;
-    const bool src = Eq::ID == 3 && P.source;
+    const bool src = Eq::K == 3 && P.source;          // ten-moment systems carry the source
     const int C = a.C;
     const size_t nes = (size_t)a.ne;
 
@@ -723,6 +734,14 @@ __device__ void local_body(const StepArgs<real>& a, int vblock)
             Eq::fxy(uf, ff, gf, P);
 #pragma unroll
             for (int v = 0; v < M; ++v) tr[j][v] += bi * (sd < 2 ? ff[v] : gf[v]);
+            if (act && (a.dissipation == DISS_DCSX || (i == 0 && a.dissipation == DISS_D1))) {
+                // stage values at the face (D-CSX), or u^n in place of U (D1)
+                real* base = sd < 2 ? a.trx : a.trY;
+                const int npt = sd < 2 ? nq : nd, side = sd & 1, t = fpos(fp);
+                const int c0 = a.dissipation == DISS_DCSX ? trace_stage_offset<M>() + i * M : M;
+#pragma unroll
+                for (int v = 0; v < M; ++v) base[((size_t)(side * C + c0 + v) * nes + e) * npt + t] = uf[v];
+            }
             if (i == 0) {
                 real nodev[M];
                 const int kadj = (sd & 1) ? fkn[j][N] : fkn[j][0];
@@ -786,7 +805,10 @@ __device__ void local_body(const StepArgs<real>& a, int vblock)
             }
         }
 #pragma unroll
-        for (int v = 0; v < M; ++v) sh_h[le][v][sd * nd + t] = hf[v];
+        for (int v = 0; v < M; ++v) {
+            sh_h[le][v][sd * nd + t] = hf[v];
+            if (a.central == CENTRAL_AE) tr[j][v] = hf[v];   // extrapolated averaged flux as the central part
+        }
     }
     __syncthreads();
     if (!act) return;
@@ -806,10 +828,11 @@ __device__ void local_body(const StepArgs<real>& a, int vblock)
         const int sd = fside(fp), t = fpos(fp), side = sd & 1;
         real* base = sd < 2 ? a.trx : a.trY;
         const int npt = sd < 2 ? nq : nd;
+        const bool write_U = a.dissipation != DISS_D1;
 #pragma unroll
         for (int v = 0; v < M; ++v) {
             base[((size_t)(side * C + v) * nes + e) * npt + t] = tr[j][v];
-            base[((size_t)(side * C + M + v) * nes + e) * npt + t] = Ut[j][v];
+            if (write_U) base[((size_t)(side * C + M + v) * nes + e) * npt + t] = Ut[j][v];
         }
         base[((size_t)(side * C + 2 * M) * nes + e) * npt + t] = sig[j];
     }
@@ -951,6 +974,37 @@ __device__ void face_body(const StepArgs<real>& a, int vblock)
     real F[M];
 #pragma unroll
     for (int v = 0; v < M; ++v) F[v] = (real)0.5 * (Fm[v] + Fp[v]) - (real)0.5 * lam * (Up[v] - Um[v]);
+    if (a.dissipation == DISS_DCSX) {
+        // eq. dcsx: one wave speed per stage from that stage's face values
+#pragma unroll
+        for (int v = 0; v < M; ++v) F[v] = (real)0.5 * (Fm[v] + Fp[v]);
+        for (int i = 0; i < a.stages; ++i) {
+            real sm_[M], sp_[M];
+            const int c0 = trace_stage_offset<M>() + i * M;
+            if (hA) {
+#pragma unroll
+                for (int v = 0; v < M; ++v) sm_[v] = TRA(c0 + v);
+            }
+            if (hB) {
+#pragma unroll
+                for (int v = 0; v < M; ++v) sp_[v] = TRB(c0 + v);
+            }
+            if (!hA) {
+#pragma unroll
+                for (int v = 0; v < M; ++v)
+                    sm_[v] = gA ? gA[v] : (wA && mirror_flips<Eq>(D, v) ? -sp_[v] : sp_[v]);
+            }
+            if (!hB) {
+#pragma unroll
+                for (int v = 0; v < M; ++v)
+                    sp_[v] = gB ? gB[v] : (wB && mirror_flips<Eq>(D, v) ? -sm_[v] : sm_[v]);
+            }
+            const real li = fmax(Eq::sig_trace(D, sm_, uA, P), Eq::sig_trace(D, sp_, uB, P));
+            const real bi = a.R.tb[i];
+#pragma unroll
+            for (int v = 0; v < M; ++v) F[v] -= bi * (real)0.5 * li * (sp_[v] - sm_[v]);
+        }
+    }
 
     if constexpr (LIM) {
         real sA[M], sB[M], fLO[M];

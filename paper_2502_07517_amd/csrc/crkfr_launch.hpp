@@ -188,5 +188,7 @@ CRKFR_DECLARE_EQ(linadv1d)
 CRKFR_DECLARE_EQ(euler1d)
 CRKFR_DECLARE_EQ(euler2d)
 CRKFR_DECLARE_EQ(tenmom2d)
+CRKFR_DECLARE_EQ(burgers1d)
+CRKFR_DECLARE_EQ(tenmom1d)
 
 }  // namespace crkfr

@@ -2,7 +2,8 @@
 // functions, indicator quantity and the ten-moment source.
 //   linear advection            f = a u                         (Sec. 5.1.1)
 //   1D / 2D Euler               eqs. 1deuler, state, 2deuler, 2dstate
-//   ten-moment system           eq. tmp, source eq. tenmom.source
+//   ten-moment system           eq. tmp, source eq. tenmom.source (2D and 1D)
+//   Burgers                     f = u^2 / 2                     (Sec. 5.1.3)
 // Bulk arithmetic is in `real` (double or float); admissibility functions
 // P_k (eq. uad.form) are always evaluated in double.
 #pragma once
@@ -39,6 +40,23 @@ struct LinAdv1D {
     __device__ static inline bool concave(int) { return true; }
     __device__ static inline real ind(const real* u, const Phys&) { return u[0]; }
     __device__ static inline real sig_trace(int, const real*, const real*, const Phys& P) { return fabs((real)P.adv); }
+    __device__ static inline void src(const real*, real, real, real* s, const Phys&) { s[0] = 0; }
+    __device__ static inline void fxy(const real* u, real* f, real* g, const Phys& P) { fx(u, f, P); g[0] = 0; }
+};
+
+// ---------------------------------------------------------------- Burgers
+template <class real>
+struct Burgers1D {
+    static constexpr int M = 1, DIM = 1, K = 0, ID = 4;
+    __device__ static inline void fx(const real* u, real* f, const Phys&) { f[0] = (real)0.5 * u[0] * u[0]; }
+    __device__ static inline void gy(const real*, real* g, const Phys&) { g[0] = 0; }
+    __device__ static inline real sx(const real* u, const Phys&) { return fabs(u[0]); }
+    __device__ static inline real sy(const real*, const Phys&) { return 0; }
+    __device__ static inline double adm(int, const double*, const Phys&) { return 1.0; }
+    __device__ static inline bool adm_ge(int, const double*, double eps, const Phys&) { return 1.0 >= eps; }
+    __device__ static inline bool concave(int) { return true; }
+    __device__ static inline real ind(const real* u, const Phys&) { return u[0]; }
+    __device__ static inline real sig_trace(int, const real* tr, const real*, const Phys&) { return fabs(tr[0]); }
     __device__ static inline void src(const real*, real, real, real* s, const Phys&) { s[0] = 0; }
     __device__ static inline void fxy(const real* u, real* f, real* g, const Phys& P) { fx(u, f, P); g[0] = 0; }
 };
@@ -274,6 +292,51 @@ struct TenMom2D {
         s[3] = (real)-0.5 * r * v1 * Wx;
         s[4] = (real)-0.25 * r * v2 * Wx - (real)0.25 * r * v1 * Wy;
         s[5] = (real)-0.5 * r * v2 * Wy;
+    }
+};
+
+// ---------------------------------------------------------------- ten-moment 1D
+// The six-variable ten-moment system with x dependence only (eq. tmp with
+// g = 0): x flux, x wave speed and the source with W = W(x) (the potential's
+// y offset is dropped; the linear y term gy still acts on rho v2, E12, E22).
+template <class real>
+struct TenMom1D {
+    using T2 = TenMom2D<real>;
+    static constexpr int M = 6, DIM = 1, K = 3, ID = 5;
+    __device__ static inline void fx(const real* u, real* f, const Phys& P) { T2::fx(u, f, P); }
+    __device__ static inline void gy(const real*, real* g, const Phys&)
+    {
+#pragma unroll
+        for (int v = 0; v < M; ++v) g[v] = 0;
+    }
+    __device__ static inline real sx(const real* u, const Phys& P) { return T2::sx(u, P); }
+    __device__ static inline real sy(const real*, const Phys&) { return 0; }
+    __device__ static inline double adm(int k, const double* u, const Phys& P) { return T2::adm(k, u, P); }
+    __device__ static inline bool adm_ge(int k, const double* u, double eps, const Phys& P)
+    {
+        return T2::adm_ge(k, u, eps, P);
+    }
+    __device__ static inline bool concave(int k) { return T2::concave(k); }
+    __device__ static inline real ind(const real* u, const Phys& P) { return T2::ind(u, P); }
+    __device__ static inline real sig_trace(int, const real* tr, const real* node, const Phys& P)
+    {
+        return T2::sig_trace(0, tr, node, P);
+    }
+    __device__ static inline void fxy(const real* u, real* f, real* g, const Phys& P)
+    {
+        real r = u[0], ir = (real)1 / r, v1 = u[1] * ir, v2 = u[2] * ir;
+        real P11 = 2 * u[3] - r * v1 * v1, P12 = 2 * u[4] - r * v1 * v2;
+        f[0] = u[1];
+        f[1] = P11 + r * v1 * v1;
+        f[2] = P12 + r * v1 * v2;
+        f[3] = (u[3] + P11) * v1;
+        f[4] = u[4] * v1 + (real)0.5 * (P11 * v2 + P12 * v1);
+        f[5] = u[5] * v1 + P12 * v2;
+        gy(u, g, P);
+    }
+    __device__ static inline void src(const real* u, real x, real, real* s, const Phys& P)
+    {
+        T2::src(u, x, (real)P.yc, s, P);
     }
 };
 
