@@ -22,14 +22,18 @@ With the D1 dissipation (eq. D1) the dissipative part acts on the solution
 at the current time instead of the time average: the face operators split
 into a central part applied to U = P u and a dissipative part applied to u.
 D-CSX (eq. dcsx) equals D2 for a linear flux.
+
+With Gauss-Legendre-Lobatto points (points = 1) the same formulas hold with
+the GLL nodes and weights: the g2 correction enters through the same
+identity g_R'(xi_p) = l_p(1)/w_p (eq. fr.equiv).
 """
 import numpy as np
 
-from .oracle import gl, diff_matrix, lagrange_at, tableau
+from .oracle import nodes, diff_matrix, lagrange_at, tableau
 
 
-def amplification_matrix(N, s, nu, kappa, ratio=1.0, d1=False):
-    xi, w = gl(N)
+def amplification_matrix(N, s, nu, kappa, ratio=1.0, d1=False, points=0):
+    xi, w = nodes(N, points)
     D = diff_matrix(N, xi)
     l0 = lagrange_at(N, xi, 0.0)
     l1 = lagrange_at(N, xi, 1.0)
@@ -53,25 +57,25 @@ def amplification_matrix(N, s, nu, kappa, ratio=1.0, d1=False):
     return I - central @ P - diss @ (I if d1 else P)
 
 
-def max_growth(N, s, nu, nk=4096, ratios=(1.0,), d1=False):
+def max_growth(N, s, nu, nk=4096, ratios=(1.0,), d1=False, points=0):
     ks = np.linspace(0.0, 2.0 * np.pi, nk)
-    return max(np.max(np.abs(np.linalg.eigvals(amplification_matrix(N, s, nu, k, r, d1))))
+    return max(np.max(np.abs(np.linalg.eigvals(amplification_matrix(N, s, nu, k, r, d1, points))))
                for r in ratios for k in ks)
 
 
 SYSTEM_RATIOS = tuple(np.linspace(0.0, 1.0, 21))
 
 
-def cfl_number(N, s=None, tol=1e-12, nk=4096, iters=50, ratios=(1.0,), d1=False):
+def cfl_number(N, s=None, tol=1e-12, nk=4096, iters=50, ratios=(1.0,), d1=False, points=0):
     """Largest stable nu by bisection on max_{k, ratio} rho(G) <= 1 + tol."""
     if s is None:
         s = min(N + 1, 4)
     lo, hi = 0.0, 1.0
-    while max_growth(N, s, hi, nk, ratios, d1) <= 1.0 + tol:
+    while max_growth(N, s, hi, nk, ratios, d1, points) <= 1.0 + tol:
         hi *= 2.0
     for _ in range(iters):
         mid = 0.5 * (lo + hi)
-        if max_growth(N, s, mid, nk, ratios, d1) <= 1.0 + tol:
+        if max_growth(N, s, mid, nk, ratios, d1, points) <= 1.0 + tol:
             lo = mid
         else:
             hi = mid

@@ -66,6 +66,31 @@ void ref_gl(int N, double* xi, double* w)
     }
 }
 
+/* Gauss-Legendre-Lobatto nodes and weights mapped to [0,1]: the end points
+ * and the roots of P_N' (Newton with P_N'' from Legendre's equation
+ * (1 - x^2) P'' = 2 x P' - N (N+1) P); weights 2 / (N (N+1) P_N(x)^2) on
+ * [-1,1]; exact to degree 2N-1 */
+void ref_gll(int N, double* xi, double* w)
+{
+    for (int i = 0; i <= N; ++i) {
+        double x = -cos(M_PI * i / N);
+        if (i > 0 && i < N)
+            for (int it = 0; it < 100; ++it) {
+                double P, dP;
+                legendre(N, x, &P, &dP);
+                double d2P = (2.0 * x * dP - N * (N + 1.0) * P) / (1.0 - x * x);
+                double dx = dP / d2P;
+                x -= dx;
+                if (fabs(dx) < 1e-16) break;
+            }
+        double P, dP;
+        if (i == 0 || i == N) P = (i == 0 && N % 2 == 1) ? -1.0 : 1.0;
+        else legendre(N, x, &P, &dP);
+        xi[i] = 0.5 * (x + 1.0);
+        w[i] = 0.5 * 2.0 / (N * (N + 1.0) * P * P);
+    }
+}
+
 /* l_q(x) = prod_{p != q} (x - xi_p)/(xi_q - xi_p) */
 void ref_lagrange_at(int N, const double* xi, double x, double* l)
 {
@@ -134,17 +159,35 @@ typedef struct {
     int N, nd;
     double xi[ND], w[ND], D[ND * ND], l0[ND], l1[ND];
     double sub[ND + 1];   /* subfaces xi_{p-1/2}, p = 0..N+1 (eq. subcell.defn) */
-    double L[ND * ND];    /* orthonormal Legendre at the nodes */
+    double Pm[ND * ND];   /* Pm[k][p]: coefficient k of the orthonormal Legendre
+                             expansion of the interpolant of nodal values */
 } refel;
 
-static void refel_init(refel* r, int N)
+/* Solution points GL or GLL (eq. soln.points).  The FR correction enters
+ * through g_R'(xi_p) = l_p(1)/w_p and g_L'(xi_p) = -l_p(0)/w_p, which hold
+ * for the Radau correction with GL points and for g2 with GLL points
+ * (eq. fr.equiv).  Modal coefficients: exact projection of the interpolant
+ * onto the orthonormal Legendre basis by GL quadrature of N+1 points (for GL
+ * solution points the nodal quadrature itself). */
+static void refel_init(refel* r, int N, int points)
 {
     r->N = N; r->nd = N + 1;
-    ref_gl(N, r->xi, r->w);
+    if (points == REF_POINTS_GLL) ref_gll(N, r->xi, r->w);
+    else ref_gl(N, r->xi, r->w);
     ref_lagrange_at(N, r->xi, 0.0, r->l0);
     ref_lagrange_at(N, r->xi, 1.0, r->l1);
     ref_diff_matrix(N, r->xi, r->D);
-    ref_legendre_orthonormal(N, r->xi, r->L);
+    double xg[ND], wg[ND], Lg[ND * ND];
+    ref_gl(N, xg, wg);
+    ref_legendre_orthonormal(N, xg, Lg);
+    for (int k = 0; k <= N; ++k)
+        for (int p = 0; p <= N; ++p) r->Pm[k * (N + 1) + p] = 0.0;
+    for (int j = 0; j <= N; ++j) {
+        double lj[ND];
+        ref_lagrange_at(N, r->xi, xg[j], lj);
+        for (int k = 0; k <= N; ++k)
+            for (int p = 0; p <= N; ++p) r->Pm[k * (N + 1) + p] += wg[j] * Lg[k * (N + 1) + j] * lj[p];
+    }
     r->sub[0] = 0.0;
     for (int p = 0; p <= N; ++p) r->sub[p + 1] = r->sub[p] + r->w[p];
     r->sub[N + 1] = 1.0;
@@ -511,7 +554,7 @@ void ref_local_crk(const ref_config* c, const double* ue, double dt, double xe0,
                    double* F, double* G, double* U, double* S)
 {
     refel r;
-    refel_init(&r, c->N);
+    refel_init(&r, c->N, c->points);
     double dx = (c->x1 - c->x0) / c->nx, dy = (c->y1 - c->y0) / c->ny;
     local_out* o = (local_out*)malloc(sizeof(local_out));
     local_crk(c, &r, ue, dt, dx, dy, xe0, ye0, o);
@@ -551,13 +594,13 @@ static double indicator_raw(const ref_config* c, const refel* r, const double* u
         for (int v = 0; v < M; ++v) u[v] = ue[v * np + k];
         eps[k] = indicator_quantity(c, u);
     }
-    /* orthonormal Legendre coefficients by GL quadrature (exact here) */
+    /* orthonormal Legendre coefficients of the interpolant */
     double e[ND];
     for (int k = 0; k <= N; ++k) e[k] = 0.0;
     if (dim == 1) {
         for (int i = 0; i <= N; ++i) {
             double m = 0.0;
-            for (int p = 0; p <= N; ++p) m += r->w[p] * r->L[i * nd + p] * eps[p];
+            for (int p = 0; p <= N; ++p) m += r->Pm[i * nd + p] * eps[p];
             e[i] += m * m;
         }
     } else {
@@ -566,7 +609,7 @@ static double indicator_raw(const ref_config* c, const refel* r, const double* u
                 double m = 0.0;
                 for (int q = 0; q <= N; ++q)
                     for (int p = 0; p <= N; ++p)
-                        m += r->w[p] * r->w[q] * r->L[i * nd + p] * r->L[j * nd + q] * eps[q * nd + p];
+                        m += r->Pm[i * nd + p] * r->Pm[j * nd + q] * eps[q * nd + p];
                 e[i > j ? i : j] += m * m;
             }
     }
@@ -588,7 +631,7 @@ static double indicator_raw(const ref_config* c, const refel* r, const double* u
 double ref_indicator_raw(const ref_config* c, const double* ue, double* energy_out)
 {
     refel r;
-    refel_init(&r, c->N);
+    refel_init(&r, c->N, c->points);
     return indicator_raw(c, &r, ue, energy_out);
 }
 
@@ -614,7 +657,7 @@ static void features_from_energies(int N, const double* en, double* feat)
 void ref_indicator_features(const ref_config* c, const double* ue, double* feat)
 {
     refel r;
-    refel_init(&r, c->N);
+    refel_init(&r, c->N, c->points);
     double en[ND];
     indicator_raw(c, &r, ue, en);
     features_from_energies(c->N, en, feat);
@@ -638,7 +681,7 @@ static double learned_alpha(const ref_config* c, const refel* r, const double* u
 double ref_learned_alpha(const ref_config* c, const double* ue, int* fallback)
 {
     refel r;
-    refel_init(&r, c->N);
+    refel_init(&r, c->N, c->points);
     int fb = 0;
     double a = learned_alpha(c, &r, ue, &fb);
     if (fallback) *fallback = fb;
@@ -691,7 +734,7 @@ static double scale_element(const ref_config* c, const refel* r, double* ue, int
 double ref_scale_element(const ref_config* c, double* ue, int* mean_bad)
 {
     refel r;
-    refel_init(&r, c->N);
+    refel_init(&r, c->N, c->points);
     return scale_element(c, &r, ue, mean_bad);
 }
 
@@ -711,7 +754,7 @@ static size_t sidx(int M, int np, int e, int k, int v) { return ((size_t)e * np 
 void ref_step_crkfr_form(const ref_config* c, const double* u_in, double* u_out, double dt)
 {
     refel r;
-    refel_init(&r, c->N);
+    refel_init(&r, c->N, c->points);
     const int M = ref_nvar(c->eq), nd = r.nd, dim = eq_dim(c->eq), N = c->N;
     const int nq = dim == 2 ? nd : 1, np = nd * nq, nx = c->nx, ny = c->ny, ne = nx * ny;
     const double dx = (c->x1 - c->x0) / nx, dy = dim == 2 ? (c->y1 - c->y0) / ny : 1.0;
@@ -806,7 +849,7 @@ void ref_step_crkfr_form(const ref_config* c, const double* u_in, double* u_out,
 void ref_means(const ref_config* c, const double* u, double* ubar)
 {
     refel r;
-    refel_init(&r, c->N);
+    refel_init(&r, c->N, c->points);
     int M = ref_nvar(c->eq), nd = r.nd, dim = eq_dim(c->eq);
     int nq = dim == 2 ? nd : 1, np = nd * nq, ne = c->nx * c->ny;
     for (int v = 0; v < M; ++v)
@@ -1057,7 +1100,7 @@ static double dir_share(const ref_config* c, const refel* r, int d, int t, doubl
 void ref_boundary_traces(const ref_config* c, const double* u, double* ghost)
 {
     refel r;
-    refel_init(&r, c->N);
+    refel_init(&r, c->N, c->points);
     int M = ref_nvar(c->eq), nd = r.nd, dim = eq_dim(c->eq);
     int nq = dim == 2 ? nd : 1, np = nd * nq, nx = c->nx, ny = c->ny, ne = nx * ny;
     size_t xsz = (size_t)ny * nq * M, ysz = (size_t)nx * nd * M;
@@ -1091,8 +1134,9 @@ void ref_boundary_traces(const ref_config* c, const double* u, double* ghost)
 int ref_step(const ref_config* c, const double* u_in, double* u_out, double dt,
              const double* alpha_given, double* alpha_out, ref_diag* diag, const double* ghost)
 {
+    if (c->points == REF_POINTS_GLL && c->blend == REF_BLEND_MH) return -1;
     refel r;
-    refel_init(&r, c->N);
+    refel_init(&r, c->N, c->points);
     int M = ref_nvar(c->eq), nd = r.nd, N = c->N, dim = eq_dim(c->eq);
     int nq = dim == 2 ? nd : 1, np = nd * nq, nx = c->nx, ny = c->ny, ne = nx * ny;
     int K = ref_nadm(c->eq);

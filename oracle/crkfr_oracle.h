@@ -31,6 +31,9 @@ enum { REF_CENTRAL_EA = 0, REF_CENTRAL_AE = 1 };
 enum { REF_BC_PERIODIC = 0, REF_BC_OUTFLOW = 1, REF_BC_FARFIELD = 2, REF_BC_REFLECT = 3 };
 enum { REF_BLEND_OFF = 0, REF_BLEND_FO = 1, REF_BLEND_MH = 2 };
 enum { REF_IND_PAPER = 0, REF_IND_CONST = 1, REF_IND_GIVEN = 2, REF_IND_LEARNED = 3 };
+/* solution points (Sec. 2, eq. soln.points): Gauss-Legendre with the Radau
+ * correction, or Gauss-Legendre-Lobatto with the g2 correction */
+enum { REF_POINTS_GL = 0, REF_POINTS_GLL = 1 };
 
 typedef struct {
     int eq, N, nx, ny, stages;
@@ -52,6 +55,7 @@ typedef struct {
     const double* mlp_hi;
     int dissipation;      /* REF_DISS_* */
     int central;          /* REF_CENTRAL_* */
+    int points;           /* REF_POINTS_*; MUSCL-Hancock blending needs GL points */
 } ref_config;
 
 typedef struct {
@@ -67,6 +71,7 @@ typedef struct {
 
 /* reference element on [0,1] */
 void ref_gl(int N, double* xi, double* w);
+void ref_gll(int N, double* xi, double* w);   /* N >= 1; exact to degree 2N-1 */
 void ref_lagrange_at(int N, const double* xi, double x, double* l);
 void ref_diff_matrix(int N, const double* xi, double* D);
 void ref_legendre_orthonormal(int N, const double* xi, double* L); /* L[k*(N+1)+p] = L_k(xi_p) */
@@ -110,6 +115,8 @@ void ref_boundary_traces(const ref_config* c, const double* u, double* ghost);
 /* one full step; alpha_given used when indicator == GIVEN; alpha_out (optional)
  * receives the final blending coefficient per element; ghost (far-field
  * boundaries only) as written by ref_boundary_traces. */
+/* status: 0, -5 (a mean left the admissible set), -1 (unsupported options:
+ * MUSCL-Hancock blending with GLL points) */
 int ref_step(const ref_config* c, const double* u_in, double* u_out, double dt,
              const double* alpha_given, double* alpha_out, ref_diag* diag, const double* ghost);
 

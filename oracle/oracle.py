@@ -8,6 +8,7 @@ import numpy as np
 LINADV1D, EULER1D, EULER2D, TENMOM2D, BURGERS1D, TENMOM1D = 0, 1, 2, 3, 4, 5
 DISS_D2, DISS_D1, DISS_DCSX = 0, 1, 2
 CENTRAL_EA, CENTRAL_AE = 0, 1
+POINTS_GL, POINTS_GLL = 0, 1
 PERIODIC, OUTFLOW, FARFIELD, REFLECT = 0, 1, 2, 3
 BLEND_OFF, BLEND_FO, BLEND_MH = 0, 1, 2
 IND_PAPER, IND_CONST, IND_GIVEN, IND_LEARNED = 0, 1, 2, 3
@@ -41,7 +42,7 @@ class RefConfig(ctypes.Structure):
         ("mlp_nl", ctypes.c_int), ("mlp_dims", ctypes.POINTER(ctypes.c_int)),
         ("mlp_params", ctypes.POINTER(ctypes.c_double)),
         ("mlp_lo", ctypes.POINTER(ctypes.c_double)), ("mlp_hi", ctypes.POINTER(ctypes.c_double)),
-        ("dissipation", ctypes.c_int), ("central", ctypes.c_int),
+        ("dissipation", ctypes.c_int), ("central", ctypes.c_int), ("points", ctypes.c_int),
     ]
 
     @staticmethod
@@ -50,7 +51,7 @@ class RefConfig(ctypes.Structure):
              domain=(0.0, 1.0, 0.0, 1.0), gamma=1.4, adv=1.0, cfl=0.0, cs=0.98,
              alpha_min=1e-3, alpha_max=1.0, alpha_const=0.0,
              src=(0.0, 0.0, 0.0, 0.0), src_lin=(0.0, 0.0), mlp=None, dissipation=DISS_D2,
-             central=CENTRAL_EA):
+             central=CENTRAL_EA, points=POINTS_GL):
         """mlp: (dims, params, lo, hi) of the learned indicator (dims[0] = N)."""
         c = RefConfig()
         c.eq, c.N, c.nx, c.ny = eq, N, nx, ny
@@ -64,7 +65,7 @@ class RefConfig(ctypes.Structure):
         c.alpha_min, c.alpha_max, c.alpha_const = alpha_min, alpha_max, alpha_const
         c.src_amp, c.src_kappa, c.src_xc, c.src_yc = src
         c.src_gx, c.src_gy = src_lin
-        c.dissipation, c.central = dissipation, central
+        c.dissipation, c.central, c.points = dissipation, central, points
         if mlp is not None:
             c.set_mlp(*mlp)
         return c
@@ -105,6 +106,7 @@ def lib():
         dp = ctypes.POINTER(ctypes.c_double)
         cp = ctypes.POINTER(RefConfig)
         L.ref_gl.argtypes = [ctypes.c_int, dp, dp]
+        L.ref_gll.argtypes = [ctypes.c_int, dp, dp]
         L.ref_lagrange_at.argtypes = [ctypes.c_int, dp, ctypes.c_double, dp]
         L.ref_diff_matrix.argtypes = [ctypes.c_int, dp, dp]
         L.ref_legendre_orthonormal.argtypes = [ctypes.c_int, dp, dp]
@@ -149,6 +151,17 @@ def gl(N):
     xi, w = np.zeros(N + 1), np.zeros(N + 1)
     lib().ref_gl(N, _p(xi), _p(w))
     return xi, w
+
+
+def gll(N):
+    xi, w = np.zeros(N + 1), np.zeros(N + 1)
+    lib().ref_gll(N, _p(xi), _p(w))
+    return xi, w
+
+
+def nodes(N, points=0):
+    """Solution points and weights on [0, 1]: GL (points = POINTS_GL) or GLL."""
+    return gll(N) if points == POINTS_GLL else gl(N)
 
 
 def lagrange_at(N, xi, x):

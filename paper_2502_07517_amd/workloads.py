@@ -1,10 +1,11 @@
 """Seeded synthetic inputs for the cRKFR step: initial conditions sampled at
-the Gauss-Legendre solution points (collocation).
+the solution points (collocation), Gauss-Legendre by default.
 
 This module holds no arithmetic of the method.  It only draws seeded problem
 data and samples analytic initial conditions at node positions, which it takes
-from numpy's Gauss-Legendre rule.  Both the oracle tests and the HIP path read
-their inputs from here.
+from numpy's Gauss-Legendre rule (Gauss-Legendre-Lobatto: the end points and
+the roots of numpy's P_N').  Both the oracle tests and the HIP path read their
+inputs from here.
 
 Node layout of every returned array: ``u[var][ey][ex][q][p]`` (1D: ``u[var][ex][p]``),
 p the x-node, q the y-node.
@@ -20,15 +21,25 @@ def gl_nodes(N):
     return 0.5 * (x + 1.0)
 
 
-def node_coords_1d(nx, N, x0, x1):
-    xi = gl_nodes(N)
+def gll_nodes(N):
+    """Gauss-Legendre-Lobatto nodes on [0, 1]: 0, 1 and the roots of P_N'."""
+    inner = np.sort(np.polynomial.legendre.Legendre.basis(N).deriv().roots().real) if N > 1 else np.zeros(0)
+    return 0.5 * (np.concatenate([[-1.0], inner, [1.0]]) + 1.0)
+
+
+def solution_nodes(N, points=0):
+    return gll_nodes(N) if points == 1 else gl_nodes(N)
+
+
+def node_coords_1d(nx, N, x0, x1, points=0):
+    xi = solution_nodes(N, points)
     dx = (x1 - x0) / nx
     return x0 + (np.arange(nx)[:, None] + xi[None, :]) * dx          # [ex][p]
 
 
-def node_coords_2d(nx, ny, N, dom):
+def node_coords_2d(nx, ny, N, dom, points=0):
     x0, x1, y0, y1 = dom
-    xi = gl_nodes(N)
+    xi = solution_nodes(N, points)
     dx, dy = (x1 - x0) / nx, (y1 - y0) / ny
     X = x0 + (np.arange(nx)[None, :, None, None] + xi[None, None, None, :]) * dx
     Y = y0 + (np.arange(ny)[:, None, None, None] + xi[None, None, :, None]) * dy
@@ -103,10 +114,10 @@ def euler1d_smooth(seed, nx, N, x0=0.0, x1=1.0, amp=0.3, gamma=GAMMA):
     return euler1d_cons(rho, v, p, gamma)
 
 
-def burgers_sine(nx, N, amp=0.2, x0=0.0, x1=2 * np.pi, shift=0.0):
+def burgers_sine(nx, N, amp=0.2, x0=0.0, x1=2 * np.pi, shift=0.0, points=0):
     """Burgers data u0 = shift + amp sin(x) (the smooth Burgers test uses amp
     0.2 on [0, 2 pi]: smooth until t = 1/amp = 5)."""
-    return (shift + amp * np.sin(node_coords_1d(nx, N, x0, x1)))[None].copy()
+    return (shift + amp * np.sin(node_coords_1d(nx, N, x0, x1, points)))[None].copy()
 
 
 def blast1d(nx, N):
