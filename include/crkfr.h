@@ -53,6 +53,13 @@ enum { CRKFR_LINADV1D = 0, CRKFR_EULER1D = 1, CRKFR_EULER2D = 2, CRKFR_TENMOM2D 
  * sum_i b_i f(u(i)+-) (eq. evaluate, the default) or the extrapolated
  * time-averaged flux (eq. extrapolate) */
 enum { CRKFR_DISS_D2 = 0, CRKFR_DISS_D1 = 1, CRKFR_DISS_DCSX = 2 };
+
+/* solution points (Sec. 2, eq. soln.points) and their correction function:
+ * Gauss-Legendre with the Radau correction, or Gauss-Legendre-Lobatto with
+ * g2; both enter through g_R'(xi_p) = l_p(1)/w_p (eq. fr.equiv).  The state
+ * holds nodal values at the chosen points; MUSCL-Hancock blending needs GL
+ * points (first-order blending works with both). */
+enum { CRKFR_POINTS_GL = 0, CRKFR_POINTS_GLL = 1 };
 enum { CRKFR_CENTRAL_EA = 0, CRKFR_CENTRAL_AE = 1 };
 
 /* boundary kinds (Sec. 3.3): periodic; outflow (ghost values copy the
@@ -78,7 +85,7 @@ enum { CRKFR_BLEND_OFF = 0, CRKFR_BLEND_FO = 1, CRKFR_BLEND_MH = 2 };
 enum { CRKFR_IND_PAPER = 0, CRKFR_IND_CONST = 1, CRKFR_IND_GIVEN = 2, CRKFR_IND_LEARNED = 3 };
 
 typedef struct {
-    int equation;       /* CRKFR_LINADV1D .. CRKFR_TENMOM2D */
+    int equation;       /* CRKFR_LINADV1D .. CRKFR_TENMOM1D */
     int N;              /* polynomial degree, 1..4; the cRK tableau has min(N+1, 4) stages */
     int nx, ny;         /* elements per direction (ny = 1 in 1D) */
     int bc[4];          /* x-left, x-right, y-bottom, y-top */
@@ -88,6 +95,7 @@ typedef struct {
     double adv;         /* linear advection speed */
     double cfl;         /* CFL(N) of eq. time.step.2d; <= 0: the library's Fourier analysis */
     double cs;          /* safety factor C_s of eq. time.step.2d (paper: 0.98) */
+    int points;         /* CRKFR_POINTS_GL (default, Radau correction) or CRKFR_POINTS_GLL (g2) */
 } crkfr_config;
 
 typedef struct {
@@ -203,8 +211,8 @@ double crkfr_cfl_in_use(const crkfr_solver* s);
  * numbers; system = 0: wave speed equal to the dissipation speed (scalar
  * linear flux), system = 1: every ratio of wave to dissipation speed in [0,1];
  * stages 0 = min(N+1, 4); dissipation CRKFR_DISS_* (D-CSX equals D2 for a
- * linear flux).  Returns -1 for bad arguments. */
-double crkfr_fourier_cfl(int N, int stages, int system, int dissipation, double tol);
+ * linear flux); points CRKFR_POINTS_*.  Returns -1 for bad arguments. */
+double crkfr_fourier_cfl(int N, int stages, int system, int dissipation, int points, double tol);
 
 /* Device time per kernel of the last step measured with HIP events (ms):
  * [0] local cRK, [1] x faces, [2] y faces, [3] update; needs timing = 1. */

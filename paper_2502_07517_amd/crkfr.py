@@ -11,6 +11,7 @@ import numpy as np
 
 LINADV1D, EULER1D, EULER2D, TENMOM2D, BURGERS1D, TENMOM1D = 0, 1, 2, 3, 4, 5
 DISS_D2, DISS_D1, DISS_DCSX = 0, 1, 2
+POINTS_GL, POINTS_GLL = 0, 1
 CENTRAL_EA, CENTRAL_AE = 0, 1
 PERIODIC, OUTFLOW, FARFIELD, REFLECT = 0, 1, 2, 3
 FP64, MP32 = 0, 1
@@ -27,7 +28,8 @@ class Config(ctypes.Structure):
     _fields_ = [("equation", ctypes.c_int), ("N", ctypes.c_int), ("nx", ctypes.c_int), ("ny", ctypes.c_int),
                 ("bc", ctypes.c_int * 4), ("dtype", ctypes.c_int),
                 ("x0", ctypes.c_double), ("x1", ctypes.c_double), ("y0", ctypes.c_double), ("y1", ctypes.c_double),
-                ("gamma", ctypes.c_double), ("adv", ctypes.c_double), ("cfl", ctypes.c_double), ("cs", ctypes.c_double)]
+                ("gamma", ctypes.c_double), ("adv", ctypes.c_double), ("cfl", ctypes.c_double), ("cs", ctypes.c_double),
+                ("points", ctypes.c_int)]
 
 
 class LimiterOpts(ctypes.Structure):
@@ -108,7 +110,7 @@ def lib():
         L.crkfr_nodes_per_element.argtypes = [vp]
         L.crkfr_cfl_in_use.argtypes = [vp]
         L.crkfr_cfl_in_use.restype = ctypes.c_double
-        L.crkfr_fourier_cfl.argtypes = [ip, ip, ip, ip, ctypes.c_double]
+        L.crkfr_fourier_cfl.argtypes = [ip, ip, ip, ip, ip, ctypes.c_double]
         L.crkfr_set_scheme.argtypes = [vp, ctypes.POINTER(Scheme)]
         L.crkfr_fourier_cfl.restype = ctypes.c_double
         L.crkfr_set_timing.argtypes = [vp, ip]
@@ -164,15 +166,15 @@ def _ptr(a):
     return ctypes.c_void_p(a.ctypes.data), 0
 
 
-def fourier_cfl(N, stages=0, system=1, tol=1e-10, dissipation=DISS_D2):
-    return lib().crkfr_fourier_cfl(N, stages, system, dissipation, tol)
+def fourier_cfl(N, stages=0, system=1, tol=1e-10, dissipation=DISS_D2, points=POINTS_GL):
+    return lib().crkfr_fourier_cfl(N, stages, system, dissipation, points, tol)
 
 
 class Solver:
     """One cRKFR solver on the current HIP device (see include/crkfr.h)."""
 
     def __init__(self, equation, N, nx, ny=1, *, bc=(PERIODIC,) * 4, dtype=FP64,
-                 domain=(0.0, 1.0, 0.0, 1.0), gamma=1.4, adv=1.0, cfl=0.0, cs=0.98, stream=None):
+                 domain=(0.0, 1.0, 0.0, 1.0), gamma=1.4, adv=1.0, cfl=0.0, cs=0.98, points=0, stream=None):
         c = Config()
         c.equation, c.N, c.nx, c.ny = equation, N, nx, ny
         for i in range(4):
@@ -180,6 +182,7 @@ class Solver:
         c.dtype = dtype
         c.x0, c.x1, c.y0, c.y1 = domain
         c.gamma, c.adv, c.cfl, c.cs = gamma, adv, cfl, cs
+        c.points = points
         self.cfg = c
         self.M = NVAR[equation]
         self.dim = 2 if equation in (EULER2D, TENMOM2D) else 1

@@ -46,8 +46,9 @@ int crkfr::set_error(int code, const std::string& msg) { return fail(code, msg);
 // reference element (FP64, host)
 // ----------------------------------------------------------------------------
 struct RefElem {
-    int N;
-    double xi[MAXND], w[MAXND], D[MAXND][MAXND], l0[MAXND], l1[MAXND], sub[MAXND + 1], L[MAXND][MAXND];
+    int N, points;
+    double xi[MAXND], w[MAXND], D[MAXND][MAXND], l0[MAXND], l1[MAXND], sub[MAXND + 1];
+    double Pm[MAXND][MAXND];   // Pm[k][p]: orthonormal Legendre coefficient k of the nodal interpolant
 };
 
 // Legendre P_n and P_n' on [-1,1] by the Bonnet recurrence
@@ -64,24 +65,53 @@ static void legendre_pair(int n, double x, double& P, double& dP)
     dP = n * (pm1 - x * p) / (1.0 - x * x);
 }
 
-static void make_ref(int N, RefElem& r)
+// Solution points on [0,1] (eq. soln.points): Gauss-Legendre, or
+// Gauss-Legendre-Lobatto (the zeros of P_{N+1} - P_{N-1}, which vanishes at
+// x = +-1 and is (1 - x^2) P_N' up to a factor; its derivative is
+// (2N+1) P_N).  The correction enters as g_R'(xi_p) = l_p(1)/w_p and
+// g_L'(xi_p) = -l_p(0)/w_p, the identity of the Radau correction with GL
+// points and of g2 with GLL points (eq. fr.equiv).
+static void make_ref(int N, int points, RefElem& r)
 {
     const int n = N + 1;
     r.N = N;
-    // Gauss-Legendre nodes: Newton from the asymptotic guess, then weights
-    for (int i = 0; i < n; ++i) {
-        double x = std::cos(M_PI * (4.0 * (n - 1 - i) + 3.0) / (4.0 * n + 2.0));
-        for (int it = 0; it < 50; ++it) {
+    r.points = points;
+    if (points == CRKFR_POINTS_GLL) {
+        for (int i = 0; i < n; ++i) {
+            double x = -std::cos(M_PI * i / N);
+            if (i > 0 && i < N)
+                for (int it = 0; it < 50; ++it) {
+                    double Pp, dPp, Pm1, dPm1, PN, dPN;
+                    legendre_pair(N + 1, x, Pp, dPp);
+                    legendre_pair(N - 1, x, Pm1, dPm1);
+                    legendre_pair(N, x, PN, dPN);
+                    const double step = (Pp - Pm1) / ((2.0 * N + 1.0) * PN);
+                    x -= step;
+                    if (std::fabs(step) < 1e-17) break;
+                }
+            double PN = 1.0, dPN = 0.0;
+            if (i > 0 && i < N) legendre_pair(N, x, PN, dPN);
+            r.xi[i] = 0.5 + 0.5 * x;
+            r.w[i] = 1.0 / (N * (N + 1.0) * PN * PN);   // 2/(N(N+1)P_N^2) halved for [0,1]
+        }
+        r.xi[0] = 0.0;
+        r.xi[N] = 1.0;
+    } else {
+        // Gauss-Legendre nodes: Newton from the asymptotic guess, then weights
+        for (int i = 0; i < n; ++i) {
+            double x = std::cos(M_PI * (4.0 * (n - 1 - i) + 3.0) / (4.0 * n + 2.0));
+            for (int it = 0; it < 50; ++it) {
+                double P, dP;
+                legendre_pair(n, x, P, dP);
+                double step = P / dP;
+                x -= step;
+                if (std::fabs(step) < 1e-17) break;
+            }
             double P, dP;
             legendre_pair(n, x, P, dP);
-            double step = P / dP;
-            x -= step;
-            if (std::fabs(step) < 1e-17) break;
+            r.xi[i] = 0.5 + 0.5 * x;
+            r.w[i] = 1.0 / ((1.0 - x * x) * dP * dP);   // 2/((1-x^2)P'^2) halved for [0,1]
         }
-        double P, dP;
-        legendre_pair(n, x, P, dP);
-        r.xi[i] = 0.5 + 0.5 * x;
-        r.w[i] = 1.0 / ((1.0 - x * x) * dP * dP);   // 2/((1-x^2)P'^2) halved for [0,1]
     }
     // barycentric weights, Lagrange values at 0 and 1, differentiation matrix
     double bw[MAXND];
@@ -92,12 +122,21 @@ static void make_ref(int N, RefElem& r)
         bw[j] = 1.0 / prod;
     }
     for (int side = 0; side < 2; ++side) {
-        double x = side ? 1.0 : 0.0, den = 0.0, num[MAXND];
+        const double x = side ? 1.0 : 0.0;
+        double* l = side ? r.l1 : r.l0;
+        bool hit = false;
+        for (int j = 0; j < n; ++j)
+            if (r.xi[j] == x) hit = true;
+        if (hit) {   // a node on the face: the Lagrange values are a unit vector
+            for (int j = 0; j < n; ++j) l[j] = r.xi[j] == x ? 1.0 : 0.0;
+            continue;
+        }
+        double den = 0.0, num[MAXND];
         for (int j = 0; j < n; ++j) {
             num[j] = bw[j] / (x - r.xi[j]);
             den += num[j];
         }
-        for (int j = 0; j < n; ++j) (side ? r.l1 : r.l0)[j] = num[j] / den;
+        for (int j = 0; j < n; ++j) l[j] = num[j] / den;
     }
     for (int i = 0; i < n; ++i) {
         double diag = 0.0;
@@ -111,12 +150,40 @@ static void make_ref(int N, RefElem& r)
     r.sub[0] = 0.0;
     for (int p = 0; p < n; ++p) r.sub[p + 1] = r.sub[p] + r.w[p];
     r.sub[n] = 1.0;
-    for (int k = 0; k < n; ++k)
-        for (int p = 0; p < n; ++p) {
+    // modal projection: V[p][k] = L_k(xi_p) with L_k = sqrt(2k+1) P_k(2 xi - 1);
+    // GL: Pm = diag-weighted transpose (the nodal rule is exact to 2N+1);
+    // GLL: Pm = V^{-1} by Gauss-Jordan elimination with partial pivoting
+    double V[MAXND][MAXND];
+    for (int p = 0; p < n; ++p)
+        for (int k = 0; k < n; ++k) {
             double P, dP;
             legendre_pair(k, 2.0 * r.xi[p] - 1.0, P, dP);
-            r.L[k][p] = std::sqrt(2.0 * k + 1.0) * P;
+            V[p][k] = std::sqrt(2.0 * k + 1.0) * P;
         }
+    if (points != CRKFR_POINTS_GLL) {
+        for (int k = 0; k < n; ++k)
+            for (int p = 0; p < n; ++p) r.Pm[k][p] = r.w[p] * V[p][k];
+    } else {
+        double A[MAXND][2 * MAXND];
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < 2 * n; ++j) A[i][j] = j < n ? V[i][j] : (j - n == i ? 1.0 : 0.0);
+        for (int col = 0; col < n; ++col) {
+            int piv = col;
+            for (int i = col + 1; i < n; ++i)
+                if (std::fabs(A[i][col]) > std::fabs(A[piv][col])) piv = i;
+            for (int j = 0; j < 2 * n; ++j) std::swap(A[col][j], A[piv][j]);
+            const double d = A[col][col];
+            for (int j = 0; j < 2 * n; ++j) A[col][j] /= d;
+            for (int i = 0; i < n; ++i) {
+                if (i == col) continue;
+                const double f = A[i][col];
+                for (int j = 0; j < 2 * n; ++j) A[i][j] -= f * A[col][j];
+            }
+        }
+        // V c = u  =>  c = V^{-1} u: rows of V^{-1} give the coefficients
+        for (int k = 0; k < n; ++k)
+            for (int p = 0; p < n; ++p) r.Pm[k][p] = A[k][n + p];
+    }
 }
 
 template <class real>
@@ -126,7 +193,7 @@ static void fill_tab(const RefElem& r, int S, RefTab<real>& t)
     for (int i = 0; i <= r.N; ++i) {
         for (int j = 0; j <= r.N; ++j) {
             t.D[i][j] = (real)r.D[i][j];
-            t.L[i][j] = (real)r.L[i][j];
+            t.Pm[i][j] = (real)r.Pm[i][j];
         }
         t.l0[i] = (real)r.l0[i];
         t.l1[i] = (real)r.l1[i];
@@ -137,10 +204,12 @@ static void fill_tab(const RefElem& r, int S, RefTab<real>& t)
     }
     for (int i = 0; i <= r.N + 1; ++i) t.sub[i] = (real)r.sub[i];
     for (int i = 0; i <= r.N; ++i) {
+        // (GLL points meet across faces: distance 0, unused since MUSCL-Hancock
+        // blending needs GL points)
         const double xm = i > 0 ? r.xi[i - 1] : r.xi[r.N] - 1.0;
         const double xp = i < r.N ? r.xi[i + 1] : 1.0 + r.xi[0];
-        t.rdm[i] = (real)(1.0 / (r.xi[i] - xm));
-        t.rdp[i] = (real)(1.0 / (xp - r.xi[i]));
+        t.rdm[i] = r.xi[i] > xm ? (real)(1.0 / (r.xi[i] - xm)) : (real)0;
+        t.rdp[i] = xp > r.xi[i] ? (real)(1.0 / (xp - r.xi[i])) : (real)0;
     }
     for (int i = 0; i < S; ++i) {
         t.tb[i] = (real)tab_b(S, i);
@@ -231,12 +300,14 @@ static double max_growth(const RefElem& r, int S, double nu, double ratio, int n
     return worst;
 }
 
-extern "C" double crkfr_fourier_cfl(int N, int stages, int system, int dissipation, double tol)
+extern "C" double crkfr_fourier_cfl(int N, int stages, int system, int dissipation, int points, double tol)
 {
-    if (N < 1 || N > 4 || stages == 1 || stages < 0 || stages > 4 || dissipation < 0 || dissipation > 2) return -1.0;
+    if (N < 1 || N > 4 || stages == 1 || stages < 0 || stages > 4 || dissipation < 0 || dissipation > 2 ||
+        points < 0 || points > 1)
+        return -1.0;
     const bool d1 = dissipation == CRKFR_DISS_D1;
     RefElem r;
-    make_ref(N, r);
+    make_ref(N, points, r);
     const int S = stages > 0 ? stages : std::min(N + 1, 4);
     const int nr = system ? 11 : 1, nk = 385;
     auto stable = [&](double nu) {
@@ -247,6 +318,10 @@ extern "C" double crkfr_fourier_cfl(int N, int stages, int system, int dissipati
         return true;
     };
     double lo = 0.0, hi = 1.0;
+    for (int it = 0; it < 4 && stable(hi); ++it) {
+        lo = hi;
+        hi *= 2.0;
+    }
     for (int it = 0; it < 40; ++it) {
         double mid = 0.5 * (lo + hi);
         if (stable(mid)) lo = mid; else hi = mid;
@@ -256,15 +331,16 @@ extern "C" double crkfr_fourier_cfl(int N, int stages, int system, int dissipati
 
 // CFL(N) for (equation kind, stages, D1 or not); the tolerance is 1e-10 except
 // for the 4-stage tableau at N = 4 (weak growth below 5e-6 per step)
-static double cached_cfl(int eq, int N, int stages, int dissipation)
+static double cached_cfl(int eq, int N, int stages, int dissipation, int points)
 {
     static std::mutex mu;
-    static double cache[2][5][5][2] = {};
+    static double cache[2][5][5][2][2] = {};
     const int sys = eq == CRKFR_LINADV1D ? 0 : 1;
     const int d1 = dissipation == CRKFR_DISS_D1 ? 1 : 0;
     std::lock_guard<std::mutex> lk(mu);
-    double& v = cache[sys][N][stages][d1];
-    if (v == 0.0) v = crkfr_fourier_cfl(N, stages, sys, dissipation, N == 4 && stages == 4 ? 1e-5 : 1e-10);
+    double& v = cache[sys][N][stages][d1][points];
+    if (v == 0.0)
+        v = crkfr_fourier_cfl(N, stages, sys, dissipation, points, N == 4 && stages == 4 ? 1e-5 : 1e-10);
     return v;
 }
 
@@ -505,6 +581,17 @@ static void free_all(crkfr_solver* s)
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
 }
 
+// CFL(N) when the configuration gives none: the Fourier value of the scheme;
+// with GLL points and blending also at most the end subcells' width w_0 =
+// 1/(N(N+1)), below which the first-order subcell update (and so the flux
+// limiter's guarantee of admissible means) holds
+static double default_cfl(const crkfr_solver* s)
+{
+    double c = cached_cfl(s->cfg.equation, s->cfg.N, s->stages, s->dissipation, s->cfg.points);
+    if (s->cfg.points == CRKFR_POINTS_GLL && s->lim.blend != CRKFR_BLEND_OFF) c = std::min(c, s->ref.w[0]);
+    return c;
+}
+
 extern "C" int crkfr_create(const crkfr_config* cfg, void* hip_stream, crkfr_solver** out)
 {
     if (!cfg || !out) return fail(CRKFR_EINVAL, "null argument");
@@ -514,6 +601,8 @@ extern "C" int crkfr_create(const crkfr_config* cfg, void* hip_stream, crkfr_sol
     const int dim = cfg->equation == CRKFR_EULER2D || cfg->equation == CRKFR_TENMOM2D ? 2 : 1;
     if (cfg->nx < 1 || cfg->ny < 1 || (dim == 1 && cfg->ny != 1)) return fail(CRKFR_EINVAL, "bad grid size");
     if (cfg->dtype != CRKFR_FP64 && cfg->dtype != CRKFR_MP32) return fail(CRKFR_EINVAL, "bad dtype");
+    if (cfg->points != CRKFR_POINTS_GL && cfg->points != CRKFR_POINTS_GLL)
+        return fail(CRKFR_EINVAL, "bad solution points");
     for (int i = 0; i < (dim == 2 ? 4 : 2); ++i)
         if (cfg->bc[i] < 0 || cfg->bc[i] > 3) return fail(CRKFR_EINVAL, "bad boundary kind");
     for (int i = 0; i < (dim == 2 ? 4 : 2); ++i)
@@ -548,13 +637,13 @@ extern "C" int crkfr_create(const crkfr_config* cfg, void* hip_stream, crkfr_sol
     s->dissipation = CRKFR_DISS_D2;
     s->central = CRKFR_CENTRAL_EA;
     s->mp = cfg->dtype == CRKFR_MP32;
-    s->cfl = cfg->cfl > 0.0 ? cfg->cfl : cached_cfl(cfg->equation, cfg->N, s->stages, s->dissipation);
     if (s->cfg.cs <= 0.0) s->cfg.cs = 0.98;
     s->lim.blend = CRKFR_BLEND_OFF;
     s->lim.alpha_min = 1e-3;
     s->lim.alpha_max = 1.0;
     s->lim.smooth_nbr = 1;
-    make_ref(cfg->N, s->ref);
+    make_ref(cfg->N, cfg->points, s->ref);
+    s->cfl = cfg->cfl > 0.0 ? cfg->cfl : default_cfl(s);
 
     const size_t rs = real_size(s), M = s->M, ne = s->ne, np = s->np;
     const size_t nstate = M * ne * np;
@@ -628,7 +717,10 @@ extern "C" int crkfr_set_limiter(crkfr_solver* s, const crkfr_limiter_opts* o)
         return fail(CRKFR_EINVAL, "bad limiter option");
     if (o->flux_limiter && o->blend == CRKFR_BLEND_OFF)
         return fail(CRKFR_EINVAL, "the flux limiter needs a low-order blend (FO or MH)");
+    if (o->blend == CRKFR_BLEND_MH && s->cfg.points == CRKFR_POINTS_GLL)
+        return fail(CRKFR_EINVAL, "MUSCL-Hancock blending needs Gauss-Legendre points");
     s->lim = *o;
+    if (s->cfg.cfl <= 0.0) s->cfl = default_cfl(s);
     invalidate_graph(s);
     return 0;
 }
@@ -672,7 +764,7 @@ extern "C" int crkfr_set_scheme(crkfr_solver* s, const crkfr_scheme* o)
     s->stages = S;
     s->dissipation = o->dissipation;
     s->central = o->central;
-    if (s->cfg.cfl <= 0.0) s->cfl = cached_cfl(s->cfg.equation, s->cfg.N, S, o->dissipation);
+    if (s->cfg.cfl <= 0.0) s->cfl = default_cfl(s);
     invalidate_graph(s);
     return 0;
 }

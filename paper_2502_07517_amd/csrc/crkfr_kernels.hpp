@@ -53,7 +53,7 @@ struct RefTab {
     real D[MAXND][MAXND];
     real l0[MAXND], l1[MAXND], bR[MAXND], bL[MAXND], w[MAXND], xi[MAXND];
     real sub[MAXND + 1];
-    real L[MAXND][MAXND];   // L[k][p] = orthonormal Legendre L_k(xi_p)
+    real Pm[MAXND][MAXND];  // Pm[k][p]: orthonormal Legendre coefficient k of the nodal interpolant
     real rdm[MAXND], rdp[MAXND];   // 1 / distance to the previous / next solution point (across faces too)
     real ta[4], tb[4];      // cRK tableau: a_{i+1,i}, b_i
 };
@@ -425,8 +425,9 @@ __device__ void mh_subcell(const StepArgs<real>& a, int e, int ex, int ey, int p
 // smoothness indicator (reading of the Hennemann indicator, Sec. 4) and the
 // learned indicator's features
 // ----------------------------------------------------------------------------
-// orthonormal Legendre coefficient (p, q) of the element's indicator quantity
-// eps[k * stride], by Gauss-Legendre quadrature (exact for degree <= N)
+// orthonormal Legendre coefficient (p, q) of the interpolant of the element's
+// indicator quantity eps[k * stride] (projection table Pm: GL quadrature for
+// GL points, the inverse Vandermonde matrix for GLL points)
 template <int DIM, int N, class real>
 __device__ __forceinline__ real modal_coeff(const RefTab<real>& R, int p, int q, const real* eps, int stride)
 {
@@ -437,10 +438,10 @@ __device__ __forceinline__ real modal_coeff(const RefTab<real>& R, int p, int q,
         for (int s2 = 0; s2 < nd; ++s2)
 #pragma unroll
             for (int r = 0; r < nd; ++r)
-                m += R.w[r] * R.w[s2] * R.L[p][r] * R.L[q][s2] * eps[(s2 * nd + r) * stride];
+                m += R.Pm[p][r] * R.Pm[q][s2] * eps[(s2 * nd + r) * stride];
     } else {
 #pragma unroll
-        for (int r = 0; r < nd; ++r) m += R.w[r] * R.L[p][r] * eps[r * stride];
+        for (int r = 0; r < nd; ++r) m += R.Pm[p][r] * eps[r * stride];
     }
     return m;
 }
