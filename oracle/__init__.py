@@ -6,7 +6,7 @@ HIP library.  ``crkfr_oracle.c`` holds the arithmetic; this module is ctypes
 marshalling plus the Fourier stability analysis in ``cfl.py``.
 """
 from .oracle import (  # noqa: F401
-    LINADV1D, EULER1D, EULER2D, TENMOM2D, BURGERS1D, TENMOM1D, PERIODIC, OUTFLOW, FARFIELD, REFLECT,
+    LINADV1D, EULER1D, EULER2D, TENMOM2D, BURGERS1D, TENMOM1D, PERIODIC, OUTFLOW, FARFIELD, REFLECT, INFLOW,
     DISS_D2, DISS_D1, DISS_DCSX, CENTRAL_EA, CENTRAL_AE, POINTS_GL, POINTS_GLL, step_crkfr_form,
     BLEND_OFF, BLEND_FO, BLEND_MH, IND_PAPER, IND_CONST, IND_GIVEN, IND_LEARNED,
     RefConfig, lib, build, gl, gll, nodes, diff_matrix, lagrange_at, legendre_orthonormal,

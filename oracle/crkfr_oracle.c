@@ -905,6 +905,7 @@ typedef struct {
     int ne, np, nd, nq, dim, M;
     double dx, dy;
     const double* ghost;   /* far-field ghost states, or NULL */
+    double dt;             /* step size (inflow data at the stage times) */
 } grid_ctx;
 
 /* far-field ghost state at boundary face point t of the face of element
@@ -918,6 +919,69 @@ static const double* ghost_at(const grid_ctx* g, int ex, int ey, int dir, int si
     size_t xsz = (size_t)ny * nq * M, ysz = (size_t)nx * nd * M;
     if (dir == 0) return g->ghost + side * xsz + ((size_t)ey * nq + t) * M;
     return g->ghost + 2 * xsz + side * ysz + ((size_t)ex * nd + t) * M;
+}
+
+/* time-dependent inflow data (Sec. 3.3): g(tau) at a boundary face point,
+ * from the polynomial coefficients in the far-field ghost layout */
+static int inflow_at(const grid_ctx* g, int ex, int ey, int dir, int side, int t, double tau, double* out)
+{
+    const ref_config* c = g->c;
+    if (c->bc[dir * 2 + side] != REF_BC_INFLOW || !c->inflow) return 0;
+    int M = g->M, nq = g->nq, nd = g->nd, nx = c->nx, ny = c->ny;
+    size_t xsz = (size_t)ny * nq * M, ysz = (size_t)nx * nd * M;
+    size_t gsz = 2 * xsz + (g->dim == 2 ? 2 * ysz : 0);
+    size_t off = dir == 0 ? side * xsz + ((size_t)ey * nq + t) * M : 2 * xsz + side * ysz + ((size_t)ex * nd + t) * M;
+    double s = tau - c->inflow_tref;
+    for (int v = 0; v < M; ++v) {
+        double val = 0.0, pw = 1.0;
+        for (int k = 0; k < c->inflow_ncoef; ++k) {
+            val += c->inflow[(size_t)k * gsz + off + v] * pw;
+            pw *= s;
+        }
+        out[v] = val;
+    }
+    return 1;
+}
+
+/* interface ghost values of an inflow boundary (Sec. 3.3): u^- = g(t^n),
+ * U^- = sum_i b_i g(t^n + c_i dt), F^- = sum_i b_i f(g(t^n + c_i dt)) */
+static int inflow_ghost(const grid_ctx* g, int ex, int ey, int dir, int side, int t, double* un, double* U,
+                        double* F)
+{
+    const ref_config* c = g->c;
+    if (!inflow_at(g, ex, ey, dir, side, t, c->time, un)) return 0;
+    double ta[16], tb[4], tc[4];
+    ref_tableau(c->stages, ta, tb, tc);
+    for (int v = 0; v < g->M; ++v) { U[v] = 0.0; F[v] = 0.0; }
+    for (int i = 0; i < c->stages; ++i) {
+        double gi[MM], f[MM];
+        inflow_at(g, ex, ey, dir, side, t, c->time + tc[i] * g->dt, gi);
+        phys_flux(c, dir, gi, f);
+        for (int v = 0; v < g->M; ++v) { U[v] += tb[i] * gi[v]; F[v] += tb[i] * f[v]; }
+    }
+    return 1;
+}
+
+/* smallest / largest eigenvalue of the normal flux Jacobian in direction d
+ * (for the inflow test: a boundary is fully inflow when every wave enters) */
+static double eig_min(const ref_config* c, int d, const double* u)
+{
+    if (c->eq == REF_LINADV1D) return c->adv;
+    if (c->eq == REF_BURGERS1D) return u[0];
+    double vn = u[1 + d] / u[0];
+    double sx, sy;
+    ref_sigma(c->eq, c->gamma, c->adv, u, &sx, &sy);
+    return vn - ((d == 0 ? sx : sy) - fabs(vn));
+}
+
+static double eig_max(const ref_config* c, int d, const double* u)
+{
+    if (c->eq == REF_LINADV1D) return c->adv;
+    if (c->eq == REF_BURGERS1D) return u[0];
+    double vn = u[1 + d] / u[0];
+    double sx, sy;
+    ref_sigma(c->eq, c->gamma, c->adv, u, &sx, &sy);
+    return vn + ((d == 0 ? sx : sy) - fabs(vn));
 }
 
 /* solid wall normal to direction d (Sec. 3.3, eq. reflect.time.avg): the
@@ -987,7 +1051,9 @@ static void mh_element(const grid_ctx* g, int ex, int ey, double dt, int blend, 
                     } else {
                         int en = nbr_elem(g, ex, ey, d, 0);
                         int kn = d == 0 ? q * nd + N : N * nd + p;
+                        double ginb[MM];
                         const double* gh = en < 0 ? ghost_at(g, ex, ey, d, 0, d == 0 ? q : p) : NULL;
+                        if (en < 0 && inflow_at(g, ex, ey, d, 0, d == 0 ? q : p, c->time, ginb)) gh = ginb;
                         const int wl = en < 0 && wall(c, d, 0);
                         for (int v = 0; v < M; ++v)
                             um[v] = en >= 0 ? g->u[gidx(g, v, en, kn)]
@@ -1001,7 +1067,9 @@ static void mh_element(const grid_ctx* g, int ex, int ey, double dt, int blend, 
                     } else {
                         int en = nbr_elem(g, ex, ey, d, 1);
                         int kn = d == 0 ? q * nd + 0 : 0 * nd + p;
+                        double ginb[MM];
                         const double* gh = en < 0 ? ghost_at(g, ex, ey, d, 1, d == 0 ? q : p) : NULL;
+                        if (en < 0 && inflow_at(g, ex, ey, d, 1, d == 0 ? q : p, c->time, ginb)) gh = ginb;
                         const int wl = en < 0 && wall(c, d, 1);
                         for (int v = 0; v < M; ++v)
                             up[v] = en >= 0 ? g->u[gidx(g, v, en, kn)]
@@ -1141,7 +1209,7 @@ int ref_step(const ref_config* c, const double* u_in, double* u_out, double dt,
     int nq = dim == 2 ? nd : 1, np = nd * nq, nx = c->nx, ny = c->ny, ne = nx * ny;
     int K = ref_nadm(c->eq);
     double dx = (c->x1 - c->x0) / nx, dy = (c->y1 - c->y0) / ny;
-    grid_ctx g = {c, &r, u_in, ne, np, nd, nq, dim, M, dx, dy, ghost};
+    grid_ctx g = {c, &r, u_in, ne, np, nd, nq, dim, M, dx, dy, ghost, dt};
     int blend = c->blend;
     int limit = c->flux_limiter && blend != REF_BLEND_OFF && K > 0;
 
@@ -1257,8 +1325,18 @@ int ref_step(const ref_config* c, const double* u_in, double* u_out, double dt,
                 const int wA = !A && wall(c, d, 0), wB = !B && wall(c, d, 1);
                 const double* gA = !A ? ghost_at(&g, ex, ey, d, 0, t) : NULL;
                 const double* gB = !B ? ghost_at(&g, d == 0 ? ex - 1 : ex, d == 0 ? ey : ey - 1, d, 1, t) : NULL;
+                /* time-dependent inflow: u^- = g(t^n) serves as the ghost state,
+                 * F^- and U^- are the time averages of the boundary data */
+                const int exB = d == 0 ? ex - 1 : ex, eyB = d == 0 ? ey : ey - 1;
+                double giA[MM], giB[MM], UiA[MM], UiB[MM], FiA[MM], FiB[MM];
+                const int iA = !A && inflow_ghost(&g, ex, ey, d, 0, t, giA, UiA, FiA);
+                const int iB = !B && inflow_ghost(&g, exB, eyB, d, 1, t, giB, UiB, FiB);
+                if (iA) gA = giA;
+                if (iB) gB = giB;
                 if (!A) {
-                    if (gA) {
+                    if (iA) {
+                        for (int v = 0; v < M; ++v) { Fm[v] = FiA[v]; Um[v] = UiA[v]; unm[v] = giA[v]; }
+                    } else if (gA) {
                         phys_flux(c, d, gA, Fm);
                         for (int v = 0; v < M; ++v) { Um[v] = gA[v]; unm[v] = gA[v]; }
                     } else if (wA) {
@@ -1271,7 +1349,9 @@ int ref_step(const ref_config* c, const double* u_in, double* u_out, double dt,
                     }
                 }
                 if (!B) {
-                    if (gB) {
+                    if (iB) {
+                        for (int v = 0; v < M; ++v) { Fp[v] = FiB[v]; Up[v] = UiB[v]; unp[v] = giB[v]; }
+                    } else if (gB) {
                         phys_flux(c, d, gB, Fp);
                         for (int v = 0; v < M; ++v) { Up[v] = gB[v]; unp[v] = gB[v]; }
                     } else if (wB) {
@@ -1307,8 +1387,10 @@ int ref_step(const ref_config* c, const double* u_in, double* u_out, double dt,
                             if (A) um[v] = d == 0 ? A->uixR[i][t][v] : A->uiyT[i][t][v];
                             if (B) up[v] = d == 0 ? B->uixL[i][t][v] : B->uiyB[i][t][v];
                         }
-                        if (!A) for (int v = 0; v < M; ++v) um[v] = gA ? gA[v] : (wA ? mirror_sign(c->eq, d, v) : 1.0) * up[v];
-                        if (!B) for (int v = 0; v < M; ++v) up[v] = gB ? gB[v] : (wB ? mirror_sign(c->eq, d, v) : 1.0) * um[v];
+                        if (iA) inflow_at(&g, ex, ey, d, 0, t, c->time + tc[i] * dt, um);
+                        else if (!A) for (int v = 0; v < M; ++v) um[v] = gA ? gA[v] : (wA ? mirror_sign(c->eq, d, v) : 1.0) * up[v];
+                        if (iB) inflow_at(&g, exB, eyB, d, 1, t, c->time + tc[i] * dt, up);
+                        else if (!B) for (int v = 0; v < M; ++v) up[v] = gB ? gB[v] : (wB ? mirror_sign(c->eq, d, v) : 1.0) * um[v];
                         double li = fmax(sigma_trace(c, d, um, uA), sigma_trace(c, d, up, uB));
                         for (int v = 0; v < M; ++v) Dis[v] += tb[i] * 0.5 * li * (up[v] - um[v]);
                     }
@@ -1319,6 +1401,10 @@ int ref_step(const ref_config* c, const double* u_in, double* u_out, double dt,
                 }
                 double F[MM];
                 for (int v = 0; v < M; ++v) F[v] = 0.5 * (Fm[v] + Fp[v]) - Dis[v];
+                /* a fully inflow boundary (every wave enters) takes F = F^- */
+                const int fiA = iA && eig_min(c, d, giA) > 0.0, fiB = iB && eig_max(c, d, giB) < 0.0;
+                if (fiA) for (int v = 0; v < M; ++v) F[v] = Fm[v];
+                if (fiB) for (int v = 0; v < M; ++v) F[v] = Fp[v];
 
                 if (blend != REF_BLEND_OFF) {
                     /* predicted values at the face-adjacent subcells */
@@ -1327,9 +1413,16 @@ int ref_step(const ref_config* c, const double* u_in, double* u_out, double dt,
                         if (A) sA[v] = d == 0 ? mh[eL].xp[kA][v] : mh[eL].yp[kA][v];
                         if (B) sB[v] = d == 0 ? mh[eR].xm[kB][v] : mh[eR].ym[kB][v];
                     }
-                    if (!A) for (int v = 0; v < M; ++v) sA[v] = gA ? gA[v] : (wA ? mirror_sign(c->eq, d, v) : 1.0) * sB[v];
-                    if (!B) for (int v = 0; v < M; ++v) sB[v] = gB ? gB[v] : (wB ? mirror_sign(c->eq, d, v) : 1.0) * sA[v];
+                    /* inflow: the boundary data at the half time (the predicted
+                     * subcell values are centred there); a fully inflow face
+                     * takes its flux */
+                    if (iA) inflow_at(&g, ex, ey, d, 0, t, c->time + 0.5 * dt, sA);
+                    else if (!A) for (int v = 0; v < M; ++v) sA[v] = gA ? gA[v] : (wA ? mirror_sign(c->eq, d, v) : 1.0) * sB[v];
+                    if (iB) inflow_at(&g, exB, eyB, d, 1, t, c->time + 0.5 * dt, sB);
+                    else if (!B) for (int v = 0; v < M; ++v) sB[v] = gB ? gB[v] : (wB ? mirror_sign(c->eq, d, v) : 1.0) * sA[v];
                     rusanov(c, d, sA, sB, fLO);   /* eq. mh.at.face (fo.at.face when FO) */
+                    if (fiA) phys_flux(c, d, sA, fLO);
+                    if (fiB) phys_flux(c, d, sB, fLO);
                     double af = A && B ? 0.5 * (alpha[eL] + alpha[eR]) : alpha[A ? eL : eR];
                     for (int v = 0; v < M; ++v) F[v] = (1.0 - af) * F[v] + af * fLO[v];   /* eq. Fblend */
 

@@ -28,7 +28,7 @@ enum { REF_LINADV1D = 0, REF_EULER1D = 1, REF_EULER2D = 2, REF_TENMOM2D = 3, REF
 enum { REF_DISS_D2 = 0, REF_DISS_D1 = 1, REF_DISS_DCSX = 2 };
 /* central part (Sec. 3.1.2): eq. evaluate (EA) or eq. extrapolate (AE) */
 enum { REF_CENTRAL_EA = 0, REF_CENTRAL_AE = 1 };
-enum { REF_BC_PERIODIC = 0, REF_BC_OUTFLOW = 1, REF_BC_FARFIELD = 2, REF_BC_REFLECT = 3 };
+enum { REF_BC_PERIODIC = 0, REF_BC_OUTFLOW = 1, REF_BC_FARFIELD = 2, REF_BC_REFLECT = 3, REF_BC_INFLOW = 4 };
 enum { REF_BLEND_OFF = 0, REF_BLEND_FO = 1, REF_BLEND_MH = 2 };
 enum { REF_IND_PAPER = 0, REF_IND_CONST = 1, REF_IND_GIVEN = 2, REF_IND_LEARNED = 3 };
 /* solution points (Sec. 2, eq. soln.points): Gauss-Legendre with the Radau
@@ -56,6 +56,14 @@ typedef struct {
     int dissipation;      /* REF_DISS_* */
     int central;          /* REF_CENTRAL_* */
     int points;           /* REF_POINTS_*; MUSCL-Hancock blending needs GL points */
+    /* time-dependent inflow boundaries (REF_BC_INFLOW, Sec. 3.3): boundary
+     * data g(tau) = sum_k inflow[k][...] (tau - inflow_tref)^k, k <
+     * inflow_ncoef, with [...] the layout of the far-field ghost states;
+     * time = t^n of the step */
+    const double* inflow;
+    int inflow_ncoef;
+    double inflow_tref;
+    double time;
 } ref_config;
 
 typedef struct {

@@ -9,7 +9,7 @@ LINADV1D, EULER1D, EULER2D, TENMOM2D, BURGERS1D, TENMOM1D = 0, 1, 2, 3, 4, 5
 DISS_D2, DISS_D1, DISS_DCSX = 0, 1, 2
 CENTRAL_EA, CENTRAL_AE = 0, 1
 POINTS_GL, POINTS_GLL = 0, 1
-PERIODIC, OUTFLOW, FARFIELD, REFLECT = 0, 1, 2, 3
+PERIODIC, OUTFLOW, FARFIELD, REFLECT, INFLOW = 0, 1, 2, 3, 4
 BLEND_OFF, BLEND_FO, BLEND_MH = 0, 1, 2
 IND_PAPER, IND_CONST, IND_GIVEN, IND_LEARNED = 0, 1, 2, 3
 
@@ -43,6 +43,8 @@ class RefConfig(ctypes.Structure):
         ("mlp_params", ctypes.POINTER(ctypes.c_double)),
         ("mlp_lo", ctypes.POINTER(ctypes.c_double)), ("mlp_hi", ctypes.POINTER(ctypes.c_double)),
         ("dissipation", ctypes.c_int), ("central", ctypes.c_int), ("points", ctypes.c_int),
+        ("inflow", ctypes.POINTER(ctypes.c_double)), ("inflow_ncoef", ctypes.c_int),
+        ("inflow_tref", ctypes.c_double), ("time", ctypes.c_double),
     ]
 
     @staticmethod
@@ -69,6 +71,15 @@ class RefConfig(ctypes.Structure):
         if mlp is not None:
             c.set_mlp(*mlp)
         return c
+
+    def set_inflow(self, coeffs, t_ref):
+        """Inflow boundary data g(tau) = sum_k coeffs[k] (tau - t_ref)^k, each
+        coeffs[k] in the layout of the far-field ghost states."""
+        keep = _f64(coeffs)
+        self._inflow_keep = keep   # the C side only borrows the array
+        self.inflow = keep.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        self.inflow_ncoef = keep.shape[0]
+        self.inflow_tref = float(t_ref)
 
     def set_mlp(self, dims, params, lo, hi):
         keep = (np.ascontiguousarray(dims, dtype=np.int32), _f64(params), _f64(lo), _f64(hi))
@@ -285,8 +296,11 @@ def has_farfield(cfg):
     return any(cfg.bc[i] == FARFIELD for i in range(4))
 
 
-def step(cfg, u, dt, alpha_given=None, ghost=None):
-    """One cRKFR step; returns (u_new, alpha, diag dict, status)."""
+def step(cfg, u, dt, alpha_given=None, ghost=None, t=None):
+    """One cRKFR step; returns (u_new, alpha, diag dict, status).  t: the
+    time t^n of the step (inflow boundaries)."""
+    if t is not None:
+        cfg.time = float(t)
     u = _f64(u)
     out = np.empty_like(u)
     ne = cfg.nx * cfg.ny
