@@ -70,8 +70,15 @@ enum { CRKFR_CENTRAL_EA = 0, CRKFR_CENTRAL_AE = 1 };
  * solid wall (eq. reflect.time.avg: the ghost traces mirror the interior
  * ones — normal momentum, and the ten-moment E12, change sign in u and U,
  * the other components in F — and the subcell ghosts mirror the boundary
- * subcell; Euler and ten-moment only) */
-enum { CRKFR_BC_PERIODIC = 0, CRKFR_BC_OUTFLOW = 1, CRKFR_BC_FARFIELD = 2, CRKFR_BC_REFLECT = 3 };
+ * subcell; Euler and ten-moment only); time-dependent inflow (the boundary
+ * data g(x_b, t) of crkfr_set_inflow: u^- = g(t^n), U^- = sum_i b_i
+ * g(t^n + c_i dt), F^- = sum_i b_i f(g(t^n + c_i dt)); F = F^- where every
+ * wave of the normal flux Jacobian at g(t^n) enters the domain, otherwise
+ * the D2 flux with these ghost values; the subcell ghost is g(t^n), its
+ * predicted value g(t^n + dt/2)) */
+enum { CRKFR_BC_PERIODIC = 0, CRKFR_BC_OUTFLOW = 1, CRKFR_BC_FARFIELD = 2, CRKFR_BC_REFLECT = 3,
+       CRKFR_BC_INFLOW = 4 };
+#define CRKFR_INFLOW_MAXCOEF 5
 
 /* arithmetic: FP64 throughout, or FP32 bulk with FP64 element means and
  * FP64 admissibility roots (the state is held as FP64 means plus FP32
@@ -160,6 +167,19 @@ int crkfr_set_limiter(crkfr_solver* s, const crkfr_limiter_opts* opts);
 
 /* Source term (App. B; ten-moment only).  Default: none. */
 int crkfr_set_source(crkfr_solver* s, const crkfr_source* src);
+
+/* Boundary data of the inflow boundaries (Sec. 3.3) as a polynomial in time:
+ * g(x_b, t) = sum_{k < ncoef} coeffs[k][...] (t - t_ref)^k, 1 <= ncoef <= 5.
+ * coeffs[k] holds one state per boundary face point in the layout x-left
+ * [ny][nq][nvar], x-right [ny][nq][nvar], then in 2D y-bottom [nx][nd][nvar],
+ * y-top [nx][nd][nvar] (nq = N+1 in 2D, 1 in 1D; nd = N+1); entries of
+ * boundaries that are not inflow are ignored.  Host (on_device = 0, copied
+ * before return) or device memory (copied in stream order).  The data stays
+ * until the next call: callers with data that a polynomial of degree 4 does
+ * not represent re-anchor it (e.g. the Taylor expansion at t^n before each
+ * step).  Steps fail with ESTATE until it is set.  Errors: EINVAL (no inflow
+ * boundary, bad ncoef). */
+int crkfr_set_inflow(crkfr_solver* s, const double* coeffs, int ncoef, double t_ref, int on_device);
 
 /* Set the nodal state (layout above, nvar*ny*nx*(N+1)^d doubles).  u points
  * to host memory, or to device memory when on_device = 1.  Also sets t = 0,

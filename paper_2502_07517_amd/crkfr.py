@@ -13,7 +13,7 @@ LINADV1D, EULER1D, EULER2D, TENMOM2D, BURGERS1D, TENMOM1D = 0, 1, 2, 3, 4, 5
 DISS_D2, DISS_D1, DISS_DCSX = 0, 1, 2
 POINTS_GL, POINTS_GLL = 0, 1
 CENTRAL_EA, CENTRAL_AE = 0, 1
-PERIODIC, OUTFLOW, FARFIELD, REFLECT = 0, 1, 2, 3
+PERIODIC, OUTFLOW, FARFIELD, REFLECT, INFLOW = 0, 1, 2, 3, 4
 FP64, MP32 = 0, 1
 BLEND_OFF, BLEND_FO, BLEND_MH = 0, 1, 2
 IND_PAPER, IND_CONST, IND_GIVEN, IND_LEARNED = 0, 1, 2, 3
@@ -71,7 +71,7 @@ SYMBOLS = ["crkfr_create", "crkfr_destroy", "crkfr_set_limiter", "crkfr_set_sour
            "crkfr_mlp_num_params", "crkfr_mlp_set_params", "crkfr_mlp_get_params", "crkfr_mlp_set_box",
            "crkfr_mlp_get_box", "crkfr_mlp_fit_box", "crkfr_mlp_forward", "crkfr_mlp_loss_grad",
            "crkfr_mlp_train", "crkfr_batch_set_t_end", "crkfr_batch_set_timing", "crkfr_batch_phase_times",
-           "crkfr_set_scheme"]
+           "crkfr_set_scheme", "crkfr_set_inflow"]
 
 _lib = None
 
@@ -112,6 +112,7 @@ def lib():
         L.crkfr_cfl_in_use.restype = ctypes.c_double
         L.crkfr_fourier_cfl.argtypes = [ip, ip, ip, ip, ip, ctypes.c_double]
         L.crkfr_set_scheme.argtypes = [vp, ctypes.POINTER(Scheme)]
+        L.crkfr_set_inflow.argtypes = [vp, ctypes.c_void_p, ip, ctypes.c_double, ip]
         L.crkfr_fourier_cfl.restype = ctypes.c_double
         L.crkfr_set_timing.argtypes = [vp, ip]
         L.crkfr_get_kernel_times.argtypes = [vp, ctypes.POINTER(ctypes.c_float)]
@@ -218,6 +219,16 @@ class Solver:
     def set_scheme(self, stages=0, dissipation=DISS_D2, central=CENTRAL_EA):
         o = Scheme(stages, dissipation, central)
         _check(lib().crkfr_set_scheme(self.h, ctypes.byref(o)))
+
+    def set_inflow(self, coeffs, t_ref):
+        """coeffs[k][...]: polynomial coefficients of the inflow data in the
+        far-field ghost layout (numpy array or device tensor of float64)."""
+        if not hasattr(coeffs, "data_ptr"):
+            coeffs = np.ascontiguousarray(coeffs, dtype=np.float64)
+        elif not coeffs.is_contiguous() or coeffs.element_size() != 8 or not coeffs.is_floating_point():
+            raise ValueError("coeffs must be a contiguous float64 tensor")
+        p, dev = _ptr(coeffs)
+        _check(lib().crkfr_set_inflow(self.h, p, int(coeffs.shape[0]), float(t_ref), dev))
 
     def set_source(self, enabled=1, amp=0.0, kappa=0.0, xc=0.0, yc=0.0, gx=0.0, gy=0.0):
         s = Source(enabled, amp, kappa, xc, yc, gx, gy)

@@ -363,6 +363,8 @@ struct crkfr_solver {
     void* u[2];
     double* ubar[2];
     void *uHp, *trx, *trY, *Fx, *Gy, *dtS, *ghost;
+    double* inflow;          // inflow data: t_ref, number of coefficients, coefficients
+    bool has_inflow_data;
     double *alpha_raw, *alpha_out, *alpha_given;
     double* alpha_judge;     // the smoothness indicator's alpha (learned-indicator runs, features)
     float* feat;             // learned-indicator features [e][N]
@@ -438,6 +440,8 @@ static StepArgs<real> step_args(const crkfr_solver* s, int in, int out)
     a.alpha_out = s->alpha_out;
     a.alpha_given = s->alpha_given;
     a.ghost = (const real*)s->ghost;
+    a.inflow = s->inflow;
+    a.tn_dev = s->t_dev + 1;
     a.dt_dev = s->dt_dev;
     a.blend = s->lim.blend;
     a.indicator = s->lim.indicator;
@@ -571,7 +575,7 @@ static void free_all(crkfr_solver* s)
 {
     void* ptrs[] = {s->u[0], s->u[1], s->ubar[0], s->ubar[1], s->uHp, s->trx, s->trY, s->Fx, s->Gy, s->dtS,
                     s->ghost, s->alpha_raw, s->alpha_out, s->alpha_given, s->alpha_judge, s->feat,
-                    s->dt_dev, s->t_dev,
+                    s->dt_dev, s->t_dev, s->inflow,
                     s->rate_bits, s->diag, s->steps};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -579,6 +583,13 @@ static void free_all(crkfr_solver* s)
     for (int i = 0; i < 6; ++i)
         if (s->ev[i]) (void)hipEventDestroy(s->ev[i]);
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+}
+
+// values in the far-field ghost layout: x-left, x-right [ny][nq][M], then in 2D
+// y-bottom, y-top [nx][nd][M]
+static size_t ghost_size(const crkfr_solver* s)
+{
+    return (2 * (size_t)s->cfg.ny * s->nq + (s->dim == 2 ? 2 * (size_t)s->cfg.nx * s->nd : 0)) * s->M;
 }
 
 // CFL(N) when the configuration gives none: the Fourier value of the scheme;
@@ -604,7 +615,7 @@ extern "C" int crkfr_create(const crkfr_config* cfg, void* hip_stream, crkfr_sol
     if (cfg->points != CRKFR_POINTS_GL && cfg->points != CRKFR_POINTS_GLL)
         return fail(CRKFR_EINVAL, "bad solution points");
     for (int i = 0; i < (dim == 2 ? 4 : 2); ++i)
-        if (cfg->bc[i] < 0 || cfg->bc[i] > 3) return fail(CRKFR_EINVAL, "bad boundary kind");
+        if (cfg->bc[i] < 0 || cfg->bc[i] > 4) return fail(CRKFR_EINVAL, "bad boundary kind");
     for (int i = 0; i < (dim == 2 ? 4 : 2); ++i)
         if (cfg->bc[i] == CRKFR_BC_REFLECT && (cfg->equation == CRKFR_LINADV1D || cfg->equation == CRKFR_BURGERS1D))
             return fail(CRKFR_EINVAL, "solid walls are defined for the Euler and ten-moment systems");
@@ -665,13 +676,19 @@ extern "C" int crkfr_create(const crkfr_config* cfg, void* hip_stream, crkfr_sol
     if (dim == 2) ok &= alloc(&s->Gy, M * (size_t)(cfg->ny + 1) * cfg->nx * s->nd * rs);
     if (is_tenmom(cfg->equation)) ok &= alloc(&s->dtS, nstate * rs);
     ok &= alloc(&s->ghost, (2 * (size_t)cfg->ny * s->nq + (dim == 2 ? 2 * (size_t)cfg->nx * s->nd : 0)) * M * rs);
+    bool any_inflow = false;
+    for (int i = 0; i < (dim == 2 ? 4 : 2); ++i) any_inflow |= cfg->bc[i] == CRKFR_BC_INFLOW;
+    if (any_inflow) {
+        ok &= alloc((void**)&s->inflow, (2 + CRKFR_INFLOW_MAXCOEF * ghost_size(s)) * sizeof(double));
+        if (s->inflow) ok &= hipMemset(s->inflow, 0, 2 * sizeof(double)) == hipSuccess;   // no data yet
+    }
     ok &= alloc((void**)&s->alpha_raw, ne * sizeof(double));
     ok &= alloc((void**)&s->alpha_out, ne * sizeof(double));
     ok &= alloc((void**)&s->alpha_given, ne * sizeof(double));
     ok &= alloc((void**)&s->alpha_judge, ne * sizeof(double));
     ok &= alloc((void**)&s->feat, ne * (size_t)cfg->N * sizeof(float));
     ok &= alloc((void**)&s->dt_dev, sizeof(double));
-    ok &= alloc((void**)&s->t_dev, sizeof(double));
+    ok &= alloc((void**)&s->t_dev, 2 * sizeof(double));   // t, and t^n of the current step
     ok &= alloc((void**)&s->rate_bits, RATE_SLOTS * sizeof(unsigned long long));
     ok &= alloc((void**)&s->diag, D_NCOUNT * sizeof(unsigned long long));
     ok &= alloc((void**)&s->steps, sizeof(long long));
@@ -722,6 +739,22 @@ extern "C" int crkfr_set_limiter(crkfr_solver* s, const crkfr_limiter_opts* o)
     s->lim = *o;
     if (s->cfg.cfl <= 0.0) s->cfl = default_cfl(s);
     invalidate_graph(s);
+    return 0;
+}
+
+extern "C" int crkfr_set_inflow(crkfr_solver* s, const double* coeffs, int ncoef, double t_ref, int on_device)
+{
+    if (!s || !coeffs) return fail(CRKFR_EINVAL, "null argument");
+    if (!s->inflow) return fail(CRKFR_EINVAL, "the configuration has no inflow boundary");
+    if (ncoef < 1 || ncoef > CRKFR_INFLOW_MAXCOEF) return fail(CRKFR_EINVAL, "ncoef must be in 1..5");
+    const size_t n = ghost_size(s) * ncoef;
+    const double head[2] = {t_ref, (double)ncoef};
+    // the step kernels read the buffer on the solver's stream: ordered after this copy
+    HIP_TRY(hipMemcpyAsync(s->inflow, head, sizeof(head), hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipMemcpyAsync(s->inflow + 2, coeffs, n * sizeof(double),
+                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s->stream));
+    if (!on_device) HIP_TRY(hipStreamSynchronize(s->stream));   // the caller may reuse its host buffer
+    s->has_inflow_data = true;
     return 0;
 }
 
@@ -864,6 +897,7 @@ static int enqueue_step(crkfr_solver* s, double dt_fixed, double t_end)
 {
     int lrc = check_learned(s);
     if (lrc) return lrc;
+    if (s->inflow && !s->has_inflow_data) return fail(CRKFR_ESTATE, "inflow boundaries need data (crkfr_set_inflow)");
     PrepArgs pa;
     pa.dt_dev = s->dt_dev;
     pa.t_dev = s->t_dev;
@@ -1212,6 +1246,8 @@ extern "C" int crkfr_batch_create(crkfr_solver* const* solvers, int count, void*
             return fail(CRKFR_ESTATE, "every batch member needs a state");
         }
         int lrc = check_learned(s);
+        if (!lrc && s->inflow && !s->has_inflow_data)
+            lrc = fail(CRKFR_ESTATE, "inflow boundaries need data (crkfr_set_inflow)");
         if (lrc) {
             free_batch(b);
             delete b;

@@ -33,7 +33,7 @@
 namespace crkfr {
 
 constexpr int MAXND = 5;
-enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_FARFIELD = 2, BC_REFLECT = 3 };
+enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_FARFIELD = 2, BC_REFLECT = 3, BC_INFLOW = 4 };
 enum { BLEND_OFF = 0, BLEND_FO = 1, BLEND_MH = 2 };
 enum { IND_PAPER = 0, IND_CONST = 1, IND_GIVEN = 2, IND_LEARNED = 3 };
 enum { DISS_D2 = 0, DISS_D1 = 1, DISS_DCSX = 2 };
@@ -77,6 +77,10 @@ struct StepArgs {
     double* alpha_out;     // per element, final
     const double* alpha_given;
     const real* ghost;     // far-field ghost states, xL [ny][nq][M] | xR | yB [nx][nd][M] | yT
+    // time-dependent inflow data: [0] t_ref, [1] number of coefficients, then
+    // coefficient k at 2 + k * (ghost size) in the far-field ghost layout
+    const double* inflow;
+    const double* tn_dev;  // t^n of the current step (written by the time-step kernel)
     const double* dt_dev;
     int blend, indicator, smooth, flux_limiter, scaling, C;
     double alpha_min, alpha_max, alpha_const;
@@ -174,6 +178,43 @@ __device__ __forceinline__ const real* ghost_at(const StepArgs<real>& a, int M, 
     size_t xsz = (size_t)a.ny * nq * M, ysz = (size_t)a.nx * nd * M;
     if (dir == 0) return a.ghost + side * xsz + ((size_t)ey * nq + t) * M;
     return a.ghost + 2 * xsz + side * ysz + ((size_t)ex * nd + t) * M;
+}
+
+// time-dependent inflow (Sec. 3.3): the boundary data g(tau) at a boundary
+// face point, from its polynomial in tau - t_ref (Horner's rule in FP64)
+template <class real>
+__device__ __forceinline__ bool inflow_at(const StepArgs<real>& a, int M, int nd, int nq, int dim, int ex, int ey,
+                                          int dir, int side, int t, double tau, real* out)
+{
+    if (a.bc[dir * 2 + side] != BC_INFLOW) return false;
+    const size_t xsz = (size_t)a.ny * nq * M, ysz = (size_t)a.nx * nd * M;
+    const size_t gsz = 2 * xsz + (dim == 2 ? 2 * ysz : 0);
+    const size_t off = dir == 0 ? side * xsz + ((size_t)ey * nq + t) * M
+                                : 2 * xsz + side * ysz + ((size_t)ex * nd + t) * M;
+    const double s = tau - a.inflow[0];
+    const double ncd = a.inflow[1];
+    const int nc = ncd >= 1.0 && ncd <= 5.0 ? (int)ncd : 0;   // at most the coefficients the buffer holds
+    const double* cf = a.inflow + 2 + off;
+    for (int v = 0; v < M; ++v) {
+        double val = 0.0;
+        for (int k = nc - 1; k >= 0; --k) val = val * s + cf[(size_t)k * gsz + v];
+        out[v] = (real)val;
+    }
+    return true;
+}
+
+// smallest / largest eigenvalue of the normal flux Jacobian (fully inflow
+// faces: every wave enters the domain)
+template <class Eq, class real>
+__device__ __forceinline__ real eig_extreme(int d, const real* u, bool largest, const Phys& P)
+{
+    if constexpr (Eq::ID == 0) return (real)P.adv;
+    else if constexpr (Eq::ID == 4) return u[0];
+    else {
+        const real vn = u[1 + d] / u[0];
+        const real c = (d == 0 ? Eq::sx(u, P) : Eq::sy(u, P)) - fabs(vn);
+        return largest ? vn + c : vn - c;
+    }
 }
 
 // solid wall normal to direction dir (Sec. 3.3, eq. reflect.time.avg): the
@@ -307,6 +348,7 @@ __device__ void mh_subcell(const StepArgs<real>& a, int e, int ex, int ey, int p
                     if (g) {
 #pragma unroll
                         for (int v = 0; v < M; ++v) um[v] = g[v];
+                    } else if (inflow_at(a, M, nd, nq, Eq::DIM, ex, ey, d, 0, d == 0 ? q : p, *a.tn_dev, um)) {
                     } else if (is_wall(a, d, 0)) {
 #pragma unroll
                         for (int v = 0; v < M; ++v) um[v] = mirror_flips<Eq>(d, v) ? -u[v] : u[v];
@@ -329,6 +371,7 @@ __device__ void mh_subcell(const StepArgs<real>& a, int e, int ex, int ey, int p
                     if (g) {
 #pragma unroll
                         for (int v = 0; v < M; ++v) up[v] = g[v];
+                    } else if (inflow_at(a, M, nd, nq, Eq::DIM, ex, ey, d, 1, d == 0 ? q : p, *a.tn_dev, up)) {
                     } else if (is_wall(a, d, 1)) {
 #pragma unroll
                         for (int v = 0; v < M; ++v) up[v] = mirror_flips<Eq>(d, v) ? -u[v] : u[v];
@@ -929,7 +972,37 @@ __device__ void face_body(const StepArgs<real>& a, int vblock)
         load_node<Eq>(a, np, eR, kB, uB);
     }
     const bool wA = !hA && is_wall(a, D, 0), wB = !hB && is_wall(a, D, 1);
-    if (!hA) {
+    // time-dependent inflow: u^- = g(t^n), U^- = sum b_i g(t^n + c_i dt),
+    // F^- = sum b_i f(g(t^n + c_i dt)) (c_i = a_{i,i-1} for these tableaux)
+    const bool iA = !hA && a.bc[D * 2 + 0] == BC_INFLOW, iB = !hB && a.bc[D * 2 + 1] == BC_INFLOW;
+    const double tn = (iA || iB) ? *a.tn_dev : 0.0, dtn = (iA || iB) ? *a.dt_dev : 0.0;
+    // the ghost of a missing side belongs to the boundary element on the other side
+    const int gex = iA ? exR : exL, gey = iA ? eyR : eyL, gside = iA ? 0 : 1;
+    real gn[M];
+    if (iA || iB) {
+        real gU[M], gF[M];
+        inflow_at(a, M, nd, nq, Eq::DIM, gex, gey, D, gside, t, tn, gn);
+#pragma unroll
+        for (int v = 0; v < M; ++v) { gU[v] = 0; gF[v] = 0; }
+        for (int i = 0; i < a.stages; ++i) {
+            real gi[M], fi[M];
+            const double ci = i > 0 ? (double)a.R.ta[i - 1] : 0.0;
+            inflow_at(a, M, nd, nq, Eq::DIM, gex, gey, D, gside, t, tn + ci * dtn, gi);
+            flux_dir<Eq>(D, gi, fi, P);
+            const real bi = a.R.tb[i];
+#pragma unroll
+            for (int v = 0; v < M; ++v) { gU[v] += bi * gi[v]; gF[v] += bi * fi[v]; }
+        }
+        const real sg = Eq::sig_trace(D, gn, gn, P);
+        const bool d1 = a.dissipation == DISS_D1;
+#pragma unroll
+        for (int v = 0; v < M; ++v) {
+            if (iA) { Fm[v] = gF[v]; Um[v] = d1 ? gn[v] : gU[v]; uA[v] = gn[v]; }
+            else { Fp[v] = gF[v]; Up[v] = d1 ? gn[v] : gU[v]; uB[v] = gn[v]; }
+        }
+        if (iA) sm = sg; else sp = sg;
+    }
+    if (!hA && !iA) {
         if (gA) {
             flux_dir<Eq>(D, gA, Fm, P);
 #pragma unroll
@@ -950,7 +1023,7 @@ __device__ void face_body(const StepArgs<real>& a, int vblock)
             sm = sp;
         }
     }
-    if (!hB) {
+    if (!hB && !iB) {
         if (gB) {
             flux_dir<Eq>(D, gB, Fp, P);
 #pragma unroll
@@ -990,12 +1063,16 @@ __device__ void face_body(const StepArgs<real>& a, int vblock)
 #pragma unroll
                 for (int v = 0; v < M; ++v) sp_[v] = TRB(c0 + v);
             }
-            if (!hA) {
+            if (iA || iB) {
+                const double ci = i > 0 ? (double)a.R.ta[i - 1] : 0.0;
+                inflow_at(a, M, nd, nq, Eq::DIM, gex, gey, D, gside, t, tn + ci * dtn, iA ? sm_ : sp_);
+            }
+            if (!hA && !iA) {
 #pragma unroll
                 for (int v = 0; v < M; ++v)
                     sm_[v] = gA ? gA[v] : (wA && mirror_flips<Eq>(D, v) ? -sp_[v] : sp_[v]);
             }
-            if (!hB) {
+            if (!hB && !iB) {
 #pragma unroll
                 for (int v = 0; v < M; ++v)
                     sp_[v] = gB ? gB[v] : (wB && mirror_flips<Eq>(D, v) ? -sm_[v] : sm_[v]);
@@ -1005,6 +1082,12 @@ __device__ void face_body(const StepArgs<real>& a, int vblock)
 #pragma unroll
             for (int v = 0; v < M; ++v) F[v] -= bi * (real)0.5 * li * (sp_[v] - sm_[v]);
         }
+    }
+    // a fully inflow boundary (every wave enters) takes F = F^-
+    const bool fi = (iA && eig_extreme<Eq>(D, gn, false, P) > 0) || (iB && eig_extreme<Eq>(D, gn, true, P) < 0);
+    if (fi) {
+#pragma unroll
+        for (int v = 0; v < M; ++v) F[v] = iA ? Fm[v] : Fp[v];
     }
 
     if constexpr (LIM) {
@@ -1017,15 +1100,19 @@ __device__ void face_body(const StepArgs<real>& a, int vblock)
 #pragma unroll
             for (int v = 0; v < M; ++v) sB[v] = TRB(2 * M + 1 + v);
         }
-        if (!hA) {
+        // inflow: the boundary data at the half time, where the predicted
+        // subcell values are centred; a fully inflow face takes its flux
+        if (iA || iB) inflow_at(a, M, nd, nq, Eq::DIM, gex, gey, D, gside, t, tn + 0.5 * dtn, iA ? sA : sB);
+        if (!hA && !iA) {
 #pragma unroll
             for (int v = 0; v < M; ++v) sA[v] = gA ? gA[v] : (wA && mirror_flips<Eq>(D, v) ? -sB[v] : sB[v]);
         }
-        if (!hB) {
+        if (!hB && !iB) {
 #pragma unroll
             for (int v = 0; v < M; ++v) sB[v] = gB ? gB[v] : (wB && mirror_flips<Eq>(D, v) ? -sA[v] : sA[v]);
         }
         rusanov<Eq>(D, sA, sB, fLO, P);
+        if (fi) flux_dir<Eq>(D, iA ? sA : sB, fLO, P);
         double aA = hA ? alpha_smoothed(a, eL, Eq::DIM) : 0.0;
         double aB = hB ? alpha_smoothed(a, eR, Eq::DIM) : 0.0;
         const real af = (real)(hA && hB ? 0.5 * (aA + aB) : (hA ? aA : aB));
@@ -1493,6 +1580,7 @@ __device__ __forceinline__ void prep_body(const PrepArgs& a)
     if (a.t_end > 0.0 && tt + dt > a.t_end) dt = a.t_end - tt;
     if (dt < 0.0) dt = 0.0;
     *a.dt_dev = dt;
+    a.t_dev[1] = tt;   // t^n of this step (inflow data)
     *a.t_dev = tt + dt;
     for (int i = 0; i < D_THFLUX; ++i) a.diag[i] = 0ull;
     a.diag[D_THFLUX] = (unsigned long long)__double_as_longlong(1.0);

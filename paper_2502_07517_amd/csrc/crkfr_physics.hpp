@@ -17,6 +17,15 @@ struct Phys {
     double amp, kappa, xc, yc, gx, gy;   // W = amp exp(-kappa r^2) + gx x + gy y
 };
 
+// reciprocal of the density: v_rcp_f32 (1 ulp for normal numbers) in the FP32
+// bulk arithmetic, a correctly rounded division in FP64
+template <class real>
+__device__ __forceinline__ real recip(real x)
+{
+    if constexpr (sizeof(real) == 4) return __builtin_amdgcn_rcpf(x);
+    else return (real)1 / x;
+}
+
 // trace value, or the face-adjacent node where the trace density is not positive
 // (value selection keeps both arrays in registers)
 template <int M, class real>
@@ -67,11 +76,12 @@ struct Euler1D {
     static constexpr int M = 3, DIM = 1, K = 2, ID = 1;
     __device__ static inline real pres(const real* u, const Phys& P)
     {
-        return ((real)P.gamma - 1) * (u[2] - (real)0.5 * u[1] * u[1] / u[0]);
+        return ((real)P.gamma - 1) * (u[2] - (real)0.5 * u[1] * u[1] * recip(u[0]));
     }
     __device__ static inline void fx(const real* u, real* f, const Phys& P)
     {
-        real v = u[1] / u[0], p = pres(u, P);
+        real v = u[1] * recip(u[0]);
+        real p = ((real)P.gamma - 1) * (u[2] - (real)0.5 * u[1] * v);
         f[0] = u[1];
         f[1] = u[1] * v + p;
         f[2] = (u[2] + p) * v;
@@ -79,7 +89,9 @@ struct Euler1D {
     __device__ static inline void gy(const real*, real* g, const Phys&) { g[0] = g[1] = g[2] = 0; }
     __device__ static inline real sx(const real* u, const Phys& P)
     {
-        return fabs(u[1] / u[0]) + sqrt((real)P.gamma * pres(u, P) / u[0]);
+        real ir = recip(u[0]), v = u[1] * ir;
+        real p = ((real)P.gamma - 1) * (u[2] - (real)0.5 * u[1] * v);
+        return fabs(v) + sqrt((real)P.gamma * p * ir);
     }
     __device__ static inline real sy(const real*, const Phys&) { return 0; }
     __device__ static inline double adm(int k, const double* u, const Phys& P)
@@ -95,19 +107,24 @@ struct Euler1D {
         return (P.gamma - 1.0) * (u[2] * u[0] - 0.5 * u[1] * u[1]) >= eps * u[0];
     }
     __device__ static inline bool concave(int) { return true; }
-    __device__ static inline real ind(const real* u, const Phys& P) { return u[0] * pres(u, P); }
+    // rho p = (gamma - 1) (rho E - m^2 / 2): no division
+    __device__ static inline real ind(const real* u, const Phys& P)
+    {
+        return ((real)P.gamma - 1) * (u[0] * u[2] - (real)0.5 * u[1] * u[1]);
+    }
     // trace wave speed: pressure clipped at zero; non-positive density -> node
     __device__ static inline real sig_trace(int, const real* tr, const real* node, const Phys& P)
     {
         real u[M];
         pick_trace<M>(tr, node, u);
-        real p = pres(u, P);
-        return fabs(u[1] / u[0]) + sqrt((real)P.gamma * fmax(p, (real)0) / u[0]);
+        real ir = recip(u[0]), v = u[1] * ir;
+        real p = ((real)P.gamma - 1) * (u[2] - (real)0.5 * u[1] * v);
+        return fabs(v) + sqrt((real)P.gamma * fmax(p, (real)0) * ir);
     }
     __device__ static inline void src(const real*, real, real, real* s, const Phys&) { s[0] = s[1] = s[2] = 0; }
     __device__ static inline void fxy(const real* u, real* f, real* g, const Phys& P)
     {
-        real ir = (real)1 / u[0], v = u[1] * ir;
+        real ir = recip(u[0]), v = u[1] * ir;
         real p = ((real)P.gamma - 1) * (u[2] - (real)0.5 * u[1] * v);
         f[0] = u[1];
         f[1] = u[1] * v + p;
@@ -122,11 +139,19 @@ struct Euler2D {
     static constexpr int M = 4, DIM = 2, K = 2, ID = 2;
     __device__ static inline real pres(const real* u, const Phys& P)
     {
-        return ((real)P.gamma - 1) * (u[3] - (real)0.5 * (u[1] * u[1] + u[2] * u[2]) / u[0]);
+        return ((real)P.gamma - 1) * (u[3] - (real)0.5 * (u[1] * u[1] + u[2] * u[2]) * recip(u[0]));
+    }
+    // pressure and velocities with one reciprocal of the density
+    __device__ static inline real pvv(const real* u, real& v1, real& v2, real& ir, const Phys& P)
+    {
+        ir = recip(u[0]);
+        v1 = u[1] * ir;
+        v2 = u[2] * ir;
+        return ((real)P.gamma - 1) * (u[3] - (real)0.5 * (u[1] * v1 + u[2] * v2));
     }
     __device__ static inline void fx(const real* u, real* f, const Phys& P)
     {
-        real v1 = u[1] / u[0], p = pres(u, P);
+        real v1, v2, ir, p = pvv(u, v1, v2, ir, P);
         f[0] = u[1];
         f[1] = u[1] * v1 + p;
         f[2] = u[2] * v1;
@@ -134,7 +159,7 @@ struct Euler2D {
     }
     __device__ static inline void gy(const real* u, real* g, const Phys& P)
     {
-        real v2 = u[2] / u[0], p = pres(u, P);
+        real v1, v2, ir, p = pvv(u, v1, v2, ir, P);
         g[0] = u[2];
         g[1] = u[1] * v2;
         g[2] = u[2] * v2 + p;
@@ -142,11 +167,13 @@ struct Euler2D {
     }
     __device__ static inline real sx(const real* u, const Phys& P)
     {
-        return fabs(u[1] / u[0]) + sqrt((real)P.gamma * pres(u, P) / u[0]);
+        real v1, v2, ir, p = pvv(u, v1, v2, ir, P);
+        return fabs(v1) + sqrt((real)P.gamma * p * ir);
     }
     __device__ static inline real sy(const real* u, const Phys& P)
     {
-        return fabs(u[2] / u[0]) + sqrt((real)P.gamma * pres(u, P) / u[0]);
+        real v1, v2, ir, p = pvv(u, v1, v2, ir, P);
+        return fabs(v2) + sqrt((real)P.gamma * p * ir);
     }
     __device__ static inline double adm(int k, const double* u, const Phys& P)
     {
@@ -161,20 +188,24 @@ struct Euler2D {
         return (P.gamma - 1.0) * (u[3] * u[0] - 0.5 * (u[1] * u[1] + u[2] * u[2])) >= eps * u[0];
     }
     __device__ static inline bool concave(int) { return true; }
-    __device__ static inline real ind(const real* u, const Phys& P) { return u[0] * pres(u, P); }
+    // rho p = (gamma - 1) (rho E - |m|^2 / 2): no division
+    __device__ static inline real ind(const real* u, const Phys& P)
+    {
+        return ((real)P.gamma - 1) * (u[0] * u[3] - (real)0.5 * (u[1] * u[1] + u[2] * u[2]));
+    }
     __device__ static inline real sig_trace(int d, const real* tr, const real* node, const Phys& P)
     {
         real u[M];
         pick_trace<M>(tr, node, u);
-        real c = sqrt((real)P.gamma * fmax(pres(u, P), (real)0) / u[0]);
-        return fabs((d == 0 ? u[1] : u[2]) / u[0]) + c;
+        real v1, v2, ir, p = pvv(u, v1, v2, ir, P);
+        real c = sqrt((real)P.gamma * fmax(p, (real)0) * ir);
+        return fabs(d == 0 ? v1 : v2) + c;
     }
     __device__ static inline void src(const real*, real, real, real* s, const Phys&) { s[0] = s[1] = s[2] = s[3] = 0; }
     // both fluxes with one reciprocal of the density
     __device__ static inline void fxy(const real* u, real* f, real* g, const Phys& P)
     {
-        real ir = (real)1 / u[0], v1 = u[1] * ir, v2 = u[2] * ir;
-        real p = ((real)P.gamma - 1) * (u[3] - (real)0.5 * (u[1] * v1 + u[2] * v2));
+        real v1, v2, ir, p = pvv(u, v1, v2, ir, P);
         real ep = u[3] + p;
         f[0] = u[1];
         f[1] = u[1] * v1 + p;
@@ -193,35 +224,35 @@ struct TenMom2D {
     static constexpr int M = 6, DIM = 2, K = 3, ID = 3;
     __device__ static inline void fx(const real* u, real* f, const Phys&)
     {
-        real r = u[0], v1 = u[1] / r, v2 = u[2] / r;
-        real P11 = 2 * u[3] - r * v1 * v1, P12 = 2 * u[4] - r * v1 * v2;
-        f[0] = r * v1;
-        f[1] = P11 + r * v1 * v1;
-        f[2] = P12 + r * v1 * v2;
+        real ir = recip(u[0]), v1 = u[1] * ir, v2 = u[2] * ir;
+        real P11 = 2 * u[3] - u[1] * v1, P12 = 2 * u[4] - u[1] * v2;
+        f[0] = u[1];
+        f[1] = P11 + u[1] * v1;
+        f[2] = P12 + u[1] * v2;
         f[3] = (u[3] + P11) * v1;
         f[4] = u[4] * v1 + (real)0.5 * (P11 * v2 + P12 * v1);
         f[5] = u[5] * v1 + P12 * v2;
     }
     __device__ static inline void gy(const real* u, real* g, const Phys&)
     {
-        real r = u[0], v1 = u[1] / r, v2 = u[2] / r;
-        real P12 = 2 * u[4] - r * v1 * v2, P22 = 2 * u[5] - r * v2 * v2;
-        g[0] = r * v2;
-        g[1] = P12 + r * v1 * v2;
-        g[2] = P22 + r * v2 * v2;
+        real ir = recip(u[0]), v1 = u[1] * ir, v2 = u[2] * ir;
+        real P12 = 2 * u[4] - u[1] * v2, P22 = 2 * u[5] - u[2] * v2;
+        g[0] = u[2];
+        g[1] = P12 + u[1] * v2;
+        g[2] = P22 + u[2] * v2;
         g[3] = u[3] * v2 + P12 * v1;
         g[4] = u[4] * v2 + (real)0.5 * (P12 * v2 + P22 * v1);
         g[5] = (u[5] + P22) * v2;
     }
     __device__ static inline real sx(const real* u, const Phys&)
     {
-        real r = u[0], v1 = u[1] / r;
-        return fabs(v1) + sqrt(3 * (2 * u[3] - r * v1 * v1) / r);
+        real ir = recip(u[0]), v1 = u[1] * ir;
+        return fabs(v1) + sqrt(3 * (2 * u[3] - u[1] * v1) * ir);
     }
     __device__ static inline real sy(const real* u, const Phys&)
     {
-        real r = u[0], v2 = u[2] / r;
-        return fabs(v2) + sqrt(3 * (2 * u[5] - r * v2 * v2) / r);
+        real ir = recip(u[0]), v2 = u[2] * ir;
+        return fabs(v2) + sqrt(3 * (2 * u[5] - u[2] * v2) * ir);
     }
     __device__ static inline double adm(int k, const double* u, const Phys&)
     {
@@ -246,34 +277,31 @@ struct TenMom2D {
     __device__ static inline bool concave(int k) { return k != 2; }   // det P is not concave
     __device__ static inline real ind(const real* u, const Phys&)
     {
-        real r = u[0], v1 = u[1] / r, v2 = u[2] / r;
-        return r * (real)0.5 * ((2 * u[3] - r * v1 * v1) + (2 * u[5] - r * v2 * v2));
+        // rho (P11 + P22) / 2 = rho (E11 + E22) - |rho v|^2 / 2: no division
+        return u[0] * (u[3] + u[5]) - (real)0.5 * (u[1] * u[1] + u[2] * u[2]);
     }
     __device__ static inline real sig_trace(int d, const real* tr, const real* node, const Phys&)
     {
         real u[M];
         pick_trace<M>(tr, node, u);
-        real r = u[0];
-        if (d == 0) {
-            real v1 = u[1] / r;
-            return fabs(v1) + sqrt(3 * fmax(2 * u[3] - r * v1 * v1, (real)0) / r);
-        }
-        real v2 = u[2] / r;
-        return fabs(v2) + sqrt(3 * fmax(2 * u[5] - r * v2 * v2, (real)0) / r);
+        const real ir = recip(u[0]);
+        const real m = d == 0 ? u[1] : u[2], en = d == 0 ? u[3] : u[5];
+        const real vn = m * ir;
+        return fabs(vn) + sqrt(3 * fmax(2 * en - m * vn, (real)0) * ir);
     }
     __device__ static inline void fxy(const real* u, real* f, real* g, const Phys& P)
     {
-        real r = u[0], ir = (real)1 / r, v1 = u[1] * ir, v2 = u[2] * ir;
-        real P11 = 2 * u[3] - r * v1 * v1, P12 = 2 * u[4] - r * v1 * v2, P22 = 2 * u[5] - r * v2 * v2;
+        real ir = recip(u[0]), v1 = u[1] * ir, v2 = u[2] * ir;
+        real P11 = 2 * u[3] - u[1] * v1, P12 = 2 * u[4] - u[1] * v2, P22 = 2 * u[5] - u[2] * v2;
         f[0] = u[1];
-        f[1] = P11 + r * v1 * v1;
-        f[2] = P12 + r * v1 * v2;
+        f[1] = P11 + u[1] * v1;
+        f[2] = P12 + u[1] * v2;
         f[3] = (u[3] + P11) * v1;
         f[4] = u[4] * v1 + (real)0.5 * (P11 * v2 + P12 * v1);
         f[5] = u[5] * v1 + P12 * v2;
         g[0] = u[2];
         g[1] = f[2];
-        g[2] = P22 + r * v2 * v2;
+        g[2] = P22 + u[2] * v2;
         g[3] = u[3] * v2 + P12 * v1;
         g[4] = u[4] * v2 + (real)0.5 * (P12 * v2 + P22 * v1);
         g[5] = (u[5] + P22) * v2;
@@ -285,13 +313,13 @@ struct TenMom2D {
         real W = (real)P.amp * exp(-(real)P.kappa * (dx * dx + dy * dy));
         real Wx = -2 * (real)P.kappa * dx * W + (real)P.gx;
         real Wy = -2 * (real)P.kappa * dy * W + (real)P.gy;
-        real r = u[0], v1 = u[1] / r, v2 = u[2] / r;
+        // rho v = the momentum: no division
         s[0] = 0;
-        s[1] = (real)-0.5 * r * Wx;
-        s[2] = (real)-0.5 * r * Wy;
-        s[3] = (real)-0.5 * r * v1 * Wx;
-        s[4] = (real)-0.25 * r * v2 * Wx - (real)0.25 * r * v1 * Wy;
-        s[5] = (real)-0.5 * r * v2 * Wy;
+        s[1] = (real)-0.5 * u[0] * Wx;
+        s[2] = (real)-0.5 * u[0] * Wy;
+        s[3] = (real)-0.5 * u[1] * Wx;
+        s[4] = (real)-0.25 * u[2] * Wx - (real)0.25 * u[1] * Wy;
+        s[5] = (real)-0.5 * u[2] * Wy;
     }
 };
 
@@ -324,14 +352,7 @@ struct TenMom1D {
     }
     __device__ static inline void fxy(const real* u, real* f, real* g, const Phys& P)
     {
-        real r = u[0], ir = (real)1 / r, v1 = u[1] * ir, v2 = u[2] * ir;
-        real P11 = 2 * u[3] - r * v1 * v1, P12 = 2 * u[4] - r * v1 * v2;
-        f[0] = u[1];
-        f[1] = P11 + r * v1 * v1;
-        f[2] = P12 + r * v1 * v2;
-        f[3] = (u[3] + P11) * v1;
-        f[4] = u[4] * v1 + (real)0.5 * (P11 * v2 + P12 * v1);
-        f[5] = u[5] * v1 + P12 * v2;
+        T2::fx(u, f, P);
         gy(u, g, P);
     }
     __device__ static inline void src(const real* u, real x, real, real* s, const Phys& P)
