@@ -1,0 +1,246 @@
+"""The benchmark workloads at their full sizes, in the launch configurations
+the benchmark times, against the oracle where it finishes in seconds (one
+step, or a whole run on the 1D grids) and through properties that hold at
+any size elsewhere:
+
+  * scalar linear advection, N = 3, 100 elements, t = 1 (whole run);
+  * 1D Euler Riemann problems, N = 4, 2000 elements, limiter chain, FP64 and
+    FP32 bulk (single steps from the oracle's states, whole 40-step runs);
+  * 2D Euler vortex, 512^2 elements, N = 3 (one step against the oracle;
+    runs to t = 2: error against the exact solution, conserved means);
+  * ten-moment system with the Gaussian source, 1024 x 256 elements, N = 4,
+    limiter chain, smoothness indicator and learned indicator (one step);
+  * the batch of 256 uneven 2D Euler instances (sides 64-512, N = 2-4) in
+    FP32 bulk with the learned indicator, captured and autotuned: sampled
+    members equal the same solvers stepped alone, the smallest member
+    against the oracle, means conserved in every member.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from gpu_cases import rel_l1, rel_linf
+from oracle_runs import cfl_for
+from paper_2502_07517_amd import crkfr as C
+from paper_2502_07517_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+FF = (C.FARFIELD,) * 4
+LIM = dict(blend=C.BLEND_MH, flux_limiter=1, scaling=1)
+VDOM = (-5.0, 5.0, -5.0, 5.0)
+TM_DOM = (-2.0, 2.0, -0.5, 0.5)
+TM_SRC = (25.0, 200.0, 1.0, 0.0, 0.0, 0.0)
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _mass(u, N, M, ne, np_, w2):
+    return (u.reshape(M, ne, np_) * w2[None, None, :]).sum(axis=(1, 2))
+
+
+def test_linear_advection_100_elements_whole_run():
+    N, nx = 3, 100
+    cfl = cfl_for(N, system=False)
+    u0 = W.linadv_modes(0, nx, N)
+    cfg = O.RefConfig.make(O.LINADV1D, N, nx, cfl=cfl)
+    u, t, k = u0.copy(), 0.0, 0
+    while t < 1.0 - 1e-14:
+        dt = min(O.compute_dt(cfg, u), 1.0 - t)
+        u, _, _, st = O.step(cfg, u, dt)
+        t, k = t + dt, k + 1
+    s = C.Solver(C.LINADV1D, N, nx, cfl=cfl)
+    s.set_state(u0)
+    s.advance(1.0, 100000)
+    d, rc = s.get_diag()
+    assert rc == 0 and abs(d["t"] - 1.0) < 1e-14 and d["steps"] == k
+    ug = s.get_state().reshape(u.shape)
+    _say(f"linear advection: {k} steps, rel. Linf vs oracle {rel_linf(u, ug):.2e}")
+    assert rel_linf(u, ug) <= 1e-11
+    # one period: back to the initial data up to the scheme's error
+    assert np.max(np.abs(ug - u0)) < 1e-5
+
+
+def test_euler1d_riemann_2000_elements():
+    N, nx, steps = 4, 2000, 40
+    u0 = W.euler1d_riemann(7, nx, N)
+    cfg = O.RefConfig.make(O.EULER1D, N, nx, bc=FF, cfl=cfl_for(N), **LIM)
+    ghost = O.boundary_traces(cfg, u0)
+    g64 = C.Solver(C.EULER1D, N, nx, bc=FF, cfl=cfl_for(N))
+    g64.set_limiter(**LIM)
+    g64.set_state(u0)      # far-field ghosts from this state
+    u, traj, acted = u0.copy(), [], 0
+    for k in range(steps):
+        dt = O.compute_dt(cfg, u)
+        un, _, do, st = O.step(cfg, u, dt, ghost=ghost)
+        assert st == 0 and do["n_mean_inadmissible"] == 0
+        traj.append(dt)
+        if k % 10 == 0:
+            # (the far-field ghosts come from the state given; the boundary
+            # elements keep their initial states over these steps)
+            g = C.Solver(C.EULER1D, N, nx, bc=FF, cfl=cfl_for(N))
+            g.set_limiter(**LIM)
+            g.set_state(u.copy())
+            g.step(dt)
+            dg, _ = g.get_diag()
+            e = rel_l1(un, g.get_state().reshape(un.shape))
+            _say(f"Riemann 2000 elements, step {k}: single-step rel. L1 {e:.2e}")
+            assert e <= 1e-12
+            assert do["n_troubled"] == dg["n_troubled"]
+            acted += do["n_troubled"]
+        u = un
+    assert acted > 0
+    for dt in traj:
+        g64.step(dt)
+    e64 = rel_l1(u, g64.get_state().reshape(u.shape))
+    g32 = C.Solver(C.EULER1D, N, nx, bc=FF, dtype=C.MP32, cfl=cfl_for(N))
+    g32.set_limiter(**LIM)
+    g32.set_state(u0)
+    for dt in traj:
+        g32.step(dt)
+    e32 = rel_l1(u, g32.get_state().reshape(u.shape))
+    _say(f"Riemann 2000 elements, {steps} steps: FP64 rel. L1 {e64:.2e}, FP32 bulk {e32:.2e}")
+    assert e64 <= 1e-6 and e32 <= 1e-3
+
+
+def test_vortex_512sq_one_step_and_runs():
+    N, n = 3, 512
+    u0 = W.vortex2d(n, N, 0.0, VDOM)
+    cfg = O.RefConfig.make(O.EULER2D, N, n, n, domain=VDOM, cfl=cfl_for(N))
+    dt = O.compute_dt(cfg, u0)
+    uo, _, _, st = O.step(cfg, u0, dt)
+    assert st == 0
+    _, w = O.gl(N)
+    w2 = np.outer(w, w).reshape(-1)
+    for dtype, tl1, tinf, terr in ((C.FP64, 1e-14, 1e-12, 1e-10), (C.MP32, 2e-7, 2e-5, 3e-6)):
+        s = C.Solver(C.EULER2D, N, n, n, domain=VDOM, dtype=dtype, cfl=cfl_for(N))
+        s.set_state(u0)
+        s.step(dt)
+        ug = s.get_state().reshape(uo.shape)
+        _say(f"vortex 512^2 dtype {dtype}: one step rel. L1 {rel_l1(uo, ug):.2e}, Linf {rel_linf(uo, ug):.2e}")
+        assert rel_l1(uo, ug) <= tl1 and rel_linf(uo, ug) <= tinf
+        # the whole run to t = 2 (the benchmark's launch: captured advance)
+        s.set_state(u0)
+        m0 = _mass(u0, N, 4, n * n, 16, w2)
+        s.advance(2.0, 100000)
+        d, rc = s.get_diag()
+        assert rc == 0 and abs(d["t"] - 2.0) < 1e-12
+        ut = s.get_state()
+        ex = W.vortex2d(n, N, 2.0, VDOM)
+        l1 = float((np.abs(ut[0] - ex[0]).reshape(n * n, 16) * w2).sum() / (n * n))
+        mt = _mass(ut, N, 4, n * n, 16, w2)
+        _say(f"vortex 512^2 dtype {dtype}: t = 2 density L1 {l1:.2e}, mass drift {abs(mt[0] - m0[0]) / m0[0]:.1e}")
+        assert l1 <= terr
+        assert np.max(np.abs(mt - m0) / np.abs(m0)) <= (1e-13 if dtype == C.FP64 else 1e-11)
+
+
+@pytest.fixture(scope="module")
+def tenmom_net():
+    net = C.Mlp(4, 16, seed=11)
+    p = (0.8 * np.random.default_rng(11).standard_normal(net.num_params())).astype(np.float32)
+    net.set_params(p)
+    return net, p
+
+
+@pytest.mark.parametrize("indicator", [C.IND_PAPER, C.IND_LEARNED])
+def test_tenmom_1024x256_one_step(indicator, tenmom_net):
+    N, nx, ny = 4, 1024, 256
+    u0 = W.tenmom2d_quadrants(3, nx, ny, N, TM_DOM)
+    cfg = O.RefConfig.make(O.TENMOM2D, N, nx, ny, bc=FF, domain=TM_DOM, cfl=cfl_for(N), indicator=indicator,
+                           source=1, src=TM_SRC[:4], src_lin=TM_SRC[4:], **LIM)
+    net, p = tenmom_net
+    s = C.Solver(C.TENMOM2D, N, nx, ny, bc=FF, domain=TM_DOM, cfl=cfl_for(N))
+    s.set_limiter(indicator=indicator, **LIM)
+    s.set_source(1, *TM_SRC)
+    if indicator == C.IND_LEARNED:
+        s.set_mlp(net)
+        lo, hi = net.get_box()
+        cfg.set_mlp(net.dims, p.astype(np.float64), lo.astype(np.float64), hi.astype(np.float64))
+    s.set_state(u0)
+    dt = O.compute_dt(cfg, u0)
+    uo, ao, do, st = O.step(cfg, u0, dt, ghost=O.boundary_traces(cfg, u0))
+    assert st == 0
+    s.step(dt)
+    ug = s.get_state().reshape(uo.shape)
+    dg, _ = s.get_diag()
+    _say(f"ten-moment 1024x256 indicator {indicator}: rel. L1 {rel_l1(uo, ug):.2e}, troubled {do['n_troubled']}")
+    assert rel_l1(uo, ug) <= 1e-12
+    for key in ("n_troubled", "n_flux_limited", "n_scaled", "n_mean_inadmissible"):
+        assert do[key] == dg[key], key
+    assert do["n_troubled"] > 0
+    assert np.max(np.abs(s.get_alpha().reshape(ao.shape) - ao)) <= 1e-9
+
+
+def test_batch_256_uneven_instances_full_size():
+    """4.3e8 DoF in one batch: FP32 bulk + learned indicator (one network
+    per degree, random weights), captured two-step graph, autotuned grids."""
+    specs = W.batch_instances(2026, 256, sides=(64, 512), degrees=(2, 3, 4))
+    dof = sum(sp["n"] ** 2 * (sp["N"] + 1) ** 2 for sp in specs)
+    _say(f"batch: {len(specs)} instances, {dof:.3e} DoF")
+    assert 3.5e8 < dof < 5.5e8
+    nets = {}
+    for N in (2, 3, 4):
+        net = C.Mlp(N, 16, seed=N)
+        p = (0.8 * np.random.default_rng(N).standard_normal(net.num_params())).astype(np.float32)
+        net.set_params(p)
+        nets[N] = (net, p)
+    order = sorted(range(len(specs)), key=lambda i: specs[i]["n"] ** 2 * (specs[i]["N"] + 1) ** 2)
+    sample = [order[0], order[len(order) // 2], order[-1]]
+
+    def make(i):
+        sp = specs[i]
+        s = C.Solver(C.EULER2D, sp["N"], sp["n"], sp["n"], bc=FF, dtype=C.MP32, cfl=cfl_for(sp["N"]))
+        s.set_limiter(indicator=C.IND_LEARNED, **LIM)
+        s.set_mlp(nets[sp["N"]][0])
+        s.set_state(W.euler2d_quadrants(sp["seed"] % 1000, sp["n"], sp["N"]))
+        return s
+    members = []
+    for i in range(len(specs)):
+        members.append(make(i))
+        if i % 32 == 31:
+            _say(f"batch: {i + 1} members created")
+    alone = {i: make(i) for i in sample}
+    masses0 = {}
+    for i in sample:
+        N = specs[i]["N"]
+        _, w = O.gl(N)
+        masses0[i] = _mass(members[i].get_state(), N, 4, specs[i]["n"] ** 2, (N + 1) ** 2, np.outer(w, w).reshape(-1))
+    b = C.Batch(members)
+    grids = b.autotune(2)
+    _say(f"batch: autotuned grids {grids}")
+    b.step()
+    b.advance(2)
+    b.sync()
+    for s in alone.values():
+        for _ in range(3):
+            s.step(0.0)
+    for i in sample:
+        sp = specs[i]
+        assert np.array_equal(members[i].get_state(), alone[i].get_state()), i
+        d, rc = members[i].get_diag()
+        assert rc == 0 and d["n_mean_inadmissible"] == 0 and d["steps"] == 3
+        N = sp["N"]
+        _, w = O.gl(N)
+        m = _mass(members[i].get_state(), N, 4, sp["n"] ** 2, (N + 1) ** 2, np.outer(w, w).reshape(-1))
+        # far-field boundaries: mass changes only through the boundary fluxes;
+        # the states near the boundary are constant per quadrant, so the
+        # change over 3 steps is small against the total
+        assert np.all(np.isfinite(m)) and abs(m[0] - masses0[i][0]) < 1e-2 * masses0[i][0]
+    # the smallest member against the FP64 oracle with the same network, three steps
+    i = sample[0]
+    sp = specs[i]
+    N, n = sp["N"], sp["n"]
+    net, p = nets[N]
+    cfg = O.RefConfig.make(O.EULER2D, N, n, n, bc=FF, cfl=cfl_for(N), indicator=O.IND_LEARNED, **LIM)
+    lo, hi = net.get_box()
+    cfg.set_mlp(net.dims, p.astype(np.float64), lo.astype(np.float64), hi.astype(np.float64))
+    u = W.euler2d_quadrants(sp["seed"] % 1000, n, N)
+    ghost = O.boundary_traces(cfg, u)
+    for _ in range(3):
+        u, _, _, st = O.step(cfg, u, O.compute_dt(cfg, u), ghost=ghost)
+        assert st == 0
+    e = rel_l1(u, members[i].get_state().reshape(u.shape))
+    _say(f"batch: smallest member n={n} N={N} FP32 bulk vs FP64 oracle rel. L1 {e:.2e}")
+    assert e <= 1e-3
+    b.close()
