@@ -457,7 +457,11 @@ static StepArgs<real> step_args(const crkfr_solver* s, int in, int out)
     a.alpha_const = s->lim.alpha_const;
     a.phys = make_phys(s);
     fill_tab(s->ref, s->stages, a.R);
-    for (int i = 0; i < MAXND; ++i) a.w64[i] = i <= s->cfg.N ? s->ref.w[i] : 0.0;
+    for (int i = 0; i < MAXND; ++i) {
+        a.w64[i] = i <= s->cfg.N ? s->ref.w[i] : 0.0;
+        a.iwdx[i] = i <= s->cfg.N ? 1.0 / (s->ref.w[i] * a.dx) : 0.0;
+        a.iwdy[i] = i <= s->cfg.N ? 1.0 / (s->ref.w[i] * a.dy) : 0.0;
+    }
     a.diag = s->diag;
     a.rate_bits = s->rate_bits;
     a.mlp = s->mlp ? mlp_device_params(s->mlp) : nullptr;

@@ -87,6 +87,7 @@ struct StepArgs {
     Phys phys;
     RefTab<real> R;
     double w64[MAXND];
+    double iwdx[MAXND], iwdy[MAXND];   // 1 / (w_i dx), 1 / (w_i dy)
     unsigned long long* diag;
     unsigned long long* rate_bits;
     const float* mlp;      // learned indicator: parameters, then the feature box lo[N], hi[N]
@@ -901,15 +902,18 @@ __device__ __forceinline__ double alpha_smoothed(const StepArgs<real>& a, int e,
     return al;
 }
 
-// Share of direction d in the low-order update of a face-adjacent subcell:
-// proportional to the subcell's own nodal rate sigma_d / (w h_d).
+// dt / (w h phi_d): the factor of the flux difference in direction d's part
+// of the low-order update of a face-adjacent subcell, whose share phi_d is
+// proportional to the subcell's own nodal rate sigma_d / (w h_d).  With
+// a_x = sigma_x / (w_x dx), a_y = sigma_y / (w_y dy) and d = 0 it is
+// dt (a_x + a_y) / sigma_x = dt (1/(w_x dx) + (sigma_y/sigma_x) / (w_y dy)).
+// i: index of the subcell along d (0 or N; the weights are symmetric).
 template <class Eq, int N, class real>
-__device__ __forceinline__ double dir_share(const StepArgs<real>& a, int d, int t, const real* u)
+__device__ __forceinline__ double lo_factor(const StepArgs<real>& a, int d, int t, int i, const real* u, double dt)
 {
-    if constexpr (Eq::DIM == 1) return 1.0;
-    double ax = (double)Eq::sx(u, a.phys) / ((double)(d == 0 ? a.R.w[N] : a.R.w[t]) * a.dx);
-    double ay = (double)Eq::sy(u, a.phys) / ((double)(d == 0 ? a.R.w[t] : a.R.w[N]) * a.dy);
-    return (d == 0 ? ax : ay) / (ax + ay);
+    if constexpr (Eq::DIM == 1) return dt * a.iwdx[i];
+    const double sx = (double)Eq::sx(u, a.phys), sy = (double)Eq::sy(u, a.phys);
+    return dt * (d == 0 ? a.iwdx[i] + (sy / sx) * a.iwdy[t] : a.iwdy[i] + (sx / sy) * a.iwdx[t]);
 }
 
 // ----------------------------------------------------------------------------
@@ -1122,11 +1126,10 @@ __device__ void face_body(const StepArgs<real>& a, int vblock)
         if constexpr (K > 0) {
             if (a.flux_limiter) {
                 const double dt = *a.dt_dev;
-                const double h = D == 0 ? a.dx : a.dy;
                 double kA2 = 0.0, kB2 = 0.0;
                 double adjA[M], adjB[M], SA[M], SB[M], cAlo[M], cBlo[M], uAd[M], uBd[M];
                 if (hA) {
-                    kA2 = dt / ((double)a.R.w[N] * h * dir_share<Eq, N>(a, D, t, uA));
+                    kA2 = lo_factor<Eq, N>(a, D, t, N, uA, dt);
 #pragma unroll
                     for (int v = 0; v < M; ++v) {
                         adjA[v] = (double)TRA(3 * M + 1 + v);
@@ -1136,7 +1139,7 @@ __device__ void face_body(const StepArgs<real>& a, int vblock)
                     }
                 }
                 if (hB) {
-                    kB2 = dt / ((double)a.R.w[0] * h * dir_share<Eq, N>(a, D, t, uB));
+                    kB2 = lo_factor<Eq, N>(a, D, t, 0, uB, dt);
 #pragma unroll
                     for (int v = 0; v < M; ++v) {
                         adjB[v] = (double)TRB(3 * M + 1 + v);
