@@ -919,6 +919,10 @@ __device__ __forceinline__ double lo_factor(const StepArgs<real>& a, int d, int 
 // ----------------------------------------------------------------------------
 // k_face: one lane per face point of direction D
 // ----------------------------------------------------------------------------
+template <class Eq, int N, class real, bool LIM, int D, bool INTERIOR>
+__device__ __forceinline__ void face_point(const StepArgs<real>& a, int t, int eL, int eR, int exL, int eyL, int exR,
+                                           int eyR, size_t outi);
+
 template <class Eq, int N, class real, bool LIM, int D>
 __device__ void face_body(const StepArgs<real>& a, int vblock)
 {
@@ -931,9 +935,6 @@ __device__ void face_body(const StepArgs<real>& a, int vblock)
     if (tid >= total) return;
     const int t = (int)(tid % npt);
     int eL, eR, exL, eyL, exR, eyR;
-    const real* trb = D == 0 ? a.trx : a.trY;
-    const size_t nes = (size_t)a.ne;
-    const int C = a.C;
     size_t outi;
     if (D == 0) {
         const int i = (int)((tid / npt) % (a.nx + 1));
@@ -952,7 +953,24 @@ __device__ void face_body(const StepArgs<real>& a, int vblock)
         exR = ex; eyR = j < a.ny ? j : 0;
         outi = ((size_t)j * a.nx + ex) * nd + t;
     }
-    const bool hA = eL >= 0, hB = eR >= 0;
+    // interior faces (both elements present: every face of a periodic grid)
+    // take a path without the boundary cases
+    if (eL >= 0 && eR >= 0) face_point<Eq, N, real, LIM, D, true>(a, t, eL, eR, exL, eyL, exR, eyR, outi);
+    else face_point<Eq, N, real, LIM, D, false>(a, t, eL, eR, exL, eyL, exR, eyR, outi);
+}
+
+template <class Eq, int N, class real, bool LIM, int D, bool INTERIOR>
+__device__ __forceinline__ void face_point(const StepArgs<real>& a, int t, int eL, int eR, int exL, int eyL, int exR,
+                                           int eyR, size_t outi)
+{
+    using G = Geo<Eq::DIM, N>;
+    constexpr int M = Eq::M, nd = G::nd, nq = G::nq, np = G::np, K = Eq::K;
+    const Phys& P = a.phys;
+    const int npt = D == 0 ? nq : nd;
+    const real* trb = D == 0 ? a.trx : a.trY;
+    const size_t nes = (size_t)a.ne;
+    const int C = a.C;
+    const bool hA = INTERIOR || eL >= 0, hB = INTERIOR || eR >= 0;
     // ghost states (far-field) for a missing side
     const real* gA = hA ? nullptr : ghost_at(a, M, nd, nq, exR, eyR, D, 0, t);
     const real* gB = hB ? nullptr : ghost_at(a, M, nd, nq, exL, eyL, D, 1, t);
