@@ -150,6 +150,70 @@ def run_c3(dtype, steps, warmup, limited=False):
 
 
 # ---------------------------------------------------------------- learned indicator for 2D Euler N=3
+def train_network_for(N, seed=0):
+    """A network for degree N from three 4-quadrant runs (32^2) and four
+    element-pattern states (64^2), 40 epochs (the batch of uneven members)."""
+    import torch
+    from paper_2502_07517_amd import crkfr as C
+    from paper_2502_07517_amd import learned as LI
+    from paper_2502_07517_amd import workloads as W
+    ff = (C.FARFIELD,) * 4
+    runs = []
+    for sd in range(3):
+        s = C.Solver(C.EULER2D, N, 32, 32, bc=ff)
+        s.set_limiter(blend=C.BLEND_MH, indicator=C.IND_PAPER, flux_limiter=1, scaling=1)
+        s.set_state(W.euler2d_quadrants(sd, 32, N))
+        runs.append(s)
+    X1, y1 = LI.collect_pairs(runs, steps=80, every=2)
+    ps = C.Solver(C.EULER2D, N, 64, 64, bc=ff)
+    X2, y2 = LI.pairs_of_states(ps, [W.element_patterns_2d(500 + i, 64, 64, N) for i in range(4)])
+    net, _ = LI.train_indicator(torch.cat([X1, X2]), torch.cat([y1, y2]), epochs=40, batch=2048, seed=seed + N)
+    return net
+
+
+def run_c5(nets, steps, warmup):
+    """The batch of 256 uneven 2D Euler 4-quadrant instances (sides 64-512,
+    N = 2, 3, 4; 4.3e8 DoF), FP32 bulk + learned indicator, autotuned,
+    captured two-step graph replay; aggregate DoF*steps/s."""
+    import torch
+    from paper_2502_07517_amd import crkfr as C
+    from paper_2502_07517_amd import workloads as W
+    st = torch.cuda.current_stream().cuda_stream
+    specs = W.batch_instances(2026, 256, sides=(64, 512), degrees=(2, 3, 4))
+    solvers, dof = [], 0
+    for sp in specs:
+        n, N = sp["n"], sp["N"]
+        s = C.Solver(C.EULER2D, N, n, n, bc=(C.FARFIELD,) * 4, dtype=C.MP32, stream=st)
+        _limited(s, C, C.IND_LEARNED, nets[N])
+        s.set_state(torch.from_numpy(np.ascontiguousarray(W.euler2d_quadrants(sp["seed"] % 1000, n, N))).to("cuda"))
+        solvers.append(s)
+        dof += n * n * (N + 1) ** 2
+    b = C.Batch(solvers, stream=st)
+    grids = b.autotune(2)
+    b.advance(warmup)
+    torch.cuda.synchronize()
+    e0, e1 = _events()
+    e0.record()
+    b.advance(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    b.set_timing(True)
+    acc = np.zeros(4)
+    for _ in range(4):
+        b.advance(1)
+        acc += np.array(b.phase_times())
+    b.set_timing(False)
+    b.sync()
+    bad = sum(1 for s in solvers if s.get_diag()[1] != 0)
+    b.close()
+    for s in solvers:
+        s.close()
+    return {"instances": len(specs), "dof": dof, "ms_per_step": ms, "dofsteps_per_s": dof / (ms * 1e-3),
+            "phase_ms": (acc / 4).tolist(), "grids": grids, "members_with_errors": bad,
+            "steps": steps + warmup + 4}
+
+
 def train_network(seed=0):
     """Training pairs from the method itself: snapshots of four 4-quadrant
     Riemann runs (64^2, smoothness indicator) and eight states of
@@ -320,6 +384,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=1000000,
                     help="cap on the oracle's steps (the CPU leg also stops after 15 s)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-c5", action="store_true", help="skip the 256-instance uneven batch")
     ap.add_argument("--part", choices=["all", "sweep", "c3", "optimized"], default="all",
                     help="c3: only the 512^2 single-instance step; optimized: only the optimized path "
                          "on the --sweep grids (profiling)")
@@ -376,6 +441,14 @@ def main():
         print(json.dumps({"part": args.part, "c3": {k: {kk: vv for kk, vv in v.items() if kk != "state"}
                                                   for k, v in c3.items()}, "optimized": opt}), flush=True)
         return
+
+    c5 = None
+    if args.part == "all" and not args.no_c5:
+        nets = {3: net}
+        nets.update({N: train_network_for(N) for N in (2, 4)})
+        c5 = run_c5(nets, 20, 2)
+        print(f"# c5 batch: {c5['instances']} instances, {c5['dof']:.3e} DoF, {c5['dofsteps_per_s']:.3e} DoF*steps/s, "
+              f"phases {np.round(c5['phase_ms'], 3).tolist()}", flush=True)
 
     # decomposition of the speed-up on the headline grid: batching alone
     # (FP64, smoothness indicator), then FP32 bulk (smoothness indicator)
@@ -440,6 +513,7 @@ def main():
                      "frac": achieved / HBM_PEAK, "traffic": recorded_traffic(ro["n"], ro["copies"]),
                      "algorithmic_bytes_per_launch": lb, "avg_ms": lms},
         "learned_indicator": train,
+        "c5_uneven_batch": c5,
         "sweep": {"plain": plain, "optimized": opt},
     }
     if c3:
