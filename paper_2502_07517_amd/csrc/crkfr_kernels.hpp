@@ -27,6 +27,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <type_traits>
 
 #include "crkfr_physics.hpp"
 
@@ -41,8 +42,10 @@ enum { CENTRAL_EA = 0, CENTRAL_AE = 1 };
 enum { D_TROUBLED = 0, D_FLUXLIM, D_LOBAD, D_SLOPELIM, D_FALLBACK, D_SCALED, D_MEANBAD, D_LFALLBACK,
        D_THFLUX, D_THSCALE, D_NCOUNT };
 
-// learned indicator: network N -> H -> H -> 1 (tanh, tanh, sigmoid), H <= MLP_HMAX
+// learned indicator: network N -> H -> H -> 1 (tanh, tanh, sigmoid), H <= MLP_HMAX;
+// width MLP_HFAST has an unrolled evaluation with one hidden unit per lane
 constexpr int MLP_HMAX = 32;
+constexpr int MLP_HFAST = 16;
 __host__ __device__ constexpr int mlp_nparams(int nin, int H) { return H * nin + H + H * H + H + H + 1; }
 // the wave-speed rate of eq. time.step.2d is max-reduced into RATE_SLOTS
 // addresses (slot = workgroup index mod RATE_SLOTS) to spread the atomics
@@ -122,6 +125,56 @@ struct LGeo {
     static constexpr int EB = TPB / np;
     static constexpr int BLOCK = EB * np;
 };
+
+// the np lanes of an element lie in one wavefront at a power-of-two offset
+template <int np>
+__device__ __forceinline__ constexpr bool elem_in_wave()
+{
+    return np == 2 || np == 4 || np == 8 || np == 16 || np == 32 || np == 64;
+}
+
+// lane exchange within DPP rows (16 lanes) or quads, as VALU moves: row_ror:n
+// for 16-lane elements, quad permutations swapping lanes 1 and 2 apart for 2-
+// and 4-lane elements
+template <int CTRL>
+__device__ __forceinline__ double dpp_double(double x)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_float(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+constexpr int DPP_QUAD_XOR1 = 0xB1, DPP_QUAD_XOR2 = 0x4E, DPP_ROW_ROR = 0x120;   // + n for row_ror:n
+
+template <int np>
+__device__ __forceinline__ constexpr bool elem_in_dpp() { return np == 2 || np == 4 || np == 16; }
+
+// sum (MIN false) or minimum (MIN true) over the element's lanes, every lane
+// gets the same bits; np in {2, 4, 16}
+template <int np, bool MIN, class T>
+__device__ __forceinline__ T dpp_elem_reduce(T x)
+{
+    auto op = [](T a, T b) { return MIN ? (b < a ? b : a) : a + b; };
+    auto mv = [](T y, auto ctrl) {
+        if constexpr (sizeof(T) == 8) return dpp_double<decltype(ctrl)::value>(y);
+        else return dpp_float<decltype(ctrl)::value>(y);
+    };
+    if constexpr (np == 16) {
+        x = op(x, mv(x, std::integral_constant<int, DPP_ROW_ROR + 8>{}));
+        x = op(x, mv(x, std::integral_constant<int, DPP_ROW_ROR + 4>{}));
+        x = op(x, mv(x, std::integral_constant<int, DPP_ROW_ROR + 2>{}));
+        x = op(x, mv(x, std::integral_constant<int, DPP_ROW_ROR + 1>{}));
+    } else {
+        x = op(x, mv(x, std::integral_constant<int, DPP_QUAD_XOR1>{}));
+        if constexpr (np == 4) x = op(x, mv(x, std::integral_constant<int, DPP_QUAD_XOR2>{}));
+    }
+    return x;
+}
 
 // cRK tableaux of eqs. crk22, crk33, crk44: sub-diagonal a_{i+1,i} and weights b_i
 __host__ __device__ constexpr double tab_a(int S, int i)
@@ -541,6 +594,23 @@ __device__ __forceinline__ void learned_features(const real* en, real* ft)
     }
 }
 
+// activations of the learned indicator's network: the library functions in
+// FP64 steps; in FP32-bulk steps tanh x = 1 - 2 / (1 + e^(2x)) and the
+// logistic function from the hardware exponential and reciprocal (exact limits
+// at +-infinity, absolute error about 1e-7)
+template <class real>
+__device__ __forceinline__ real act_tanh(real x)
+{
+    if constexpr (sizeof(real) == 4) return 1.0f - 2.0f * __builtin_amdgcn_rcpf(1.0f + __expf(2.0f * x));
+    else return tanh(x);
+}
+template <class real>
+__device__ __forceinline__ real act_sigmoid(real x)
+{
+    if constexpr (sizeof(real) == 4) return __builtin_amdgcn_rcpf(1.0f + __expf(-x));
+    else return (real)1 / ((real)1 + exp(-x));
+}
+
 // ----------------------------------------------------------------------------
 // k_local
 // ----------------------------------------------------------------------------
@@ -624,23 +694,63 @@ __device__ void local_body(const StepArgs<real>& a, int vblock)
             const float* W2 = b1 + H;
             const float* b2 = W2 + H * H;
             const float* w3 = b2 + H;
-            for (int j = k; j < H; j += np) {
+            real out = 0;                     // output layer's sum, valid on lane 0
+            if (np >= MLP_HFAST && H == MLP_HFAST) {
+                // one unit per lane; the unit's rows of W2 as 16-byte loads
+                // (W2 starts H (N + 1) floats into a 256-byte aligned buffer)
+                const int j = k < H ? k : H - 1;
+                const float4* row = reinterpret_cast<const float4*>(W2 + j * MLP_HFAST);
+                float4 w2r[MLP_HFAST / 4];
+#pragma unroll
+                for (int c = 0; c < MLP_HFAST / 4; ++c) w2r[c] = row[c];
                 real s = (real)b1[j];
 #pragma unroll
                 for (int i = 0; i < N; ++i) s += (real)W1[j * N + i] * sh_f[le][i][0];
-                sh_m[le][0][j] = tanh(s);
+                if (k < H) sh_m[le][0][k] = act_tanh(s);
+                __syncthreads();
+                real s2 = (real)b2[j];
+#pragma unroll
+                for (int c = 0; c < MLP_HFAST / 4; ++c) {
+                    s2 += (real)w2r[c].x * sh_m[le][0][4 * c];
+                    s2 += (real)w2r[c].y * sh_m[le][0][4 * c + 1];
+                    s2 += (real)w2r[c].z * sh_m[le][0][4 * c + 2];
+                    s2 += (real)w2r[c].w * sh_m[le][0][4 * c + 3];
+                }
+                const real h2 = k < H ? act_tanh(s2) : (real)0;
+                if constexpr (np == MLP_HFAST && elem_in_dpp<np>() && is_mp<real>()) {
+                    // FP32 bulk: sum of w3_j h2_j over the element's lanes
+                    // (FP64 steps keep the sequential order of the general path)
+                    out = dpp_elem_reduce<np, false>((real)w3[j] * h2) + (real)w3[H];
+                } else {
+                    if (k < H) sh_m[le][1][k] = h2;
+                    __syncthreads();
+                    if (k == 0) {
+                        out = (real)w3[H];
+#pragma unroll
+                        for (int i = 0; i < MLP_HFAST; ++i) out += (real)w3[i] * sh_m[le][1][i];
+                    }
+                }
+            } else {
+                for (int j = k; j < H; j += np) {
+                    real s = (real)b1[j];
+#pragma unroll
+                    for (int i = 0; i < N; ++i) s += (real)W1[j * N + i] * sh_f[le][i][0];
+                    sh_m[le][0][j] = act_tanh(s);
+                }
+                __syncthreads();
+                for (int j = k; j < H; j += np) {
+                    real s = (real)b2[j];
+                    for (int i = 0; i < H; ++i) s += (real)W2[j * H + i] * sh_m[le][0][i];
+                    sh_m[le][1][j] = act_tanh(s);
+                }
+                __syncthreads();
+                if (k == 0) {
+                    out = (real)w3[H];
+                    for (int j = 0; j < H; ++j) out += (real)w3[j] * sh_m[le][1][j];
+                }
             }
-            __syncthreads();
-            for (int j = k; j < H; j += np) {
-                real s = (real)b2[j];
-                for (int i = 0; i < H; ++i) s += (real)W2[j * H + i] * sh_m[le][0][i];
-                sh_m[le][1][j] = tanh(s);
-            }
-            __syncthreads();
             if (k == 0 && act) {
-                real s = (real)w3[H];
-                for (int j = 0; j < H; ++j) s += (real)w3[j] * sh_m[le][1][j];
-                double y = (double)((real)1 / ((real)1 + exp(-s)));
+                double y = (double)act_sigmoid(out);
                 if (y < a.alpha_min) y = 0.0;
                 if (y > a.alpha_max) y = a.alpha_max;
                 a.alpha_raw[e] = inbox ? y : al_ind;
@@ -921,7 +1031,7 @@ __device__ __forceinline__ double lo_factor(const StepArgs<real>& a, int d, int 
 // ----------------------------------------------------------------------------
 template <class Eq, int N, class real, bool LIM, int D, bool INTERIOR>
 __device__ __forceinline__ void face_point(const StepArgs<real>& a, int t, int eL, int eR, int exL, int eyL, int exR,
-                                           int eyR, size_t outi);
+                                           int eyR, size_t outi, bool owner);
 
 template <class Eq, int N, class real, bool LIM, int D>
 __device__ void face_body(const StepArgs<real>& a, int vblock)
@@ -936,6 +1046,7 @@ __device__ void face_body(const StepArgs<real>& a, int vblock)
     const int t = (int)(tid % npt);
     int eL, eR, exL, eyL, exR, eyR;
     size_t outi;
+    bool owner = false;     // this lane stores the smoothed alpha of element eR
     if (D == 0) {
         const int i = (int)((tid / npt) % (a.nx + 1));
         const int ey = (int)(tid / ((long long)npt * (a.nx + 1)));
@@ -944,6 +1055,7 @@ __device__ void face_body(const StepArgs<real>& a, int vblock)
         exL = i > 0 ? i - 1 : a.nx - 1; eyL = ey;
         exR = i < a.nx ? i : 0; eyR = ey;
         outi = ((size_t)ey * (a.nx + 1) + i) * nq + t;
+        owner = t == 0 && i < a.nx;
     } else {
         const int ex = (int)((tid / npt) % a.nx);
         const int j = (int)(tid / ((long long)npt * a.nx));
@@ -955,13 +1067,13 @@ __device__ void face_body(const StepArgs<real>& a, int vblock)
     }
     // interior faces (both elements present: every face of a periodic grid)
     // take a path without the boundary cases
-    if (eL >= 0 && eR >= 0) face_point<Eq, N, real, LIM, D, true>(a, t, eL, eR, exL, eyL, exR, eyR, outi);
-    else face_point<Eq, N, real, LIM, D, false>(a, t, eL, eR, exL, eyL, exR, eyR, outi);
+    if (eL >= 0 && eR >= 0) face_point<Eq, N, real, LIM, D, true>(a, t, eL, eR, exL, eyL, exR, eyR, outi, owner);
+    else face_point<Eq, N, real, LIM, D, false>(a, t, eL, eR, exL, eyL, exR, eyR, outi, owner);
 }
 
 template <class Eq, int N, class real, bool LIM, int D, bool INTERIOR>
 __device__ __forceinline__ void face_point(const StepArgs<real>& a, int t, int eL, int eR, int exL, int eyL, int exR,
-                                           int eyR, size_t outi)
+                                           int eyR, size_t outi, bool owner)
 {
     using G = Geo<Eq::DIM, N>;
     constexpr int M = Eq::M, nd = G::nd, nq = G::nq, np = G::np, K = Eq::K;
@@ -1135,8 +1247,18 @@ __device__ __forceinline__ void face_point(const StepArgs<real>& a, int t, int e
         }
         rusanov<Eq>(D, sA, sB, fLO, P);
         if (fi) flux_dir<Eq>(D, iA ? sA : sB, fLO, P);
-        double aA = hA ? alpha_smoothed(a, eL, Eq::DIM) : 0.0;
-        double aB = hB ? alpha_smoothed(a, eR, Eq::DIM) : 0.0;
+        // smoothed alphas: the x faces compute them, the lane at position 0
+        // of the face to the left of each element stores that element's;
+        // the y faces and the update read them
+        double aA, aB;
+        if constexpr (D == 0) {
+            aA = hA ? alpha_smoothed(a, eL, Eq::DIM) : 0.0;
+            aB = hB ? alpha_smoothed(a, eR, Eq::DIM) : 0.0;
+            if (owner) a.alpha_out[eR] = aB;
+        } else {
+            aA = hA ? a.alpha_out[eL] : 0.0;
+            aB = hB ? a.alpha_out[eR] : 0.0;
+        }
         const real af = (real)(hA && hB ? 0.5 * (aA + aB) : (hA ? aA : aB));
 #pragma unroll
         for (int v = 0; v < M; ++v) F[v] = (1 - af) * F[v] + af * fLO[v];
@@ -1218,17 +1340,14 @@ __device__ __forceinline__ void face_point(const StepArgs<real>& a, int t, int e
 // otherwise the M sums go through LDS with two barriers.  Every lane gets
 // every total.
 // ----------------------------------------------------------------------------
-template <int np>
-__device__ __forceinline__ constexpr bool elem_in_wave()
-{
-    return np == 2 || np == 4 || np == 8 || np == 16 || np == 32 || np == 64;
-}
-
 template <int M, int np, int EB>
 __device__ __forceinline__ void elem_sums(const double* in, double* out, double (*sh)[M][np], double (*shm)[M],
                                           int le, int k)
 {
-    if constexpr (elem_in_wave<np>()) {
+    if constexpr (elem_in_dpp<np>()) {
+#pragma unroll
+        for (int v = 0; v < M; ++v) out[v] = dpp_elem_reduce<np, false>(in[v]);
+    } else if constexpr (elem_in_wave<np>()) {
 #pragma unroll
         for (int v = 0; v < M; ++v) {
             double x = in[v];
@@ -1256,7 +1375,9 @@ __device__ __forceinline__ void elem_sums(const double* in, double* out, double 
 template <int np>
 __device__ __forceinline__ double elem_min(double x, double (*sh)[np], int le, int k)
 {
-    if constexpr (elem_in_wave<np>()) {
+    if constexpr (elem_in_dpp<np>()) {
+        return dpp_elem_reduce<np, true>(x);
+    } else if constexpr (elem_in_wave<np>()) {
 #pragma unroll
         for (int m = 1; m < np; m <<= 1) {
             double y = __shfl_xor(x, m, np);
@@ -1339,11 +1460,8 @@ __device__ void update_body(const StepArgs<real>& a, int vblock)
     for (int v = 0; v < M; ++v) unew[v] = uH[v];
 
     if constexpr (LIM) {
-        const double al = alpha_smoothed(a, e, DIM);
-        if (k == 0 && act) {
-            a.alpha_out[e] = al;
-            if (al > 0.0) atomicAdd(&a.diag[D_TROUBLED], 1ull);
-        }
+        const double al = a.alpha_out[e];            // smoothed by the x-face phase
+        if (k == 0 && act && al > 0.0) atomicAdd(&a.diag[D_TROUBLED], 1ull);
         const bool any = __syncthreads_or(act && al > 0.0);
         if (any) {
             // recompute the subcell predictor and the low-order update (eq. low.order.update)
@@ -1464,7 +1582,10 @@ __device__ void update_body(const StepArgs<real>& a, int vblock)
                         else t = bisect_root<Eq>(kk, um, ud, eps, P);
                     }
                 }
-                const double th = elem_min<np>(t, sh_d, le, k);
+                // (an element's lanes in one wavefront: no exchange when no lane scales)
+                double th;
+                if constexpr (elem_in_wave<np>()) th = __all(t >= 1.0) ? 1.0 : elem_min<np>(t, sh_d, le, k);
+                else th = elem_min<np>(t, sh_d, le, k);
                 if (!mean_bad) {
                     if (th < 1.0) {
 #pragma unroll
@@ -1541,6 +1662,26 @@ __device__ __forceinline__ void batch_item(const StepArgs<real>& a, int block)
     else update_body<Eq, N, real, LIM>(a, block);
 }
 
+// an instance's arguments in the table.  The local and face phases read them
+// through the constant address space (the table does not change during a
+// launch): the pointers loaded from there are known to address global memory,
+// so their accesses compile to global, not flat, memory instructions (flat
+// loads also count against the LDS wait counter; 13 % off the limited FP32
+// local phase).  The update phase keeps the generic reads: compiled with
+// global accesses it held 104 instead of 90 VGPRs (four instead of five
+// wavefronts per SIMD) and ran 10 % slower when no element is troubled.
+template <class real, int PH>
+__device__ __forceinline__ const StepArgs<real>& table_args(const StepArgs<real>* args, int i)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    if constexpr (PH != BPH_UPDATE) {
+        using CArgs = const __attribute__((address_space(4))) StepArgs<real>;
+        return ((CArgs*)args)[i];
+    }
+#endif
+    return args[i];
+}
+
 // one workgroup per (instance, block) work item
 template <class Eq, int N, class real, bool LIM, int PH>
 __global__ void __launch_bounds__(256) k_batch(const StepArgs<real>* __restrict__ args,
@@ -1548,7 +1689,7 @@ __global__ void __launch_bounds__(256) k_batch(const StepArgs<real>* __restrict_
 {
     if ((int)blockIdx.x >= nwork) return;
     const int2 it = work[blockIdx.x];
-    batch_item<Eq, N, real, LIM, PH>(args[it.x], it.y);
+    batch_item<Eq, N, real, LIM, PH>(table_args<real, PH>(args, it.x), it.y);
 }
 
 // persistent workgroups walking the work table (the loop keeps more values
@@ -1559,7 +1700,7 @@ __global__ void __launch_bounds__(256) k_batch_persistent(const StepArgs<real>* 
 {
     for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
         const int2 it = work[w];
-        batch_item<Eq, N, real, LIM, PH>(args[it.x], it.y);
+        batch_item<Eq, N, real, LIM, PH>(table_args<real, PH>(args, it.x), it.y);
         __syncthreads();   // LDS of this work item is reused by the next
     }
 }
