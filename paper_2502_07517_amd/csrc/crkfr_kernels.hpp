@@ -154,12 +154,37 @@ constexpr int DPP_QUAD_XOR1 = 0xB1, DPP_QUAD_XOR2 = 0x4E, DPP_ROW_ROR = 0x120;  
 template <int np>
 __device__ __forceinline__ constexpr bool elem_in_dpp() { return np == 2 || np == 4 || np == 16; }
 
-// sum (MIN false) or minimum (MIN true) over the element's lanes, every lane
-// gets the same bits; np in {2, 4, 16}
-template <int np, bool MIN, class T>
+// ordering of an element's LDS exchanges: when the element's lanes share one
+// wavefront, a wavefront-scope fence (the wavefront's LDS accesses complete in
+// issue order) instead of a workgroup barrier, so wavefronts without a
+// troubled element do not wait for the others
+template <int np>
+__device__ __forceinline__ void elem_sync()
+{
+    if constexpr (elem_in_wave<np>()) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+// whether any lane of the workgroup (elements across wavefronts) or of the
+// wavefront (elements within one) has pred
+template <int np>
+__device__ __forceinline__ bool elem_any(bool pred)
+{
+    if constexpr (elem_in_wave<np>()) return __any(pred);
+    else return __syncthreads_or(pred);
+}
+
+// sum, minimum or maximum over the element's lanes, every lane gets the same
+// bits; np in {2, 4, 16}
+enum { RED_SUM = 0, RED_MIN = 1, RED_MAX = 2 };
+template <int np, int OP, class T>
 __device__ __forceinline__ T dpp_elem_reduce(T x)
 {
-    auto op = [](T a, T b) { return MIN ? (b < a ? b : a) : a + b; };
+    auto op = [](T a, T b) { return OP == RED_MIN ? (b < a ? b : a) : (OP == RED_MAX ? (b > a ? b : a) : a + b); };
     auto mv = [](T y, auto ctrl) {
         if constexpr (sizeof(T) == 8) return dpp_double<decltype(ctrl)::value>(y);
         else return dpp_float<decltype(ctrl)::value>(y);
@@ -720,7 +745,7 @@ __device__ void local_body(const StepArgs<real>& a, int vblock)
                 if constexpr (np == MLP_HFAST && elem_in_dpp<np>() && is_mp<real>()) {
                     // FP32 bulk: sum of w3_j h2_j over the element's lanes
                     // (FP64 steps keep the sequential order of the general path)
-                    out = dpp_elem_reduce<np, false>((real)w3[j] * h2) + (real)w3[H];
+                    out = dpp_elem_reduce<np, RED_SUM>((real)w3[j] * h2) + (real)w3[H];
                 } else {
                     if (k < H) sh_m[le][1][k] = h2;
                     __syncthreads();
@@ -1346,7 +1371,7 @@ __device__ __forceinline__ void elem_sums(const double* in, double* out, double 
 {
     if constexpr (elem_in_dpp<np>()) {
 #pragma unroll
-        for (int v = 0; v < M; ++v) out[v] = dpp_elem_reduce<np, false>(in[v]);
+        for (int v = 0; v < M; ++v) out[v] = dpp_elem_reduce<np, RED_SUM>(in[v]);
     } else if constexpr (elem_in_wave<np>()) {
 #pragma unroll
         for (int v = 0; v < M; ++v) {
@@ -1376,7 +1401,7 @@ template <int np>
 __device__ __forceinline__ double elem_min(double x, double (*sh)[np], int le, int k)
 {
     if constexpr (elem_in_dpp<np>()) {
-        return dpp_elem_reduce<np, true>(x);
+        return dpp_elem_reduce<np, RED_MIN>(x);
     } else if constexpr (elem_in_wave<np>()) {
 #pragma unroll
         for (int m = 1; m < np; m <<= 1) {
@@ -1410,6 +1435,21 @@ __device__ __forceinline__ void block_rate_max(double rate, int le, int k, int v
         for (int l = 0; l < EB; ++l) r = sh_w[l] > r ? sh_w[l] : r;
         atomic_max_pos(&slots[vblock % RATE_SLOTS], r);
     }
+}
+
+// wavefront max of the per-element rates (lane k = 0 of each element holds
+// its rate, the other lanes 0), one atomic per wavefront into slot (wavefront
+// index mod RATE_SLOTS), no workgroup barrier: a wavefront that is done
+// leaves without waiting for the workgroup's other wavefronts
+__device__ __forceinline__ void wave_rate_max(double rate, int vblock, unsigned long long* slots)
+{
+    double r = dpp_elem_reduce<16, RED_MAX>(rate);          // each 16-lane row
+    double y = __shfl_xor(r, 16, 64);
+    r = y > r ? y : r;
+    y = __shfl_xor(r, 32, 64);
+    r = y > r ? y : r;
+    if ((threadIdx.x & 63) == 0)
+        atomic_max_pos(&slots[(vblock * (blockDim.x / 64) + threadIdx.x / 64) % RATE_SLOTS], r);
 }
 
 // ----------------------------------------------------------------------------
@@ -1462,24 +1502,24 @@ __device__ void update_body(const StepArgs<real>& a, int vblock)
     if constexpr (LIM) {
         const double al = a.alpha_out[e];            // smoothed by the x-face phase
         if (k == 0 && act && al > 0.0) atomicAdd(&a.diag[D_TROUBLED], 1ull);
-        const bool any = __syncthreads_or(act && al > 0.0);
+        const bool any = elem_any<np>(act && al > 0.0);
         if (any) {
             // recompute the subcell predictor and the low-order update (eq. low.order.update)
             real un[M];
             load_node<Eq>(a, np, e, k, un);
 #pragma unroll
             for (int v = 0; v < M; ++v) sh_u[le][k][v] = un[v];
-            __syncthreads();
+            elem_sync<np>();
             real xm[M], xp[M], ym[M], yp[M];
             int nlim = 0, nfb = 0;
             if (al > 0.0) mh_subcell<Eq, N>(a, e, ex, ey, p, q, un, sh_u[le], dt, xm, xp, ym, yp, nlim, nfb);
-            __syncthreads();
+            elem_sync<np>();
 #pragma unroll
             for (int v = 0; v < M; ++v) {
                 sh_f[le][k][v] = xm[v];
                 if constexpr (DIM == 2) sh_g[le][k][v] = ym[v];
             }
-            __syncthreads();
+            elem_sync<np>();
             real fxp[M], gyp[M];
 #pragma unroll
             for (int v = 0; v < M; ++v) { fxp[v] = 0; gyp[v] = 0; }
@@ -1499,13 +1539,13 @@ __device__ void update_body(const StepArgs<real>& a, int vblock)
                     }
                 }
             }
-            __syncthreads();
+            elem_sync<np>();
 #pragma unroll
             for (int v = 0; v < M; ++v) {
                 sh_f[le][k][v] = fxp[v];
                 if constexpr (DIM == 2) sh_g[le][k][v] = gyp[v];
             }
-            __syncthreads();
+            elem_sync<np>();
             if (al > 0.0) {
                 const real ralpha = (real)al;
 #pragma unroll
@@ -1631,7 +1671,8 @@ __device__ void update_body(const StepArgs<real>& a, int vblock)
         rate = (double)Eq::sx(ur, P) / a.dx + (DIM == 2 ? (double)Eq::sy(ur, P) / a.dy : 0.0);
         if (!(rate == rate)) rate = 1e300;
     }
-    block_rate_max<EB>(rate, le, k, vblock, a.rate_bits);
+    if constexpr (elem_in_dpp<np>() && Geo<DIM, N>::BLOCK % 64 == 0) wave_rate_max(rate, vblock, a.rate_bits);
+    else block_rate_max<EB>(rate, le, k, vblock, a.rate_bits);
 }
 
 // ----------------------------------------------------------------------------
