@@ -370,6 +370,28 @@ __device__ __forceinline__ void rusanov(int d, const real* a, const real* b, rea
     for (int v = 0; v < Eq::M; ++v) out[v] = (real)0.5 * (fa[v] + fb[v]) - (real)0.5 * lam * (b[v] - a[v]);
 }
 
+// Rusanov flux normal to a direction that may differ between the lanes of a
+// wavefront: branch-free where the system provides fn / sn, else rusanov()
+template <class Eq, class = void>
+struct has_normal_flux : std::false_type {};
+template <class Eq>
+struct has_normal_flux<Eq, std::void_t<decltype(&Eq::fn)>> : std::true_type {};
+
+template <class Eq, class real>
+__device__ __forceinline__ void rusanov_n(int d, const real* a, const real* b, real* out, const Phys& P)
+{
+    if constexpr (has_normal_flux<Eq>::value) {
+        real fa[Eq::M], fb[Eq::M];
+        Eq::fn(d, a, fa, P);
+        Eq::fn(d, b, fb, P);
+        real lam = fmax(Eq::sn(d, a, P), Eq::sn(d, b, P));
+#pragma unroll
+        for (int v = 0; v < Eq::M; ++v) out[v] = (real)0.5 * (fa[v] + fb[v]) - (real)0.5 * lam * (b[v] - a[v]);
+    } else {
+        rusanov<Eq>(d, a, b, out, P);
+    }
+}
+
 __device__ __forceinline__ void atomic_min_pos(unsigned long long* p, double v)
 {
     atomicMin(p, (unsigned long long)__double_as_longlong(v));
@@ -649,7 +671,9 @@ __device__ void local_body(const StepArgs<real>& a, int vblock)
     __shared__ real sh_u[EB][np][M];
     __shared__ real sh_f[EB][np][M];
     __shared__ real sh_g[EB][np][MY];
-    __shared__ real sh_h[EB][M][4 * nd];
+    // face values of the final part; before it, the predicted yp of the subcells
+    constexpr int HW = 4 * nd > np ? 4 * nd : np;
+    __shared__ real sh_h[EB][M][HW];
 
     const Phys& P = a.phys;
     const int le = threadIdx.x / np, k = threadIdx.x - le * np;
@@ -781,55 +805,59 @@ __device__ void local_body(const StepArgs<real>& a, int vblock)
                 a.alpha_raw[e] = inbox ? y : al_ind;
             }
         }
-        // ---- MUSCL-Hancock predictor and interior subface fluxes ----
+        // ---- MUSCL-Hancock predictor; the face-adjacent subcells' predicted
+        //      values and the subface fluxes next to them, spread over the
+        //      lanes like the face points (one subface flux per face point) ----
         real xm[M], xp[M], ym[M], yp[M];
         int nlim = 0, nfb = 0;
         mh_subcell<Eq, N>(a, e, ex, ey, p, q, un, sh_u[le], dt, xm, xp, ym, yp, nlim, nfb);
         __syncthreads();
+        // xm, xp, ym, yp in sh_f, sh_u (the nodal values are no longer needed), sh_g, sh_h
+        real* sh_yp = &sh_h[le][0][0];
 #pragma unroll
         for (int v = 0; v < M; ++v) {
             sh_f[le][k][v] = xm[v];
-            if constexpr (DIM == 2) sh_g[le][k][v] = ym[v];
+            sh_u[le][k][v] = xp[v];
+            if constexpr (DIM == 2) {
+                sh_g[le][k][v] = ym[v];
+                sh_yp[k * M + v] = yp[v];
+            }
         }
         __syncthreads();
         if (act) {
-            if (p < N) {
-                real nb[M], fs[M];
+            constexpr int NFP = DIM == 2 ? 4 * nd : 2;
 #pragma unroll
-                for (int v = 0; v < M; ++v) nb[v] = sh_f[le][k + 1][v];
-                rusanov<Eq>(0, xp, nb, fs, P);
-                if (p == N - 1)
+            for (int j = 0; j < (NFP + np - 1) / np; ++j) {
+                const int fp = k + j * np;
+                if (fp >= NFP) break;
+                const int sd = DIM == 2 ? fp / nd : fp, t = DIM == 2 ? fp % nd : 0, side = sd & 1;
+                const int d = sd >> 1;
+                // subcells i0 | i0 + 1 along d at line position t; the face's own subcell
+                const int i0 = side ? N - 1 : 0;
+                const int kl = d == 0 ? t * nd + i0 : i0 * nd + t, kr = kl + (d == 0 ? 1 : nd);
+                const int kf = side ? kr : kl;
+                real lft[M], rgt[M], own[M], fs[M];
 #pragma unroll
-                    for (int v = 0; v < M; ++v) a.trx[((size_t)(1 * C + 2 * M + 1 + M + v) * nes + e) * nq + q] = fs[v];
-                if (p == 0)
-#pragma unroll
-                    for (int v = 0; v < M; ++v) a.trx[((size_t)(0 * C + 2 * M + 1 + M + v) * nes + e) * nq + q] = fs[v];
-            }
-            if (p == N)
-#pragma unroll
-                for (int v = 0; v < M; ++v) a.trx[((size_t)(1 * C + 2 * M + 1 + v) * nes + e) * nq + q] = xp[v];
-            if (p == 0)
-#pragma unroll
-                for (int v = 0; v < M; ++v) a.trx[((size_t)(0 * C + 2 * M + 1 + v) * nes + e) * nq + q] = xm[v];
-            if constexpr (DIM == 2) {
-                if (q < N) {
-                    real nb[M], fs[M];
-#pragma unroll
-                    for (int v = 0; v < M; ++v) nb[v] = sh_g[le][k + nd][v];
-                    rusanov<Eq>(1, yp, nb, fs, P);
-                    if (q == N - 1)
-#pragma unroll
-                        for (int v = 0; v < M; ++v) a.trY[((size_t)(1 * C + 2 * M + 1 + M + v) * nes + e) * nd + p] = fs[v];
-                    if (q == 0)
-#pragma unroll
-                        for (int v = 0; v < M; ++v) a.trY[((size_t)(0 * C + 2 * M + 1 + M + v) * nes + e) * nd + p] = fs[v];
+                for (int v = 0; v < M; ++v) {
+                    if constexpr (DIM == 2) {
+                        lft[v] = d == 0 ? sh_u[le][kl][v] : sh_yp[kl * M + v];
+                        rgt[v] = d == 0 ? sh_f[le][kr][v] : sh_g[le][kr][v];
+                        own[v] = side ? (d == 0 ? sh_u[le][kf][v] : sh_yp[kf * M + v])
+                                      : (d == 0 ? sh_f[le][kf][v] : sh_g[le][kf][v]);
+                    } else {
+                        lft[v] = sh_u[le][kl][v];
+                        rgt[v] = sh_f[le][kr][v];
+                        own[v] = side ? sh_u[le][kf][v] : sh_f[le][kf][v];
+                    }
                 }
-                if (q == N)
+                real* base = d == 0 ? a.trx : a.trY;
+                const int npt = d == 0 ? nq : nd;
+                rusanov_n<Eq>(d, lft, rgt, fs, P);
 #pragma unroll
-                    for (int v = 0; v < M; ++v) a.trY[((size_t)(1 * C + 2 * M + 1 + v) * nes + e) * nd + p] = yp[v];
-                if (q == 0)
-#pragma unroll
-                    for (int v = 0; v < M; ++v) a.trY[((size_t)(0 * C + 2 * M + 1 + v) * nes + e) * nd + p] = ym[v];
+                for (int v = 0; v < M; ++v) {
+                    base[((size_t)(side * C + 2 * M + 1 + v) * nes + e) * npt + t] = own[v];
+                    base[((size_t)(side * C + 2 * M + 1 + M + v) * nes + e) * npt + t] = fs[v];
+                }
             }
             if (nlim) atomicAdd(&a.diag[D_SLOPELIM], (unsigned long long)nlim);
             if (nfb) atomicAdd(&a.diag[D_FALLBACK], (unsigned long long)nfb);

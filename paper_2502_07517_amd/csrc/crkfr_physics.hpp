@@ -175,6 +175,24 @@ struct Euler2D {
         real v1, v2, ir, p = pvv(u, v1, v2, ir, P);
         return fabs(v2) + sqrt((real)P.gamma * p * ir);
     }
+    // flux and wave speed normal to direction d (0: x, 1: y) without a branch
+    // on d (lanes of one wavefront may differ in d): the arithmetic of fx / gy
+    // and sx / sy (a product plus zero is the product)
+    __device__ static inline void fn(int d, const real* u, real* f, const Phys& P)
+    {
+        real v1, v2, ir, p = pvv(u, v1, v2, ir, P);
+        const bool y = d != 0;
+        const real vn = y ? v2 : v1;
+        f[0] = y ? u[2] : u[1];
+        f[1] = u[1] * vn + (y ? (real)0 : p);
+        f[2] = u[2] * vn + (y ? p : (real)0);
+        f[3] = (u[3] + p) * vn;
+    }
+    __device__ static inline real sn(int d, const real* u, const Phys& P)
+    {
+        real v1, v2, ir, p = pvv(u, v1, v2, ir, P);
+        return fabs(d != 0 ? v2 : v1) + sqrt((real)P.gamma * p * ir);
+    }
     __device__ static inline double adm(int k, const double* u, const Phys& P)
     {
         if (k == 0) return u[0];
