@@ -628,6 +628,14 @@ __device__ __forceinline__ double indicator_alpha(const real* en, double amin, d
 // features of the learned indicator: for shells s = 1..N the share r_s of
 // shell s in the energy of shells 0..s, as log10(max(r_s, 1e-12)) / 6 + 1
 // (at least -1)
+// feature of shell s from its energy and the cumulative energy of shells 0..s
+template <class real>
+__device__ __forceinline__ real learned_feature(real es, real cum)
+{
+    const real r = cum > 0 ? es / cum : (real)0;
+    // floor exactly -1, so a box edge at -1 is decided the same everywhere
+    return r > (real)1e-12 ? fmax(log10(r) / (real)6 + (real)1, (real)-1) : (real)-1;
+}
 template <int N, class real>
 __device__ __forceinline__ void learned_features(const real* en, real* ft)
 {
@@ -635,9 +643,7 @@ __device__ __forceinline__ void learned_features(const real* en, real* ft)
 #pragma unroll
     for (int s2 = 1; s2 <= N; ++s2) {
         cum += en[s2];
-        const real r = cum > 0 ? en[s2] / cum : (real)0;
-        // floor exactly -1, so a box edge at -1 is decided the same everywhere
-        ft[s2 - 1] = r > (real)1e-12 ? fmax(log10(r) / (real)6 + (real)1, (real)-1) : (real)-1;
+        ft[s2 - 1] = learned_feature(en[s2], cum);
     }
 }
 
@@ -709,34 +715,43 @@ __device__ void local_body(const StepArgs<real>& a, int vblock)
         __syncthreads();
         double al_ind = 0.0;
         bool inbox = true;
-        if (k == 0 && act) {
-            if (modal) {
-                real en[nd];
-                shell_energies<DIM, N>(&sh_g[le][0][0], MY, en);
+        if (modal) {
+            // every lane sums the shell energies in the same order (same bits);
+            // lane 0 forms the indicator's alpha, lanes 1..N the learned
+            // indicator's features (feature s on lane s)
+            real en[nd];
+            shell_energies<DIM, N>(&sh_g[le][0][0], MY, en);
+            if (k == 0 && act) {
                 al_ind = indicator_alpha<N>(en, a.alpha_min, a.alpha_max, a.ind_T, a.ind_kT);
-                if (a.indicator == IND_PAPER) {
-                    a.alpha_raw[e] = al_ind;
-                } else {
-                    real ft[N];
-                    learned_features<N>(en, ft);
-                    const float* box = a.mlp + mlp_nparams(N, a.mlp_hidden);
-#pragma unroll
-                    for (int j = 0; j < N; ++j) {
-                        if (!(ft[j] >= (double)box[j] && ft[j] <= (double)box[N + j])) inbox = false;
-                        sh_f[le][j][0] = (real)ft[j];
-                    }
-                    a.alpha_judge[e] = al_ind;
-                    if (!inbox) atomicAdd(&a.diag[D_LFALLBACK], 1ull);
-                }
-            } else if (a.indicator == IND_CONST) {
-                a.alpha_raw[e] = a.alpha_const;
-            } else if (a.indicator == IND_GIVEN) {
-                a.alpha_raw[e] = a.alpha_given[e];
+                if (a.indicator == IND_PAPER) a.alpha_raw[e] = al_ind;
+                else a.alpha_judge[e] = al_ind;
             }
+            if (a.indicator == IND_LEARNED && k >= 1 && k <= N) {
+                real cum = en[0], es = 0, cs = 0;
+#pragma unroll
+                for (int s2 = 1; s2 <= N; ++s2) {
+                    cum += en[s2];
+                    if (s2 == k) { es = en[s2]; cs = cum; }
+                }
+                sh_f[le][k - 1][0] = learned_feature(es, cs);
+            }
+        } else if (k == 0 && act) {
+            if (a.indicator == IND_CONST) a.alpha_raw[e] = a.alpha_const;
+            else if (a.indicator == IND_GIVEN) a.alpha_raw[e] = a.alpha_given[e];
         }
         if (a.indicator == IND_LEARNED) {
             // the network: hidden units spread over the element's lanes
             __syncthreads();
+            if (k == 0) {
+                // the features inside the training box, else the indicator decides
+                const float* box = a.mlp + mlp_nparams(N, a.mlp_hidden);
+#pragma unroll
+                for (int j = 0; j < N; ++j) {
+                    const real ft = sh_f[le][j][0];
+                    if (!(ft >= (double)box[j] && ft <= (double)box[N + j])) inbox = false;
+                }
+                if (act && !inbox) atomicAdd(&a.diag[D_LFALLBACK], 1ull);
+            }
             const int H = a.mlp_hidden;
             const float* W1 = a.mlp;
             const float* b1 = W1 + H * N;
@@ -939,9 +954,15 @@ __device__ void local_body(const StepArgs<real>& a, int vblock)
 #pragma unroll
                 for (int v = 0; v < M; ++v) uf[v] += fw[j][r] * sh_u[le][kn][v];
             }
-            Eq::fxy(uf, ff, gf, P);
+            if constexpr (has_normal_flux<Eq>::value) {
+                Eq::fn(sd < 2 ? 0 : 1, uf, ff, P);
 #pragma unroll
-            for (int v = 0; v < M; ++v) tr[j][v] += bi * (sd < 2 ? ff[v] : gf[v]);
+                for (int v = 0; v < M; ++v) tr[j][v] += bi * ff[v];
+            } else {
+                Eq::fxy(uf, ff, gf, P);
+#pragma unroll
+                for (int v = 0; v < M; ++v) tr[j][v] += bi * (sd < 2 ? ff[v] : gf[v]);
+            }
             if (act && (a.dissipation == DISS_DCSX || (i == 0 && a.dissipation == DISS_D1))) {
                 // stage values at the face (D-CSX), or u^n in place of U (D1)
                 real* base = sd < 2 ? a.trx : a.trY;
