@@ -144,7 +144,8 @@ typedef struct crkfr_mlp crkfr_mlp;
 /* Create a solver on the current HIP device, ordered on hip_stream (a
  * hipStream_t; NULL: the solver creates a stream of its own, default
  * priority, destroyed with it).  Allocates every device buffer the step
- * needs.  Errors: EINVAL (N outside 1..4, sizes < 1, bad enums), ENOMEM, EHIP. */
+ * needs.  Errors: EINVAL (N outside 1..4, sizes < 1, 2^31 or more nodes or
+ * face points in one direction, bad enums), ENOMEM, EHIP. */
 int crkfr_create(const crkfr_config* cfg, void* hip_stream, crkfr_solver** out);
 void crkfr_destroy(crkfr_solver* s);
 

@@ -627,6 +627,13 @@ extern "C" int crkfr_create(const crkfr_config* cfg, void* hip_stream, crkfr_sol
         (dim == 2 && (cfg->bc[2] == CRKFR_BC_PERIODIC) != (cfg->bc[3] == CRKFR_BC_PERIODIC)))
         return fail(CRKFR_EINVAL, "periodic boundaries come in pairs");
     if (!(cfg->x1 > cfg->x0) || (dim == 2 && !(cfg->y1 > cfg->y0))) return fail(CRKFR_EINVAL, "bad domain");
+    {   // the kernels index nodes and face points with 32-bit integers
+        const long long nd1 = cfg->N + 1, nq1 = dim == 2 ? nd1 : 1, lim = 1ll << 31;
+        const long long nodes = (long long)cfg->nx * cfg->ny * nd1 * nq1;
+        const long long fxp = (long long)(cfg->nx + 1) * cfg->ny * nq1, fyp = (long long)(cfg->ny + 1) * cfg->nx * nd1;
+        if (nodes >= lim || fxp >= lim || fyp >= lim)
+            return fail(CRKFR_EINVAL, "grid too large: nodes and face points per direction must stay below 2^31");
+    }
 
     crkfr_solver* s = new crkfr_solver();
     std::memset(s, 0, sizeof(*s));

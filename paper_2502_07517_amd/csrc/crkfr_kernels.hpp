@@ -687,7 +687,7 @@ __device__ void local_body(const StepArgs<real>& a, int vblock)
     const int e0 = vblock * EB + le;
     const bool act = e0 < a.ne;
     const int e = act ? e0 : a.ne - 1;
-    const int ex = e % a.nx, ey = e / a.nx;
+    const int ey = (int)((unsigned)e / (unsigned)a.nx), ex = e - ey * a.nx;
     const double dt = *a.dt_dev;
     const real rdt = (real)dt, idx = (real)(1.0 / a.dx), idy = (real)(1.0 / a.dy);
     const real xn = (real)(a.x0 + ((double)ex + (double)a.R.xi[p]) * a.dx);
@@ -1113,17 +1113,20 @@ __device__ void face_body(const StepArgs<real>& a, int vblock)
     using G = Geo<Eq::DIM, N>;
     constexpr int M = Eq::M, nd = G::nd, nq = G::nq, np = G::np, K = Eq::K;
     const Phys& P = a.phys;
-    const int npt = D == 0 ? nq : nd;
-    const long long total = D == 0 ? (long long)a.ny * (a.nx + 1) * nq : (long long)(a.ny + 1) * a.nx * nd;
-    const long long tid = (long long)vblock * blockDim.x + threadIdx.x;
+    constexpr int npt = D == 0 ? nq : nd;
+    // 32-bit indices: face points per direction stay below 2^31 (checked when
+    // the solver is created)
+    const unsigned total = D == 0 ? (unsigned)a.ny * (unsigned)(a.nx + 1) * nq : (unsigned)(a.ny + 1) * (unsigned)a.nx * nd;
+    const unsigned tid = (unsigned)vblock * blockDim.x + threadIdx.x;
     if (tid >= total) return;
     const int t = (int)(tid % npt);
+    const unsigned line = tid / npt;
     int eL, eR, exL, eyL, exR, eyR;
     size_t outi;
     bool owner = false;     // this lane stores the smoothed alpha of element eR
     if (D == 0) {
-        const int i = (int)((tid / npt) % (a.nx + 1));
-        const int ey = (int)(tid / ((long long)npt * (a.nx + 1)));
+        const int i = (int)(line % (unsigned)(a.nx + 1));
+        const int ey = (int)(line / (unsigned)(a.nx + 1));
         eL = i > 0 ? ey * a.nx + i - 1 : (a.bc[0] == BC_PERIODIC ? ey * a.nx + a.nx - 1 : -1);
         eR = i < a.nx ? ey * a.nx + i : (a.bc[1] == BC_PERIODIC ? ey * a.nx : -1);
         exL = i > 0 ? i - 1 : a.nx - 1; eyL = ey;
@@ -1131,8 +1134,8 @@ __device__ void face_body(const StepArgs<real>& a, int vblock)
         outi = ((size_t)ey * (a.nx + 1) + i) * nq + t;
         owner = t == 0 && i < a.nx;
     } else {
-        const int ex = (int)((tid / npt) % a.nx);
-        const int j = (int)(tid / ((long long)npt * a.nx));
+        const int ex = (int)(line % (unsigned)a.nx);
+        const int j = (int)(line / (unsigned)a.nx);
         eL = j > 0 ? (j - 1) * a.nx + ex : (a.bc[2] == BC_PERIODIC ? (a.ny - 1) * a.nx + ex : -1);
         eR = j < a.ny ? j * a.nx + ex : (a.bc[3] == BC_PERIODIC ? ex : -1);
         exL = ex; eyL = j > 0 ? j - 1 : a.ny - 1;
@@ -1525,7 +1528,7 @@ __device__ void update_body(const StepArgs<real>& a, int vblock)
     const int e0 = vblock * EB + le;
     const bool act = e0 < a.ne;
     const int e = act ? e0 : a.ne - 1;
-    const int ex = e % a.nx, ey = e / a.nx;
+    const int ey = (int)((unsigned)e / (unsigned)a.nx), ex = e - ey * a.nx;
     const double dt = *a.dt_dev;
     const real rdt = (real)dt, idx = (real)(1.0 / a.dx), idy = (real)(1.0 / a.dy);
     const size_t nes = (size_t)a.ne, gi = (size_t)e * np + k;

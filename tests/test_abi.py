@@ -34,3 +34,14 @@ def test_config_struct_matches_header_field_count():
             continue
         names += [n.strip().split("[")[0] for n in d.rstrip(";").split(None, 1)[1].split(",")]
     assert names == [f for f, _ in crkfr.Config._fields_]
+
+
+def test_create_rejects_grids_beyond_32bit_indices():
+    """Nodes and face points are indexed with 32-bit integers in the kernels;
+    larger grids are refused before any device call."""
+    import pytest
+    for eq, N, nx, ny in [(crkfr.EULER2D, 3, 11586, 11586), (crkfr.EULER2D, 1, 1, 2 ** 29),
+                          (crkfr.EULER1D, 4, 2 ** 29, 1)]:
+        with pytest.raises(crkfr.CrkfrError) as e:
+            crkfr.Solver(eq, N, nx, ny)
+        assert e.value.code == -1 and "2^31" in str(e.value)      # CRKFR_EINVAL
