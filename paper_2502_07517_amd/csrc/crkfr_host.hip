@@ -457,6 +457,8 @@ static StepArgs<real> step_args(const crkfr_solver* s, int in, int out)
     a.alpha_const = s->lim.alpha_const;
     a.phys = make_phys(s);
     fill_tab(s->ref, s->stages, a.R);
+    a.idx = 1.0 / a.dx;
+    a.idy = 1.0 / a.dy;
     for (int i = 0; i < MAXND; ++i) {
         a.w64[i] = i <= s->cfg.N ? s->ref.w[i] : 0.0;
         a.iwdx[i] = i <= s->cfg.N ? 1.0 / (s->ref.w[i] * a.dx) : 0.0;

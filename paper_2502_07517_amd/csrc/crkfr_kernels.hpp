@@ -91,6 +91,7 @@ struct StepArgs {
     RefTab<real> R;
     double w64[MAXND];
     double iwdx[MAXND], iwdy[MAXND];   // 1 / (w_i dx), 1 / (w_i dy)
+    double idx, idy;                   // 1 / dx, 1 / dy (correctly rounded, as on the device)
     unsigned long long* diag;
     unsigned long long* rate_bits;
     const float* mlp;      // learned indicator: parameters, then the feature box lo[N], hi[N]
@@ -689,7 +690,7 @@ __device__ void local_body(const StepArgs<real>& a, int vblock)
     const int e = act ? e0 : a.ne - 1;
     const int ey = (int)((unsigned)e / (unsigned)a.nx), ex = e - ey * a.nx;
     const double dt = *a.dt_dev;
-    const real rdt = (real)dt, idx = (real)(1.0 / a.dx), idy = (real)(1.0 / a.dy);
+    const real rdt = (real)dt, idx = (real)a.idx, idy = (real)a.idy;
     const real xn = (real)(a.x0 + ((double)ex + (double)a.R.xi[p]) * a.dx);
     const real yn = DIM == 2 ? (real)(a.y0 + ((double)ey + (double)a.R.xi[q]) * a.dy) : (real)0;
     const bool src = Eq::K == 3 && P.source;          // ten-moment systems carry the source
@@ -1530,7 +1531,7 @@ __device__ void update_body(const StepArgs<real>& a, int vblock)
     const int e = act ? e0 : a.ne - 1;
     const int ey = (int)((unsigned)e / (unsigned)a.nx), ex = e - ey * a.nx;
     const double dt = *a.dt_dev;
-    const real rdt = (real)dt, idx = (real)(1.0 / a.dx), idy = (real)(1.0 / a.dy);
+    const real rdt = (real)dt, idx = (real)a.idx, idy = (real)a.idy;
     const size_t nes = (size_t)a.ne, gi = (size_t)e * np + k;
     const size_t nfx = (size_t)a.ny * (a.nx + 1) * nq, nfy = (size_t)(a.ny + 1) * a.nx * nd;
     const size_t iL = ((size_t)ey * (a.nx + 1) + ex) * nq + q, iR = iL + nq;
@@ -1627,11 +1628,11 @@ __device__ void update_body(const StepArgs<real>& a, int vblock)
         double c = 0.0;
         if constexpr (MP) {
             if (p == 0)
-                c -= dt / a.dx * (DIM == 2 ? a.w64[q] : 1.0)
+                c -= dt * a.idx * (DIM == 2 ? a.w64[q] : 1.0)
                      * ((double)a.Fx[v * nfx + iR] - (double)a.Fx[v * nfx + iL]);
             if constexpr (DIM == 2) {
                 if (q == 0)
-                    c -= dt / a.dy * a.w64[p] * ((double)a.Gy[v * nfy + iT] - (double)a.Gy[v * nfy + iB]);
+                    c -= dt * a.idy * a.w64[p] * ((double)a.Gy[v * nfy + iT] - (double)a.Gy[v * nfy + iB]);
             }
             if (a.dtS) c += wk * (double)a.dtS[(size_t)v * nes * np + gi];
         }
