@@ -1070,11 +1070,10 @@ __device__ void local_body(const StepArgs<real>& a, int vblock)
 
 // smoothed blending coefficient alpha_e <- max(alpha_e, max_nbr alpha / 2)
 template <class real>
-__device__ __forceinline__ double alpha_smoothed(const StepArgs<real>& a, int e, int dim)
+__device__ __forceinline__ double alpha_smoothed(const StepArgs<real>& a, int e, int ex, int ey, int dim)
 {
     double al = a.alpha_raw[e];
     if ((a.indicator == IND_PAPER || a.indicator == IND_LEARNED) && a.smooth) {
-        int ex = e % a.nx, ey = e / a.nx;
         for (int d = 0; d < dim; ++d)
             for (int s = 0; s < 2; ++s) {
                 int en = nbr(a, ex, ey, d, s);
@@ -1330,8 +1329,8 @@ __device__ __forceinline__ void face_point(const StepArgs<real>& a, int t, int e
         // the y faces and the update read them
         double aA, aB;
         if constexpr (D == 0) {
-            aA = hA ? alpha_smoothed(a, eL, Eq::DIM) : 0.0;
-            aB = hB ? alpha_smoothed(a, eR, Eq::DIM) : 0.0;
+            aA = hA ? alpha_smoothed(a, eL, exL, eyL, Eq::DIM) : 0.0;
+            aB = hB ? alpha_smoothed(a, eR, exR, eyR, Eq::DIM) : 0.0;
             if (owner) a.alpha_out[eR] = aB;
         } else {
             aA = hA ? a.alpha_out[eL] : 0.0;
@@ -1493,7 +1492,8 @@ __device__ __forceinline__ void block_rate_max(double rate, int le, int k, int v
 // wavefront max of the per-element rates (lane k = 0 of each element holds
 // its rate, the other lanes 0), one atomic per wavefront into slot (wavefront
 // index mod RATE_SLOTS), no workgroup barrier: a wavefront that is done
-// leaves without waiting for the workgroup's other wavefronts
+// leaves without waiting for the workgroup's other wavefronts.  Every lane of
+// the wavefront calls it (DPP rows and shuffles read all 64 lanes).
 __device__ __forceinline__ void wave_rate_max(double rate, int vblock, unsigned long long* slots)
 {
     double r = dpp_elem_reduce<16, RED_MAX>(rate);          // each 16-lane row
