@@ -124,13 +124,15 @@ def _learned_pair(N, n, m, dtype, params, lo, hi, hidden):
     return ref, gpu, net
 
 
+@pytest.mark.parametrize("hidden", [16, 8, 32])
 @pytest.mark.parametrize("N", [2, 3, 4])
 @pytest.mark.parametrize("box", ["full", "partial"])
-def test_learned_step_matches_oracle_fp64(N, box):
+def test_learned_step_matches_oracle_fp64(N, box, hidden):
     """A network with outputs across (0, 1) and, with the partial box, some
-    elements falling back to the indicator: same result as the oracle."""
+    elements falling back to the indicator: same result as the oracle.
+    Width 16 takes the unrolled one-unit-per-lane evaluation where an element
+    has at least 16 lanes (N >= 3), widths 8 and 32 the general loop."""
     n, m = 12, 15
-    hidden = 16
     u0 = _quadrants(N, n, m, 2)
     p = (0.8 * np.random.default_rng(N).standard_normal(C.Mlp(N, hidden).num_params())).astype(np.float32)
     lo, hi = -np.ones(N, np.float32), np.ones(N, np.float32)
@@ -165,8 +167,11 @@ def test_learned_step_matches_oracle_fp64(N, box):
         assert fb > 0
 
 
-def test_learned_step_matches_oracle_mp32():
-    N, n, m, hidden = 3, 12, 15, 16
+@pytest.mark.parametrize("N,hidden", [(3, 16), (4, 16), (3, 32)])
+def test_learned_step_matches_oracle_mp32(N, hidden):
+    """FP32 bulk: the hardware activations and, for N = 3 and width 16, the
+    output layer summed across the element's lanes."""
+    n, m = 12, 15
     u0 = _quadrants(N, n, m, 2)
     p = (0.8 * np.random.default_rng(7).standard_normal(C.Mlp(N, hidden).num_params())).astype(np.float32)
     lo, hi = -np.ones(N, np.float32), np.ones(N, np.float32)
