@@ -193,10 +193,19 @@ def test_dt_and_cfl_match_oracle():
         assert abs(C.fourier_cfl(Nn, 0, 0, 1e-10) - cfl_for(Nn, system=False)) < 1e-4 * cfl_for(Nn, system=False)
 
 
-def test_device_dt_steps_match_oracle_dt_rule():
-    n, N = 8, 2
-    ref, gpu = make_pair(C.EULER2D, N, n, n)
-    u = W.euler2d_smooth_periodic(5, n, N)
+@pytest.mark.parametrize("eq,N", [(C.EULER2D, 1), (C.EULER2D, 2), (C.EULER2D, 3), (C.EULER2D, 4),
+                                  (C.EULER1D, 1), (C.EULER1D, 3)])
+def test_device_dt_steps_match_oracle_dt_rule(eq, N):
+    """The device's time step (the update's rate maximum: per wavefront for
+    elements of 2, 4 or 16 lanes, per workgroup through LDS otherwise) follows
+    the oracle's rule."""
+    n = 8
+    if eq == C.EULER2D:
+        ref, gpu = make_pair(C.EULER2D, N, n, n)
+        u = W.euler2d_smooth_periodic(5, n, N)
+    else:
+        ref, gpu = make_pair(C.EULER1D, N, 3 * n)
+        u = W.euler1d_smooth(5, 3 * n, N)
     gpu.set_state(u)
     for _ in range(5):
         dt = O.compute_dt(ref, u)
