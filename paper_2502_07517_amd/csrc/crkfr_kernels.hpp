@@ -410,7 +410,7 @@ __device__ __forceinline__ void atomic_max_pos(unsigned long long* p, double v)
 // Outputs the predicted values at the x faces (xm, xp) and y faces (ym, yp).
 // ----------------------------------------------------------------------------
 template <class Eq, int N, class real>
-__device__ void mh_subcell(const StepArgs<real>& a, int e, int ex, int ey, int p, int q,
+__device__ void mh_subcell(const StepArgs<real>& a, int ex, int ey, int p, int q,
                            const real* u, const real (*sh)[Eq::M], double dt,
                            real* xm, real* xp, real* ym, real* yp, int& nlim, int& nfb)
 {
@@ -826,7 +826,7 @@ __device__ void local_body(const StepArgs<real>& a, int vblock)
         //      lanes like the face points (one subface flux per face point) ----
         real xm[M], xp[M], ym[M], yp[M];
         int nlim = 0, nfb = 0;
-        mh_subcell<Eq, N>(a, e, ex, ey, p, q, un, sh_u[le], dt, xm, xp, ym, yp, nlim, nfb);
+        mh_subcell<Eq, N>(a, ex, ey, p, q, un, sh_u[le], dt, xm, xp, ym, yp, nlim, nfb);
         __syncthreads();
         // xm, xp, ym, yp in sh_f, sh_u (the nodal values are no longer needed), sh_g, sh_h
         real* sh_yp = &sh_h[le][0][0];
@@ -1111,8 +1111,7 @@ template <class Eq, int N, class real, bool LIM, int D>
 __device__ void face_body(const StepArgs<real>& a, int vblock)
 {
     using G = Geo<Eq::DIM, N>;
-    constexpr int M = Eq::M, nd = G::nd, nq = G::nq, np = G::np, K = Eq::K;
-    const Phys& P = a.phys;
+    constexpr int nd = G::nd, nq = G::nq;
     constexpr int npt = D == 0 ? nq : nd;
     // 32-bit indices: face points per direction stay below 2^31 (checked when
     // the solver is created)
@@ -1565,7 +1564,7 @@ __device__ void update_body(const StepArgs<real>& a, int vblock)
             elem_sync<np>();
             real xm[M], xp[M], ym[M], yp[M];
             int nlim = 0, nfb = 0;
-            if (al > 0.0) mh_subcell<Eq, N>(a, e, ex, ey, p, q, un, sh_u[le], dt, xm, xp, ym, yp, nlim, nfb);
+            if (al > 0.0) mh_subcell<Eq, N>(a, ex, ey, p, q, un, sh_u[le], dt, xm, xp, ym, yp, nlim, nfb);
             elem_sync<np>();
 #pragma unroll
             for (int v = 0; v < M; ++v) {
@@ -1871,10 +1870,10 @@ __device__ __forceinline__ void prep_body(const PrepArgs& a)
     if (dt > 0.0) *a.steps += 1;   // steps past the end time (dt = 0) do not count
 }
 
-static __global__ void __launch_bounds__(RATE_SLOTS) k_prep(PrepArgs a) { prep_body(a); }
+[[maybe_unused]] static __global__ void __launch_bounds__(RATE_SLOTS) k_prep(PrepArgs a) { prep_body(a); }
 
 // one workgroup per instance of a batch
-static __global__ void __launch_bounds__(RATE_SLOTS) k_prep_batch(const PrepArgs* __restrict__ arr)
+[[maybe_unused]] static __global__ void __launch_bounds__(RATE_SLOTS) k_prep_batch(const PrepArgs* __restrict__ arr)
 {
     prep_body(arr[blockIdx.x]);
 }

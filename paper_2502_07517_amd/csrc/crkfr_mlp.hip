@@ -234,7 +234,7 @@ __global__ void __launch_bounds__(256) k_mlp_box(const float* __restrict__ x, in
     smax[threadIdx.x] = hi;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) {
+        if ((int)threadIdx.x < w) {
             smin[threadIdx.x] = fminf(smin[threadIdx.x], smin[threadIdx.x + w]);
             smax[threadIdx.x] = fmaxf(smax[threadIdx.x], smax[threadIdx.x + w]);
         }

@@ -307,7 +307,7 @@ struct TenMom2D {
         const real vn = m * ir;
         return fabs(vn) + sqrt(3 * fmax(2 * en - m * vn, (real)0) * ir);
     }
-    __device__ static inline void fxy(const real* u, real* f, real* g, const Phys& P)
+    __device__ static inline void fxy(const real* u, real* f, real* g, const Phys&)
     {
         real ir = recip(u[0]), v1 = u[1] * ir, v2 = u[2] * ir;
         real P11 = 2 * u[3] - u[1] * v1, P12 = 2 * u[4] - u[1] * v2, P22 = 2 * u[5] - u[2] * v2;
