@@ -404,7 +404,7 @@ def main():
         print("copied 3 x 1 GiB", flush=True)
         return
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path", file=sys.stderr)
+        print("bench.py measures one GPU: the solver has no multi-GPU path, run it with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     from paper_2502_07517_amd import crkfr as C
