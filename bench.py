@@ -385,9 +385,9 @@ def main():
                     help="cap on the oracle's steps (the CPU leg also stops after 15 s)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-c5", action="store_true", help="skip the 256-instance uneven batch")
-    ap.add_argument("--part", choices=["all", "sweep", "c3", "optimized"], default="all",
+    ap.add_argument("--part", choices=["all", "sweep", "c3", "optimized", "c5"], default="all",
                     help="c3: only the 512^2 single-instance step; optimized: only the optimized path "
-                         "on the --sweep grids (profiling)")
+                         "on the --sweep grids; c5: only the 256-instance uneven batch (profiling)")
     ap.add_argument("--c3-limiter", action="store_true",
                     help="also run the 512^2 step with the limiter chain (smoothness indicator)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -412,6 +412,12 @@ def main():
     assert abs(lib_cfl - CFL3) < 1e-6, lib_cfl
     sweep = [int(v) for v in args.sweep.split(",")]
     line = {}
+
+    if args.part == "c5":
+        nets = {3: train_network()[0]}
+        nets.update({N: train_network_for(N) for N in (2, 4)})
+        print(json.dumps({"part": "c5", "c5": run_c5(nets, args.steps, args.warmup)}), flush=True)
+        return
 
     c3 = {}
     if args.part in ("all", "c3"):
