@@ -1793,14 +1793,15 @@ __device__ __forceinline__ const StepArgs<real>& table_args(const StepArgs<real>
 }
 
 // one workgroup per (instance, block) work item.  The limited FP32 update of
-// 16-point elements is held to six wavefronts per SIMD (80 VGPRs, a few
-// registers spilled in the troubled-element path): 10 % faster when few
-// elements are troubled, 6 % slower when most are; the other phases and
-// configurations keep the compiler's choice
+// 16-point 2D Euler elements is held to six wavefronts per SIMD (80 VGPRs, a
+// few registers spilled in the troubled-element path): 10 % faster when few
+// elements are troubled, 6 % slower when most are.  The other phases and
+// configurations keep the compiler's choice (the six-variable ten-moment
+// update would spill some 80 registers).
 template <class Eq, int N, class real, bool LIM, int PH>
 constexpr int batch_min_waves()
 {
-    return PH == BPH_UPDATE && LIM && sizeof(real) == 4 && Geo<Eq::DIM, N>::np == 16 ? 6 : 1;
+    return PH == BPH_UPDATE && LIM && sizeof(real) == 4 && Eq::M == 4 && Geo<Eq::DIM, N>::np == 16 ? 6 : 1;
 }
 
 template <class Eq, int N, class real, bool LIM, int PH>
