@@ -113,7 +113,10 @@ __host__ __device__ constexpr int trace_stage_offset() { return 4 * M + 1; }
 template <int DIM, int N>
 struct Geo {
     static constexpr int nd = N + 1, nq = DIM == 2 ? N + 1 : 1, np = nd * nq;
-    static constexpr int EB = 256 / np;          // elements per workgroup
+    // elements per workgroup: 256 lanes, except one wavefront for elements of
+    // 3, 5 or 9 points (their sums go through LDS; a one-wavefront workgroup
+    // makes the barriers local to the wavefront)
+    static constexpr int EB = (np <= 16 && np != 2 && np != 4 && np != 16 ? 64 : 256) / np;
     static constexpr int BLOCK = EB * np;
 };
 
