@@ -11,7 +11,7 @@ from .oracle import (  # noqa: F401
     BLEND_OFF, BLEND_FO, BLEND_MH, IND_PAPER, IND_CONST, IND_GIVEN, IND_LEARNED,
     RefConfig, lib, build, gl, gll, nodes, diff_matrix, lagrange_at, legendre_orthonormal,
     tableau, flux, sigma, adm, nvar, nadm, local_crk, indicator_raw, indicator_features, learned_alpha,
-    scale_element, compute_dt, step, means, mlp_forward, mlp_loss_grad,
+    scale_element, compute_dt, lo_factor, flux_limit_face, mh_predict, step, means, mlp_forward, mlp_loss_grad,
     boundary_traces, has_farfield,
 )
 from .cfl import cfl_number, amplification_matrix  # noqa: F401

@@ -1161,6 +1161,108 @@ static double dir_share(const ref_config* c, const refel* r, int d, int t, doubl
     return (d == 0 ? ax : ay) / (ax + ay);
 }
 
+/* factor dt / (w_i h_d phi_d) of the flux difference in the low-order update
+ * of the face-adjacent subcell with index i (0 or N) along d at line
+ * position t, from eq. low.order.update with the direction share above */
+static double lo_factor(const ref_config* c, const refel* r, int d, int t, int i, double dx, double dy,
+                        const double* u, double dt)
+{
+    double h = d == 0 ? dx : dy;
+    return dt / (r->w[i] * h * dir_share(c, r, d, t, dx, dy, u));
+}
+
+double ref_lo_factor(const ref_config* c, int d, int t, int i, const double* u, double dt)
+{
+    refel r;
+    refel_init(&r, c->N, c->points);
+    return lo_factor(c, &r, d, t, i, (c->x1 - c->x0) / c->nx, (c->y1 - c->y0) / c->ny, u, dt);
+}
+
+/* ------------------------------------------------------------------ */
+/* Flux limiter for admissibility in means at one face point (Sec. 4.3;
+ * reading).  Side A is the element below the face, B the one above; u
+ * their face-adjacent solution points, adj the interior subface flux next
+ * to them, S their time-averaged source, k the factors above.  The
+ * low-order candidates of the two subcells with face flux G are
+ *   A: u_A - kA (G - adj_A) + dt S_A,    B: u_B - kB (adj_B - G) + dt S_B;
+ * with G = fLO (the low-order face flux) they are admissible by Theorem 1.
+ * For each constraint P_k in order, eps = 0.1 P_k(candidate with fLO), and
+ * theta in [0,1] is the fraction of the segment from the fLO candidate to
+ * the F candidate keeping P_k >= eps (concavity bound, bisection for a
+ * non-concave P_k); F <- theta F + (1 - theta) fLO.  Returns the smallest
+ * theta; *bad = 1 when a low-order candidate is itself not admissible
+ * (theta = 0 then).                                                      */
+/* ------------------------------------------------------------------ */
+
+static double flux_limit_face(const ref_config* c, int hasA, int hasB, const double* uA, const double* uB,
+                              const double* adjA, const double* adjB, const double* SA, const double* SB,
+                              double kAfac, double kBfac, double dt, const double* fLO, double* F, int* bad)
+{
+    int M = ref_nvar(c->eq), K = ref_nadm(c->eq);
+    double cA[MM], cB[MM], cAlo[MM], cBlo[MM];
+    for (int v = 0; v < M; ++v) {
+        if (hasA) cAlo[v] = uA[v] - kAfac * (fLO[v] - adjA[v]) + dt * SA[v];
+        if (hasB) cBlo[v] = uB[v] - kBfac * (adjB[v] - fLO[v]) + dt * SB[v];
+    }
+    double theta_face = 1.0;
+    *bad = 0;
+    for (int k = 0; k < K; ++k) {
+        double th = 1.0;
+        for (int v = 0; v < M; ++v) {
+            if (hasA) cA[v] = uA[v] - kAfac * (F[v] - adjA[v]) + dt * SA[v];
+            if (hasB) cB[v] = uB[v] - kBfac * (adjB[v] - F[v]) + dt * SB[v];
+        }
+        for (int side = 0; side < 2; ++side) {
+            if ((side == 0 && !hasA) || (side == 1 && !hasB)) continue;
+            const double* lo_c = side == 0 ? cAlo : cBlo;
+            const double* hi_c = side == 0 ? cA : cB;
+            double Plo = ref_adm(c->eq, k, c->gamma, lo_c);
+            if (!(Plo > 0.0)) { *bad = 1; th = 0.0; continue; }
+            double eps = 0.1 * Plo;
+            double t2 = segment_fraction(c, k, lo_c, hi_c, eps);
+            if (t2 < th) th = t2;
+        }
+        if (th < 1.0)
+            for (int v = 0; v < M; ++v) F[v] = th * F[v] + (1.0 - th) * fLO[v];
+        if (th < theta_face) theta_face = th;
+    }
+    return theta_face;
+}
+
+double ref_flux_limit_face(const ref_config* c, int hasA, int hasB, const double* uA, const double* uB,
+                           const double* adjA, const double* adjB, const double* SA, const double* SB,
+                           double kAfac, double kBfac, double dt, const double* fLO, double* F, int* bad)
+{
+    return flux_limit_face(c, hasA, hasB, uA, uB, adjA, adjB, SA, SB, kAfac, kBfac, dt, fLO, F, bad);
+}
+
+/* MUSCL-Hancock predicted face values of every subcell of element (ex, ey)
+ * of the state u (the step's own routine; ghost: far-field states or NULL).
+ * Outputs [k][v] for the x faces (xm, xp) and y faces (ym, yp); counts[0]
+ * subcells with a scaled slope, counts[1] Hancock fallbacks. */
+void ref_mh_predict(const ref_config* c, const double* u, int ex, int ey, double dt, const double* ghost,
+                    double* xm, double* xp, double* ym, double* yp, int* counts)
+{
+    refel r;
+    refel_init(&r, c->N, c->points);
+    int M = ref_nvar(c->eq), nd = r.nd, dim = eq_dim(c->eq);
+    int nq = dim == 2 ? nd : 1, np = nd * nq, ne = c->nx * c->ny;
+    double dx = (c->x1 - c->x0) / c->nx, dy = (c->y1 - c->y0) / c->ny;
+    grid_ctx g = {c, &r, u, ne, np, nd, nq, dim, M, dx, dy, ghost, dt};
+    mh_out* o = (mh_out*)malloc(sizeof(mh_out));
+    mh_element(&g, ex, ey, dt, c->blend, o);
+    for (int k = 0; k < np; ++k)
+        for (int v = 0; v < M; ++v) {
+            xm[k * M + v] = o->xm[k][v];
+            xp[k * M + v] = o->xp[k][v];
+            ym[k * M + v] = o->ym[k][v];
+            yp[k * M + v] = o->yp[k][v];
+        }
+    counts[0] = o->slope_limited;
+    counts[1] = o->fallback;
+    free(o);
+}
+
 /* ------------------------------------------------------------------ */
 /* Far-field ghost states: boundary traces of a given state             */
 /* ------------------------------------------------------------------ */
@@ -1428,12 +1530,10 @@ int ref_step(const ref_config* c, const double* u_in, double* u_out, double dt,
 
                     if (limit) {
                         /* candidate low-order updates at the two face-adjacent subcells */
-                        double wA = r.w[N], wB = r.w[0], h = d == 0 ? dx : dy;
-                        double cA[MM], cB[MM], cAlo[MM], cBlo[MM], adjA[MM], adjB[MM], SA[MM], SB[MM];
+                        double adjA[MM], adjB[MM], SA[MM], SB[MM];
                         double kAfac = 0.0, kBfac = 0.0;
                         if (A) {
-                            double ph = dir_share(c, &r, d, t, dx, dy, uA);
-                            kAfac = dt / (wA * h * ph);
+                            kAfac = lo_factor(c, &r, d, t, N, dx, dy, uA, dt);
                             for (int v = 0; v < M; ++v) {
                                 adjA[v] = d == 0 ? fsx[(((size_t)eL * nq + t) * N + N - 1) * M + v]
                                                  : fsy[(((size_t)eL * nd + t) * N + N - 1) * M + v];
@@ -1441,43 +1541,16 @@ int ref_step(const ref_config* c, const double* u_in, double* u_out, double dt,
                             }
                         }
                         if (B) {
-                            double ph = dir_share(c, &r, d, t, dx, dy, uB);
-                            kBfac = dt / (wB * h * ph);
+                            kBfac = lo_factor(c, &r, d, t, 0, dx, dy, uB, dt);
                             for (int v = 0; v < M; ++v) {
                                 adjB[v] = d == 0 ? fsx[(((size_t)eR * nq + t) * N + 0) * M + v]
                                                  : fsy[(((size_t)eR * nd + t) * N + 0) * M + v];
                                 SB[v] = lo[eR].S[kB][v];
                             }
                         }
-                        /* the limiter raises alpha_{e+1/2} of eq. Fblend, i.e. moves F
-                         * towards the low-order face flux; candidates with that flux are
-                         * the low-order updates themselves */
-                        for (int v = 0; v < M; ++v) {
-                            if (A) cAlo[v] = uA[v] - kAfac * (fLO[v] - adjA[v]) + dt * SA[v];
-                            if (B) cBlo[v] = uB[v] - kBfac * (adjB[v] - fLO[v]) + dt * SB[v];
-                        }
-                        double theta_face = 1.0;
                         int bad = 0;
-                        for (int k = 0; k < K; ++k) {
-                            double th = 1.0;
-                            for (int v = 0; v < M; ++v) {
-                                if (A) cA[v] = uA[v] - kAfac * (F[v] - adjA[v]) + dt * SA[v];
-                                if (B) cB[v] = uB[v] - kBfac * (adjB[v] - F[v]) + dt * SB[v];
-                            }
-                            for (int side = 0; side < 2; ++side) {
-                                if ((side == 0 && !A) || (side == 1 && !B)) continue;
-                                const double* lo_c = side == 0 ? cAlo : cBlo;
-                                const double* hi_c = side == 0 ? cA : cB;
-                                double Plo = ref_adm(c->eq, k, c->gamma, lo_c);
-                                if (!(Plo > 0.0)) { bad = 1; th = 0.0; continue; }
-                                double eps = 0.1 * Plo;
-                                double t2 = segment_fraction(c, k, lo_c, hi_c, eps);
-                                if (t2 < th) th = t2;
-                            }
-                            if (th < 1.0)
-                                for (int v = 0; v < M; ++v) F[v] = th * F[v] + (1.0 - th) * fLO[v];
-                            if (th < theta_face) theta_face = th;
-                        }
+                        double theta_face = flux_limit_face(c, A != NULL, B != NULL, uA, uB, adjA, adjB, SA, SB,
+                                                            kAfac, kBfac, dt, fLO, F, &bad);
                         if (theta_face < 1.0) n_lim++;
                         if (bad) n_bad++;
                         if (theta_face < min_th) min_th = theta_face;

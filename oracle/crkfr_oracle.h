@@ -120,6 +120,24 @@ double ref_compute_dt(const ref_config* c, const double* u);
  * y-bottom [nx][N+1][M], y-top [nx][N+1][M], concatenated (1D: one point per side) */
 void ref_boundary_traces(const ref_config* c, const double* u, double* ghost);
 
+/* factor dt / (w_i h_d phi_d) of the flux difference in the low-order update
+ * of the face-adjacent subcell with index i (0 or N) along direction d at
+ * line position t (the state u of that subcell gives phi_d; 1D: phi = 1) */
+double ref_lo_factor(const ref_config* c, int d, int t, int i, const double* u, double dt);
+
+/* flux limiter at one face point (the routine ref_step uses): F (in/out)
+ * moves towards fLO so that the low-order candidates of both face-adjacent
+ * subcells keep P_k >= 0.1 P_k(candidate with fLO); returns the smallest
+ * theta, *bad = 1 when a candidate with fLO is not admissible */
+double ref_flux_limit_face(const ref_config* c, int hasA, int hasB, const double* uA, const double* uB,
+                           const double* adjA, const double* adjB, const double* SA, const double* SB,
+                           double kAfac, double kBfac, double dt, const double* fLO, double* F, int* bad);
+
+/* MUSCL-Hancock predicted face values [k][v] of the subcells of element
+ * (ex, ey) (the routine ref_step uses); counts: slope scalings, fallbacks */
+void ref_mh_predict(const ref_config* c, const double* u, int ex, int ey, double dt, const double* ghost,
+                    double* xm, double* xp, double* ym, double* yp, int* counts);
+
 /* one full step; alpha_given used when indicator == GIVEN; alpha_out (optional)
  * receives the final blending coefficient per element; ghost (far-field
  * boundaries only) as written by ref_boundary_traces. */

@@ -139,6 +139,14 @@ def lib():
         L.ref_boundary_traces.argtypes = [cp, dp, dp]
         L.ref_means.argtypes = [cp, dp, dp]
         L.ref_step_crkfr_form.argtypes = [cp, dp, dp, ctypes.c_double]
+        L.ref_lo_factor.argtypes = [cp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, ctypes.c_double]
+        L.ref_lo_factor.restype = ctypes.c_double
+        L.ref_flux_limit_face.argtypes = [cp, ctypes.c_int, ctypes.c_int, dp, dp, dp, dp, dp, dp,
+                                          ctypes.c_double, ctypes.c_double, ctypes.c_double, dp, dp,
+                                          ctypes.POINTER(ctypes.c_int)]
+        L.ref_flux_limit_face.restype = ctypes.c_double
+        L.ref_mh_predict.argtypes = [cp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, dp, dp, dp, dp,
+                                     ctypes.POINTER(ctypes.c_int)]
         ip = ctypes.POINTER(ctypes.c_int)
         L.ref_indicator_features.argtypes = [cp, dp, dp]
         L.ref_learned_alpha.argtypes = [cp, dp, ctypes.POINTER(ctypes.c_int)]
@@ -262,6 +270,39 @@ def learned_alpha(cfg, ue):
     fb = ctypes.c_int(0)
     a = lib().ref_learned_alpha(ctypes.byref(cfg), _p(ue), ctypes.byref(fb))
     return a, bool(fb.value)
+
+
+def lo_factor(cfg, d, t, i, u, dt):
+    """dt / (w_i h_d phi_d) of the low-order update of a face-adjacent subcell."""
+    return lib().ref_lo_factor(ctypes.byref(cfg), d, t, i, _p(_f64(u)), float(dt))
+
+
+def flux_limit_face(cfg, F, fLO, dt, A=None, B=None):
+    """Flux limiter at one face point.  A, B: (u, adj, S, k) of the subcell
+    below / above the face, or None for a missing side.  Returns (F limited,
+    theta, bad)."""
+    M = nvar(cfg.eq)
+    z = np.zeros(M)
+    ua, adja, sa, ka = A if A is not None else (z, z, z, 0.0)
+    ub, adjb, sb, kb = B if B is not None else (z, z, z, 0.0)
+    Fo = _f64(F).copy()
+    bad = ctypes.c_int(0)
+    th = lib().ref_flux_limit_face(ctypes.byref(cfg), int(A is not None), int(B is not None),
+                                   _p(_f64(ua)), _p(_f64(ub)), _p(_f64(adja)), _p(_f64(adjb)),
+                                   _p(_f64(sa)), _p(_f64(sb)), float(ka), float(kb), float(dt),
+                                   _p(_f64(fLO)), _p(Fo), ctypes.byref(bad))
+    return Fo, th, bool(bad.value)
+
+
+def mh_predict(cfg, u, ex, ey, dt, ghost=None):
+    """MUSCL-Hancock predicted face values of element (ex, ey): (xm, xp, ym,
+    yp) as [node][var] arrays, and (slope scalings, fallbacks)."""
+    M, npn = nvar(cfg.eq), _np(cfg)
+    outs = [np.zeros((npn, M)) for _ in range(4)]
+    cnt = (ctypes.c_int * 2)()
+    gp = _p(_f64(ghost)) if ghost is not None else None
+    lib().ref_mh_predict(ctypes.byref(cfg), _p(_f64(u)), ex, ey, float(dt), gp, *[_p(o) for o in outs], cnt)
+    return outs, (cnt[0], cnt[1])
 
 
 def scale_element(cfg, ue):
