@@ -113,7 +113,7 @@ def _limited(s, C, indicator, net=None):
 
 
 # ---------------------------------------------------------------- the 512^2 single-instance step
-def run_c3(dtype, steps, warmup, limited=False):
+def run_c3(dtype, steps, warmup, limited=False, fused=False):
     """The 512^2 vortex step: graph-replayed steps for the rate, then the
     same number of eagerly enqueued steps with HIP events between the
     kernels on the solver's stream for the per-kernel times."""
@@ -125,6 +125,7 @@ def run_c3(dtype, steps, warmup, limited=False):
                  stream=torch.cuda.current_stream().cuda_stream)
     if limited:
         _limited(s, C, C.IND_PAPER)
+    s.set_fused(fused)
     s.set_state(torch.from_numpy(np.ascontiguousarray(W.vortex2d(n, N_DEG, 0.0, DOM))).to("cuda"))
     s.advance(0.0, warmup)
     torch.cuda.synchronize()
@@ -145,9 +146,11 @@ def run_c3(dtype, steps, warmup, limited=False):
     if rc != 0:
         raise RuntimeError(f"512^2 step ({dtype}, limited={limited}) failed: {d}")
     out = s.get_state()
+    used = s.fused_in_use()
     s.close()
     return {"ms_per_step": ms, "dofsteps_per_s": n * n * (N_DEG + 1) ** 2 / (ms * 1e-3),
-            "kernel_ms": kt.tolist(), "state": out, "n_troubled_last": int(d["n_troubled"])}
+            "kernel_ms": kt.tolist(), "state": out, "n_troubled_last": int(d["n_troubled"]),
+            "tile_fused": bool(used)}
 
 
 # ---------------------------------------------------------------- learned indicator for 2D Euler
@@ -514,6 +517,12 @@ def main():
         "kernel_ms": dict(zip(PHASES, kms)),
         "roofline": roofline,
     }
+    tile = run_c3(C.FP64, args.steps, args.warmup, fused=True)
+    line["tile_fused_512"] = {k: v for k, v in tile.items() if k != "state"}
+    line["tile_fused_512"]["rel_linf_vs_split"] = float(np.abs(tile["state"] - head["state"]).max()
+                                                        / np.abs(head["state"]).max())
+    print(f"# 512^2 FP64 tile-fused: {tile['ms_per_step']:.4f} ms/step, kernels (ms) "
+          f"{np.round(tile['kernel_ms'], 4).tolist()}", flush=True)
     if args.part == "c3":
         print(json.dumps(line), flush=True)
         return

@@ -112,6 +112,13 @@ typedef struct {
     int flux_limiter;   /* 1: flux limiter for admissibility in means (needs blend != OFF) */
     int scaling;        /* 1: Zhang-Shu scaling limiter */
     double alpha_min, alpha_max, alpha_const;
+    /* admissibility margins (<= 0: the defaults).  eps_rel (0.1): the flux
+     * limiter keeps P_k of each face-adjacent low-order candidate at least
+     * eps_rel P_k(candidate with the low-order face flux) (Sec. 4.3), and the
+     * MUSCL-Hancock reconstruction keeps its face and predicted values at
+     * eps_rel P_k(subcell value) (Sec. 4.2); eps_abs (1e-13): the scaling
+     * limiter (Sec. 3.2) keeps every node at P_k >= min(eps_abs, P_k(mean)). */
+    double eps_rel, eps_abs;
 } crkfr_limiter_opts;
 
 /* ten-moment source (eq. tenmom.source) with the potential
@@ -136,6 +143,14 @@ typedef struct {
     long long n_learned_fallback;  /* elements whose features left the network's box (indicator used) */
     long long n_learned_disagree;  /* elements troubled (alpha > 0) by one indicator but not the other */
     double max_alpha_dev;          /* max over elements of |alpha_learned - alpha_indicator| (raw) */
+    /* the current state, reduced on the device when crkfr_get_diag is called
+     * (the constraints P_k of eq. uad.form at the nodes, in FP64): */
+    double min_rho;                /* min over nodes of the density (linear advection, Burgers: of u) */
+    double min_p;                  /* min over nodes of P_1: Euler pressure, ten-moment P11 (0 if none) */
+    double min_p2;                 /* min over nodes of P_2: ten-moment det P (0 if none) */
+    long long n_nonfinite;         /* nodes with a non-finite variable */
+    double mass;                   /* integral of the density (of u) over the domain */
+    double mass_drift;             /* (mass - mass at set_state) / |mass at set_state| (absolute if 0) */
 } crkfr_diag;
 
 typedef struct crkfr_solver crkfr_solver;
@@ -188,6 +203,23 @@ int crkfr_set_inflow(crkfr_solver* s, const double* coeffs, int ncoef, double t_
  * far-field ghost states.  Errors: EINADMISSIBLE_INPUT if a node has P_k <= 0. */
 int crkfr_set_state(crkfr_solver* s, const double* u, int on_device);
 
+/* Bind a caller-owned FP64 device buffer (nvar*ny*nx*(N+1)^d doubles, the
+ * nodal layout above) as the solver's state, without a copy (eq. crkfr.avg
+ * advances it in place of a library buffer).  The buffer becomes one of the
+ * two buffers the steps alternate between: the state is in it now and after
+ * every even number of steps since this call (crkfr_advance and
+ * crkfr_batch_advance keep step pairs), in a library buffer after odd
+ * numbers; crkfr_state_ptr says where it is.  The caller keeps ownership and
+ * must keep the buffer alive until crkfr_destroy or the next set_state or
+ * bind_state.  Otherwise like crkfr_set_state with a device pointer (t = 0,
+ * means, time-step rate, far-field ghosts; the data is only read here).
+ * Errors: EINVAL (MP32 solver: its state is FP64 means plus FP32 deviations,
+ * use set_state; null pointer), EINADMISSIBLE_INPUT, ESTATE (batch member). */
+int crkfr_bind_state(crkfr_solver* s, double* u_dev);
+/* Device pointer of the current FP64 nodal state (the bound buffer or a
+ * library buffer); EINVAL for MP32 solvers. */
+int crkfr_state_ptr(crkfr_solver* s, double** u_dev);
+
 /* Per-element blending coefficients for CRKFR_IND_GIVEN, [ey][ex] doubles. */
 int crkfr_set_alpha(crkfr_solver* s, const double* alpha, int on_device);
 
@@ -219,7 +251,10 @@ int crkfr_advance(crkfr_solver* s, double t_end, int max_steps);
 int crkfr_get_state(crkfr_solver* s, double* out, int on_device);
 int crkfr_get_means(crkfr_solver* s, double* out);
 int crkfr_get_alpha(crkfr_solver* s, double* out);
-/* Diagnostics of the last step; returns EINADMISSIBLE_MEAN if it had any. */
+/* Diagnostics of the last step (counters) and of the current state (min_rho,
+ * min_p, min_p2, n_nonfinite, mass, mass_drift: a device reduction, so the
+ * call synchronises and launches one kernel); returns EINADMISSIBLE_MEAN if
+ * the last step left an element mean outside U_ad. */
 int crkfr_get_diag(crkfr_solver* s, crkfr_diag* out);
 
 /* Number of variables, nodes per element and the CFL number in use. */
@@ -235,8 +270,22 @@ double crkfr_cfl_in_use(const crkfr_solver* s);
  * linear flux); points CRKFR_POINTS_*.  Returns -1 for bad arguments. */
 double crkfr_fourier_cfl(int N, int stages, int system, int dissipation, int points, double tol);
 
+/* Tile-fused step (on = 1) or the split step (on = 0, the default).  The
+ * tile-fused step serves 2D Euler with N = 1 or 3, the limiter chain off and
+ * the D2 dissipation: one workgroup per tile of elements (N = 3: 8 x 4 in
+ * FP64, 8 x 8 in FP32 bulk; N = 1: 16 x 8, 16 x 16) runs the local cRK procedure, the time-averaged
+ * numerical flux of the faces inside the tile and the whole update of the
+ * elements whose four neighbours lie in the tile, out of LDS; then the faces
+ * on tile edges (with the boundary conditions) and the update of the tile-edge
+ * elements follow.  Results equal the split step's up to rounding order.
+ * crkfr_fused_in_use returns 1 when the next step takes the tile-fused path. */
+int crkfr_set_fused(crkfr_solver* s, int on);
+int crkfr_fused_in_use(const crkfr_solver* s);
+
 /* Device time per kernel of the last step measured with HIP events (ms):
- * [0] local cRK, [1] x faces, [2] y faces, [3] update; needs timing = 1. */
+ * [0] local cRK, [1] x faces, [2] y faces, [3] update; with the tile-fused
+ * step: [0] the tile kernel, [1], [2] the faces on tile edges, [3] the update
+ * of the tile-edge elements.  Needs timing = 1. */
 int crkfr_set_timing(crkfr_solver* s, int on);
 int crkfr_get_kernel_times(crkfr_solver* s, float* ms4);
 
@@ -247,7 +296,7 @@ int crkfr_get_kernel_times(crkfr_solver* s, float* ms4);
  * persistent workgroups walking a table of (instance, block) work items.  The
  * solvers stay owned by the caller, must have a state, and must not be used
  * on their own while the batch runs; call crkfr_batch_sync before reading
- * their state.  Members must outlive the batch; the batch keeps the options
+ * their state.  Batches run the split step (crkfr_set_fused does not apply).  Members must outlive the batch; the batch keeps the options
  * each member had at creation.  Each member keeps its own time step (eq.
  * time.step.2d). */
 typedef struct crkfr_batch crkfr_batch;

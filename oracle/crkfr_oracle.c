@@ -318,6 +318,11 @@ double ref_adm(int eq, int k, double gamma, const double* u)
 
 /* P_k concave once P_j > 0 for j < k: true for all but the determinant */
 static int is_tenmom(int eq) { return eq == REF_TENMOM2D || eq == REF_TENMOM1D; }
+
+/* admissibility margins of the limiter chain: relative (flux limiter and
+ * subcell reconstruction, default 0.1) and absolute (scaling, default 1e-13) */
+static double eps_rel(const ref_config* c) { return c->eps_rel > 0.0 ? c->eps_rel : 0.1; }
+static double eps_abs(const ref_config* c) { return c->eps_abs > 0.0 ? c->eps_abs : 1e-13; }
 static int adm_concave(int eq, int k) { return !(is_tenmom(eq) && k == 2); }
 
 /* ten-moment source s^x + s^y (eq. tenmom.source) with the potential
@@ -710,7 +715,7 @@ static double scale_element(const ref_config* c, const refel* r, double* ue, int
     for (int k = 0; k < K; ++k) {
         double Pbar = ref_adm(c->eq, k, c->gamma, ubar);
         if (!(Pbar > 0.0)) { *mean_bad = 1; return 0.0; }
-        double eps = Pbar < 1e-13 ? Pbar : 1e-13;
+        double eps = Pbar < eps_abs(c) ? Pbar : eps_abs(c);
         double theta = 1.0;
         for (int n = 0; n < np; ++n) {
             double un[MM];
@@ -1036,7 +1041,7 @@ static void mh_element(const grid_ctx* g, int ex, int ey, double dt, int blend, 
             double u[MM], sx[MM], sy[MM];
             for (int v = 0; v < M; ++v) { u[v] = g->u[gidx(g, v, e, k)]; sx[v] = 0.0; sy[v] = 0.0; }
             double eps[MM];
-            for (int kk = 0; kk < K; ++kk) eps[kk] = 0.1 * ref_adm(c->eq, kk, c->gamma, u);
+            for (int kk = 0; kk < K; ++kk) eps[kk] = eps_rel(c) * ref_adm(c->eq, kk, c->gamma, u);
             int u_ok = 1;
             for (int kk = 0; kk < K; ++kk) if (!(eps[kk] > 0.0)) u_ok = 0;
             if (blend == REF_BLEND_MH && u_ok) {
@@ -1218,7 +1223,7 @@ static double flux_limit_face(const ref_config* c, int hasA, int hasB, const dou
             const double* hi_c = side == 0 ? cA : cB;
             double Plo = ref_adm(c->eq, k, c->gamma, lo_c);
             if (!(Plo > 0.0)) { *bad = 1; th = 0.0; continue; }
-            double eps = 0.1 * Plo;
+            double eps = eps_rel(c) * Plo;
             double t2 = segment_fraction(c, k, lo_c, hi_c, eps);
             if (t2 < th) th = t2;
         }

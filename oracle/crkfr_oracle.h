@@ -64,6 +64,11 @@ typedef struct {
     int inflow_ncoef;
     double inflow_tref;
     double time;
+    /* admissibility margins of the limiter chain (<= 0: the defaults): the
+     * flux limiter and the subcell reconstruction keep P_k >= eps_rel times
+     * P_k of their reference state (0.1); the scaling limiter keeps P_k >=
+     * min(eps_abs, P_k(mean)) (1e-13) */
+    double eps_rel, eps_abs;
 } ref_config;
 
 typedef struct {

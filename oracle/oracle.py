@@ -45,6 +45,7 @@ class RefConfig(ctypes.Structure):
         ("dissipation", ctypes.c_int), ("central", ctypes.c_int), ("points", ctypes.c_int),
         ("inflow", ctypes.POINTER(ctypes.c_double)), ("inflow_ncoef", ctypes.c_int),
         ("inflow_tref", ctypes.c_double), ("time", ctypes.c_double),
+        ("eps_rel", ctypes.c_double), ("eps_abs", ctypes.c_double),
     ]
 
     @staticmethod
@@ -53,7 +54,7 @@ class RefConfig(ctypes.Structure):
              domain=(0.0, 1.0, 0.0, 1.0), gamma=1.4, adv=1.0, cfl=0.0, cs=0.98,
              alpha_min=1e-3, alpha_max=1.0, alpha_const=0.0,
              src=(0.0, 0.0, 0.0, 0.0), src_lin=(0.0, 0.0), mlp=None, dissipation=DISS_D2,
-             central=CENTRAL_EA, points=POINTS_GL):
+             central=CENTRAL_EA, points=POINTS_GL, eps_rel=0.0, eps_abs=0.0):
         """mlp: (dims, params, lo, hi) of the learned indicator (dims[0] = N)."""
         c = RefConfig()
         c.eq, c.N, c.nx, c.ny = eq, N, nx, ny
@@ -68,6 +69,7 @@ class RefConfig(ctypes.Structure):
         c.src_amp, c.src_kappa, c.src_xc, c.src_yc = src
         c.src_gx, c.src_gy = src_lin
         c.dissipation, c.central, c.points = dissipation, central, points
+        c.eps_rel, c.eps_abs = eps_rel, eps_abs
         if mlp is not None:
             c.set_mlp(*mlp)
         return c

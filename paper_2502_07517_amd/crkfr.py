@@ -35,7 +35,8 @@ class Config(ctypes.Structure):
 class LimiterOpts(ctypes.Structure):
     _fields_ = [("blend", ctypes.c_int), ("indicator", ctypes.c_int), ("smooth_nbr", ctypes.c_int),
                 ("flux_limiter", ctypes.c_int), ("scaling", ctypes.c_int),
-                ("alpha_min", ctypes.c_double), ("alpha_max", ctypes.c_double), ("alpha_const", ctypes.c_double)]
+                ("alpha_min", ctypes.c_double), ("alpha_max", ctypes.c_double), ("alpha_const", ctypes.c_double),
+                ("eps_rel", ctypes.c_double), ("eps_abs", ctypes.c_double)]
 
 
 class Scheme(ctypes.Structure):
@@ -55,7 +56,9 @@ class Diag(ctypes.Structure):
                 ("min_theta_flux", ctypes.c_double), ("min_theta_scale", ctypes.c_double),
                 ("t", ctypes.c_double), ("dt", ctypes.c_double), ("steps", ctypes.c_longlong),
                 ("n_learned_fallback", ctypes.c_longlong), ("n_learned_disagree", ctypes.c_longlong),
-                ("max_alpha_dev", ctypes.c_double)]
+                ("max_alpha_dev", ctypes.c_double), ("min_rho", ctypes.c_double), ("min_p", ctypes.c_double),
+                ("min_p2", ctypes.c_double), ("n_nonfinite", ctypes.c_longlong), ("mass", ctypes.c_double),
+                ("mass_drift", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -71,7 +74,8 @@ SYMBOLS = ["crkfr_create", "crkfr_destroy", "crkfr_set_limiter", "crkfr_set_sour
            "crkfr_mlp_num_params", "crkfr_mlp_set_params", "crkfr_mlp_get_params", "crkfr_mlp_set_box",
            "crkfr_mlp_get_box", "crkfr_mlp_fit_box", "crkfr_mlp_forward", "crkfr_mlp_loss_grad",
            "crkfr_mlp_train", "crkfr_batch_set_t_end", "crkfr_batch_set_timing", "crkfr_batch_phase_times",
-           "crkfr_set_scheme", "crkfr_set_inflow"]
+           "crkfr_set_scheme", "crkfr_set_inflow", "crkfr_bind_state", "crkfr_state_ptr",
+           "crkfr_set_fused", "crkfr_fused_in_use"]
 
 _lib = None
 
@@ -98,6 +102,10 @@ def lib():
         L.crkfr_set_limiter.argtypes = [vp, ctypes.POINTER(LimiterOpts)]
         L.crkfr_set_source.argtypes = [vp, ctypes.POINTER(Source)]
         L.crkfr_set_state.argtypes = [vp, vp, ip]
+        L.crkfr_bind_state.argtypes = [vp, vp]
+        L.crkfr_set_fused.argtypes = [vp, ip]
+        L.crkfr_fused_in_use.argtypes = [vp]
+        L.crkfr_state_ptr.argtypes = [vp, ctypes.POINTER(vp)]
         L.crkfr_set_alpha.argtypes = [vp, vp, ip]
         L.crkfr_compute_dt.argtypes = [vp, dp]
         L.crkfr_step.argtypes = [vp, ctypes.c_double]
@@ -212,8 +220,9 @@ class Solver:
         return (self.M, self.cfg.nx, N1)
 
     def set_limiter(self, blend=BLEND_OFF, indicator=IND_PAPER, smooth_nbr=1, flux_limiter=0, scaling=0,
-                    alpha_min=1e-3, alpha_max=1.0, alpha_const=0.0):
-        o = LimiterOpts(blend, indicator, smooth_nbr, flux_limiter, scaling, alpha_min, alpha_max, alpha_const)
+                    alpha_min=1e-3, alpha_max=1.0, alpha_const=0.0, eps_rel=0.0, eps_abs=0.0):
+        o = LimiterOpts(blend, indicator, smooth_nbr, flux_limiter, scaling, alpha_min, alpha_max, alpha_const,
+                        eps_rel, eps_abs)
         _check(lib().crkfr_set_limiter(self.h, ctypes.byref(o)))
 
     def set_scheme(self, stages=0, dissipation=DISS_D2, central=CENTRAL_EA):
@@ -248,7 +257,31 @@ class Solver:
     def set_state(self, u):
         u = self._check_array(u, self.M * self.ne * self.np)
         p, dev = _ptr(u)
-        return _check(lib().crkfr_set_state(self.h, p, dev))
+        rc = _check(lib().crkfr_set_state(self.h, p, dev))
+        self._bound = None
+        return rc
+
+    def bind_state(self, u):
+        """Bind a contiguous float64 device tensor as the state (no copy; the
+        caller keeps it alive, see crkfr_bind_state)."""
+        if not hasattr(u, "data_ptr") or not u.is_cuda:
+            raise ValueError("bind_state needs a device tensor")
+        u = self._check_array(u, self.M * self.ne * self.np)
+        self._bound = u
+        _check(lib().crkfr_bind_state(self.h, ctypes.c_void_p(u.data_ptr())))
+
+    def set_fused(self, on=True):
+        """Tile-fused step where the configuration allows it, or the split step (default)."""
+        _check(lib().crkfr_set_fused(self.h, int(on)))
+
+    def fused_in_use(self):
+        return bool(lib().crkfr_fused_in_use(self.h))
+
+    def state_ptr(self):
+        """Device address of the current FP64 nodal state."""
+        p = ctypes.c_void_p()
+        _check(lib().crkfr_state_ptr(self.h, ctypes.byref(p)))
+        return p.value
 
     def set_alpha(self, alpha):
         a = self._check_array(alpha, self.ne)

@@ -372,6 +372,13 @@ struct crkfr_solver {
     double *dt_dev, *t_dev;
     unsigned long long *rate_bits, *diag;
     long long* steps;
+    double* stats;           // k_stats partial results [block][STAT_N]
+    int stats_blocks;
+    double mass0;            // integral of the density when the state was set
+    double* bound;           // caller-owned FP64 state bound as u[0] (crkfr_bind_state), or null
+    int* edge_list;          // tile-fused step: elements at the tile edges (device), null without a tile shape
+    int n_edge;
+    bool fused;              // use the tile-fused step where the configuration allows it
     bool timing;
     hipEvent_t ev[6];
     float kernel_ms[4];
@@ -455,6 +462,8 @@ static StepArgs<real> step_args(const crkfr_solver* s, int in, int out)
     a.alpha_min = s->lim.alpha_min;
     a.alpha_max = s->lim.alpha_max;
     a.alpha_const = s->lim.alpha_const;
+    a.eps_rel = s->lim.eps_rel > 0.0 ? s->lim.eps_rel : 0.1;
+    a.eps_abs = s->lim.eps_abs > 0.0 ? s->lim.eps_abs : 1e-13;
     a.phys = make_phys(s);
     fill_tab(s->ref, s->stages, a.R);
     a.idx = 1.0 / a.dx;
@@ -498,6 +507,7 @@ static IoArgs<real> io_args(const crkfr_solver* s)
     }
     a.diag = s->diag;
     a.rate_bits = s->rate_bits;
+    a.stats = s->stats;
     return a;
 }
 
@@ -509,6 +519,7 @@ static int dispatch_step(const crkfr_solver* s, int phase, int in, int out)
     int rc = -1;
     if (s->mp) {
         StepArgs<float> a = step_args<float>(s, in, out);
+        if (phase == PH_EDGE_UPDATE) { a.edge_list = s->edge_list; a.n_edge = s->n_edge; }
         switch (s->cfg.equation) {
         case CRKFR_LINADV1D: rc = linadv1d_step_f32(N, lim, phase, a, st); break;
         case CRKFR_BURGERS1D: rc = burgers1d_step_f32(N, lim, phase, a, st); break;
@@ -519,6 +530,7 @@ static int dispatch_step(const crkfr_solver* s, int phase, int in, int out)
         }
     } else {
         StepArgs<double> a = step_args<double>(s, in, out);
+        if (phase == PH_EDGE_UPDATE) { a.edge_list = s->edge_list; a.n_edge = s->n_edge; }
         switch (s->cfg.equation) {
         case CRKFR_LINADV1D: rc = linadv1d_step_f64(N, lim, phase, a, st); break;
         case CRKFR_BURGERS1D: rc = burgers1d_step_f64(N, lim, phase, a, st); break;
@@ -579,7 +591,7 @@ static int run_io(const crkfr_solver* s, int phase, const double* uin, double* u
 
 static void free_all(crkfr_solver* s)
 {
-    void* ptrs[] = {s->u[0], s->u[1], s->ubar[0], s->ubar[1], s->uHp, s->trx, s->trY, s->Fx, s->Gy, s->dtS,
+    void* ptrs[] = {s->bound ? nullptr : s->u[0], s->u[1], s->stats, s->edge_list, s->ubar[0], s->ubar[1], s->uHp, s->trx, s->trY, s->Fx, s->Gy, s->dtS,
                     s->ghost, s->alpha_raw, s->alpha_out, s->alpha_given, s->alpha_judge, s->feat,
                     s->dt_dev, s->t_dev, s->inflow,
                     s->rate_bits, s->diag, s->steps};
@@ -705,6 +717,42 @@ extern "C" int crkfr_create(const crkfr_config* cfg, void* hip_stream, crkfr_sol
     ok &= alloc((void**)&s->rate_bits, RATE_SLOTS * sizeof(unsigned long long));
     ok &= alloc((void**)&s->diag, D_NCOUNT * sizeof(unsigned long long));
     ok &= alloc((void**)&s->steps, sizeof(long long));
+    {
+        int el = 0, eu = 0, nq1 = 0;
+        int grc = -1;
+        switch (cfg->equation) {
+        case CRKFR_LINADV1D: grc = linadv1d_geometry(cfg->N, &el, &eu, &nq1); break;
+        case CRKFR_BURGERS1D: grc = burgers1d_geometry(cfg->N, &el, &eu, &nq1); break;
+        case CRKFR_TENMOM1D: grc = tenmom1d_geometry(cfg->N, &el, &eu, &nq1); break;
+        case CRKFR_EULER1D: grc = euler1d_geometry(cfg->N, &el, &eu, &nq1); break;
+        case CRKFR_EULER2D: grc = euler2d_geometry(cfg->N, &el, &eu, &nq1); break;
+        case CRKFR_TENMOM2D: grc = tenmom2d_geometry(cfg->N, &el, &eu, &nq1); break;
+        }
+        s->stats_blocks = grc == 0 ? (s->ne + eu - 1) / eu : 0;
+        ok &= grc == 0 && alloc((void**)&s->stats, (size_t)s->stats_blocks * STAT_N * sizeof(double));
+    }
+    s->fused = false;
+    {   // tile-fused step: the elements at the tile edges, in tile order
+        int tx = 0, ty = 0;
+        if (ok && cfg->equation == CRKFR_EULER2D && euler2d_tile_shape(cfg->N, cfg->dtype == CRKFR_MP32, &tx, &ty) == 0) {
+            std::vector<int> list;
+            const int nx = cfg->nx, ny = cfg->ny;
+            for (int gy0 = 0; gy0 < ny; gy0 += ty)
+                for (int gx0 = 0; gx0 < nx; gx0 += tx)
+                    for (int iy = 0; iy < ty && gy0 + iy < ny; ++iy)
+                        for (int ix = 0; ix < tx && gx0 + ix < nx; ++ix) {
+                            const int gx = gx0 + ix, gy = gy0 + iy;
+                            const bool inner = ix > 0 && ix < tx - 1 && iy > 0 && iy < ty - 1 && gx + 1 < nx &&
+                                               gy + 1 < ny;
+                            if (!inner) list.push_back(gy * nx + gx);
+                        }
+            s->n_edge = (int)list.size();
+            ok &= alloc((void**)&s->edge_list, list.size() * sizeof(int));
+            if (ok && !list.empty())
+                ok &= hipMemcpy(s->edge_list, list.data(), list.size() * sizeof(int), hipMemcpyHostToDevice) ==
+                      hipSuccess;
+        }
+    }
     if (!ok) {
         free_all(s);
         delete s;
@@ -815,10 +863,53 @@ extern "C" int crkfr_set_scheme(crkfr_solver* s, const crkfr_scheme* o)
     return 0;
 }
 
+// statistics of the current state (k_stats), reduced over the blocks in a fixed order
+struct StateStats {
+    double min_rho, min_p1, min_p2, mass;
+    long long nonfinite;
+};
+
+static int state_stats(crkfr_solver* s, StateStats* out)
+{
+    int rc = run_io(s, PH_STATS, nullptr, nullptr, nullptr);
+    if (rc) return rc;
+    std::vector<double> h((size_t)s->stats_blocks * STAT_N);
+    HIP_TRY(hipMemcpyAsync(h.data(), s->stats, h.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    const double big = 1.79769313486231570e308;
+    StateStats r = {big, big, big, 0.0, 0};
+    for (int b = 0; b < s->stats_blocks; ++b) {
+        const double* x = &h[(size_t)b * STAT_N];
+        r.min_rho = std::min(r.min_rho, x[STAT_MINRHO]);
+        r.min_p1 = std::min(r.min_p1, x[STAT_MINP1]);
+        r.min_p2 = std::min(r.min_p2, x[STAT_MINP2]);
+        r.nonfinite += (long long)x[STAT_NONFINITE];
+        r.mass += x[STAT_MASS];
+    }
+    const int K = s->cfg.equation == CRKFR_EULER1D || s->cfg.equation == CRKFR_EULER2D ? 2
+                : (is_tenmom(s->cfg.equation) ? 3 : 0);
+    if (K < 2) r.min_p1 = 0.0;
+    if (K < 3) r.min_p2 = 0.0;
+    *out = r;
+    return 0;
+}
+
+static int load_state(crkfr_solver* s, const double* src, double* tmp);
+
 extern "C" int crkfr_set_state(crkfr_solver* s, const double* u, int on_device)
 {
     if (!s || !u) return fail(CRKFR_EINVAL, "null argument");
+    if (s->batch_refs > 0 && s->bound) return fail(CRKFR_ESTATE, "solver is a batch member: destroy the batch first");
     const size_t n = (size_t)s->M * s->ne * s->np;
+    if (s->bound) {
+        // the bound buffer goes back to the caller: a buffer of the library's own again
+        HIP_TRY(hipStreamSynchronize(s->stream));
+        if (hipMalloc(&s->u[0], n * real_size(s)) != hipSuccess) {
+            s->u[0] = s->bound;
+            return fail(CRKFR_ENOMEM, "device allocation failed");
+        }
+        s->bound = nullptr;
+    }
     const double* src = u;
     double* tmp = nullptr;
     if (!on_device) {
@@ -826,6 +917,34 @@ extern "C" int crkfr_set_state(crkfr_solver* s, const double* u, int on_device)
         HIP_TRY(hipMemcpyAsync(tmp, u, n * sizeof(double), hipMemcpyHostToDevice, s->stream));
         src = tmp;
     }
+    return load_state(s, src, tmp);
+}
+
+extern "C" int crkfr_bind_state(crkfr_solver* s, double* u_dev)
+{
+    if (!s || !u_dev) return fail(CRKFR_EINVAL, "null argument");
+    if (s->mp) return fail(CRKFR_EINVAL, "an MP32 state is FP64 means plus FP32 deviations: use crkfr_set_state");
+    if (s->batch_refs > 0) return fail(CRKFR_ESTATE, "solver is a batch member: destroy the batch first");
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    if (!s->bound && s->u[0]) (void)hipFree(s->u[0]);
+    s->bound = u_dev;
+    s->u[0] = u_dev;
+    return load_state(s, u_dev, nullptr);
+}
+
+extern "C" int crkfr_state_ptr(crkfr_solver* s, double** u_dev)
+{
+    if (!s || !u_dev) return fail(CRKFR_EINVAL, "null argument");
+    if (s->mp) return fail(CRKFR_EINVAL, "an MP32 state has no FP64 nodal buffer");
+    if (!s->has_state) return fail(CRKFR_ESTATE, "no state set");
+    *u_dev = (double*)s->u[s->cur];
+    return 0;
+}
+
+// import src (device) as the state in buffer 0: admissibility, means, rate,
+// ghosts, the mass for the drift diagnostic; tmp (if any) is freed
+static int load_state(crkfr_solver* s, const double* src, double* tmp)
+{
     s->cur = 0;
     const double zero = 0.0;
     HIP_TRY(hipMemcpyAsync(s->t_dev, &zero, sizeof(double), hipMemcpyHostToDevice, s->stream));
@@ -843,6 +962,10 @@ extern "C" int crkfr_set_state(crkfr_solver* s, const double* u, int on_device)
     HIP_TRY(hipMemsetAsync(s->diag, 0, D_NCOUNT * sizeof(unsigned long long), s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
     if (rc) return rc;
+    StateStats st;
+    rc = state_stats(s, &st);
+    if (rc) return rc;
+    s->mass0 = st.mass;
     s->has_state = true;
     invalidate_graph(s);
     if (bad) return fail(CRKFR_EINADMISSIBLE_INPUT, std::to_string(bad) + " nodes violate the admissibility constraints");
@@ -906,6 +1029,23 @@ static int check_learned(const crkfr_solver* s)
     return 0;
 }
 
+// the tile-fused step serves 2D Euler with elements of 4 or 16 points, the
+// limiter chain off and the D2 dissipation
+static bool use_tile(const crkfr_solver* s)
+{
+    return s->fused && s->edge_list && s->lim.blend == CRKFR_BLEND_OFF && s->dissipation == CRKFR_DISS_D2;
+}
+
+extern "C" int crkfr_set_fused(crkfr_solver* s, int on)
+{
+    if (!s) return fail(CRKFR_EINVAL, "null argument");
+    s->fused = on != 0;
+    invalidate_graph(s);
+    return 0;
+}
+
+extern "C" int crkfr_fused_in_use(const crkfr_solver* s) { return s && use_tile(s) ? 1 : 0; }
+
 static int enqueue_step(crkfr_solver* s, double dt_fixed, double t_end)
 {
     int lrc = check_learned(s);
@@ -923,14 +1063,15 @@ static int enqueue_step(crkfr_solver* s, double dt_fixed, double t_end)
     hipLaunchKernelGGL(k_prep, dim3(1), dim3(RATE_SLOTS), 0, s->stream, pa);
     const int in = s->cur, out = 1 - s->cur;
     const bool tm = s->timing;
+    const bool tile = use_tile(s);
     if (tm) (void)hipEventRecord(s->ev[0], s->stream);
-    int rc = dispatch_step(s, PH_LOCAL, in, out);
+    int rc = dispatch_step(s, tile ? PH_TILE : PH_LOCAL, in, out);
     if (tm) (void)hipEventRecord(s->ev[1], s->stream);
-    if (!rc) rc = dispatch_step(s, PH_FACE_X, in, out);
+    if (!rc) rc = dispatch_step(s, tile ? PH_TILE_FACE_X : PH_FACE_X, in, out);
     if (tm) (void)hipEventRecord(s->ev[2], s->stream);
-    if (!rc && s->dim == 2) rc = dispatch_step(s, PH_FACE_Y, in, out);
+    if (!rc && s->dim == 2) rc = dispatch_step(s, tile ? PH_TILE_FACE_Y : PH_FACE_Y, in, out);
     if (tm) (void)hipEventRecord(s->ev[3], s->stream);
-    if (!rc) rc = dispatch_step(s, PH_UPDATE, in, out);
+    if (!rc && (!tile || s->n_edge > 0)) rc = dispatch_step(s, tile ? PH_EDGE_UPDATE : PH_UPDATE, in, out);
     if (tm) (void)hipEventRecord(s->ev[4], s->stream);
     s->cur = out;
     return rc;
@@ -1082,6 +1223,17 @@ extern "C" int crkfr_get_diag(crkfr_solver* s, crkfr_diag* out)
             if (dv > out->max_alpha_dev) out->max_alpha_dev = dv;
         }
     }
+    StateStats st = {0.0, 0.0, 0.0, 0.0, 0};
+    if (s->has_state) {
+        int rc = state_stats(s, &st);
+        if (rc) return rc;
+    }
+    out->min_rho = st.min_rho;
+    out->min_p = st.min_p1;
+    out->min_p2 = st.min_p2;
+    out->n_nonfinite = st.nonfinite;
+    out->mass = st.mass;
+    out->mass_drift = (st.mass - s->mass0) / (s->mass0 != 0.0 ? std::fabs(s->mass0) : 1.0);
     if (out->n_mean_inadmissible > 0)
         return fail(CRKFR_EINADMISSIBLE_MEAN, "an element mean left the admissible set");
     return 0;

@@ -87,6 +87,9 @@ struct StepArgs {
     const double* dt_dev;
     int blend, indicator, smooth, flux_limiter, scaling, C;
     double alpha_min, alpha_max, alpha_const;
+    // admissibility margins: relative (flux limiter, subcell reconstruction)
+    // and absolute (scaling limiter floor)
+    double eps_rel, eps_abs;
     Phys phys;
     RefTab<real> R;
     double w64[MAXND];
@@ -102,6 +105,10 @@ struct StepArgs {
     int stages;            // cRK stages (tableau in R.ta, R.tb)
     int dissipation;       // DISS_*: D2 (eq. D2), D1 (eq. D1), D-CSX (eq. dcsx)
     int central;           // CENTRAL_*: EA traces (eq. evaluate) or extrapolation (eq. extrapolate)
+    // tile-fused step: the elements at the edges of the tiles (updated by the
+    // update phase), null for the split step
+    const int* edge_list;
+    int n_edge;
 };
 
 // trace components per face point: F (M), U (M; u^n for D1), sigma (1),
@@ -219,6 +226,23 @@ __host__ __device__ constexpr double tab_b(int S, int i)
 
 template <class real>
 __device__ __forceinline__ constexpr bool is_mp() { return sizeof(real) == 4; }
+
+// LDS layouts of an element's nodal values: node-major (value v of node k at
+// k M + v), or split into 16-byte planes (value v of node k at
+// ((v / W) np + k) W + v % W, W values per 16 bytes).  With planes a wide
+// access reads one plane of one node, and the np <= 16 nodes of an element
+// sit in distinct 16-byte bank groups: writes of every node, derivative
+// reads along a row or a column and trace reads are free of bank conflicts.
+template <int M, int np>
+struct NodeMajor {
+    static constexpr int SIZE = np * M;
+    __host__ __device__ static constexpr int at(int k, int v) { return k * M + v; }
+};
+template <class real, int M, int np>
+struct Planes {
+    static constexpr int W = 16 / (int)sizeof(real), NPL = (M + W - 1) / W, SIZE = NPL * np * W;
+    __host__ __device__ static constexpr int at(int k, int v) { return ((v / W) * np + k) * W + v % W; }
+};
 
 // ----------------------------------------------------------------------------
 // state access
@@ -412,9 +436,9 @@ __device__ __forceinline__ void atomic_max_pos(unsigned long long* p, double v)
 // values are not admissible).  The element's nodal values are in sh[k][v].
 // Outputs the predicted values at the x faces (xm, xp) and y faces (ym, yp).
 // ----------------------------------------------------------------------------
-template <class Eq, int N, class real>
+template <class Eq, int N, class L, class real>
 __device__ void mh_subcell(const StepArgs<real>& a, int ex, int ey, int p, int q,
-                           const real* u, const real (*sh)[Eq::M], double dt,
+                           const real* u, const real* sh, double dt,
                            real* xm, real* xp, real* ym, real* yp, int& nlim, int& nfb)
 {
     using G = Geo<Eq::DIM, N>;
@@ -431,7 +455,7 @@ __device__ void mh_subcell(const StepArgs<real>& a, int ex, int ey, int p, int q
 #pragma unroll
     for (int kk = 0; kk < K; ++kk) {
         Pu[kk] = Eq::adm(kk, ud, P);
-        eps[kk] = 0.1 * Pu[kk];
+        eps[kk] = a.eps_rel * Pu[kk];
         if (!(eps[kk] > 0.0)) u_ok = false;
     }
     const bool mh = a.blend == BLEND_MH && u_ok;
@@ -443,7 +467,7 @@ __device__ void mh_subcell(const StepArgs<real>& a, int ex, int ey, int p, int q
             if (pos > 0) {
                 const int kn = d == 0 ? k - 1 : k - nd;
 #pragma unroll
-                for (int v = 0; v < M; ++v) um[v] = sh[kn][v];
+                for (int v = 0; v < M; ++v) um[v] = sh[L::at(kn, v)];
             } else {
                 int en = nbr(a, ex, ey, d, 0);
                 if (en >= 0) {
@@ -466,7 +490,7 @@ __device__ void mh_subcell(const StepArgs<real>& a, int ex, int ey, int p, int q
             if (pos < N) {
                 const int kn = d == 0 ? k + 1 : k + nd;
 #pragma unroll
-                for (int v = 0; v < M; ++v) up[v] = sh[kn][v];
+                for (int v = 0; v < M; ++v) up[v] = sh[L::at(kn, v)];
             } else {
                 int en = nbr(a, ex, ey, d, 1);
                 if (en >= 0) {
@@ -577,7 +601,8 @@ __device__ void mh_subcell(const StepArgs<real>& a, int ex, int ey, int p, int q
 // indicator quantity eps[k * stride] (projection table Pm: GL quadrature for
 // GL points, the inverse Vandermonde matrix for GLL points)
 template <int DIM, int N, class real>
-__device__ __forceinline__ real modal_coeff(const RefTab<real>& R, int p, int q, const real* eps, int stride)
+__device__ __forceinline__ real modal_coeff(const RefTab<real>& R, int p, int q, const real* eps, int stride,
+                                            int rstride)
 {
     constexpr int nd = N + 1;
     real m = 0;
@@ -586,7 +611,7 @@ __device__ __forceinline__ real modal_coeff(const RefTab<real>& R, int p, int q,
         for (int s2 = 0; s2 < nd; ++s2)
 #pragma unroll
             for (int r = 0; r < nd; ++r)
-                m += R.Pm[p][r] * R.Pm[q][s2] * eps[(s2 * nd + r) * stride];
+                m += R.Pm[p][r] * R.Pm[q][s2] * eps[s2 * rstride + r * stride];
     } else {
 #pragma unroll
         for (int r = 0; r < nd; ++r) m += R.Pm[p][r] * eps[r * stride];
@@ -597,7 +622,7 @@ __device__ __forceinline__ real modal_coeff(const RefTab<real>& R, int p, int q,
 // shell energies en[s] = sum of squared coefficients whose highest degree is s
 // (the indicator's arithmetic runs in the step's precision)
 template <int DIM, int N, class real>
-__device__ __forceinline__ void shell_energies(const real* m2, int stride, real* en)
+__device__ __forceinline__ void shell_energies(const real* m2, int stride, int rstride, real* en)
 {
     constexpr int nd = N + 1, np = DIM == 2 ? nd * nd : nd;
 #pragma unroll
@@ -605,7 +630,7 @@ __device__ __forceinline__ void shell_energies(const real* m2, int stride, real*
 #pragma unroll
     for (int kk = 0; kk < np; ++kk) {
         int pp = kk % nd, qq = kk / nd;
-        en[pp > qq ? pp : qq] += m2[kk * stride];
+        en[pp > qq ? pp : qq] += m2[qq * rstride + pp * stride];
     }
 }
 
@@ -671,16 +696,39 @@ __device__ __forceinline__ real act_sigmoid(real x)
 // ----------------------------------------------------------------------------
 // k_local
 // ----------------------------------------------------------------------------
-template <class Eq, int N, class real, bool LIM>
-__device__ void local_body(const StepArgs<real>& a, int vblock)
+// LDS reals per element in the tile-fused step: the stage arrays u, f, g in
+// 16-byte planes, then the 4 (N+1) face points x (2M + 1) trace components
+template <class Eq, int N, class real>
+__host__ __device__ constexpr int elem_region()
 {
-    using G = LGeo<Eq::DIM, N>;
+    constexpr int nd = N + 1, np = Eq::DIM == 2 ? nd * nd : nd;
+    using L = Planes<real, Eq::M, np>;
+    constexpr int stage = 2 * L::SIZE + (Eq::DIM == 2 ? L::SIZE : np);
+    constexpr int traces = (Eq::DIM == 2 ? 4 * nd : 2) * (2 * Eq::M + 1);
+    return stage > traces ? stage : traces;
+}
+// TG = void: the split step (LGeo blocks of elements; uHp and the face traces
+// to HBM).  TG = a tile geometry: one tile of TX x TY elements per workgroup
+// (the tile-fused step); the element's stage arrays lie in tile_buf, uHp goes
+// to uhp_out (registers), the face traces to the element's part of tile_buf
+// and, for faces on the tile's edge, to HBM as well.
+template <class Eq, int N, class real, bool LIM, class TG = void>
+__device__ void local_body(const StepArgs<real>& a, int vblock, real* tile_buf = nullptr, real* uhp_out = nullptr)
+{
+    constexpr bool TILE = !std::is_void<TG>::value;
+    static_assert(!(TILE && LIM), "the tile-fused step has no limiter chain");
+    using G = std::conditional_t<TILE, TG, LGeo<Eq::DIM, N>>;
     constexpr int M = Eq::M, DIM = Eq::DIM, nd = G::nd, nq = G::nq, np = G::np, EB = G::EB;
     const int S = a.stages;
     constexpr int MY = DIM == 2 ? M : 1;
-    __shared__ real sh_u[EB][np][M];
-    __shared__ real sh_f[EB][np][M];
-    __shared__ real sh_g[EB][np][MY];
+    // element arrays in 16-byte planes (L::at(node, v)); the y fluxes (2D)
+    // likewise, one value per node in 1D
+    using L = Planes<real, M, np>;
+    constexpr int PW = L::W;
+    constexpr int GS = DIM == 2 ? PW : 1;     // node stride of value 0 in sh_g
+    // one region of SB reals per element: the stage arrays u, f, g (in the
+    // tile-fused step then the element's face traces)
+    constexpr int SB = TILE ? elem_region<Eq, N, real>() : 2 * L::SIZE + (DIM == 2 ? L::SIZE : np);
     // face values of the final part; before it, the predicted yp of the subcells
     constexpr int HW = 4 * nd > np ? 4 * nd : np;
     __shared__ real sh_h[EB][M][HW];
@@ -688,10 +736,34 @@ __device__ void local_body(const StepArgs<real>& a, int vblock)
     const Phys& P = a.phys;
     const int le = threadIdx.x / np, k = threadIdx.x - le * np;
     const int p = k % nd, q = k / nd;
-    const int e0 = vblock * EB + le;
-    const bool act = e0 < a.ne;
-    const int e = act ? e0 : a.ne - 1;
-    const int ey = (int)((unsigned)e / (unsigned)a.nx), ex = e - ey * a.nx;
+    auto at = [](int kk, int v) { return L::at(kk, v); };
+    real* su;
+    if constexpr (TILE) {
+        su = tile_buf + le * SB;
+    } else {
+        __shared__ real sh_buf[EB][SB];
+        su = &sh_buf[le][0];
+    }
+    real* const sf = su + L::SIZE;
+    real* const sg = su + 2 * L::SIZE;
+    int ex, ey, e, tix = 0, tiy = 0;
+    bool act;
+    if constexpr (TILE) {
+        const int ntx = (a.nx + G::TX - 1) / G::TX;
+        tix = le % G::TX;
+        tiy = le / G::TX;
+        const int gx = (vblock % ntx) * G::TX + tix, gy = (vblock / ntx) * G::TY + tiy;
+        act = gx < a.nx && gy < a.ny;
+        ex = gx < a.nx ? gx : a.nx - 1;
+        ey = gy < a.ny ? gy : a.ny - 1;
+        e = ey * a.nx + ex;
+    } else {
+        const int e0 = vblock * EB + le;
+        act = e0 < a.ne;
+        e = act ? e0 : a.ne - 1;
+        ey = (int)((unsigned)e / (unsigned)a.nx);
+        ex = e - ey * a.nx;
+    }
     const double dt = *a.dt_dev;
     const real rdt = (real)dt, idx = (real)a.idx, idy = (real)a.idy;
     const real xn = (real)(a.x0 + ((double)ex + (double)a.R.xi[p]) * a.dx);
@@ -708,15 +780,15 @@ __device__ void local_body(const StepArgs<real>& a, int vblock)
         //      the learned indicator over the same modal energies ----
         __shared__ real sh_m[EB][2][MLP_HMAX];
 #pragma unroll
-        for (int v = 0; v < M; ++v) sh_u[le][k][v] = un[v];
+        for (int v = 0; v < M; ++v) su[at(k, v)] = un[v];
         const bool modal = a.indicator == IND_PAPER || a.indicator == IND_LEARNED;
-        if (modal) sh_f[le][k][0] = Eq::ind(un, P);
-        __syncthreads();
+        if (modal) sf[at(k, 0)] = Eq::ind(un, P);
+        elem_sync<np>();
         if (modal) {
-            real m = modal_coeff<DIM, N>(a.R, p, q, &sh_f[le][0][0], M);
-            sh_g[le][k][0] = m * m;
+            real m = modal_coeff<DIM, N>(a.R, p, q, sf, PW, nd * PW);
+            sg[k * GS] = m * m;
         }
-        __syncthreads();
+        elem_sync<np>();
         double al_ind = 0.0;
         bool inbox = true;
         if (modal) {
@@ -724,7 +796,7 @@ __device__ void local_body(const StepArgs<real>& a, int vblock)
             // lane 0 forms the indicator's alpha, lanes 1..N the learned
             // indicator's features (feature s on lane s)
             real en[nd];
-            shell_energies<DIM, N>(&sh_g[le][0][0], MY, en);
+            shell_energies<DIM, N>(sg, GS, nd * GS, en);
             if (k == 0 && act) {
                 al_ind = indicator_alpha<N>(en, a.alpha_min, a.alpha_max, a.ind_T, a.ind_kT);
                 if (a.indicator == IND_PAPER) a.alpha_raw[e] = al_ind;
@@ -737,7 +809,7 @@ __device__ void local_body(const StepArgs<real>& a, int vblock)
                     cum += en[s2];
                     if (s2 == k) { es = en[s2]; cs = cum; }
                 }
-                sh_f[le][k - 1][0] = learned_feature(es, cs);
+                sf[at(k - 1, 0)] = learned_feature(es, cs);
             }
         } else if (k == 0 && act) {
             if (a.indicator == IND_CONST) a.alpha_raw[e] = a.alpha_const;
@@ -745,13 +817,13 @@ __device__ void local_body(const StepArgs<real>& a, int vblock)
         }
         if (a.indicator == IND_LEARNED) {
             // the network: hidden units spread over the element's lanes
-            __syncthreads();
+            elem_sync<np>();
             if (k == 0) {
                 // the features inside the training box, else the indicator decides
                 const float* box = a.mlp + mlp_nparams(N, a.mlp_hidden);
 #pragma unroll
                 for (int j = 0; j < N; ++j) {
-                    const real ft = sh_f[le][j][0];
+                    const real ft = sf[at(j, 0)];
                     if (!(ft >= (double)box[j] && ft <= (double)box[N + j])) inbox = false;
                 }
                 if (act && !inbox) atomicAdd(&a.diag[D_LFALLBACK], 1ull);
@@ -773,9 +845,9 @@ __device__ void local_body(const StepArgs<real>& a, int vblock)
                 for (int c = 0; c < MLP_HFAST / 4; ++c) w2r[c] = row[c];
                 real s = (real)b1[j];
 #pragma unroll
-                for (int i = 0; i < N; ++i) s += (real)W1[j * N + i] * sh_f[le][i][0];
+                for (int i = 0; i < N; ++i) s += (real)W1[j * N + i] * sf[at(i, 0)];
                 if (k < H) sh_m[le][0][k] = act_tanh(s);
-                __syncthreads();
+                elem_sync<np>();
                 real s2 = (real)b2[j];
 #pragma unroll
                 for (int c = 0; c < MLP_HFAST / 4; ++c) {
@@ -791,7 +863,7 @@ __device__ void local_body(const StepArgs<real>& a, int vblock)
                     out = dpp_elem_reduce<np, RED_SUM>((real)w3[j] * h2) + (real)w3[H];
                 } else {
                     if (k < H) sh_m[le][1][k] = h2;
-                    __syncthreads();
+                    elem_sync<np>();
                     if (k == 0) {
                         out = (real)w3[H];
 #pragma unroll
@@ -802,16 +874,16 @@ __device__ void local_body(const StepArgs<real>& a, int vblock)
                 for (int j = k; j < H; j += np) {
                     real s = (real)b1[j];
 #pragma unroll
-                    for (int i = 0; i < N; ++i) s += (real)W1[j * N + i] * sh_f[le][i][0];
+                    for (int i = 0; i < N; ++i) s += (real)W1[j * N + i] * sf[at(i, 0)];
                     sh_m[le][0][j] = act_tanh(s);
                 }
-                __syncthreads();
+                elem_sync<np>();
                 for (int j = k; j < H; j += np) {
                     real s = (real)b2[j];
                     for (int i = 0; i < H; ++i) s += (real)W2[j * H + i] * sh_m[le][0][i];
                     sh_m[le][1][j] = act_tanh(s);
                 }
-                __syncthreads();
+                elem_sync<np>();
                 if (k == 0) {
                     out = (real)w3[H];
                     for (int j = 0; j < H; ++j) out += (real)w3[j] * sh_m[le][1][j];
@@ -829,20 +901,20 @@ __device__ void local_body(const StepArgs<real>& a, int vblock)
         //      lanes like the face points (one subface flux per face point) ----
         real xm[M], xp[M], ym[M], yp[M];
         int nlim = 0, nfb = 0;
-        mh_subcell<Eq, N>(a, ex, ey, p, q, un, sh_u[le], dt, xm, xp, ym, yp, nlim, nfb);
-        __syncthreads();
-        // xm, xp, ym, yp in sh_f, sh_u (the nodal values are no longer needed), sh_g, sh_h
+        mh_subcell<Eq, N, L>(a, ex, ey, p, q, un, su, dt, xm, xp, ym, yp, nlim, nfb);
+        elem_sync<np>();
+        // xm, xp, ym, yp in sf, su (the nodal values are no longer needed), sg, sh_h
         real* sh_yp = &sh_h[le][0][0];
 #pragma unroll
         for (int v = 0; v < M; ++v) {
-            sh_f[le][k][v] = xm[v];
-            sh_u[le][k][v] = xp[v];
+            sf[at(k, v)] = xm[v];
+            su[at(k, v)] = xp[v];
             if constexpr (DIM == 2) {
-                sh_g[le][k][v] = ym[v];
+                sg[at(k, v)] = ym[v];
                 sh_yp[k * M + v] = yp[v];
             }
         }
-        __syncthreads();
+        elem_sync<np>();
         if (act) {
             constexpr int NFP = DIM == 2 ? 4 * nd : 2;
 #pragma unroll
@@ -859,14 +931,14 @@ __device__ void local_body(const StepArgs<real>& a, int vblock)
 #pragma unroll
                 for (int v = 0; v < M; ++v) {
                     if constexpr (DIM == 2) {
-                        lft[v] = d == 0 ? sh_u[le][kl][v] : sh_yp[kl * M + v];
-                        rgt[v] = d == 0 ? sh_f[le][kr][v] : sh_g[le][kr][v];
-                        own[v] = side ? (d == 0 ? sh_u[le][kf][v] : sh_yp[kf * M + v])
-                                      : (d == 0 ? sh_f[le][kf][v] : sh_g[le][kf][v]);
+                        lft[v] = d == 0 ? su[at(kl, v)] : sh_yp[kl * M + v];
+                        rgt[v] = d == 0 ? sf[at(kr, v)] : sg[at(kr, v)];
+                        own[v] = side ? (d == 0 ? su[at(kf, v)] : sh_yp[kf * M + v])
+                                      : (d == 0 ? sf[at(kf, v)] : sg[at(kf, v)]);
                     } else {
-                        lft[v] = sh_u[le][kl][v];
-                        rgt[v] = sh_f[le][kr][v];
-                        own[v] = side ? sh_u[le][kf][v] : sh_f[le][kf][v];
+                        lft[v] = su[at(kl, v)];
+                        rgt[v] = sf[at(kr, v)];
+                        own[v] = side ? su[at(kf, v)] : sf[at(kf, v)];
                     }
                 }
                 real* base = d == 0 ? a.trx : a.trY;
@@ -881,7 +953,7 @@ __device__ void local_body(const StepArgs<real>& a, int vblock)
             if (nlim) atomicAdd(&a.diag[D_SLOPELIM], (unsigned long long)nlim);
             if (nfb) atomicAdd(&a.diag[D_FALLBACK], (unsigned long long)nfb);
         }
-        __syncthreads();
+        elem_sync<np>();
     }
 
     // ---- local cRK procedure ----
@@ -905,7 +977,7 @@ __device__ void local_body(const StepArgs<real>& a, int vblock)
         const int sd = fside(fp), t = fpos(fp);
         return sd < 2 ? t * nd + r : r * nd + t;
     };
-    // this lane's face lines: LDS node indices and interpolation weights
+    // this lane's face lines: offsets of the line's nodes (value 0) and interpolation weights
     int fkn[FPL][nd];
     real fw[FPL][nd];
 #pragma unroll
@@ -914,7 +986,7 @@ __device__ void local_body(const StepArgs<real>& a, int vblock)
         const bool hi = fside(fp) & 1;
 #pragma unroll
         for (int r = 0; r < nd; ++r) {
-            fkn[j][r] = fnode(fp, r);
+            fkn[j][r] = at(fnode(fp, r), 0);
             fw[j][r] = hi ? a.R.l1[r] : a.R.l0[r];
         }
     }
@@ -938,11 +1010,11 @@ __device__ void local_body(const StepArgs<real>& a, int vblock)
             if constexpr (DIM == 2) Gs[v] += bi * g[v];
             U[v] += bi * ui[v];
             Sa[v] += bi * s[v];
-            sh_u[le][k][v] = ui[v];
-            sh_f[le][k][v] = f[v];
-            if constexpr (DIM == 2) sh_g[le][k][v] = g[v];
+            su[at(k, v)] = ui[v];
+            sf[at(k, v)] = f[v];
+            if constexpr (DIM == 2) sg[at(k, v)] = g[v];
         }
-        __syncthreads();
+        elem_sync<np>();
         // EA traces: normal flux of the interpolated stage value at the face points
 #pragma unroll
         for (int j = 0; j < FPL; ++j) {
@@ -956,7 +1028,7 @@ __device__ void local_body(const StepArgs<real>& a, int vblock)
             for (int r = 0; r < nd; ++r) {
                 const int kn = fkn[j][r];
 #pragma unroll
-                for (int v = 0; v < M; ++v) uf[v] += fw[j][r] * sh_u[le][kn][v];
+                for (int v = 0; v < M; ++v) uf[v] += fw[j][r] * su[kn + at(0, v)];
             }
             if constexpr (has_normal_flux<Eq>::value) {
                 Eq::fn(sd < 2 ? 0 : 1, uf, ff, P);
@@ -967,7 +1039,7 @@ __device__ void local_body(const StepArgs<real>& a, int vblock)
 #pragma unroll
                 for (int v = 0; v < M; ++v) tr[j][v] += bi * (sd < 2 ? ff[v] : gf[v]);
             }
-            if (act && (a.dissipation == DISS_DCSX || (i == 0 && a.dissipation == DISS_D1))) {
+            if (!TILE && act && (a.dissipation == DISS_DCSX || (i == 0 && a.dissipation == DISS_D1))) {
                 // stage values at the face (D-CSX), or u^n in place of U (D1)
                 real* base = sd < 2 ? a.trx : a.trY;
                 const int npt = sd < 2 ? nq : nd, side = sd & 1, t = fpos(fp);
@@ -979,7 +1051,7 @@ __device__ void local_body(const StepArgs<real>& a, int vblock)
                 real nodev[M];
                 const int kadj = (sd & 1) ? fkn[j][N] : fkn[j][0];
 #pragma unroll
-                for (int v = 0; v < M; ++v) nodev[v] = sh_u[le][kadj][v];
+                for (int v = 0; v < M; ++v) nodev[v] = su[kadj + at(0, v)];
                 sig[j] = Eq::sig_trace(sd < 2 ? 0 : 1, uf, nodev, P);
             }
         }
@@ -989,34 +1061,34 @@ __device__ void local_body(const StepArgs<real>& a, int vblock)
             for (int v = 0; v < M; ++v) {
                 real df = 0, dg = 0;
 #pragma unroll
-                for (int r = 0; r < nd; ++r) df += Dx[r] * sh_f[le][q * nd + r][v];
+                for (int r = 0; r < nd; ++r) df += Dx[r] * sf[at(q * nd + r, v)];
                 if constexpr (DIM == 2) {
 #pragma unroll
-                    for (int r = 0; r < nd; ++r) dg += Dy[r] * sh_g[le][r * nd + p][v];
+                    for (int r = 0; r < nd; ++r) dg += Dy[r] * sg[at(r * nd + p, v)];
                 }
                 ui[v] = un[v] - rdt * ai * (df * idx + dg * idy - s[v]);
             }
         }
-        __syncthreads();
+        elem_sync<np>();
     }
 
     // ---- volume part of the FR update, traces of U, extrapolated averaged flux ----
 #pragma unroll
     for (int v = 0; v < M; ++v) {
-        sh_u[le][k][v] = U[v];
-        sh_f[le][k][v] = F[v];
-        if constexpr (DIM == 2) sh_g[le][k][v] = Gs[v];
+        su[at(k, v)] = U[v];
+        sf[at(k, v)] = F[v];
+        if constexpr (DIM == 2) sg[at(k, v)] = Gs[v];
     }
-    __syncthreads();
+    elem_sync<np>();
     real vol[M], Ut[FPL][M];
 #pragma unroll
     for (int v = 0; v < M; ++v) {
         real df = 0, dg = 0;
 #pragma unroll
-        for (int r = 0; r < nd; ++r) df += Dx[r] * sh_f[le][q * nd + r][v];
+        for (int r = 0; r < nd; ++r) df += Dx[r] * sf[at(q * nd + r, v)];
         if constexpr (DIM == 2) {
 #pragma unroll
-            for (int r = 0; r < nd; ++r) dg += Dy[r] * sh_g[le][r * nd + p][v];
+            for (int r = 0; r < nd; ++r) dg += Dy[r] * sg[at(r * nd + p, v)];
         }
         vol[v] = df * idx + dg * idy;
     }
@@ -1033,8 +1105,8 @@ __device__ void local_body(const StepArgs<real>& a, int vblock)
             const int kn = fkn[j][r];
 #pragma unroll
             for (int v = 0; v < M; ++v) {
-                Ut[j][v] += fw[j][r] * sh_u[le][kn][v];
-                hf[v] += fw[j][r] * (sd < 2 ? sh_f[le][kn][v] : sh_g[le][kn][DIM == 2 ? v : 0]);
+                Ut[j][v] += fw[j][r] * su[kn + at(0, v)];
+                hf[v] += fw[j][r] * (sd < 2 ? sf[kn + at(0, v)] : sg[DIM == 2 ? kn + at(0, v) : 0]);
             }
         }
 #pragma unroll
@@ -1043,7 +1115,46 @@ __device__ void local_body(const StepArgs<real>& a, int vblock)
             if (a.central == CENTRAL_AE) tr[j][v] = hf[v];   // extrapolated averaged flux as the central part
         }
     }
-    __syncthreads();
+    elem_sync<np>();
+    if constexpr (TILE) {
+        // uHp to registers; the face traces to the element's region (its
+        // stage arrays are read no more); faces on the tile's edge to HBM too
+        constexpr int TC = 2 * M + 1;
+        const size_t gi = (size_t)e * np + k;
+#pragma unroll
+        for (int v = 0; v < M; ++v) {
+            real corr = (sh_h[le][v][nd + q] * a.R.bR[p] - sh_h[le][v][q] * a.R.bL[p]) * idx;
+            if constexpr (DIM == 2)
+                corr += (sh_h[le][v][3 * nd + p] * a.R.bR[q] - sh_h[le][v][2 * nd + p] * a.R.bL[q]) * idy;
+            uhp_out[v] = un[v] - rdt * (vol[v] - Sa[v]) + rdt * corr;
+            if (act && src && a.dtS) a.dtS[(size_t)v * nes * np + gi] = rdt * Sa[v];
+        }
+#pragma unroll
+        for (int j = 0; j < FPL; ++j) {
+            const int fp = k + j * np;
+            if (j == FPL - 1 && fp >= NFP) break;
+            const int sd = fside(fp), t = fpos(fp), side = sd & 1;
+#pragma unroll
+            for (int v = 0; v < M; ++v) {
+                su[fp * TC + v] = tr[j][v];
+                su[fp * TC + M + v] = Ut[j][v];
+            }
+            su[fp * TC + 2 * M] = sig[j];
+            const bool edge_face = sd == 0 ? tix == 0 : sd == 1 ? (tix == G::TX - 1 || ex + 1 >= a.nx)
+                                 : sd == 2 ? tiy == 0 : (tiy == G::TY - 1 || ey + 1 >= a.ny);
+            if (act && edge_face) {
+                real* base = sd < 2 ? a.trx : a.trY;
+                const int npt = sd < 2 ? nq : nd;
+#pragma unroll
+                for (int v = 0; v < M; ++v) {
+                    base[((size_t)(side * C + v) * nes + e) * npt + t] = tr[j][v];
+                    base[((size_t)(side * C + M + v) * nes + e) * npt + t] = Ut[j][v];
+                }
+                base[((size_t)(side * C + 2 * M) * nes + e) * npt + t] = sig[j];
+            }
+        }
+        return;
+    }
     if (!act) return;
     const size_t gi = (size_t)e * np + k;
 #pragma unroll
@@ -1172,17 +1283,20 @@ __device__ __forceinline__ void face_point(const StepArgs<real>& a, int t, int e
 #define TRB(c) trb[(size_t)(0 * C + (c)) * nes * npt + pB]
     real Fm[M], Fp[M], Um[M], Up[M], uA[M], uB[M];
     real sm = 0, sp = 0;
+    // the face-adjacent solution points enter the flux limiter, the ghosts of
+    // a missing side and the D-CSX wave speeds only
+    const bool need_u = LIM || !INTERIOR || a.dissipation == DISS_DCSX;
     if (hA) {
 #pragma unroll
         for (int v = 0; v < M; ++v) { Fm[v] = TRA(v); Um[v] = TRA(M + v); }
         sm = TRA(2 * M);
-        load_node<Eq>(a, np, eL, kA, uA);
+        if (need_u) load_node<Eq>(a, np, eL, kA, uA);
     }
     if (hB) {
 #pragma unroll
         for (int v = 0; v < M; ++v) { Fp[v] = TRB(v); Up[v] = TRB(M + v); }
         sp = TRB(2 * M);
-        load_node<Eq>(a, np, eR, kB, uB);
+        if (need_u) load_node<Eq>(a, np, eR, kB, uB);
     }
     const bool wA = !hA && is_wall(a, D, 0), wB = !hB && is_wall(a, D, 1);
     // time-dependent inflow: u^- = g(t^n), U^- = sum b_i g(t^n + c_i dt),
@@ -1386,7 +1500,7 @@ __device__ __forceinline__ void face_point(const StepArgs<real>& a, int t, int e
                         const double* lo = side == 0 ? cAlo : cBlo;
                         double Plo = Eq::adm(kk, lo, P);
                         if (!(Plo > 0.0)) { bad = true; th = 0.0; continue; }
-                        double t2 = segment_fraction<Eq>(kk, lo, Plo, cF, 0.1 * Plo, P);
+                        double t2 = segment_fraction<Eq>(kk, lo, Plo, cF, a.eps_rel * Plo, P);
                         th = t2 < th ? t2 : th;
                     }
                     if (th < 1.0) {
@@ -1510,27 +1624,29 @@ __device__ __forceinline__ void wave_rate_max(double rate, int vblock, unsigned 
 // ----------------------------------------------------------------------------
 // k_update
 // ----------------------------------------------------------------------------
+template <class Eq, int N, class real, int EB>
+__device__ __forceinline__ void update_finish(const StepArgs<real>& a, int e, int le, int k, bool act,
+                                              const real* unew, const real* FL, const real* FR, const real* GB,
+                                              const real* GT, const real* dts, int vblock);
+
+// k_update: one lane per node; elements from 0 in order, or (tile-fused step)
+// the list of elements at the edges of the tiles
 template <class Eq, int N, class real, bool LIM>
 __device__ void update_body(const StepArgs<real>& a, int vblock)
 {
     using G = Geo<Eq::DIM, N>;
-    constexpr int M = Eq::M, DIM = Eq::DIM, nd = G::nd, nq = G::nq, np = G::np, EB = G::EB, K = Eq::K;
-    constexpr bool MP = is_mp<real>();
+    constexpr int M = Eq::M, DIM = Eq::DIM, nd = G::nd, nq = G::nq, np = G::np, EB = G::EB;
     __shared__ real sh_u[EB][np][M];
     __shared__ real sh_f[EB][np][M];
     __shared__ real sh_g[EB][np][DIM == 2 ? M : 1];
-    __shared__ double sh_d[EB][np];
-    __shared__ double sh_r[elem_in_wave<np>() ? 1 : EB][M][np];
-    __shared__ double sh_m[elem_in_wave<np>() ? 1 : EB][M];
-    __shared__ double sh_r2[elem_in_wave<np>() || !MP ? 1 : EB][2 * M][np];
-    __shared__ double sh_m2[elem_in_wave<np>() || !MP ? 1 : EB][2 * M];
 
     const Phys& P = a.phys;
     const int le = threadIdx.x / np, k = threadIdx.x - le * np;
     const int p = k % nd, q = k / nd;
     const int e0 = vblock * EB + le;
-    const bool act = e0 < a.ne;
-    const int e = act ? e0 : a.ne - 1;
+    const int nel = a.edge_list ? a.n_edge : a.ne;
+    const bool act = e0 < nel;
+    const int e = a.edge_list ? a.edge_list[act ? e0 : nel - 1] : (act ? e0 : a.ne - 1);
     const int ey = (int)((unsigned)e / (unsigned)a.nx), ex = e - ey * a.nx;
     const double dt = *a.dt_dev;
     const real rdt = (real)dt, idx = (real)a.idx, idy = (real)a.idy;
@@ -1539,16 +1655,22 @@ __device__ void update_body(const StepArgs<real>& a, int vblock)
     const size_t iL = ((size_t)ey * (a.nx + 1) + ex) * nq + q, iR = iL + nq;
     const size_t iB = ((size_t)ey * a.nx + ex) * nd + p, iT = iB + (size_t)a.nx * nd;
 
-    real uH[M];
+    real uH[M], FLv[M], FRv[M], GBv[M], GTv[M], dts[M];
 #pragma unroll
     for (int v = 0; v < M; ++v) {
-        real FL = a.Fx[v * nfx + iL], FR = a.Fx[v * nfx + iR];
-        real val = a.uHp[v * nes * np + gi] - rdt * idx * (FR * a.R.bR[p] - FL * a.R.bL[p]);
+        FLv[v] = a.Fx[v * nfx + iL];
+        FRv[v] = a.Fx[v * nfx + iR];
+        real val = a.uHp[v * nes * np + gi] - rdt * idx * (FRv[v] * a.R.bR[p] - FLv[v] * a.R.bL[p]);
         if constexpr (DIM == 2) {
-            real GB = a.Gy[v * nfy + iB], GT = a.Gy[v * nfy + iT];
-            val -= rdt * idy * (GT * a.R.bR[q] - GB * a.R.bL[q]);
+            GBv[v] = a.Gy[v * nfy + iB];
+            GTv[v] = a.Gy[v * nfy + iT];
+            val -= rdt * idy * (GTv[v] * a.R.bR[q] - GBv[v] * a.R.bL[q]);
+        } else {
+            GBv[v] = 0;
+            GTv[v] = 0;
         }
         uH[v] = val;
+        dts[v] = a.dtS ? a.dtS[(size_t)v * nes * np + gi] : (real)0;
     }
     real unew[M];
 #pragma unroll
@@ -1567,7 +1689,9 @@ __device__ void update_body(const StepArgs<real>& a, int vblock)
             elem_sync<np>();
             real xm[M], xp[M], ym[M], yp[M];
             int nlim = 0, nfb = 0;
-            if (al > 0.0) mh_subcell<Eq, N>(a, ex, ey, p, q, un, sh_u[le], dt, xm, xp, ym, yp, nlim, nfb);
+            if (al > 0.0)
+                mh_subcell<Eq, N, NodeMajor<M, np>>(a, ex, ey, p, q, un, &sh_u[le][0][0], dt, xm, xp, ym, yp, nlim,
+                                                    nfb);
             elem_sync<np>();
 #pragma unroll
             for (int v = 0; v < M; ++v) {
@@ -1620,6 +1744,35 @@ __device__ void update_body(const StepArgs<real>& a, int vblock)
         }
     }
 
+    update_finish<Eq, N, real, EB>(a, e, le, k, act, unew, FLv, FRv, GBv, GTv, dts, vblock);
+}
+
+// the update after the nodal values unew of eq. crkfr.avg (blended, eq.
+// blended.scheme): FP64 element means (MP32: the FP64 mean update of eq.
+// upmean from this lane's face fluxes FL, FR (row q) and GB, GT (column p),
+// with the source average dts = dt S of App. B), Zhang-Shu scaling, the store
+// of u^{n+1} and the wave-speed rate of the next step.  Every lane of the
+// workgroup calls it (element reductions, rate reduction); lanes with act
+// false store nothing and report no rate.
+template <class Eq, int N, class real, int EB>
+__device__ __forceinline__ void update_finish(const StepArgs<real>& a, int e, int le, int k, bool act,
+                                              const real* unew, const real* FL, const real* FR, const real* GB,
+                                              const real* GT, const real* dts, int vblock)
+{
+    using G = Geo<Eq::DIM, N>;
+    constexpr int M = Eq::M, DIM = Eq::DIM, nd = G::nd, np = G::np, K = Eq::K;
+    constexpr bool MP = is_mp<real>();
+    constexpr bool DPP = elem_in_dpp<np>();
+    __shared__ double sh_d[DPP ? 1 : EB][np];
+    __shared__ double sh_r[elem_in_wave<np>() ? 1 : EB][M][np];
+    __shared__ double sh_m[elem_in_wave<np>() ? 1 : EB][M];
+    __shared__ double sh_r2[elem_in_wave<np>() || !MP ? 1 : EB][2 * M][np];
+    __shared__ double sh_m2[elem_in_wave<np>() || !MP ? 1 : EB][2 * M];
+    const Phys& P = a.phys;
+    const int p = k % nd, q = k / nd;
+    const double dt = *a.dt_dev;
+    const size_t nes = (size_t)a.ne, gi = (size_t)e * np + k;
+
     // ---- FP64 element means (MP32: FP64 mean update from the face fluxes,
     //      eq. upmean with the source average of App. B) ----
     const double wk = a.w64[p] * (DIM == 2 ? a.w64[q] : 1.0);
@@ -1629,14 +1782,11 @@ __device__ void update_body(const StepArgs<real>& a, int vblock)
         part[v] = wk * (double)unew[v];
         double c = 0.0;
         if constexpr (MP) {
-            if (p == 0)
-                c -= dt * a.idx * (DIM == 2 ? a.w64[q] : 1.0)
-                     * ((double)a.Fx[v * nfx + iR] - (double)a.Fx[v * nfx + iL]);
+            if (p == 0) c -= dt * a.idx * (DIM == 2 ? a.w64[q] : 1.0) * ((double)FR[v] - (double)FL[v]);
             if constexpr (DIM == 2) {
-                if (q == 0)
-                    c -= dt * a.idy * a.w64[p] * ((double)a.Gy[v * nfy + iT] - (double)a.Gy[v * nfy + iB]);
+                if (q == 0) c -= dt * a.idy * a.w64[p] * ((double)GT[v] - (double)GB[v]);
             }
-            if (a.dtS) c += wk * (double)a.dtS[(size_t)v * nes * np + gi];
+            if (a.dtS) c += wk * (double)dts[v];
         }
         part[M + v] = c;
     }
@@ -1658,7 +1808,7 @@ __device__ void update_body(const StepArgs<real>& a, int vblock)
 #pragma unroll
     for (int v = 0; v < M; ++v) ud[v] = MP ? um[v] + ((double)unew[v] - ubar[v]) : (double)unew[v];
 
-    // ---- Zhang-Shu scaling (reading: eps_k = min(1e-13, P_k(mean)); linear
+    // ---- Zhang-Shu scaling (reading: eps_k = min(eps_abs, P_k(mean)); linear
     //      root for density, 60-step bisection otherwise); every lane runs
     //      every barrier, the per-element early exit is a flag ----
     if constexpr (K > 0) {
@@ -1671,7 +1821,7 @@ __device__ void update_body(const StepArgs<real>& a, int vblock)
                 if (!(Pbar > 0.0)) mean_bad = true;
                 double t = 1.0;
                 if (!mean_bad) {
-                    double eps = Pbar < 1e-13 ? Pbar : 1e-13;
+                    double eps = Pbar < a.eps_abs ? Pbar : a.eps_abs;
                     if (!Eq::adm_ge(kk, ud, eps, P)) {
                         if (kk == 0) t = (um[0] - eps) / (um[0] - ud[0]);
                         else t = bisect_root<Eq>(kk, um, ud, eps, P);
@@ -1758,6 +1908,162 @@ __global__ void __launch_bounds__(256) k_face(const StepArgs<real> a) { face_bod
 
 template <class Eq, int N, class real, bool LIM>
 __global__ void __launch_bounds__(256) k_update(const StepArgs<real> a) { update_body<Eq, N, real, LIM>(a, blockIdx.x); }
+
+// ----------------------------------------------------------------------------
+// tile-fused step (limiter off): one workgroup per tile of TX x TY elements,
+// one lane per node.  The local cRK procedure of every element, the fluxes of
+// the faces inside the tile and the whole update of the tile's inner elements
+// (all four neighbours in the tile) stay in LDS and registers; only u^n is
+// read and u^{n+1} written for them.  The elements at the tile's edge write
+// uHp, their traces on the tile's edge faces and the fluxes of their faces
+// inside the tile; the faces on tile edges (k_tile_face, the boundary
+// conditions included) and the update of the edge elements (k_update over
+// their list) follow.  Elements of 4 or 16 points (N = 1, 3 in 2D): an
+// element's lanes share a wavefront, so its exchanges need no workgroup
+// barrier.  Tiles of 512 lanes for FP64 (the local procedure holds some 190
+// VGPRs: two wavefronts per SIMD), 1024 lanes for FP32 bulk.
+// ----------------------------------------------------------------------------
+template <int DIM, int N, int RB>
+struct TGeo {
+    static constexpr int nd = N + 1, nq = DIM == 2 ? N + 1 : 1, np = nd * nq;
+    static constexpr bool OK = DIM == 2 && (np == 4 || np == 16);
+    static constexpr int TX = np == 4 ? 16 : 8, TY = np == 4 ? (RB == 8 ? 8 : 16) : (RB == 8 ? 4 : 8);
+    static constexpr int EB = TX * TY, BLOCK = EB * np;
+};
+template <class Eq, int N, class real>
+constexpr int tile_block_v = TGeo<Eq::DIM, N, (int)sizeof(real)>::BLOCK;
+
+// an element of the tile at (ix, iy) is inner when its four neighbours lie in
+// the tile (and in the grid)
+__device__ __forceinline__ bool tile_inner(int ix, int iy, int TX, int TY, int gx, int gy, int nx, int ny)
+{
+    return ix > 0 && ix < TX - 1 && iy > 0 && iy < TY - 1 && gx + 1 < nx && gy + 1 < ny;
+}
+
+template <class Eq, int N, class real>
+__global__ void __launch_bounds__((tile_block_v<Eq, N, real>)) k_tile(const StepArgs<real> a)
+{
+    using TG = TGeo<Eq::DIM, N, (int)sizeof(real)>;
+    constexpr int M = Eq::M, nd = TG::nd, nq = TG::nq, np = TG::np, TX = TG::TX, TY = TG::TY, EB = TG::EB;
+    constexpr int SB = elem_region<Eq, N, real>(), TC = 2 * M + 1;
+    __shared__ real tile_buf[EB * SB];
+    __shared__ real sh_fx[TY][TX + 1][nq][M];   // x face i of tile row iy (left of element i)
+    __shared__ real sh_gy[TY + 1][TX][nd][M];   // y face j of tile column ix (below element j)
+    const int vblock = blockIdx.x;
+    real uhp[M];
+    local_body<Eq, N, real, false, TG>(a, vblock, tile_buf, uhp);
+    __syncthreads();
+
+    const int ntx = (a.nx + TX - 1) / TX;
+    const int gx0 = (vblock % ntx) * TX, gy0 = (vblock / ntx) * TY;
+    const size_t nfx = (size_t)a.ny * (a.nx + 1) * nq, nfy = (size_t)(a.ny + 1) * a.nx * nd;
+    // ---- the faces inside the tile: time-averaged numerical flux, eqs.
+    //      numflux.general with D2 (D1: the U slots hold u^n traces) ----
+    constexpr int NXF = TY * (TX - 1) * nq, NYF = (TY - 1) * TX * nd;
+    for (int f = threadIdx.x; f < NXF + NYF; f += blockDim.x) {
+        int ixA, iyA, ixB, iyB, t, fpA, fpB;
+        if (f < NXF) {
+            t = f % nq;
+            const int r = f / nq;
+            ixA = r % (TX - 1); iyA = r / (TX - 1); ixB = ixA + 1; iyB = iyA;
+            fpA = nd + t; fpB = t;                  // right face of A, left face of B
+        } else {
+            const int f2 = f - NXF;
+            t = f2 % nd;
+            const int r = f2 / nd;
+            ixA = r % TX; iyA = r / TX; ixB = ixA; iyB = iyA + 1;
+            fpA = 3 * nd + t; fpB = 2 * nd + t;     // top face of A, bottom face of B
+        }
+        if (gx0 + ixB >= a.nx || gy0 + iyB >= a.ny) continue;   // B outside the grid (A is inside)
+        const real* tA = tile_buf + (iyA * TX + ixA) * SB + fpA * TC;
+        const real* tB = tile_buf + (iyB * TX + ixB) * SB + fpB * TC;
+        const real lam = fmax(tA[2 * M], tB[2 * M]);
+        const bool to_hbm = !tile_inner(ixA, iyA, TX, TY, gx0 + ixA, gy0 + iyA, a.nx, a.ny) ||
+                            !tile_inner(ixB, iyB, TX, TY, gx0 + ixB, gy0 + iyB, a.nx, a.ny);
+#pragma unroll
+        for (int v = 0; v < M; ++v) {
+            const real F = (real)0.5 * (tA[v] + tB[v]) - (real)0.5 * lam * (tB[M + v] - tA[M + v]);
+            if (f < NXF) {
+                sh_fx[iyA][ixB][t][v] = F;
+                if (to_hbm) a.Fx[v * nfx + ((size_t)(gy0 + iyA) * (a.nx + 1) + gx0 + ixB) * nq + t] = F;
+            } else {
+                sh_gy[iyB][ixA][t][v] = F;
+                if (to_hbm) a.Gy[v * nfy + ((size_t)(gy0 + iyB) * a.nx + gx0 + ixA) * nd + t] = F;
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- inner elements: the correction-function part of the FR update (eq.
+    //      crkfr.avg) from the LDS face fluxes, then the rest of the update;
+    //      edge elements: uHp to HBM for the update phase ----
+    const int le = threadIdx.x / np, k = threadIdx.x - le * np;
+    const int p = k % nd, q = k / nd, ix = le % TX, iy = le / TX;
+    const int gx = gx0 + ix, gy = gy0 + iy;
+    const bool act = gx < a.nx && gy < a.ny;
+    const bool in = act && tile_inner(ix, iy, TX, TY, gx, gy, a.nx, a.ny);
+    const int e = (gy < a.ny ? gy : a.ny - 1) * a.nx + (gx < a.nx ? gx : a.nx - 1);
+    const size_t nes = (size_t)a.ne, gi = (size_t)e * np + k;
+    if (act && !in) {
+#pragma unroll
+        for (int v = 0; v < M; ++v) a.uHp[(size_t)v * nes * np + gi] = uhp[v];
+    }
+    if (__any(in)) {   // whole wavefronts: the update reduces over each element's lanes
+        const real rdt = (real)*a.dt_dev, idx = (real)a.idx, idy = (real)a.idy;
+        real unew[M], FL[M], FR[M], GB[M], GT[M], dts[M];
+#pragma unroll
+        for (int v = 0; v < M; ++v) {
+            FL[v] = sh_fx[iy][ix][q][v];
+            FR[v] = sh_fx[iy][ix + 1][q][v];
+            GB[v] = sh_gy[iy][ix][p][v];
+            GT[v] = sh_gy[iy + 1][ix][p][v];
+            unew[v] = uhp[v] - rdt * idx * (FR[v] * a.R.bR[p] - FL[v] * a.R.bL[p])
+                    - rdt * idy * (GT[v] * a.R.bR[q] - GB[v] * a.R.bL[q]);
+            dts[v] = a.dtS ? a.dtS[(size_t)v * nes * np + gi] : (real)0;
+        }
+        update_finish<Eq, N, real, EB>(a, e, le, k, in, unew, FL, FR, GB, GT, dts, vblock);
+    }
+}
+
+// faces on tile edges (x: face lines i = 0, TX, 2 TX, ... and nx of every
+// row; y: j = 0, TY, ... and ny of every column), one lane per face point,
+// with the boundary conditions of k_face
+template <class Eq, int N, class real, int D>
+__global__ void __launch_bounds__(256) k_tile_face(const StepArgs<real> a)
+{
+    using TG = TGeo<Eq::DIM, N, (int)sizeof(real)>;
+    constexpr int nd = TG::nd, nq = TG::nq;
+    const unsigned tid = blockIdx.x * blockDim.x + threadIdx.x;
+    int eL, eR, exL, eyL, exR, eyR, t;
+    size_t outi;
+    if (D == 0) {
+        const int nlx = (a.nx + TG::TX - 1) / TG::TX + 1;
+        if (tid >= (unsigned)a.ny * (unsigned)nlx * nq) return;
+        t = (int)(tid % nq);
+        const unsigned line = tid / nq;
+        const int li = (int)(line % (unsigned)nlx), ey = (int)(line / (unsigned)nlx);
+        const int i = li * TG::TX < a.nx ? li * TG::TX : a.nx;
+        eL = i > 0 ? ey * a.nx + i - 1 : (a.bc[0] == BC_PERIODIC ? ey * a.nx + a.nx - 1 : -1);
+        eR = i < a.nx ? ey * a.nx + i : (a.bc[1] == BC_PERIODIC ? ey * a.nx : -1);
+        exL = i > 0 ? i - 1 : a.nx - 1; eyL = ey;
+        exR = i < a.nx ? i : 0; eyR = ey;
+        outi = ((size_t)ey * (a.nx + 1) + i) * nq + t;
+    } else {
+        const int nly = (a.ny + TG::TY - 1) / TG::TY + 1;
+        if (tid >= (unsigned)nly * (unsigned)a.nx * nd) return;
+        t = (int)(tid % nd);
+        const unsigned line = tid / nd;
+        const int ex = (int)(line % (unsigned)a.nx), lj = (int)(line / (unsigned)a.nx);
+        const int j = lj * TG::TY < a.ny ? lj * TG::TY : a.ny;
+        eL = j > 0 ? (j - 1) * a.nx + ex : (a.bc[2] == BC_PERIODIC ? (a.ny - 1) * a.nx + ex : -1);
+        eR = j < a.ny ? j * a.nx + ex : (a.bc[3] == BC_PERIODIC ? ex : -1);
+        exL = ex; eyL = j > 0 ? j - 1 : a.ny - 1;
+        exR = ex; eyR = j < a.ny ? j : 0;
+        outi = ((size_t)j * a.nx + ex) * nd + t;
+    }
+    if (eL >= 0 && eR >= 0) face_point<Eq, N, real, false, D, true>(a, t, eL, eR, exL, eyL, exR, eyR, outi, false);
+    else face_point<Eq, N, real, false, D, false>(a, t, eL, eR, exL, eyL, exR, eyR, outi, false);
+}
 
 // ----------------------------------------------------------------------------
 // batched kernels: persistent workgroups walk a table of (instance, block)
@@ -1902,7 +2208,13 @@ struct IoArgs {
     double l0_64[MAXND], l1_64[MAXND];
     unsigned long long* diag;
     unsigned long long* rate_bits;
+    double* stats;         // k_stats: per-block partial results [block][STAT_N]
 };
+
+// per-block partial results of k_stats: minima of the density (u for scalar
+// equations) and of P_1, P_2 over the nodes, the number of nodes with a
+// non-finite variable, and the block's share of the integral of the density
+enum { STAT_MINRHO = 0, STAT_MINP1, STAT_MINP2, STAT_NONFINITE, STAT_MASS, STAT_N };
 
 // import an FP64 nodal state: admissibility check, MP32 split into FP64
 // means + FP32 deviations, rate of eq. time.step.2d; one lane per node
@@ -1945,7 +2257,7 @@ __global__ void __launch_bounds__(256) k_import(const IoArgs<real> a)
 #pragma unroll
         for (int v = 0; v < M; ++v) {
             if constexpr (is_mp<real>()) a.u[(size_t)v * nes * np + gi] = (real)(u[v] - m[v]);
-            else a.u[(size_t)v * nes * np + gi] = (real)u[v];
+            else if ((const void*)a.uin != (const void*)a.u) a.u[(size_t)v * nes * np + gi] = (real)u[v];
         }
         if (k == 0) {
             if constexpr (is_mp<real>()) {
@@ -1996,6 +2308,57 @@ __global__ void __launch_bounds__(256) k_export(const IoArgs<real> a)
                 __syncthreads();
             }
         }
+    }
+}
+
+// statistics of the current state for the diagnostics (eq. uad.form at the
+// nodes, the integral of the density), one lane per node; each block writes
+// its partial results (tree reductions in a fixed order: deterministic)
+template <class Eq, int N, class real>
+__global__ void __launch_bounds__(256) k_stats(const IoArgs<real> a)
+{
+    using G = Geo<Eq::DIM, N>;
+    constexpr int M = Eq::M, DIM = Eq::DIM, nd = G::nd, np = G::np, EB = G::EB, BL = G::BLOCK, K = Eq::K;
+    __shared__ double sh[STAT_N][BL];
+    const int le = threadIdx.x / np, k = threadIdx.x - le * np;
+    const int p = k % nd, q = k / nd;
+    const int e0 = blockIdx.x * EB + le;
+    const bool act = e0 < a.ne;
+    const int e = act ? e0 : a.ne - 1;
+    const size_t nes = (size_t)a.ne, gi = (size_t)e * np + k;
+    double u[M];
+    bool fin = true;
+#pragma unroll
+    for (int v = 0; v < M; ++v) {
+        double val = (double)a.u[(size_t)v * nes * np + gi];
+        if constexpr (is_mp<real>()) val += a.ubar[(size_t)v * nes + e];
+        u[v] = val;
+        fin = fin && isfinite(val);
+    }
+    const double big = 1.79769313486231570e308;
+    const double area = a.dx * (DIM == 2 ? a.dy : 1.0);
+    double mass;
+    if constexpr (is_mp<real>()) mass = k == 0 ? a.ubar[e] * area : 0.0;   // the FP64 mean is held exactly
+    else mass = a.w64[p] * (DIM == 2 ? a.w64[q] : 1.0) * u[0] * area;
+    sh[STAT_MINRHO][threadIdx.x] = act ? u[0] : big;
+    sh[STAT_MINP1][threadIdx.x] = act && K > 1 ? Eq::adm(1 < K ? 1 : 0, u, a.phys) : big;
+    sh[STAT_MINP2][threadIdx.x] = act && K > 2 ? Eq::adm(2 < K ? 2 : 0, u, a.phys) : big;
+    sh[STAT_NONFINITE][threadIdx.x] = act && !fin ? 1.0 : 0.0;
+    sh[STAT_MASS][threadIdx.x] = act ? mass : 0.0;
+    __syncthreads();
+    for (int w = 1; w < BL; w <<= 1) {
+        if ((threadIdx.x & (2 * w - 1)) == 0 && threadIdx.x + w < BL) {
+#pragma unroll
+            for (int j = 0; j < STAT_N; ++j) {
+                const double x = sh[j][threadIdx.x], y = sh[j][threadIdx.x + w];
+                sh[j][threadIdx.x] = j < STAT_NONFINITE ? (y < x ? y : x) : x + y;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int j = 0; j < STAT_N; ++j) a.stats[(size_t)blockIdx.x * STAT_N + j] = sh[j][0];
     }
 }
 
@@ -2055,12 +2418,12 @@ __global__ void __launch_bounds__(256) k_features(const StepArgs<real> a)
     load_node<Eq>(a, np, e, k, un);
     sh_e[le][k] = Eq::ind(un, a.phys);
     __syncthreads();
-    real m = modal_coeff<DIM, N>(a.R, p, q, &sh_e[le][0], 1);
+    real m = modal_coeff<DIM, N>(a.R, p, q, &sh_e[le][0], 1, nd);
     sh_m2[le][k] = m * m;
     __syncthreads();
     if (k == 0 && act) {
         real en[nd], ft[N];
-        shell_energies<DIM, N>(&sh_m2[le][0], 1, en);
+        shell_energies<DIM, N>(&sh_m2[le][0], 1, nd, en);
         a.alpha_judge[e] = indicator_alpha<N>(en, a.alpha_min, a.alpha_max, a.ind_T, a.ind_kT);
         learned_features<N>(en, ft);
 #pragma unroll

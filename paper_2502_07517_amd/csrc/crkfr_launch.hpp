@@ -6,10 +6,10 @@
 namespace crkfr {
 
 enum { PH_LOCAL = 0, PH_FACE_X = 1, PH_FACE_Y = 2, PH_UPDATE = 3, PH_IMPORT = 4, PH_EXPORT = 5, PH_GHOST = 6,
-       PH_FEATURES = 7 };
+       PH_FEATURES = 7, PH_STATS = 8, PH_TILE = 9, PH_TILE_FACE_X = 10, PH_TILE_FACE_Y = 11, PH_EDGE_UPDATE = 12 };
 
 template <template <class> class EqT, int N, class real, bool LIM>
-static void launch_step_phase(int phase, const StepArgs<real>& a, hipStream_t st)
+static int launch_step_phase(int phase, const StepArgs<real>& a, hipStream_t st)
 {
     using Eq = EqT<real>;
     using G = Geo<Eq::DIM, N>;
@@ -38,7 +38,33 @@ static void launch_step_phase(int phase, const StepArgs<real>& a, hipStream_t st
     case PH_FEATURES:
         hipLaunchKernelGGL((k_features<Eq, N, real>), dim3(nb), dim3(G::BLOCK), 0, st, a);
         break;
+    case PH_TILE:
+    case PH_TILE_FACE_X:
+    case PH_TILE_FACE_Y:
+        // the tile-fused step: Euler 2D, elements of 4 or 16 points, limiter off
+        if constexpr (TGeo<Eq::DIM, N, (int)sizeof(real)>::OK && Eq::ID == 2 && !LIM) {
+            using TG = TGeo<Eq::DIM, N, (int)sizeof(real)>;
+            const int ntx = (a.nx + TG::TX - 1) / TG::TX, nty = (a.ny + TG::TY - 1) / TG::TY;
+            if (phase == PH_TILE) {
+                hipLaunchKernelGGL((k_tile<Eq, N, real>), dim3(ntx * nty), dim3(TG::BLOCK), 0, st, a);
+            } else if (phase == PH_TILE_FACE_X) {
+                long long tot = (long long)a.ny * (ntx + 1) * G::nq;
+                hipLaunchKernelGGL((k_tile_face<Eq, N, real, 0>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
+                                   st, a);
+            } else {
+                long long tot = (long long)(nty + 1) * a.nx * G::nd;
+                hipLaunchKernelGGL((k_tile_face<Eq, N, real, 1>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
+                                   st, a);
+            }
+            return 0;
+        }
+        return -1;
+    case PH_EDGE_UPDATE:
+        hipLaunchKernelGGL((k_update<Eq, N, real, LIM>), dim3((a.n_edge + G::EB - 1) / G::EB), dim3(G::BLOCK), 0,
+                           st, a);
+        break;
     }
+    return 0;
 }
 
 template <template <class> class EqT, int N, class real>
@@ -53,6 +79,9 @@ static void launch_io_phase(int phase, const IoArgs<real>& a, hipStream_t st)
         break;
     case PH_EXPORT:
         hipLaunchKernelGGL((k_export<Eq, N, real>), dim3(nb), dim3(G::BLOCK), 0, st, a);
+        break;
+    case PH_STATS:
+        hipLaunchKernelGGL((k_stats<Eq, N, real>), dim3(nb), dim3(G::BLOCK), 0, st, a);
         break;
     case PH_GHOST: {
         int tot = 2 * a.ny * G::nq + (Eq::DIM == 2 ? 2 * a.nx * G::nd : 0);
@@ -114,6 +143,32 @@ static int launch_batch(int N, bool lim, int phase, const StepArgs<real>* args, 
     return -1;
 }
 
+// tile of the tile-fused step (elements per direction), -1 when there is none
+template <template <class> class EqT, int N, class real>
+static int tile_shape_n(int* tx, int* ty)
+{
+    using Eq = EqT<real>;
+    using TG = TGeo<Eq::DIM, N, (int)sizeof(real)>;
+    if constexpr (TG::OK && Eq::ID == 2) {
+        *tx = TG::TX;
+        *ty = TG::TY;
+        return 0;
+    }
+    return -1;
+}
+
+template <template <class> class EqT>
+static int tile_shape(int N, int mp, int* tx, int* ty)
+{
+    switch (N) {
+    case 1: return mp ? tile_shape_n<EqT, 1, float>(tx, ty) : tile_shape_n<EqT, 1, double>(tx, ty);
+    case 2: return mp ? tile_shape_n<EqT, 2, float>(tx, ty) : tile_shape_n<EqT, 2, double>(tx, ty);
+    case 3: return mp ? tile_shape_n<EqT, 3, float>(tx, ty) : tile_shape_n<EqT, 3, double>(tx, ty);
+    case 4: return mp ? tile_shape_n<EqT, 4, float>(tx, ty) : tile_shape_n<EqT, 4, double>(tx, ty);
+    }
+    return -1;
+}
+
 template <template <class> class EqT, class real>
 static int geometry(int N, int* el, int* eu, int* nq)
 {
@@ -131,9 +186,8 @@ static int launch_step(int N, bool lim, int phase, const StepArgs<real>& a, hipS
 {
 #define CRKFR_CASE(NN)                                                            \
     case NN:                                                                      \
-        if (lim) launch_step_phase<EqT, NN, real, true>(phase, a, st);            \
-        else launch_step_phase<EqT, NN, real, false>(phase, a, st);               \
-        return 0;
+        if (lim) return launch_step_phase<EqT, NN, real, true>(phase, a, st);     \
+        return launch_step_phase<EqT, NN, real, false>(phase, a, st);
     switch (N) {
         CRKFR_CASE(1)
         CRKFR_CASE(2)
@@ -166,7 +220,8 @@ static int launch_io(int N, int phase, const IoArgs<real>& a, hipStream_t st)
                          int nwork, int grid, hipStream_t st);                                     \
     int name##_batch_f32(int N, bool lim, int phase, const StepArgs<float>* args, const int2* work,  \
                          int nwork, int grid, hipStream_t st);                                     \
-    int name##_geometry(int N, int* elems_local, int* elems_update, int* nq);
+    int name##_geometry(int N, int* elems_local, int* elems_update, int* nq);                      \
+    int name##_tile_shape(int N, int mp, int* tx, int* ty);
 #define CRKFR_DEFINE_EQ(name, EqT)                                                                  \
     int name##_step_f64(int N, bool lim, int phase, const StepArgs<double>& a, hipStream_t st)     \
     { return launch_step<EqT, double>(N, lim, phase, a, st); }                                      \
@@ -182,7 +237,8 @@ static int launch_io(int N, int phase, const IoArgs<real>& a, hipStream_t st)
     int name##_batch_f32(int N, bool lim, int phase, const StepArgs<float>* args, const int2* work,  \
                          int nwork, int grid, hipStream_t st)                                      \
     { return launch_batch<EqT, float>(N, lim, phase, args, work, nwork, grid, st); }                \
-    int name##_geometry(int N, int* el, int* eu, int* nq) { return geometry<EqT, double>(N, el, eu, nq); }
+    int name##_geometry(int N, int* el, int* eu, int* nq) { return geometry<EqT, double>(N, el, eu, nq); }   \
+    int name##_tile_shape(int N, int mp, int* tx, int* ty) { return tile_shape<EqT>(N, mp, tx, ty); }
 
 CRKFR_DECLARE_EQ(linadv1d)
 CRKFR_DECLARE_EQ(euler1d)

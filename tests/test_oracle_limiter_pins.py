@@ -114,7 +114,7 @@ def euler_c(u):
     return math.sqrt(GAMMA * euler_p(u) / u[0])
 
 
-def limit_by_hand(F, fLO, dt, sides):
+def limit_by_hand(F, fLO, dt, sides, frac=0.1):
     """The limiter of Sec. 4.3 written out: for density then pressure, the
     candidates u - k (F - adj) + dt S (side A, below the face) and
     u - k (adj - F) + dt S (side B) with F and with fLO; eps = 0.1 P(fLO
@@ -130,7 +130,7 @@ def limit_by_hand(F, fLO, dt, sides):
             sgn = 1.0 if side == "A" else -1.0
             cand = lambda G: np.asarray(u) - k * sgn * (G - np.asarray(adj)) + dt * np.asarray(S)
             Plo, PF = P(cand(fLO)), P(cand(F))
-            eps = 0.1 * Plo
+            eps = frac * Plo
             if PF < eps:
                 th = min(th, (Plo - eps) / (Plo - PF))
         F = th * F + (1.0 - th) * fLO
@@ -160,6 +160,46 @@ def test_flux_limiter_1d_face_by_hand():
     # after the density pass the density bound is attained exactly (no over-limiting)
     F1 = th_rho * F + (1.0 - th_rho) * fLO
     assert uB[0] + kB * (F1[0] - fLO[0]) == pytest.approx(0.1 * uB[0], rel=1e-13)
+
+
+@pytest.mark.parametrize("frac", [0.05, 0.3])
+def test_flux_limiter_margin_option(frac):
+    # eps_rel of the limiter options replaces the 0.1 of eps = 0.1 P(fLO candidate)
+    uA = np.array([1.0, 0.0, 2.5])
+    uB = np.array([0.125, 0.0, 0.25])
+    fLO = np.array([0.3, 0.5, 0.9])
+    F = fLO + np.array([-0.2, 0.05, -0.5])
+    z = np.zeros(3)
+    sides = {"A": (uA, fLO, z, 0.7), "B": (uB, fLO, z, 1.0)}
+    Fh, ths = limit_by_hand(F, fLO, 0.01, sides, frac=frac)
+    assert 0.0 < ths[0] < 1.0
+    cfg = O.RefConfig.make(O.EULER1D, 3, 8, eps_rel=frac)
+    Fo, th, bad = O.flux_limit_face(cfg, F, fLO, 0.01, A=sides["A"], B=sides["B"])
+    np.testing.assert_allclose(Fo, Fh, rtol=1e-14, atol=1e-15)
+
+
+@pytest.mark.parametrize("floor", [1e-3, 2e-2])
+@pytest.mark.parametrize("which", ["rho", "p"])
+def test_scaling_floor_option(floor, which):
+    # Zhang-Shu scaling with eps = min(eps_abs, P(mean)): a node below the floor
+    # ends exactly at it for the density (linear in the scaling factor), and at
+    # it within the bisection's resolution for the pressure; the mean is kept
+    N = 3
+    xi, w = gl01(N)
+    rho = np.array([1.0, 0.5, 1e-5 if which == "rho" else 0.7, 1.2])
+    p = np.array([1.0, 1e-6 if which == "p" else 0.6, 0.8, 0.9])
+    v = np.array([0.1, -0.3, 0.2, 0.0])
+    ue = np.stack([rho, rho * v, p / 0.4 + 0.5 * rho * v * v]).reshape(-1)
+    cfg = O.RefConfig.make(O.EULER1D, N, 4, scaling=1, eps_abs=floor)
+    out, th, bad = O.scale_element(cfg, ue)
+    assert not bad and 0.0 < th < 1.0
+    o = out.reshape(3, N + 1)
+    if which == "rho":
+        assert o[0].min() == pytest.approx(floor, rel=1e-12)
+    else:
+        pmin = min(euler_p(o[:, k]) for k in range(N + 1))
+        assert floor * (1 - 1e-9) <= pmin <= floor * (1 + 1e-9)
+    np.testing.assert_allclose((o * w).sum(axis=1), (ue.reshape(3, N + 1) * w).sum(axis=1), rtol=1e-14)
 
 
 def test_flux_limiter_1d_admissible_f_is_kept_and_missing_side():
