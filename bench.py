@@ -113,7 +113,7 @@ def _limited(s, C, indicator, net=None):
 
 
 # ---------------------------------------------------------------- the 512^2 single-instance step
-def run_c3(dtype, steps, warmup, limited=False, fused=False):
+def run_c3(dtype, steps, warmup, limited=False, path=None):
     """The 512^2 vortex step: graph-replayed steps for the rate, then the
     same number of eagerly enqueued steps with HIP events between the
     kernels on the solver's stream for the per-kernel times."""
@@ -125,7 +125,8 @@ def run_c3(dtype, steps, warmup, limited=False, fused=False):
                  stream=torch.cuda.current_stream().cuda_stream)
     if limited:
         _limited(s, C, C.IND_PAPER)
-    s.set_fused(fused)
+    if path is not None:
+        s.set_path(path)
     s.set_state(torch.from_numpy(np.ascontiguousarray(W.vortex2d(n, N_DEG, 0.0, DOM))).to("cuda"))
     s.advance(0.0, warmup)
     torch.cuda.synchronize()
@@ -146,11 +147,11 @@ def run_c3(dtype, steps, warmup, limited=False, fused=False):
     if rc != 0:
         raise RuntimeError(f"512^2 step ({dtype}, limited={limited}) failed: {d}")
     out = s.get_state()
-    used = s.fused_in_use()
+    used = s.path_in_use()
     s.close()
     return {"ms_per_step": ms, "dofsteps_per_s": n * n * (N_DEG + 1) ** 2 / (ms * 1e-3),
             "kernel_ms": kt.tolist(), "state": out, "n_troubled_last": int(d["n_troubled"]),
-            "tile_fused": bool(used)}
+            "path": ["split", "tile", "face_update"][used]}
 
 
 # ---------------------------------------------------------------- learned indicator for 2D Euler
@@ -483,7 +484,7 @@ def main():
 
     # ---- headline: the plain FP64 512^2 step, limiter off
     head = run_c3(C.FP64, args.steps, args.warmup)
-    print(f"# 512^2 FP64 limiter off: {head['ms_per_step']:.4f} ms/step, kernels (ms) "
+    print(f"# 512^2 FP64 limiter off ({head['path']}): {head['ms_per_step']:.4f} ms/step, kernels (ms) "
           f"{np.round(head['kernel_ms'], 4).tolist()}", flush=True)
     kms = head["kernel_ms"]
     dom = int(np.argmax(kms))
@@ -517,12 +518,17 @@ def main():
         "kernel_ms": dict(zip(PHASES, kms)),
         "roofline": roofline,
     }
-    tile = run_c3(C.FP64, args.steps, args.warmup, fused=True)
-    line["tile_fused_512"] = {k: v for k, v in tile.items() if k != "state"}
-    line["tile_fused_512"]["rel_linf_vs_split"] = float(np.abs(tile["state"] - head["state"]).max()
-                                                        / np.abs(head["state"]).max())
-    print(f"# 512^2 FP64 tile-fused: {tile['ms_per_step']:.4f} ms/step, kernels (ms) "
-          f"{np.round(tile['kernel_ms'], 4).tolist()}", flush=True)
+    # the other kernel paths of the same step (crkfr_set_path), for comparison
+    line["other_paths_512"] = {}
+    for name, pth in (("split", C.PATH_SPLIT), ("tile", C.PATH_TILE), ("face_update", C.PATH_FACE_UPDATE)):
+        if name == head["path"]:
+            continue
+        r = run_c3(C.FP64, args.steps, args.warmup, path=pth)
+        row = {k: v for k, v in r.items() if k != "state"}
+        row["rel_linf_vs_headline"] = float(np.abs(r["state"] - head["state"]).max() / np.abs(head["state"]).max())
+        line["other_paths_512"][name] = row
+        print(f"# 512^2 FP64 {name}: {r['ms_per_step']:.4f} ms/step, kernels (ms) "
+              f"{np.round(r['kernel_ms'], 4).tolist()}", flush=True)
     if args.part == "c3":
         print(json.dumps(line), flush=True)
         return

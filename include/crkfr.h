@@ -270,22 +270,32 @@ double crkfr_cfl_in_use(const crkfr_solver* s);
  * linear flux); points CRKFR_POINTS_*.  Returns -1 for bad arguments. */
 double crkfr_fourier_cfl(int N, int stages, int system, int dissipation, int points, double tol);
 
-/* Tile-fused step (on = 1) or the split step (on = 0, the default).  The
- * tile-fused step serves 2D Euler with N = 1 or 3, the limiter chain off and
- * the D2 dissipation: one workgroup per tile of elements (N = 3: 8 x 4 in
- * FP64, 8 x 8 in FP32 bulk; N = 1: 16 x 8, 16 x 16) runs the local cRK procedure, the time-averaged
- * numerical flux of the faces inside the tile and the whole update of the
- * elements whose four neighbours lie in the tile, out of LDS; then the faces
- * on tile edges (with the boundary conditions) and the update of the tile-edge
- * elements follow.  Results equal the split step's up to rounding order.
- * crkfr_fused_in_use returns 1 when the next step takes the tile-fused path. */
-int crkfr_set_fused(crkfr_solver* s, int on);
-int crkfr_fused_in_use(const crkfr_solver* s);
+/* Kernel path of a step (the results agree up to rounding order):
+ *  CRKFR_PATH_SPLIT: the local cRK procedure, the x faces, the y faces, the
+ *    update, one kernel each (face fluxes through HBM);
+ *  CRKFR_PATH_FACE_UPDATE (the default): the local procedure, then one
+ *    kernel in which each element's lanes compute its 4 (N+1) face fluxes
+ *    (every face computed by both neighbours, in the same arithmetic) and
+ *    update it;
+ *  CRKFR_PATH_TILE: for 2D Euler with N = 1 or 3, the limiter chain off and
+ *    the D2 dissipation, one workgroup per tile of elements (N = 3: 8 x 4 in
+ *    FP64, 8 x 8 in FP32 bulk; N = 1: 16 x 8, 16 x 16) runs the local
+ *    procedure, the faces inside the tile and the whole update of the
+ *    elements whose four neighbours lie in the tile out of LDS, then the
+ *    faces on tile edges and the update of the tile-edge elements follow;
+ *    other configurations take CRKFR_PATH_FACE_UPDATE.
+ * crkfr_path_in_use returns the path the next step takes.  Errors: EINVAL,
+ * ESTATE (the solver is a member of a live batch; batches take the face-update
+ * path for groups whose members all have it, the split path otherwise). */
+enum { CRKFR_PATH_SPLIT = 0, CRKFR_PATH_TILE = 1, CRKFR_PATH_FACE_UPDATE = 2 };
+int crkfr_set_path(crkfr_solver* s, int path);
+int crkfr_path_in_use(const crkfr_solver* s);
 
 /* Device time per kernel of the last step measured with HIP events (ms):
  * [0] local cRK, [1] x faces, [2] y faces, [3] update; with the tile-fused
  * step: [0] the tile kernel, [1], [2] the faces on tile edges, [3] the update
- * of the tile-edge elements.  Needs timing = 1. */
+ * of the tile-edge elements; with the face-update path [1] and [2] are 0.
+ * Needs timing = 1. */
 int crkfr_set_timing(crkfr_solver* s, int on);
 int crkfr_get_kernel_times(crkfr_solver* s, float* ms4);
 
@@ -296,7 +306,8 @@ int crkfr_get_kernel_times(crkfr_solver* s, float* ms4);
  * persistent workgroups walking a table of (instance, block) work items.  The
  * solvers stay owned by the caller, must have a state, and must not be used
  * on their own while the batch runs; call crkfr_batch_sync before reading
- * their state.  Batches run the split step (crkfr_set_fused does not apply).  Members must outlive the batch; the batch keeps the options
+ * their state.  Batches run the face-update path for groups whose members
+ * all have it and the split path otherwise (no tile-fused path).  Members must outlive the batch; the batch keeps the options
  * each member had at creation.  Each member keeps its own time step (eq.
  * time.step.2d). */
 typedef struct crkfr_batch crkfr_batch;

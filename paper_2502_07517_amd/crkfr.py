@@ -16,6 +16,7 @@ CENTRAL_EA, CENTRAL_AE = 0, 1
 PERIODIC, OUTFLOW, FARFIELD, REFLECT, INFLOW = 0, 1, 2, 3, 4
 FP64, MP32 = 0, 1
 BLEND_OFF, BLEND_FO, BLEND_MH = 0, 1, 2
+PATH_SPLIT, PATH_TILE, PATH_FACE_UPDATE = 0, 1, 2
 IND_PAPER, IND_CONST, IND_GIVEN, IND_LEARNED = 0, 1, 2, 3
 NVAR = {LINADV1D: 1, EULER1D: 3, EULER2D: 4, TENMOM2D: 6, BURGERS1D: 1, TENMOM1D: 6}
 EINADMISSIBLE_MEAN = -5
@@ -75,7 +76,7 @@ SYMBOLS = ["crkfr_create", "crkfr_destroy", "crkfr_set_limiter", "crkfr_set_sour
            "crkfr_mlp_get_box", "crkfr_mlp_fit_box", "crkfr_mlp_forward", "crkfr_mlp_loss_grad",
            "crkfr_mlp_train", "crkfr_batch_set_t_end", "crkfr_batch_set_timing", "crkfr_batch_phase_times",
            "crkfr_set_scheme", "crkfr_set_inflow", "crkfr_bind_state", "crkfr_state_ptr",
-           "crkfr_set_fused", "crkfr_fused_in_use"]
+           "crkfr_set_path", "crkfr_path_in_use"]
 
 _lib = None
 
@@ -103,8 +104,8 @@ def lib():
         L.crkfr_set_source.argtypes = [vp, ctypes.POINTER(Source)]
         L.crkfr_set_state.argtypes = [vp, vp, ip]
         L.crkfr_bind_state.argtypes = [vp, vp]
-        L.crkfr_set_fused.argtypes = [vp, ip]
-        L.crkfr_fused_in_use.argtypes = [vp]
+        L.crkfr_set_path.argtypes = [vp, ip]
+        L.crkfr_path_in_use.argtypes = [vp]
         L.crkfr_state_ptr.argtypes = [vp, ctypes.POINTER(vp)]
         L.crkfr_set_alpha.argtypes = [vp, vp, ip]
         L.crkfr_compute_dt.argtypes = [vp, dp]
@@ -177,6 +178,19 @@ def _ptr(a):
 
 def fourier_cfl(N, stages=0, system=1, tol=1e-10, dissipation=DISS_D2, points=POINTS_GL):
     return lib().crkfr_fourier_cfl(N, stages, system, dissipation, points, tol)
+
+
+def make_config(equation, N, nx, ny=1, *, bc=(PERIODIC,) * 4, dtype=FP64, domain=(0.0, 1.0, 0.0, 1.0),
+                gamma=1.4, adv=1.0, cfl=0.0, cs=0.98, points=0):
+    c = Config()
+    c.equation, c.N, c.nx, c.ny = equation, N, nx, ny
+    for i in range(4):
+        c.bc[i] = bc[i]
+    c.dtype = dtype
+    c.x0, c.x1, c.y0, c.y1 = domain
+    c.gamma, c.adv, c.cfl, c.cs = gamma, adv, cfl, cs
+    c.points = points
+    return c
 
 
 class Solver:
@@ -270,12 +284,12 @@ class Solver:
         self._bound = u
         _check(lib().crkfr_bind_state(self.h, ctypes.c_void_p(u.data_ptr())))
 
-    def set_fused(self, on=True):
-        """Tile-fused step where the configuration allows it, or the split step (default)."""
-        _check(lib().crkfr_set_fused(self.h, int(on)))
+    def set_path(self, path):
+        """Kernel path of a step: PATH_SPLIT, PATH_TILE or PATH_FACE_UPDATE (default)."""
+        _check(lib().crkfr_set_path(self.h, int(path)))
 
-    def fused_in_use(self):
-        return bool(lib().crkfr_fused_in_use(self.h))
+    def path_in_use(self):
+        return lib().crkfr_path_in_use(self.h)
 
     def state_ptr(self):
         """Device address of the current FP64 nodal state."""

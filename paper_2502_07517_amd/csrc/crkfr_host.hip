@@ -378,7 +378,7 @@ struct crkfr_solver {
     double* bound;           // caller-owned FP64 state bound as u[0] (crkfr_bind_state), or null
     int* edge_list;          // tile-fused step: elements at the tile edges (device), null without a tile shape
     int n_edge;
-    bool fused;              // use the tile-fused step where the configuration allows it
+    int path;                // CRKFR_PATH_*: split, tile-fused (where it serves), faces fused into the update
     bool timing;
     hipEvent_t ev[6];
     float kernel_ms[4];
@@ -621,10 +621,9 @@ static double default_cfl(const crkfr_solver* s)
     return c;
 }
 
-extern "C" int crkfr_create(const crkfr_config* cfg, void* hip_stream, crkfr_solver** out)
+// the checks of crkfr_create (no device call)
+static int validate_config(const crkfr_config* cfg)
 {
-    if (!cfg || !out) return fail(CRKFR_EINVAL, "null argument");
-    *out = nullptr;
     if (cfg->equation < 0 || cfg->equation > 5) return fail(CRKFR_EINVAL, "unknown equation");
     if (cfg->N < 1 || cfg->N > 4) return fail(CRKFR_EINVAL, "N must be in 1..4");
     const int dim = cfg->equation == CRKFR_EULER2D || cfg->equation == CRKFR_TENMOM2D ? 2 : 1;
@@ -648,6 +647,18 @@ extern "C" int crkfr_create(const crkfr_config* cfg, void* hip_stream, crkfr_sol
         if (nodes >= lim || fxp >= lim || fyp >= lim)
             return fail(CRKFR_EINVAL, "grid too large: nodes and face points per direction must stay below 2^31");
     }
+    return 0;
+}
+
+extern "C" int crkfr_create(const crkfr_config* cfg, void* hip_stream, crkfr_solver** out)
+{
+    if (!cfg || !out) return fail(CRKFR_EINVAL, "null argument");
+    *out = nullptr;
+    {
+        const int rc = validate_config(cfg);
+        if (rc) return rc;
+    }
+    const int dim = cfg->equation == CRKFR_EULER2D || cfg->equation == CRKFR_TENMOM2D ? 2 : 1;
 
     crkfr_solver* s = new crkfr_solver();
     std::memset(s, 0, sizeof(*s));
@@ -731,7 +742,7 @@ extern "C" int crkfr_create(const crkfr_config* cfg, void* hip_stream, crkfr_sol
         s->stats_blocks = grc == 0 ? (s->ne + eu - 1) / eu : 0;
         ok &= grc == 0 && alloc((void**)&s->stats, (size_t)s->stats_blocks * STAT_N * sizeof(double));
     }
-    s->fused = false;
+    s->path = CRKFR_PATH_FACE_UPDATE;
     {   // tile-fused step: the elements at the tile edges, in tile order
         int tx = 0, ty = 0;
         if (ok && cfg->equation == CRKFR_EULER2D && euler2d_tile_shape(cfg->N, cfg->dtype == CRKFR_MP32, &tx, &ty) == 0) {
@@ -1030,21 +1041,27 @@ static int check_learned(const crkfr_solver* s)
 }
 
 // the tile-fused step serves 2D Euler with elements of 4 or 16 points, the
-// limiter chain off and the D2 dissipation
-static bool use_tile(const crkfr_solver* s)
+// limiter chain off and the D2 dissipation; elsewhere that path takes the
+// update with the faces fused in
+static int path_in_use(const crkfr_solver* s)
 {
-    return s->fused && s->edge_list && s->lim.blend == CRKFR_BLEND_OFF && s->dissipation == CRKFR_DISS_D2;
+    if (s->path == CRKFR_PATH_TILE)
+        return s->edge_list && s->lim.blend == CRKFR_BLEND_OFF && s->dissipation == CRKFR_DISS_D2
+                   ? CRKFR_PATH_TILE : CRKFR_PATH_FACE_UPDATE;
+    return s->path;
 }
 
-extern "C" int crkfr_set_fused(crkfr_solver* s, int on)
+extern "C" int crkfr_set_path(crkfr_solver* s, int path)
 {
     if (!s) return fail(CRKFR_EINVAL, "null argument");
-    s->fused = on != 0;
+    if (path < CRKFR_PATH_SPLIT || path > CRKFR_PATH_FACE_UPDATE) return fail(CRKFR_EINVAL, "bad step path");
+    if (s->batch_refs > 0) return fail(CRKFR_ESTATE, "solver is a batch member: destroy the batch first");
+    s->path = path;
     invalidate_graph(s);
     return 0;
 }
 
-extern "C" int crkfr_fused_in_use(const crkfr_solver* s) { return s && use_tile(s) ? 1 : 0; }
+extern "C" int crkfr_path_in_use(const crkfr_solver* s) { return s ? path_in_use(s) : -1; }
 
 static int enqueue_step(crkfr_solver* s, double dt_fixed, double t_end)
 {
@@ -1063,15 +1080,17 @@ static int enqueue_step(crkfr_solver* s, double dt_fixed, double t_end)
     hipLaunchKernelGGL(k_prep, dim3(1), dim3(RATE_SLOTS), 0, s->stream, pa);
     const int in = s->cur, out = 1 - s->cur;
     const bool tm = s->timing;
-    const bool tile = use_tile(s);
+    const int path = path_in_use(s);
+    const bool tile = path == CRKFR_PATH_TILE, fu = path == CRKFR_PATH_FACE_UPDATE;
     if (tm) (void)hipEventRecord(s->ev[0], s->stream);
     int rc = dispatch_step(s, tile ? PH_TILE : PH_LOCAL, in, out);
     if (tm) (void)hipEventRecord(s->ev[1], s->stream);
-    if (!rc) rc = dispatch_step(s, tile ? PH_TILE_FACE_X : PH_FACE_X, in, out);
+    if (!rc && !fu) rc = dispatch_step(s, tile ? PH_TILE_FACE_X : PH_FACE_X, in, out);
     if (tm) (void)hipEventRecord(s->ev[2], s->stream);
-    if (!rc && s->dim == 2) rc = dispatch_step(s, tile ? PH_TILE_FACE_Y : PH_FACE_Y, in, out);
+    if (!rc && !fu && s->dim == 2) rc = dispatch_step(s, tile ? PH_TILE_FACE_Y : PH_FACE_Y, in, out);
     if (tm) (void)hipEventRecord(s->ev[3], s->stream);
-    if (!rc && (!tile || s->n_edge > 0)) rc = dispatch_step(s, tile ? PH_EDGE_UPDATE : PH_UPDATE, in, out);
+    if (!rc && (!tile || s->n_edge > 0))
+        rc = dispatch_step(s, tile ? PH_EDGE_UPDATE : (fu ? PH_UPDATE_FU : PH_UPDATE), in, out);
     if (tm) (void)hipEventRecord(s->ev[4], s->stream);
     s->cur = out;
     return rc;
@@ -1263,6 +1282,7 @@ extern "C" int crkfr_get_kernel_times(crkfr_solver* s, float* ms4)
 
 extern "C" const char* crkfr_last_error(void) { return g_last_error.c_str(); }
 
+
 // ----------------------------------------------------------------------------
 // batches: many instances advanced together, one launch per phase and degree
 // group (persistent workgroups over a table of work items), the steps
@@ -1270,6 +1290,7 @@ extern "C" const char* crkfr_last_error(void) { return g_last_error.c_str(); }
 // ----------------------------------------------------------------------------
 struct BatchGroup {
     int eq, N, lim;
+    bool fu;                  // faces fused into the update (every member on that path)
     bool mp;
     std::vector<int> members;
     void* d_args[2];          // StepArgs<real>[members] for state parity 0 / 1
@@ -1307,12 +1328,14 @@ static int eq_geometry(int eq, int N, int* el, int* eu, int* nq)
     return -1;
 }
 
-static int launch_group_phase(const crkfr_batch* b, const BatchGroup& g, int phase, int grid)
+static int launch_group_phase(const crkfr_batch* b, const BatchGroup& g, int wphase, int grid)
 {
-    if (g.nwork[phase] == 0) return 0;
+    if (g.nwork[wphase] == 0) return 0;
+    if (g.fu && (wphase == BPH_FACE_X || wphase == BPH_FACE_Y)) return 0;   // inside the update
     int rc = -1;
-    const int2* w = g.d_work[phase];
-    const int nw = g.nwork[phase];
+    const int2* w = g.d_work[wphase];
+    const int nw = g.nwork[wphase];
+    const int phase = g.fu && wphase == BPH_UPDATE ? BPH_UPDATE_FU : wphase;
     if (g.mp) {
         const StepArgs<float>* args = (const StepArgs<float>*)g.d_args[b->parity];
         switch (g.eq) {
@@ -1429,6 +1452,7 @@ extern "C" int crkfr_batch_create(crkfr_solver* const* solvers, int count, void*
         BatchGroup* g = nullptr;
         for (BatchGroup& gg : b->groups)
             if (gg.eq == s->cfg.equation && gg.N == s->cfg.N && gg.mp == s->mp && gg.lim == lim) g = &gg;
+        if (g && g->fu != (s->path == CRKFR_PATH_FACE_UPDATE)) g->fu = false;
         if (!g) {
             BatchGroup ng;
             std::memset(ng.d_args, 0, sizeof(ng.d_args));
@@ -1439,6 +1463,7 @@ extern "C" int crkfr_batch_create(crkfr_solver* const* solvers, int count, void*
             ng.N = s->cfg.N;
             ng.mp = s->mp;
             ng.lim = lim;
+            ng.fu = s->path == CRKFR_PATH_FACE_UPDATE;
             b->groups.push_back(ng);
             g = &b->groups.back();
         }
@@ -1636,7 +1661,7 @@ extern "C" int crkfr_batch_autotune(crkfr_batch* b, int reps)
     hipLaunchKernelGGL(k_prep_batch, dim3((unsigned)b->s.size()), dim3(RATE_SLOTS), 0, b->stream, b->d_prep);
     for (BatchGroup& g : b->groups)
         for (int ph = 0; ph < 4; ++ph) {
-            if (g.nwork[ph] == 0) continue;
+            if (g.nwork[ph] == 0 || (g.fu && (ph == BPH_FACE_X || ph == BPH_FACE_Y))) continue;
             const int cands[] = {0, ncu, 2 * ncu, 4 * ncu, 8 * ncu, 16 * ncu};
             float best = 1e30f;
             int best_grid = 0;

@@ -1217,9 +1217,14 @@ __device__ __forceinline__ double lo_factor(const StepArgs<real>& a, int d, int 
 // ----------------------------------------------------------------------------
 // k_face: one lane per face point of direction D
 // ----------------------------------------------------------------------------
-template <class Eq, int N, class real, bool LIM, int D, bool INTERIOR>
+// FUSED: called by the element on either side of the face (the update with
+// the faces fused in): both smoothed alphas are computed here, the flux goes
+// to Fret, and the limiter counters are kept only where count is set (one
+// side per face)
+template <class Eq, int N, class real, bool LIM, int D, bool INTERIOR, bool FUSED = false>
 __device__ __forceinline__ void face_point(const StepArgs<real>& a, int t, int eL, int eR, int exL, int eyL, int exR,
-                                           int eyR, size_t outi, bool owner);
+                                           int eyR, size_t outi, bool owner, real* Fret = nullptr,
+                                           bool count = true);
 
 template <class Eq, int N, class real, bool LIM, int D>
 __device__ void face_body(const StepArgs<real>& a, int vblock)
@@ -1261,9 +1266,9 @@ __device__ void face_body(const StepArgs<real>& a, int vblock)
     else face_point<Eq, N, real, LIM, D, false>(a, t, eL, eR, exL, eyL, exR, eyR, outi, owner);
 }
 
-template <class Eq, int N, class real, bool LIM, int D, bool INTERIOR>
+template <class Eq, int N, class real, bool LIM, int D, bool INTERIOR, bool FUSED>
 __device__ __forceinline__ void face_point(const StepArgs<real>& a, int t, int eL, int eR, int exL, int eyL, int exR,
-                                           int eyR, size_t outi, bool owner)
+                                           int eyR, size_t outi, bool owner, real* Fret, bool count)
 {
     using G = Geo<Eq::DIM, N>;
     constexpr int M = Eq::M, nd = G::nd, nq = G::nq, np = G::np, K = Eq::K;
@@ -1444,10 +1449,10 @@ __device__ __forceinline__ void face_point(const StepArgs<real>& a, int t, int e
         // of the face to the left of each element stores that element's;
         // the y faces and the update read them
         double aA, aB;
-        if constexpr (D == 0) {
+        if constexpr (D == 0 || FUSED) {
             aA = hA ? alpha_smoothed(a, eL, exL, eyL, Eq::DIM) : 0.0;
             aB = hB ? alpha_smoothed(a, eR, exR, eyR, Eq::DIM) : 0.0;
-            if (owner) a.alpha_out[eR] = aB;
+            if (!FUSED && owner) a.alpha_out[eR] = aB;
         } else {
             aA = hA ? a.alpha_out[eL] : 0.0;
             aB = hB ? a.alpha_out[eR] : 0.0;
@@ -1511,20 +1516,58 @@ __device__ __forceinline__ void face_point(const StepArgs<real>& a, int t, int e
                 }
 #pragma unroll
                 for (int v = 0; v < M; ++v) F[v] = (real)Fd[v];
-                if (theta_face < 1.0) {
+                if (theta_face < 1.0 && count) {
                     atomicAdd(&a.diag[D_FLUXLIM], 1ull);
                     atomic_min_pos(&a.diag[D_THFLUX], theta_face);
                 }
-                if (bad) atomicAdd(&a.diag[D_LOBAD], 1ull);
+                if (bad && count) atomicAdd(&a.diag[D_LOBAD], 1ull);
             }
         }
     }
 #undef TRA
 #undef TRB
-    real* out = D == 0 ? a.Fx : a.Gy;
-    const size_t nf = D == 0 ? (size_t)a.ny * (a.nx + 1) * nq : (size_t)(a.ny + 1) * a.nx * nd;
+    if constexpr (FUSED) {
 #pragma unroll
-    for (int v = 0; v < M; ++v) out[(size_t)v * nf + outi] = F[v];
+        for (int v = 0; v < M; ++v) Fret[v] = F[v];
+    } else {
+        real* out = D == 0 ? a.Fx : a.Gy;
+        const size_t nf = D == 0 ? (size_t)a.ny * (a.nx + 1) * nq : (size_t)(a.ny + 1) * a.nx * nd;
+#pragma unroll
+        for (int v = 0; v < M; ++v) out[(size_t)v * nf + outi] = F[v];
+    }
+}
+
+// the time-averaged numerical flux at face point fp of element (ex, ey) of
+// the update with the faces fused in (fp = side (nd) + t: sides left, right,
+// bottom, top); the element on the upper side of a face keeps its limiter
+// counters (and the element below a boundary face without an upper side)
+template <class Eq, int N, class real, bool LIM>
+__device__ __forceinline__ void elem_face_flux(const StepArgs<real>& a, int ex, int ey, int fp, real* F)
+{
+    using G = Geo<Eq::DIM, N>;
+    constexpr int nd = G::nd;
+    const int sd = Eq::DIM == 2 ? fp / nd : fp, t = Eq::DIM == 2 ? fp % nd : 0, side = sd & 1;
+    if (sd < 2) {
+        const int i = ex + side;   // x face i of row ey
+        const int eL = i > 0 ? ey * a.nx + i - 1 : (a.bc[0] == BC_PERIODIC ? ey * a.nx + a.nx - 1 : -1);
+        const int eR = i < a.nx ? ey * a.nx + i : (a.bc[1] == BC_PERIODIC ? ey * a.nx : -1);
+        const int exL = i > 0 ? i - 1 : a.nx - 1, exR = i < a.nx ? i : 0;
+        const bool count = side == 0 || eR < 0;
+        if (eL >= 0 && eR >= 0)
+            face_point<Eq, N, real, LIM, 0, true, true>(a, t, eL, eR, exL, ey, exR, ey, 0, false, F, count);
+        else
+            face_point<Eq, N, real, LIM, 0, false, true>(a, t, eL, eR, exL, ey, exR, ey, 0, false, F, count);
+    } else if constexpr (Eq::DIM == 2) {
+        const int j = ey + side;   // y face j of column ex
+        const int eL = j > 0 ? (j - 1) * a.nx + ex : (a.bc[2] == BC_PERIODIC ? (a.ny - 1) * a.nx + ex : -1);
+        const int eR = j < a.ny ? j * a.nx + ex : (a.bc[3] == BC_PERIODIC ? ex : -1);
+        const int eyL = j > 0 ? j - 1 : a.ny - 1, eyR = j < a.ny ? j : 0;
+        const bool count = side == 0 || eR < 0;
+        if (eL >= 0 && eR >= 0)
+            face_point<Eq, N, real, LIM, 1, true, true>(a, t, eL, eR, ex, eyL, ex, eyR, 0, false, F, count);
+        else
+            face_point<Eq, N, real, LIM, 1, false, true>(a, t, eL, eR, ex, eyL, ex, eyR, 0, false, F, count);
+    }
 }
 
 // ----------------------------------------------------------------------------
@@ -1630,8 +1673,11 @@ __device__ __forceinline__ void update_finish(const StepArgs<real>& a, int e, in
                                               const real* GT, const real* dts, int vblock);
 
 // k_update: one lane per node; elements from 0 in order, or (tile-fused step)
-// the list of elements at the edges of the tiles
-template <class Eq, int N, class real, bool LIM>
+// the list of elements at the edges of the tiles.  FU: the faces fused in --
+// the element's lanes first compute its 4 (N+1) face fluxes (each face is
+// computed by the elements on both sides, in the same arithmetic) and its
+// smoothed alpha; without FU the face phases have stored them.
+template <class Eq, int N, class real, bool LIM, bool FU = false>
 __device__ void update_body(const StepArgs<real>& a, int vblock)
 {
     using G = Geo<Eq::DIM, N>;
@@ -1639,6 +1685,8 @@ __device__ void update_body(const StepArgs<real>& a, int vblock)
     __shared__ real sh_u[EB][np][M];
     __shared__ real sh_f[EB][np][M];
     __shared__ real sh_g[EB][np][DIM == 2 ? M : 1];
+    constexpr int NFP = DIM == 2 ? 4 * nd : 2;
+    __shared__ real sh_F[FU ? EB : 1][NFP][M];
 
     const Phys& P = a.phys;
     const int le = threadIdx.x / np, k = threadIdx.x - le * np;
@@ -1655,15 +1703,24 @@ __device__ void update_body(const StepArgs<real>& a, int vblock)
     const size_t iL = ((size_t)ey * (a.nx + 1) + ex) * nq + q, iR = iL + nq;
     const size_t iB = ((size_t)ey * a.nx + ex) * nd + p, iT = iB + (size_t)a.nx * nd;
 
+    if constexpr (FU) {
+        // the element's face fluxes into LDS, face point fp = side (nd) + t
+#pragma unroll
+        for (int j = 0; j < (NFP + np - 1) / np; ++j) {
+            const int fp = k + j * np;
+            if (fp < NFP) elem_face_flux<Eq, N, real, LIM>(a, ex, ey, fp, sh_F[le][fp]);
+        }
+        elem_sync<np>();
+    }
     real uH[M], FLv[M], FRv[M], GBv[M], GTv[M], dts[M];
 #pragma unroll
     for (int v = 0; v < M; ++v) {
-        FLv[v] = a.Fx[v * nfx + iL];
-        FRv[v] = a.Fx[v * nfx + iR];
+        FLv[v] = FU ? sh_F[FU ? le : 0][DIM == 2 ? q : 0][v] : a.Fx[v * nfx + iL];
+        FRv[v] = FU ? sh_F[FU ? le : 0][DIM == 2 ? nd + q : 1][v] : a.Fx[v * nfx + iR];
         real val = a.uHp[v * nes * np + gi] - rdt * idx * (FRv[v] * a.R.bR[p] - FLv[v] * a.R.bL[p]);
         if constexpr (DIM == 2) {
-            GBv[v] = a.Gy[v * nfy + iB];
-            GTv[v] = a.Gy[v * nfy + iT];
+            GBv[v] = FU ? sh_F[FU ? le : 0][2 * nd + p][v] : a.Gy[v * nfy + iB];
+            GTv[v] = FU ? sh_F[FU ? le : 0][3 * nd + p][v] : a.Gy[v * nfy + iT];
             val -= rdt * idy * (GTv[v] * a.R.bR[q] - GBv[v] * a.R.bL[q]);
         } else {
             GBv[v] = 0;
@@ -1677,7 +1734,14 @@ __device__ void update_body(const StepArgs<real>& a, int vblock)
     for (int v = 0; v < M; ++v) unew[v] = uH[v];
 
     if constexpr (LIM) {
-        const double al = a.alpha_out[e];            // smoothed by the x-face phase
+        // smoothed by the x-face phase, or here with the faces fused in
+        double al;
+        if constexpr (FU) {
+            al = alpha_smoothed(a, e, ex, ey, DIM);
+            if (k == 0 && act) a.alpha_out[e] = al;
+        } else {
+            al = a.alpha_out[e];
+        }
         if (k == 0 && act && al > 0.0) atomicAdd(&a.diag[D_TROUBLED], 1ull);
         const bool any = elem_any<np>(act && al > 0.0);
         if (any) {
@@ -1729,12 +1793,12 @@ __device__ void update_body(const StepArgs<real>& a, int vblock)
                 const real ralpha = (real)al;
 #pragma unroll
                 for (int v = 0; v < M; ++v) {
-                    real fm = p == 0 ? a.Fx[v * nfx + iL] : sh_f[le][k - 1][v];
-                    real fp = p == N ? a.Fx[v * nfx + iR] : fxp[v];
+                    real fm = p == 0 ? FLv[v] : sh_f[le][k - 1][v];
+                    real fp = p == N ? FRv[v] : fxp[v];
                     real uL = un[v] - rdt / (a.R.w[p] * (real)a.dx) * (fp - fm);
                     if constexpr (DIM == 2) {
-                        real gm = q == 0 ? a.Gy[v * nfy + iB] : sh_g[le][k - nd][v];
-                        real gp = q == N ? a.Gy[v * nfy + iT] : gyp[v];
+                        real gm = q == 0 ? GBv[v] : sh_g[le][k - nd][v];
+                        real gp = q == N ? GTv[v] : gyp[v];
                         uL -= rdt / (a.R.w[q] * (real)a.dy) * (gp - gm);
                     }
                     if (a.dtS) uL += a.dtS[(size_t)v * nes * np + gi];
@@ -1906,8 +1970,11 @@ __global__ void __launch_bounds__(256) k_local(const StepArgs<real> a)
 template <class Eq, int N, class real, bool LIM, int D>
 __global__ void __launch_bounds__(256) k_face(const StepArgs<real> a) { face_body<Eq, N, real, LIM, D>(a, blockIdx.x); }
 
-template <class Eq, int N, class real, bool LIM>
-__global__ void __launch_bounds__(256) k_update(const StepArgs<real> a) { update_body<Eq, N, real, LIM>(a, blockIdx.x); }
+template <class Eq, int N, class real, bool LIM, bool FU = false>
+__global__ void __launch_bounds__(256) k_update(const StepArgs<real> a)
+{
+    update_body<Eq, N, real, LIM, FU>(a, blockIdx.x);
+}
 
 // ----------------------------------------------------------------------------
 // tile-fused step (limiter off): one workgroup per tile of TX x TY elements,
@@ -2070,7 +2137,7 @@ __global__ void __launch_bounds__(256) k_tile_face(const StepArgs<real> a)
 // work items of one phase over every instance of one degree; each instance's
 // arguments are read from device memory (block-uniform, scalar loads)
 // ----------------------------------------------------------------------------
-enum { BPH_LOCAL = 0, BPH_FACE_X = 1, BPH_FACE_Y = 2, BPH_UPDATE = 3 };
+enum { BPH_LOCAL = 0, BPH_FACE_X = 1, BPH_FACE_Y = 2, BPH_UPDATE = 3, BPH_UPDATE_FU = 4 };
 
 template <class Eq, int N, class real, bool LIM, int PH>
 __device__ __forceinline__ void batch_item(const StepArgs<real>& a, int block)
@@ -2078,6 +2145,7 @@ __device__ __forceinline__ void batch_item(const StepArgs<real>& a, int block)
     if constexpr (PH == BPH_LOCAL) local_body<Eq, N, real, LIM>(a, block);
     else if constexpr (PH == BPH_FACE_X) face_body<Eq, N, real, LIM, 0>(a, block);
     else if constexpr (PH == BPH_FACE_Y) face_body<Eq, N, real, LIM, 1>(a, block);
+    else if constexpr (PH == BPH_UPDATE_FU) update_body<Eq, N, real, LIM, true>(a, block);
     else update_body<Eq, N, real, LIM>(a, block);
 }
 
@@ -2093,7 +2161,7 @@ template <class real, int PH>
 __device__ __forceinline__ const StepArgs<real>& table_args(const StepArgs<real>* args, int i)
 {
 #if defined(__HIP_DEVICE_COMPILE__)
-    if constexpr (PH != BPH_UPDATE) {
+    if constexpr (PH != BPH_UPDATE && PH != BPH_UPDATE_FU) {
         using CArgs = const __attribute__((address_space(4))) StepArgs<real>;
         return ((CArgs*)args)[i];
     }
@@ -2118,7 +2186,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(batch_
 k_batch(const StepArgs<real>* __restrict__ args, const int2* __restrict__ work, int nwork)
 {
     if ((int)blockIdx.x >= nwork) return;
-    const int2 it = work[PH == BPH_LOCAL ? xcd_block(blockIdx.x, nwork) : (int)blockIdx.x];
+    const int2 it = work[PH == BPH_LOCAL || PH == BPH_UPDATE_FU ? xcd_block(blockIdx.x, nwork) : (int)blockIdx.x];
     batch_item<Eq, N, real, LIM, PH>(table_args<real, PH>(args, it.x), it.y);
 }
 
@@ -2129,7 +2197,7 @@ __global__ void __launch_bounds__(256) k_batch_persistent(const StepArgs<real>* 
                                                            const int2* __restrict__ work, int nwork)
 {
     for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
-        const int2 it = work[PH == BPH_LOCAL ? xcd_block(w, nwork) : w];
+        const int2 it = work[PH == BPH_LOCAL || PH == BPH_UPDATE_FU ? xcd_block(w, nwork) : w];
         batch_item<Eq, N, real, LIM, PH>(table_args<real, PH>(args, it.x), it.y);
         __syncthreads();   // LDS of this work item is reused by the next
     }

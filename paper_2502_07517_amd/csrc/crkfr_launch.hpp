@@ -6,7 +6,8 @@
 namespace crkfr {
 
 enum { PH_LOCAL = 0, PH_FACE_X = 1, PH_FACE_Y = 2, PH_UPDATE = 3, PH_IMPORT = 4, PH_EXPORT = 5, PH_GHOST = 6,
-       PH_FEATURES = 7, PH_STATS = 8, PH_TILE = 9, PH_TILE_FACE_X = 10, PH_TILE_FACE_Y = 11, PH_EDGE_UPDATE = 12 };
+       PH_FEATURES = 7, PH_STATS = 8, PH_TILE = 9, PH_TILE_FACE_X = 10, PH_TILE_FACE_Y = 11, PH_EDGE_UPDATE = 12,
+       PH_UPDATE_FU = 13 };
 
 template <template <class> class EqT, int N, class real, bool LIM>
 static int launch_step_phase(int phase, const StepArgs<real>& a, hipStream_t st)
@@ -34,6 +35,9 @@ static int launch_step_phase(int phase, const StepArgs<real>& a, hipStream_t st)
         break;
     case PH_UPDATE:
         hipLaunchKernelGGL((k_update<Eq, N, real, LIM>), dim3(nb), dim3(G::BLOCK), 0, st, a);
+        break;
+    case PH_UPDATE_FU:
+        hipLaunchKernelGGL((k_update<Eq, N, real, LIM, true>), dim3(nb), dim3(G::BLOCK), 0, st, a);
         break;
     case PH_FEATURES:
         hipLaunchKernelGGL((k_features<Eq, N, real>), dim3(nb), dim3(G::BLOCK), 0, st, a);
@@ -107,7 +111,8 @@ static void launch_batch_phase(int phase, const StepArgs<real>* args, const int2
 {
     using Eq = EqT<real>;
     const dim3 g(grid > 0 ? grid : nwork);
-    const int bl = phase == BPH_LOCAL ? LGeo<Eq::DIM, N>::BLOCK : (phase == BPH_UPDATE ? Geo<Eq::DIM, N>::BLOCK : 256);
+    const int bl = phase == BPH_LOCAL ? LGeo<Eq::DIM, N>::BLOCK
+                 : (phase == BPH_UPDATE || phase == BPH_UPDATE_FU ? Geo<Eq::DIM, N>::BLOCK : 256);
 #define CRKFR_BATCH_LAUNCH(PH)                                                                        \
     if (grid > 0)                                                                                     \
         hipLaunchKernelGGL((k_batch_persistent<Eq, N, real, LIM, PH>), g, dim3(bl), 0, st, args, work, nwork); \
@@ -120,6 +125,7 @@ static void launch_batch_phase(int phase, const StepArgs<real>* args, const int2
         if constexpr (Eq::DIM == 2) { CRKFR_BATCH_LAUNCH(BPH_FACE_Y) }
         break;
     case BPH_UPDATE: CRKFR_BATCH_LAUNCH(BPH_UPDATE) break;
+    case BPH_UPDATE_FU: CRKFR_BATCH_LAUNCH(BPH_UPDATE_FU) break;
     }
 #undef CRKFR_BATCH_LAUNCH
 }

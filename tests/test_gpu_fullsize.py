@@ -20,6 +20,7 @@ import pytest
 
 import oracle as O
 from gpu_cases import rel_l1, rel_linf
+import riemann_exact
 from oracle_runs import cfl_for
 from paper_2502_07517_amd import crkfr as C
 from paper_2502_07517_amd import workloads as W
@@ -101,7 +102,7 @@ def test_euler1d_riemann_2000_elements():
         g32.step(dt)
     e32 = rel_l1(u, g32.get_state().reshape(u.shape))
     _say(f"Riemann 2000 elements, {steps} steps: FP64 rel. L1 {e64:.2e}, FP32 bulk {e32:.2e}")
-    assert e64 <= 1e-6 and e32 <= 1e-3
+    assert e64 <= 1e-12 and e32 <= 1e-3
 
 
 def test_vortex_512sq_one_step_and_runs():
@@ -227,20 +228,47 @@ def test_batch_256_uneven_instances_full_size():
         # the states near the boundary are constant per quadrant, so the
         # change over 3 steps is small against the total
         assert np.all(np.isfinite(m)) and abs(m[0] - masses0[i][0]) < 1e-2 * masses0[i][0]
-    # the smallest member against the FP64 oracle with the same network, three steps
-    i = sample[0]
-    sp = specs[i]
-    N, n = sp["N"], sp["n"]
-    net, p = nets[N]
-    cfg = O.RefConfig.make(O.EULER2D, N, n, n, bc=FF, cfl=cfl_for(N), indicator=O.IND_LEARNED, **LIM)
-    lo, hi = net.get_box()
-    cfg.set_mlp(net.dims, p.astype(np.float64), lo.astype(np.float64), hi.astype(np.float64))
-    u = W.euler2d_quadrants(sp["seed"] % 1000, n, N)
-    ghost = O.boundary_traces(cfg, u)
-    for _ in range(3):
-        u, _, _, st = O.step(cfg, u, O.compute_dt(cfg, u), ghost=ghost)
-        assert st == 0
-    e = rel_l1(u, members[i].get_state().reshape(u.shape))
-    _say(f"batch: smallest member n={n} N={N} FP32 bulk vs FP64 oracle rel. L1 {e:.2e}")
-    assert e <= 1e-3
+    # the smallest member of each degree group against the FP64 oracle with the
+    # same network, three steps
+    for N in (2, 3, 4):
+        i = min((j for j in range(len(specs)) if specs[j]["N"] == N), key=lambda j: specs[j]["n"])
+        sp = specs[i]
+        n = sp["n"]
+        net, p = nets[N]
+        cfg = O.RefConfig.make(O.EULER2D, N, n, n, bc=FF, cfl=cfl_for(N), indicator=O.IND_LEARNED, **LIM)
+        lo, hi = net.get_box()
+        cfg.set_mlp(net.dims, p.astype(np.float64), lo.astype(np.float64), hi.astype(np.float64))
+        u = W.euler2d_quadrants(sp["seed"] % 1000, n, N)
+        ghost = O.boundary_traces(cfg, u)
+        for _ in range(3):
+            u, _, _, st = O.step(cfg, u, O.compute_dt(cfg, u), ghost=ghost)
+            assert st == 0
+        e = rel_l1(u, members[i].get_state().reshape(u.shape))
+        _say(f"batch: smallest N={N} member n={n}, FP32 bulk vs FP64 oracle rel. L1 {e:.2e}")
+        assert e <= 1e-3
     b.close()
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_riemann_2000_fp32_bulk_error_against_exact_solution(seed):
+    """The 1D Euler Riemann workload (N = 4, 2000 elements, limiter chain,
+    t = 0.05, device time steps): the density L1 error of FP32 bulk against
+    the exact Riemann solution is within 5 % of the FP64 step's error (the
+    FP32 roundoff stays far below the discretization error at discontinuities)."""
+    N, nx, t_end = 4, 2000, 0.05
+    L, R = W.riemann_states_1d(seed)
+    x = W.node_coords_1d(nx, N, 0, 1)
+    rex = riemann_exact.density_profile(L, R, x, t_end, x0=0.5 + W.OFF_FACE / nx)
+    _, w = O.gl(N)
+    errs = {}
+    for name, dtype in (("fp64", C.FP64), ("mp32", C.MP32)):
+        s = C.Solver(C.EULER1D, N, nx, bc=FF, dtype=dtype, cfl=cfl_for(N))
+        s.set_limiter(**LIM)
+        s.set_state(W.euler1d_riemann(seed, nx, N))
+        s.advance(t_end, 10 ** 6)
+        d, rc = s.get_diag()
+        assert rc == 0 and abs(d["t"] - t_end) < 1e-14 and d["n_mean_inadmissible"] == 0
+        u = s.get_state()
+        errs[name] = float((np.abs(u[0] - rex) * w).sum() / nx)
+    _say(f"Riemann seed {seed}: density L1 vs exact FP64 {errs['fp64']:.4e}, FP32 bulk {errs['mp32']:.4e}")
+    assert abs(errs["mp32"] - errs["fp64"]) <= 0.05 * errs["fp64"]

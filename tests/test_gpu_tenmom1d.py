@@ -100,7 +100,7 @@ def test_two_rarefaction_full_runs():
     assert rc == 0 and abs(d["t"] - 0.1) < 1e-14
     ug = gpu.get_state().reshape(u.shape)
     print(f"two rarefaction 100 elements: rel. L1 vs oracle {rel_l1(u, ug):.2e}")
-    assert rel_l1(u, ug) <= 1e-6
+    assert rel_l1(u, ug) <= 1e-12
     _, g5 = _pair(3, 500, lim=LIM)
     g5.set_state(W.tenmom1d_two_rarefaction(500, 3))
     g5.advance(0.1, 100000)
