@@ -1545,8 +1545,32 @@ template <class Eq, int N, class real, bool LIM>
 __device__ __forceinline__ void elem_face_flux(const StepArgs<real>& a, int ex, int ey, int fp, real* F)
 {
     using G = Geo<Eq::DIM, N>;
-    constexpr int nd = G::nd;
+    constexpr int M = Eq::M, nd = G::nd, nq = G::nq;
     const int sd = Eq::DIM == 2 ? fp / nd : fp, t = Eq::DIM == 2 ? fp % nd : 0, side = sd & 1;
+    if constexpr (!LIM) {
+        // an interior face without limiter or D-CSX: the Rusanov-type flux of
+        // the time-averaged traces, with the direction a run-time operand, so
+        // that the lanes of the x and the y faces of a wavefront run one
+        // instruction stream
+        const bool xd = sd < 2;
+        const int i = xd ? ex + side : ey + side;
+        const int n = xd ? a.nx : a.ny;
+        const int b = i == 0 ? (xd ? a.bc[0] : a.bc[2]) : i == n ? (xd ? a.bc[1] : a.bc[3]) : BC_PERIODIC;
+        if (a.dissipation != DISS_DCSX && b == BC_PERIODIC) {
+            const int iL = i > 0 ? i - 1 : n - 1, iR = i < n ? i : 0;
+            const int eL = xd ? ey * a.nx + iL : iL * a.nx + ex, eR = xd ? ey * a.nx + iR : iR * a.nx + ex;
+            const int npt = xd ? nq : nd;
+            const real* trb = xd ? a.trx : a.trY;
+            const size_t st = (size_t)a.ne * npt;
+            const real* A = trb + (size_t)a.C * st + (size_t)eL * npt + t;   // traces of eL on its upper side
+            const real* B = trb + (size_t)eR * npt + t;                      // traces of eR on its lower side
+            const real lam = fmax(A[2 * M * st], B[2 * M * st]);
+#pragma unroll
+            for (int v = 0; v < M; ++v)
+                F[v] = (real)0.5 * (A[v * st] + B[v * st]) - (real)0.5 * lam * (B[(M + v) * st] - A[(M + v) * st]);
+            return;
+        }
+    }
     if (sd < 2) {
         const int i = ex + side;   // x face i of row ey
         const int eL = i > 0 ? ey * a.nx + i - 1 : (a.bc[0] == BC_PERIODIC ? ey * a.nx + a.nx - 1 : -1);

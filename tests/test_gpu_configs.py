@@ -84,29 +84,67 @@ def quadrant_nets():
     return nets
 
 
+def _perturbed(u0, seed=1):
+    """u0 with every value moved by one unit in the last place (random sign)"""
+    r = np.random.default_rng(seed).choice([-1.0, 1.0], size=u0.shape)
+    return np.ascontiguousarray(u0 * (1 + 2.0 ** -52 * r))
+
+
 def test_batched_uneven_quadrants_fp64_learned_vs_oracle():
     """Uneven members (sides 6-15, N in {2, 3, 4}), FP64, a network with
     outputs across (0, 1) (most elements blended), device time steps, one
-    batch.  One step from the same input matches the oracle to rounding; over
-    eight steps the limiter's threshold decisions amplify rounding differences
-    on the members where the flux limiter and the scaling act (measured 5e-8),
-    hence the looser bound there."""
+    batch.
+
+    Step by step: the oracle restarted from each member's GPU state with the
+    GPU's time step matches the next GPU state to rounding (rel. L1 <= 1e-12)
+    with the same limiter counters, on every member at each of eight steps.
+
+    Run freely, members whose flux limiter never acts stay at rounding
+    (<= 1e-12).  On the member where the flux limiter and the scaling act
+    together from the second step (N = 3, side 12, elements 77/78 and 89/90)
+    rounding differences grow by about three orders of magnitude per step;
+    the oracle shows the same growth against itself from an input moved by
+    one ulp (the conditioning of the limited step there, not a difference of
+    the two implementations), so that member is held to 1e-5 and its growth
+    must show up in the oracle alone."""
     specs = W.batch_instances(21, 6, sides=(6, 15), degrees=(2, 3, 4))
     nets = {N: _net(N, 40 + N) for N in (2, 3, 4)}
     members, refs = _members(specs, C.FP64, nets)
+    ghosts = [O.boundary_traces(cfg, u0) for cfg, u0 in refs]
     b = C.Batch(members)
-    b.step()
-    b.sync()
-    for s, (cfg, u0) in zip(members, refs):
-        uo = _oracle_run(cfg, u0, 1)
-        assert rel_l1(uo, s.get_state().reshape(uo.shape)) <= 1e-12
-    b.advance(7)
-    b.sync()
-    for s, (cfg, u0) in zip(members, refs):
+    us = [np.ascontiguousarray(u0, dtype=np.float64) for _, u0 in refs]
+    flux_limited = [0] * len(members)
+    keys = ("n_troubled", "n_flux_limited", "n_scaled", "n_slope_limited", "n_hancock_fallback")
+    for step in range(8):
+        b.step()
+        b.sync()
+        for i, (s, (cfg, _)) in enumerate(zip(members, refs)):
+            dg, rc = s.get_diag()
+            assert rc == 0
+            un, _, do, st = O.step(cfg, us[i], dg["dt"], ghost=ghosts[i])
+            assert st == 0
+            ug = s.get_state().reshape(un.shape)
+            assert rel_l1(un, ug) <= 1e-12, (step, cfg.N, cfg.nx)
+            for k in keys:
+                assert do[k] == dg[k], (step, cfg.N, cfg.nx, k)
+            flux_limited[i] += do["n_flux_limited"]
+            us[i] = np.ascontiguousarray(ug)
+    grew = 0
+    for i, (s, (cfg, u0)) in enumerate(zip(members, refs)):
         d, rc = s.get_diag()
         assert rc == 0 and d["steps"] == 8
         uo = _oracle_run(cfg, u0, 8)
-        assert rel_l1(uo, s.get_state().reshape(uo.shape)) <= 1e-6, (cfg.N, cfg.nx)
+        err = rel_l1(uo, s.get_state().reshape(uo.shape))
+        self_err = rel_l1(uo, _oracle_run(cfg, _perturbed(u0), 8))
+        print(f"N={cfg.N} n={cfg.nx}: flux-limited faces {flux_limited[i]}, GPU vs oracle {err:.2e}, "
+              f"oracle vs oracle from u0 + 1 ulp {self_err:.2e}")
+        if self_err <= 1e-13:
+            assert err <= 1e-12, (cfg.N, cfg.nx, err)
+        else:
+            grew += 1
+            assert err <= 1e-5, (cfg.N, cfg.nx, err)
+            assert self_err >= 1e-4 * err, (cfg.N, cfg.nx, err, self_err)
+    assert grew <= 1
 
 
 def test_batched_uneven_quadrants_fp32_learned_vs_oracle(quadrant_nets):
