@@ -375,6 +375,27 @@ int crkfr_mlp_loss_grad(crkfr_mlp* m, const float* x, const float* t, int n, dou
 int crkfr_mlp_train(crkfr_mlp* m, const float* x, const float* t, int n, int epochs, int batch, float lr,
                     float* loss_per_epoch);
 
+/* ---- one step without device allocation ----------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).  One FP64
+ * step of size dt > 0 (the face-update path, D2 dissipation, EA central part,
+ * min(N+1, 4) stages) from u_in to u_out, both caller-owned device buffers of
+ * nvar*ny*nx*(N+1)^d doubles in the nodal layout above (distinct, u_in only
+ * read).  lim may be NULL (limiter off); its indicator must be
+ * CRKFR_IND_PAPER or CRKFR_IND_CONST.  Far-field ghost states are the
+ * boundary traces of u_in; inflow boundaries are refused.  The step's
+ * intermediate buffers (partial update, face traces, blending coefficients,
+ * ghost states, counters) live in a device array of
+ * CRKFR_STATIC_SCRATCH_BYTES that each GPU the library runs on holds until
+ * the process ends; grids whose buffers exceed it are refused with EINVAL
+ * (2D Euler N = 3 needs about 2.7 KB per element: some 24,000 elements).
+ * No device memory is allocated or freed.  Enqueued on hip_stream (NULL: the
+ * null stream), no synchronisation.  Every call on a GPU shares that GPU's
+ * array: calls that overlap on one GPU (other streams, other threads) race. */
+#define CRKFR_STATIC_SCRATCH_BYTES (64u << 20)
+int crkfr_step_static(const crkfr_config* cfg, const crkfr_limiter_opts* lim, const double* u_in, double* u_out,
+                      double dt, void* hip_stream);
+
 const char* crkfr_last_error(void);
 
 #ifdef __cplusplus

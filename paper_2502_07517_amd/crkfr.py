@@ -76,7 +76,7 @@ SYMBOLS = ["crkfr_create", "crkfr_destroy", "crkfr_set_limiter", "crkfr_set_sour
            "crkfr_mlp_get_box", "crkfr_mlp_fit_box", "crkfr_mlp_forward", "crkfr_mlp_loss_grad",
            "crkfr_mlp_train", "crkfr_batch_set_t_end", "crkfr_batch_set_timing", "crkfr_batch_phase_times",
            "crkfr_set_scheme", "crkfr_set_inflow", "crkfr_bind_state", "crkfr_state_ptr",
-           "crkfr_set_path", "crkfr_path_in_use"]
+           "crkfr_set_path", "crkfr_path_in_use", "crkfr_step_static"]
 
 _lib = None
 
@@ -105,6 +105,8 @@ def lib():
         L.crkfr_set_state.argtypes = [vp, vp, ip]
         L.crkfr_bind_state.argtypes = [vp, vp]
         L.crkfr_set_path.argtypes = [vp, ip]
+        L.crkfr_step_static.argtypes = [ctypes.POINTER(Config), ctypes.POINTER(LimiterOpts), vp, vp,
+                                        ctypes.c_double, vp]
         L.crkfr_path_in_use.argtypes = [vp]
         L.crkfr_state_ptr.argtypes = [vp, ctypes.POINTER(vp)]
         L.crkfr_set_alpha.argtypes = [vp, vp, ip]
@@ -191,6 +193,26 @@ def make_config(equation, N, nx, ny=1, *, bc=(PERIODIC,) * 4, dtype=FP64, domain
     c.gamma, c.adv, c.cfl, c.cs = gamma, adv, cfl, cs
     c.points = points
     return c
+
+
+def step_static(cfg, u_in, u_out, dt, limiter=None, stream=None):
+    """One FP64 step without device allocation (crkfr_step_static): cfg from
+    make_config, u_in and u_out contiguous float64 device tensors, limiter a
+    dict of set_limiter's options or None."""
+    for t in (u_in, u_out):
+        if not hasattr(t, "data_ptr") or not t.is_cuda or not t.is_contiguous():
+            raise ValueError("u_in and u_out must be contiguous device tensors")
+    o = None
+    if limiter is not None:
+        d = dict(blend=BLEND_OFF, indicator=IND_PAPER, smooth_nbr=1, flux_limiter=0, scaling=0, alpha_min=1e-3,
+                 alpha_max=1.0, alpha_const=0.0, eps_rel=0.0, eps_abs=0.0)
+        d.update(limiter)
+        o = LimiterOpts(d["blend"], d["indicator"], d["smooth_nbr"], d["flux_limiter"], d["scaling"],
+                        d["alpha_min"], d["alpha_max"], d["alpha_const"], d["eps_rel"], d["eps_abs"])
+    st = ctypes.c_void_p(stream) if stream is not None else None
+    _check(lib().crkfr_step_static(ctypes.byref(cfg), ctypes.byref(o) if o is not None else None,
+                                   ctypes.c_void_p(u_in.data_ptr()), ctypes.c_void_p(u_out.data_ptr()),
+                                   float(dt), st))
 
 
 class Solver:

@@ -1282,6 +1282,127 @@ extern "C" int crkfr_get_kernel_times(crkfr_solver* s, float* ms4)
 
 extern "C" const char* crkfr_last_error(void) { return g_last_error.c_str(); }
 
+// ----------------------------------------------------------------------------
+// one step without device allocation: the step's intermediate buffers live in
+// a file-scope device array (each device holds its own copy); host code uses
+// its device address from hipGetSymbolAddress, taken once per device
+// ----------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[CRKFR_STATIC_SCRATCH_BYTES];
+constexpr int MAX_DEVICES = 64;
+static unsigned char* g_scratch[MAX_DEVICES];
+static std::mutex g_scratch_mutex;
+
+static int scratch_on_device(unsigned char** out)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(CRKFR_EINVAL, "device index beyond the static scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(CRKFR_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch[dev] = (unsigned char*)p;
+    }
+    *out = g_scratch[dev];
+    return 0;
+}
+
+// zero n 64-bit words (a kernel rather than hipMemsetAsync, which graph
+// capture would record as a memset node)
+static __global__ void k_zero_u64(unsigned long long* p, int n)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0ull;
+}
+
+extern "C" int crkfr_step_static(const crkfr_config* cfg, const crkfr_limiter_opts* lim, const double* u_in,
+                                 double* u_out, double dt, void* hip_stream)
+{
+    if (!cfg || !u_in || !u_out) return fail(CRKFR_EINVAL, "null argument");
+    if (u_in == u_out) return fail(CRKFR_EINVAL, "input and output must be distinct buffers");
+    {
+        const int rc = validate_config(cfg);
+        if (rc) return rc;
+    }
+    if (cfg->dtype != CRKFR_FP64) return fail(CRKFR_EINVAL, "the static step is FP64 only");
+    if (!(dt > 0.0)) return fail(CRKFR_EINVAL, "the static step needs dt > 0");
+    const int dim = cfg->equation == CRKFR_EULER2D || cfg->equation == CRKFR_TENMOM2D ? 2 : 1;
+    for (int i = 0; i < (dim == 2 ? 4 : 2); ++i)
+        if (cfg->bc[i] == CRKFR_BC_INFLOW) return fail(CRKFR_EINVAL, "inflow boundaries need a solver (crkfr_set_inflow)");
+    if (lim) {
+        if (lim->blend < 0 || lim->blend > 2 || (lim->indicator != CRKFR_IND_PAPER && lim->indicator != CRKFR_IND_CONST))
+            return fail(CRKFR_EINVAL, "the static step takes the smoothness indicator or a constant alpha");
+        if (lim->flux_limiter && lim->blend == CRKFR_BLEND_OFF)
+            return fail(CRKFR_EINVAL, "the flux limiter needs a low-order blend (FO or MH)");
+        if (lim->blend == CRKFR_BLEND_MH && cfg->points == CRKFR_POINTS_GLL)
+            return fail(CRKFR_EINVAL, "MUSCL-Hancock blending needs Gauss-Legendre points");
+    }
+    unsigned char* base = nullptr;
+    {
+        const int rc = scratch_on_device(&base);
+        if (rc) return rc;
+    }
+    // a solver on the stack whose buffers are the caller's state and the scratch
+    crkfr_solver s;
+    std::memset(&s, 0, sizeof(s));
+    s.cfg = *cfg;
+    if (s.cfg.cs <= 0.0) s.cfg.cs = 0.98;
+    s.stream = (hipStream_t)hip_stream;
+    s.M = eq_nvar(cfg->equation);
+    s.dim = dim;
+    s.nd = cfg->N + 1;
+    s.nq = dim == 2 ? s.nd : 1;
+    s.np = s.nd * s.nq;
+    s.ne = cfg->nx * cfg->ny;
+    s.C_max = 4 * s.M + 1;
+    s.stages = std::min(cfg->N + 1, 4);
+    s.dissipation = CRKFR_DISS_D2;
+    s.central = CRKFR_CENTRAL_EA;
+    s.path = CRKFR_PATH_FACE_UPDATE;
+    s.cfl = 1.0;   // dt is given
+    if (lim) s.lim = *lim;
+    else s.lim.blend = CRKFR_BLEND_OFF;
+    if (s.lim.alpha_max <= 0.0) s.lim.alpha_max = 1.0;
+    make_ref(cfg->N, cfg->points, s.ref);
+    // layout: the words k_prep and the counters use, then the step's buffers
+    const size_t M = s.M, ne = s.ne, np = s.np;
+    const size_t head_words = 4 + RATE_SLOTS + D_NCOUNT;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { unsigned char* p = base + off; off += (bytes + 255) & ~(size_t)255; return p; };
+    unsigned long long* head = (unsigned long long*)take(head_words * 8);
+    s.dt_dev = (double*)head;
+    s.t_dev = (double*)(head + 1);         // t, t^n
+    s.steps = (long long*)(head + 3);
+    s.rate_bits = head + 4;
+    s.diag = head + 4 + RATE_SLOTS;
+    s.uHp = take(M * ne * np * 8);
+    s.trx = take(2 * (size_t)s.C_max * ne * s.nq * 8);
+    if (dim == 2) s.trY = take(2 * (size_t)s.C_max * ne * s.nd * 8);
+    if (s.lim.blend != CRKFR_BLEND_OFF) {
+        s.alpha_raw = (double*)take(ne * 8);
+        s.alpha_out = (double*)take(ne * 8);
+    }
+    bool farfield = false;
+    for (int i = 0; i < (dim == 2 ? 4 : 2); ++i) farfield |= cfg->bc[i] == CRKFR_BC_FARFIELD;
+    if (farfield) s.ghost = take(ghost_size(&s) * 8);
+    if (off > CRKFR_STATIC_SCRATCH_BYTES)
+        return fail(CRKFR_EINVAL, "grid too large for the static scratch (" + std::to_string(off) + " bytes needed, " +
+                                      std::to_string((size_t)CRKFR_STATIC_SCRATCH_BYTES) + " held)");
+    s.u[0] = (void*)u_in;
+    s.u[1] = u_out;
+    s.cur = 0;
+    s.has_state = true;
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(256), 0, s.stream, head, (int)head_words);
+    int rc = 0;
+    if (farfield) rc = run_io(&s, PH_GHOST, nullptr, nullptr, nullptr);
+    if (!rc) rc = enqueue_step(&s, dt, 0.0);
+    if (!rc) {
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) rc = fail(CRKFR_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
+    }
+    return rc;
+}
 
 // ----------------------------------------------------------------------------
 // batches: many instances advanced together, one launch per phase and degree

@@ -1,0 +1,87 @@
+"""crkfr_step_static (one step without device allocation, the step's buffers in
+a static device array) against crkfr_step of a solver on the same input and
+time step: equal bitwise (the same kernels on the same path), on two calls
+in a row, the second with a smaller grid, with and without the limiter
+chain; grids beyond the static array are refused."""
+import numpy as np
+import pytest
+
+from paper_2502_07517_amd import crkfr as C
+from paper_2502_07517_amd import workloads as W
+from oracle_runs import cfl_for
+
+pytestmark = pytest.mark.gpu
+
+LIM = dict(blend=C.BLEND_MH, flux_limiter=1, scaling=1)
+
+
+def _solver_step(eq, N, nx, ny, u0, dt, bc, limiter, dom):
+    s = C.Solver(eq, N, nx, ny, bc=bc, domain=dom, cfl=cfl_for(N))
+    if limiter:
+        s.set_limiter(**limiter)
+    s.set_state(u0)
+    s.step(dt)
+    return s.get_state()
+
+
+def _static_step(eq, N, nx, ny, u0, dt, bc, limiter, dom):
+    import torch
+    cfg = C.make_config(eq, N, nx, ny, bc=bc, domain=dom, cfl=cfl_for(N))
+    u_in = torch.from_numpy(np.ascontiguousarray(u0, dtype=np.float64)).to("cuda")
+    u_out = torch.full_like(u_in, np.nan)
+    C.step_static(cfg, u_in, u_out, dt, limiter=limiter)
+    torch.cuda.synchronize()
+    return u_out.cpu().numpy().reshape(u0.shape)
+
+
+CASES = [
+    # two calls in a row: a larger grid, then a smaller one
+    ((C.EULER2D, 3, 40, 40, "quadrants"), (C.EULER2D, 3, 13, 13, "quadrants")),
+    ((C.EULER2D, 2, 30, 22, "vortex"), (C.EULER2D, 4, 9, 7, "vortex")),
+    ((C.EULER1D, 4, 400, 1, "riemann"), (C.EULER1D, 3, 37, 1, "riemann")),
+]
+
+
+def _input(kind, N, nx, ny):
+    if kind == "quadrants":
+        return W.euler2d_quadrants(4, nx, N)
+    if kind == "vortex":
+        X, Y = W.node_coords_2d(nx, ny, N, (-5.0, 5.0, -5.0, 5.0))
+        return W.euler2d_cons(*W.vortex_prim(X, Y, 0.0, (-5.0, 5.0, -5.0, 5.0)))
+    return W.euler1d_riemann(2, nx, N)
+
+
+@pytest.mark.parametrize("limited", [False, True])
+@pytest.mark.parametrize("pair", range(len(CASES)))
+def test_static_step_equals_solver_step_twice(pair, limited):
+    for eq, N, nx, ny, kind in CASES[pair]:
+        dom = (-5.0, 5.0, -5.0, 5.0) if kind == "vortex" else (0.0, 1.0, 0.0, 1.0)
+        bc = (C.PERIODIC,) * 4 if kind == "vortex" else (C.FARFIELD,) * 4
+        u0 = _input(kind, N, nx, ny)
+        probe = C.Solver(eq, N, nx, ny, bc=bc, domain=dom, cfl=cfl_for(N))
+        probe.set_state(u0)
+        dt = probe.compute_dt()
+        lim = LIM if limited else None
+        ref = _solver_step(eq, N, nx, ny, u0, dt, bc, lim, dom)
+        got = _static_step(eq, N, nx, ny, u0, dt, bc, lim, dom)
+        np.testing.assert_array_equal(got.reshape(ref.shape), ref)
+
+
+def test_static_step_refuses_large_grids_and_bad_options():
+    import torch
+    cfg = C.make_config(C.EULER2D, 3, 400, 400)
+    u = torch.zeros(4 * 400 * 400 * 16, dtype=torch.float64, device="cuda")
+    v = torch.zeros_like(u)
+    with pytest.raises(C.CrkfrError) as e:
+        C.step_static(cfg, u, v, 1e-3)
+    assert e.value.code == -1 and "static scratch" in str(e.value)
+    small = C.make_config(C.EULER2D, 3, 4, 4)
+    w = torch.zeros(4 * 16 * 16, dtype=torch.float64, device="cuda")
+    with pytest.raises(C.CrkfrError):
+        C.step_static(small, w, w, 1e-3)                      # same buffer
+    with pytest.raises(C.CrkfrError):
+        C.step_static(small, w, torch.zeros_like(w), 0.0)      # no dt
+    with pytest.raises(C.CrkfrError):
+        C.step_static(C.make_config(C.EULER2D, 3, 4, 4, dtype=C.MP32), w, torch.zeros_like(w), 1e-3)
+    with pytest.raises(C.CrkfrError):
+        C.step_static(small, w, torch.zeros_like(w), 1e-3, limiter=dict(blend=C.BLEND_MH, indicator=C.IND_LEARNED))
