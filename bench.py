@@ -57,12 +57,16 @@ SWEEP = "12,16,24,32,48,64,96,128"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "vortex_512sq_n3_fp64_hbm_traffic.md")
 
 
+KERNEL_SOURCES = ("crkfr_kernels.hpp", "crkfr_physics.hpp", "crkfr_launch.hpp", "crkfr_eq_euler2d.hip")
+
+
 def kernel_sources_digest():
-    """SHA-256 over the HIP sources (file names and contents, sorted)."""
+    """SHA-256 over the sources of the 2D Euler step's kernels and their
+    launch shapes (file names and contents, in this order)."""
     import hashlib
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2502_07517_amd", "csrc")
-    for fn in sorted(os.listdir(d)):
+    for fn in KERNEL_SOURCES:
         h.update(fn.encode())
         with open(os.path.join(d, fn), "rb") as fh:
             h.update(fh.read())
@@ -436,9 +440,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="seconds per CPU-baseline leg")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-c5", action="store_true", help="skip the 256-instance uneven batch")
-    ap.add_argument("--part", choices=["all", "c3", "c3lim", "sweep", "c5"], default="all",
-                    help="c3: only the 512^2 headline step; c3lim: only the 512^2 steps with the limiter "
-                         "chain; sweep: only the matched-L1 sweep; c5: only the uneven batch (profiling)")
+    ap.add_argument("--part", choices=["all", "c3", "c3head", "c3lim", "sweep", "c5"], default="all",
+                    help="c3: only the 512^2 step on each kernel path; c3head: only the headline path "
+                         "(counter runs); c3lim: only the 512^2 steps with the limiter chain; sweep: only the "
+                         "matched-L1 sweep; c5: only the uneven batch (profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy (scale for the HBM byte counters)")
     args = ap.parse_args()
@@ -466,9 +471,19 @@ def main():
         return {k: v for k, v in r.items() if k != "state"}
 
     if args.part == "c3lim":
-        out = {k: c3_row(run_c3(dt, args.steps, args.warmup, limited=True))
-               for k, dt in (("fp64_limited", C.FP64), ("mp32_limited", C.MP32))}
+        out = {}
+        for k, dt in (("fp64_limited", C.FP64), ("mp32_limited", C.MP32)):
+            for name, pth in (("", None), ("_split", C.PATH_SPLIT), ("_face_update", C.PATH_FACE_UPDATE)):
+                r = c3_row(run_c3(dt, args.steps, args.warmup, limited=True, path=pth))
+                out[k + name] = r
+                print(f"# 512^2 {k}{name} ({r['path']}): {r['ms_per_step']:.4f} ms/step, kernels (ms) "
+                      f"{np.round(r['kernel_ms'], 4).tolist()}", flush=True)
         print(json.dumps({"part": "c3lim", "equal_occupancy_512": out}), flush=True)
+        return
+    if args.part == "c3head":
+        r = run_c3(C.FP64, args.steps, args.warmup)
+        print(f"# 512^2 FP64 limiter off ({r['path']}): {r['ms_per_step']:.4f} ms/step, kernels (ms) "
+              f"{np.round(r['kernel_ms'], 4).tolist()}", flush=True)
         return
     if args.part == "c5":
         nets = {3: train_network()[0]}

@@ -273,7 +273,7 @@ double crkfr_fourier_cfl(int N, int stages, int system, int dissipation, int poi
 /* Kernel path of a step (the results agree up to rounding order):
  *  CRKFR_PATH_SPLIT: the local cRK procedure, the x faces, the y faces, the
  *    update, one kernel each (face fluxes through HBM);
- *  CRKFR_PATH_FACE_UPDATE (the default): the local procedure, then one
+ *  CRKFR_PATH_FACE_UPDATE: the local procedure, then one
  *    kernel in which each element's lanes compute its 4 (N+1) face fluxes
  *    (every face computed by both neighbours, in the same arithmetic) and
  *    update it;
@@ -284,12 +284,37 @@ double crkfr_fourier_cfl(int N, int stages, int system, int dissipation, int poi
  *    elements whose four neighbours lie in the tile out of LDS, then the
  *    faces on tile edges and the update of the tile-edge elements follow;
  *    other configurations take CRKFR_PATH_FACE_UPDATE.
+ * Until crkfr_set_path or crkfr_autotune chooses one, a solver takes the
+ * face-update path with the limiter chain off and the split path with it on
+ * (the limited face flux would be computed by both neighbours).
  * crkfr_path_in_use returns the path the next step takes.  Errors: EINVAL,
  * ESTATE (the solver is a member of a live batch; batches take the face-update
  * path for groups whose members all have it, the split path otherwise). */
 enum { CRKFR_PATH_SPLIT = 0, CRKFR_PATH_TILE = 1, CRKFR_PATH_FACE_UPDATE = 2 };
 int crkfr_set_path(crkfr_solver* s, int path);
 int crkfr_path_in_use(const crkfr_solver* s);
+
+/* Kernel-path autotuner.  Times each path that serves the solver's
+ * configuration (the tile-fused path only where it applies) over `steps`
+ * eagerly enqueued steps from the current state after one warm-up step,
+ * keeps the fastest (crkfr_set_path), and puts the state, the clock, the
+ * time-step slots and the counters back as they were.  cache_path (may be
+ * NULL) names a JSON-lines file: one object per tuned configuration,
+ *   {"key": "eq=2 M=4 N=3 dtype=fp64 nx=512 ny=512 points=0 stages=4 diss=1
+ *    central=0 blend=0 ind=0 flux=0 scale=0 src=0", "path": "face_update",
+ *    "ms_per_step": {"split": 0.37, "tile": 0.43, "face_update": 0.33}}
+ * (the key holds N, M, the arithmetic, the grid and every option that selects
+ * kernels); a configuration found there takes its stored path without timing
+ * (from_cache = 1, ms all 0), a new one is timed and appended (the last entry
+ * of a key wins).  Needs a state; allocates one state-sized device buffer
+ * while it runs and synchronises the solver's stream.  Errors: EINVAL (bad
+ * argument, cache file not writable), ESTATE (no state, batch member), EHIP. */
+typedef struct {
+    int path;          /* the path the next step takes (CRKFR_PATH_*) */
+    int from_cache;    /* 1: read from the cache file, nothing timed */
+    float ms[3];       /* ms per step of split, tile-fused, face-update; 0: not timed */
+} crkfr_tune_result;
+int crkfr_autotune(crkfr_solver* s, int steps, const char* cache_path, crkfr_tune_result* out);
 
 /* Device time per kernel of the last step measured with HIP events (ms):
  * [0] local cRK, [1] x faces, [2] y faces, [3] update; with the tile-fused

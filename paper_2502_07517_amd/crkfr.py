@@ -49,6 +49,10 @@ class Source(ctypes.Structure):
                 ("xc", ctypes.c_double), ("yc", ctypes.c_double), ("gx", ctypes.c_double), ("gy", ctypes.c_double)]
 
 
+class TuneResult(ctypes.Structure):
+    _fields_ = [("path", ctypes.c_int), ("from_cache", ctypes.c_int), ("ms", ctypes.c_float * 3)]
+
+
 class Diag(ctypes.Structure):
     _fields_ = [("n_troubled", ctypes.c_longlong), ("n_flux_limited", ctypes.c_longlong),
                 ("n_lo_inadmissible", ctypes.c_longlong), ("n_slope_limited", ctypes.c_longlong),
@@ -76,7 +80,7 @@ SYMBOLS = ["crkfr_create", "crkfr_destroy", "crkfr_set_limiter", "crkfr_set_sour
            "crkfr_mlp_get_box", "crkfr_mlp_fit_box", "crkfr_mlp_forward", "crkfr_mlp_loss_grad",
            "crkfr_mlp_train", "crkfr_batch_set_t_end", "crkfr_batch_set_timing", "crkfr_batch_phase_times",
            "crkfr_set_scheme", "crkfr_set_inflow", "crkfr_bind_state", "crkfr_state_ptr",
-           "crkfr_set_path", "crkfr_path_in_use", "crkfr_step_static"]
+           "crkfr_set_path", "crkfr_path_in_use", "crkfr_step_static", "crkfr_autotune"]
 
 _lib = None
 
@@ -108,6 +112,7 @@ def lib():
         L.crkfr_step_static.argtypes = [ctypes.POINTER(Config), ctypes.POINTER(LimiterOpts), vp, vp,
                                         ctypes.c_double, vp]
         L.crkfr_path_in_use.argtypes = [vp]
+        L.crkfr_autotune.argtypes = [vp, ip, ctypes.c_char_p, ctypes.POINTER(TuneResult)]
         L.crkfr_state_ptr.argtypes = [vp, ctypes.POINTER(vp)]
         L.crkfr_set_alpha.argtypes = [vp, vp, ip]
         L.crkfr_compute_dt.argtypes = [vp, dp]
@@ -307,11 +312,23 @@ class Solver:
         _check(lib().crkfr_bind_state(self.h, ctypes.c_void_p(u.data_ptr())))
 
     def set_path(self, path):
-        """Kernel path of a step: PATH_SPLIT, PATH_TILE or PATH_FACE_UPDATE (default)."""
+        """Kernel path of a step: PATH_SPLIT, PATH_TILE or PATH_FACE_UPDATE (default: face-update with
+        the limiter chain off, split with it on)."""
         _check(lib().crkfr_set_path(self.h, int(path)))
 
     def path_in_use(self):
         return lib().crkfr_path_in_use(self.h)
+
+    def autotune(self, steps=5, cache=None):
+        """Time the kernel paths that serve this configuration and keep the
+        fastest (crkfr_autotune); cache: JSON-lines file of tuned
+        configurations.  Returns {"path", "from_cache", "ms_per_step"}."""
+        r = TuneResult()
+        _check(lib().crkfr_autotune(self.h, int(steps), None if cache is None else str(cache).encode(),
+                                    ctypes.byref(r)))
+        names = ("split", "tile", "face_update")
+        return {"path": r.path, "from_cache": bool(r.from_cache),
+                "ms_per_step": {names[i]: float(r.ms[i]) for i in range(3) if r.ms[i] > 0}}
 
     def state_ptr(self):
         """Device address of the current FP64 nodal state."""

@@ -379,6 +379,7 @@ struct crkfr_solver {
     int* edge_list;          // tile-fused step: elements at the tile edges (device), null without a tile shape
     int n_edge;
     int path;                // CRKFR_PATH_*: split, tile-fused (where it serves), faces fused into the update
+    bool path_set;           // path chosen by crkfr_set_path or the autotuner (else the default rule)
     bool timing;
     hipEvent_t ev[6];
     float kernel_ms[4];
@@ -1045,10 +1046,15 @@ static int check_learned(const crkfr_solver* s)
 // update with the faces fused in
 static int path_in_use(const crkfr_solver* s)
 {
-    if (s->path == CRKFR_PATH_TILE)
+    // unless the caller chose one: the faces fused into the update without
+    // the limiter chain, the split step with it (the limited face flux, done
+    // once per face there, would be computed by both neighbours)
+    const int p = s->path_set ? s->path
+                              : (s->lim.blend == CRKFR_BLEND_OFF ? CRKFR_PATH_FACE_UPDATE : CRKFR_PATH_SPLIT);
+    if (p == CRKFR_PATH_TILE)
         return s->edge_list && s->lim.blend == CRKFR_BLEND_OFF && s->dissipation == CRKFR_DISS_D2
                    ? CRKFR_PATH_TILE : CRKFR_PATH_FACE_UPDATE;
-    return s->path;
+    return p;
 }
 
 extern "C" int crkfr_set_path(crkfr_solver* s, int path)
@@ -1057,11 +1063,165 @@ extern "C" int crkfr_set_path(crkfr_solver* s, int path)
     if (path < CRKFR_PATH_SPLIT || path > CRKFR_PATH_FACE_UPDATE) return fail(CRKFR_EINVAL, "bad step path");
     if (s->batch_refs > 0) return fail(CRKFR_ESTATE, "solver is a batch member: destroy the batch first");
     s->path = path;
+    s->path_set = true;
     invalidate_graph(s);
     return 0;
 }
 
 extern "C" int crkfr_path_in_use(const crkfr_solver* s) { return s ? path_in_use(s) : -1; }
+
+static int enqueue_step(crkfr_solver* s, double dt_fixed, double t_end);
+
+// ----------------------------------------------------------------------------
+// path autotuning: time each kernel path that serves the configuration over a
+// few steps from the current state, keep the fastest, and remember it in a
+// JSON-lines cache file keyed by what selects the kernels
+// ----------------------------------------------------------------------------
+static std::string tune_key(const crkfr_solver* s)
+{
+    char buf[320];
+    std::snprintf(buf, sizeof(buf),
+                  "eq=%d M=%d N=%d dtype=%s nx=%d ny=%d points=%d stages=%d diss=%d central=%d blend=%d "
+                  "ind=%d flux=%d scale=%d src=%d",
+                  s->cfg.equation, s->M, s->cfg.N, s->mp ? "mp32" : "fp64", s->cfg.nx, s->cfg.ny, s->cfg.points,
+                  s->stages, s->dissipation, s->central, s->lim.blend, s->lim.indicator, s->lim.flux_limiter,
+                  s->lim.scaling, (int)(s->src.enabled != 0));
+    return buf;
+}
+
+static const char* const PATH_NAMES[3] = {"split", "tile", "face_update"};
+
+// the path stored for key, or -1
+static int tune_cache_lookup(const char* path, const std::string& key)
+{
+    FILE* f = std::fopen(path, "r");
+    if (!f) return -1;
+    const std::string want = "\"key\": \"" + key + "\"";
+    char line[1024];
+    int found = -1;
+    while (std::fgets(line, sizeof(line), f)) {
+        if (!std::strstr(line, want.c_str())) continue;
+        const char* p = std::strstr(line, "\"path\": \"");
+        if (!p) continue;
+        p += std::strlen("\"path\": \"");
+        for (int i = 0; i < 3; ++i) {
+            const size_t n = std::strlen(PATH_NAMES[i]);
+            if (std::strncmp(p, PATH_NAMES[i], n) == 0 && p[n] == '"') found = i;   // the last entry wins
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+extern "C" int crkfr_autotune(crkfr_solver* s, int steps, const char* cache_path, crkfr_tune_result* out)
+{
+    if (!s || !out) return fail(CRKFR_EINVAL, "null argument");
+    if (steps < 1) return fail(CRKFR_EINVAL, "steps must be >= 1");
+    if (!s->has_state) return fail(CRKFR_ESTATE, "no state set");
+    if (s->batch_refs > 0) return fail(CRKFR_ESTATE, "solver is a batch member: destroy the batch first");
+    std::memset(out, 0, sizeof(*out));
+    const std::string key = tune_key(s);
+    if (cache_path && *cache_path) {
+        const int p = tune_cache_lookup(cache_path, key);
+        if (p >= 0) {
+            s->path = p;
+            s->path_set = true;
+            invalidate_graph(s);
+            out->path = path_in_use(s);
+            out->from_cache = 1;
+            return 0;
+        }
+    }
+    // the trials advance the state, the clock, the time-step slots and the
+    // counters: keep them and put them back after each path
+    const size_t n = (size_t)s->M * s->ne * s->np;
+    const int cur0 = s->cur;
+    struct Small {
+        unsigned long long rate[RATE_SLOTS], diag[D_NCOUNT];
+        double t[2], dt;
+        long long steps;
+    } small;
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    HIP_TRY(hipMemcpy(small.rate, s->rate_bits, sizeof(small.rate), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(small.diag, s->diag, sizeof(small.diag), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(small.t, s->t_dev, sizeof(small.t), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(&small.dt, s->dt_dev, sizeof(double), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(&small.steps, s->steps, sizeof(long long), hipMemcpyDeviceToHost));
+    void* keep_u = nullptr;
+    double* keep_ubar = nullptr;
+    HIP_TRY(hipMalloc(&keep_u, n * real_size(s)));
+    if (s->mp && hipMalloc((void**)&keep_ubar, (size_t)s->M * s->ne * sizeof(double)) != hipSuccess) {
+        (void)hipFree(keep_u);
+        return fail(CRKFR_ENOMEM, "device allocation failed");
+    }
+    int rc = 0;
+    auto restore = [&]() -> int {
+        s->cur = cur0;
+        HIP_TRY(hipMemcpy(s->u[cur0], keep_u, n * real_size(s), hipMemcpyDeviceToDevice));
+        if (keep_ubar) HIP_TRY(hipMemcpy(s->ubar[cur0], keep_ubar, (size_t)s->M * s->ne * sizeof(double),
+                                         hipMemcpyDeviceToDevice));
+        HIP_TRY(hipMemcpy(s->rate_bits, small.rate, sizeof(small.rate), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(s->diag, small.diag, sizeof(small.diag), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(s->t_dev, small.t, sizeof(small.t), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(s->dt_dev, &small.dt, sizeof(double), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(s->steps, &small.steps, sizeof(long long), hipMemcpyHostToDevice));
+        return 0;
+    };
+    if (hipMemcpy(keep_u, s->u[cur0], n * real_size(s), hipMemcpyDeviceToDevice) != hipSuccess ||
+        (keep_ubar && hipMemcpy(keep_ubar, s->ubar[cur0], (size_t)s->M * s->ne * sizeof(double),
+                                hipMemcpyDeviceToDevice) != hipSuccess))
+        rc = fail(CRKFR_EHIP, "state copy failed");
+    const int path0 = s->path;
+    const bool set0 = s->path_set;
+    const bool tm = s->timing;
+    s->timing = false;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (!rc && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+        rc = fail(CRKFR_EHIP, "hipEventCreate failed");
+    int best = -1;
+    for (int p = 0; p < 3 && !rc; ++p) {
+        s->path = p;
+        s->path_set = true;
+        if (path_in_use(s) != p) continue;       // the path does not serve this configuration
+        rc = enqueue_step(s, 0.0, 0.0);         // warm-up
+        if (!rc && hipEventRecord(e0, s->stream) != hipSuccess) rc = fail(CRKFR_EHIP, "hipEventRecord failed");
+        for (int i = 0; i < steps && !rc; ++i) rc = enqueue_step(s, 0.0, 0.0);
+        if (!rc && (hipEventRecord(e1, s->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+            rc = fail(CRKFR_EHIP, "timing events failed");
+        float ms = 0.f;
+        if (!rc && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = fail(CRKFR_EHIP, "hipEventElapsedTime failed");
+        if (!rc) {
+            out->ms[p] = ms / steps;
+            if (best < 0 || out->ms[p] < out->ms[best]) best = p;
+        }
+        const int rrc = restore();
+        if (!rc) rc = rrc;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(keep_u);
+    if (keep_ubar) (void)hipFree(keep_ubar);
+    s->timing = tm;
+    s->path = rc || best < 0 ? path0 : best;
+    s->path_set = rc || best < 0 ? set0 : true;
+    invalidate_graph(s);
+    if (rc) return rc;
+    out->path = path_in_use(s);
+    if (cache_path && *cache_path) {
+        FILE* f = std::fopen(cache_path, "a");
+        if (!f) return fail(CRKFR_EINVAL, std::string("cannot append to the autotune cache ") + cache_path);
+        std::fprintf(f, "{\"key\": \"%s\", \"path\": \"%s\", \"ms_per_step\": {", key.c_str(), PATH_NAMES[best]);
+        bool first = true;
+        for (int p = 0; p < 3; ++p) {
+            if (out->ms[p] <= 0.f) continue;
+            std::fprintf(f, "%s\"%s\": %.6g", first ? "" : ", ", PATH_NAMES[p], (double)out->ms[p]);
+            first = false;
+        }
+        std::fprintf(f, "}}\n");
+        std::fclose(f);
+    }
+    return 0;
+}
 
 static int enqueue_step(crkfr_solver* s, double dt_fixed, double t_end)
 {
@@ -1359,7 +1519,8 @@ extern "C" int crkfr_step_static(const crkfr_config* cfg, const crkfr_limiter_op
     s.stages = std::min(cfg->N + 1, 4);
     s.dissipation = CRKFR_DISS_D2;
     s.central = CRKFR_CENTRAL_EA;
-    s.path = CRKFR_PATH_FACE_UPDATE;
+    s.path = CRKFR_PATH_FACE_UPDATE;   // no face flux arrays in the scratch layout
+    s.path_set = true;
     s.cfl = 1.0;   // dt is given
     if (lim) s.lim = *lim;
     else s.lim.blend = CRKFR_BLEND_OFF;
@@ -1573,7 +1734,7 @@ extern "C" int crkfr_batch_create(crkfr_solver* const* solvers, int count, void*
         BatchGroup* g = nullptr;
         for (BatchGroup& gg : b->groups)
             if (gg.eq == s->cfg.equation && gg.N == s->cfg.N && gg.mp == s->mp && gg.lim == lim) g = &gg;
-        if (g && g->fu != (s->path == CRKFR_PATH_FACE_UPDATE)) g->fu = false;
+        if (g && g->fu != (path_in_use(s) == CRKFR_PATH_FACE_UPDATE)) g->fu = false;
         if (!g) {
             BatchGroup ng;
             std::memset(ng.d_args, 0, sizeof(ng.d_args));
@@ -1584,7 +1745,7 @@ extern "C" int crkfr_batch_create(crkfr_solver* const* solvers, int count, void*
             ng.N = s->cfg.N;
             ng.mp = s->mp;
             ng.lim = lim;
-            ng.fu = s->path == CRKFR_PATH_FACE_UPDATE;
+            ng.fu = path_in_use(s) == CRKFR_PATH_FACE_UPDATE;
             b->groups.push_back(ng);
             g = &b->groups.back();
         }

@@ -707,6 +707,21 @@ __host__ __device__ constexpr int elem_region()
     constexpr int traces = (Eq::DIM == 2 ? 4 * nd : 2) * (2 * Eq::M + 1);
     return stage > traces ? stage : traces;
 }
+// component c of the face traces of element e at position t of side sd
+// (0 left, 1 right, 2 bottom, 3 top): the x faces' array for sides 0, 1, the
+// y faces' for 2, 3; components of one array lie trace_stride apart
+// (x and y faces of a 2D element carry N + 1 points each; 1D: one x point)
+template <class Eq, int N, class real>
+__device__ __forceinline__ size_t trace_stride(const StepArgs<real>& a)
+{
+    return (size_t)a.ne * (Eq::DIM == 2 ? N + 1 : 1);
+}
+template <class Eq, int N, class real>
+__device__ __forceinline__ real* trace_at(const StepArgs<real>& a, int sd, int c, int e, int t)
+{
+    constexpr int npt = Eq::DIM == 2 ? N + 1 : 1;
+    return (sd < 2 ? a.trx : a.trY) + (size_t)c * trace_stride<Eq, N>(a) + (size_t)e * npt + t;
+}
 // TG = void: the split step (LGeo blocks of elements; uHp and the face traces
 // to HBM).  TG = a tile geometry: one tile of TX x TY elements per workgroup
 // (the tile-fused step); the element's stage arrays lie in tile_buf, uHp goes
@@ -941,13 +956,13 @@ __device__ void local_body(const StepArgs<real>& a, int vblock, real* tile_buf =
                         own[v] = side ? su[at(kf, v)] : sf[at(kf, v)];
                     }
                 }
-                real* base = d == 0 ? a.trx : a.trY;
-                const int npt = d == 0 ? nq : nd;
+                real* const lb = trace_at<Eq, N>(a, sd, side * C + 2 * M + 1, e, t);
+                const size_t cs = trace_stride<Eq, N>(a);
                 rusanov_n<Eq>(d, lft, rgt, fs, P);
 #pragma unroll
                 for (int v = 0; v < M; ++v) {
-                    base[((size_t)(side * C + 2 * M + 1 + v) * nes + e) * npt + t] = own[v];
-                    base[((size_t)(side * C + 2 * M + 1 + M + v) * nes + e) * npt + t] = fs[v];
+                    lb[v * cs] = own[v];
+                    lb[(M + v) * cs] = fs[v];
                 }
             }
             if (nlim) atomicAdd(&a.diag[D_SLOPELIM], (unsigned long long)nlim);
@@ -977,22 +992,36 @@ __device__ void local_body(const StepArgs<real>& a, int vblock, real* tile_buf =
         const int sd = fside(fp), t = fpos(fp);
         return sd < 2 ? t * nd + r : r * nd + t;
     };
-    // this lane's face lines: offsets of the line's nodes (value 0) and interpolation weights
+    // this lane's face lines: offsets of the line's nodes (value 0), counted
+    // from the face.  The solution points are symmetric about the element's
+    // centre, so the value at the upper face is the sum of l_0(xi_r) times
+    // the node r places from that face: one set of weights (wavefront-uniform,
+    // in scalar registers) serves both sides of every face.
     int fkn[FPL][nd];
-    real fw[FPL][nd];
 #pragma unroll
     for (int j = 0; j < FPL; ++j) {
         const int fp = k + j * np < NFP ? k + j * np : NFP - 1;
         const bool hi = fside(fp) & 1;
 #pragma unroll
-        for (int r = 0; r < nd; ++r) {
-            fkn[j][r] = at(fnode(fp, r), 0);
-            fw[j][r] = hi ? a.R.l1[r] : a.R.l0[r];
-        }
+        for (int r = 0; r < nd; ++r) fkn[j][r] = at(fnode(fp, hi ? N - r : r), 0);
     }
+    const real* fw0 = a.R.l0;
+    // rows of the derivative matrix scaled by the inverse element widths: the
+    // divergence d f / dx + d g / dy is then one chain of products
     real Dx[nd], Dy[nd];
 #pragma unroll
-    for (int r = 0; r < nd; ++r) { Dx[r] = a.R.D[p][r]; Dy[r] = a.R.D[q][r]; }
+    for (int r = 0; r < nd; ++r) { Dx[r] = a.R.D[p][r] * idx; Dy[r] = DIM == 2 ? a.R.D[q][r] * idy : (real)0; }
+    // d f / dx + d g / dy at this lane's node from the arrays in LDS
+    auto divergence = [&](int v) {
+        real d = Dx[0] * sf[at(q * nd, v)];
+#pragma unroll
+        for (int r = 1; r < nd; ++r) d += Dx[r] * sf[at(q * nd + r, v)];
+        if constexpr (DIM == 2) {
+#pragma unroll
+            for (int r = 0; r < nd; ++r) d += Dy[r] * sg[at(r * nd + p, v)];
+        }
+        return d;
+    };
 
 #pragma unroll 1
     for (int i = 0; i < S; ++i) {
@@ -1009,7 +1038,7 @@ __device__ void local_body(const StepArgs<real>& a, int vblock, real* tile_buf =
             F[v] += bi * f[v];
             if constexpr (DIM == 2) Gs[v] += bi * g[v];
             U[v] += bi * ui[v];
-            Sa[v] += bi * s[v];
+            if (src) Sa[v] += bi * s[v];
             su[at(k, v)] = ui[v];
             sf[at(k, v)] = f[v];
             if constexpr (DIM == 2) sg[at(k, v)] = g[v];
@@ -1028,7 +1057,7 @@ __device__ void local_body(const StepArgs<real>& a, int vblock, real* tile_buf =
             for (int r = 0; r < nd; ++r) {
                 const int kn = fkn[j][r];
 #pragma unroll
-                for (int v = 0; v < M; ++v) uf[v] += fw[j][r] * su[kn + at(0, v)];
+                for (int v = 0; v < M; ++v) uf[v] += fw0[r] * su[kn + at(0, v)];
             }
             if constexpr (has_normal_flux<Eq>::value) {
                 Eq::fn(sd < 2 ? 0 : 1, uf, ff, P);
@@ -1049,7 +1078,7 @@ __device__ void local_body(const StepArgs<real>& a, int vblock, real* tile_buf =
             }
             if (i == 0) {
                 real nodev[M];
-                const int kadj = (sd & 1) ? fkn[j][N] : fkn[j][0];
+                const int kadj = fkn[j][0];
 #pragma unroll
                 for (int v = 0; v < M; ++v) nodev[v] = su[kadj + at(0, v)];
                 sig[j] = Eq::sig_trace(sd < 2 ? 0 : 1, uf, nodev, P);
@@ -1058,16 +1087,7 @@ __device__ void local_body(const StepArgs<real>& a, int vblock, real* tile_buf =
         if (i < S - 1) {
             const real ai = a.R.ta[i];
 #pragma unroll
-            for (int v = 0; v < M; ++v) {
-                real df = 0, dg = 0;
-#pragma unroll
-                for (int r = 0; r < nd; ++r) df += Dx[r] * sf[at(q * nd + r, v)];
-                if constexpr (DIM == 2) {
-#pragma unroll
-                    for (int r = 0; r < nd; ++r) dg += Dy[r] * sg[at(r * nd + p, v)];
-                }
-                ui[v] = un[v] - rdt * ai * (df * idx + dg * idy - s[v]);
-            }
+            for (int v = 0; v < M; ++v) ui[v] = un[v] - rdt * ai * (divergence(v) - s[v]);
         }
         elem_sync<np>();
     }
@@ -1082,16 +1102,7 @@ __device__ void local_body(const StepArgs<real>& a, int vblock, real* tile_buf =
     elem_sync<np>();
     real vol[M], Ut[FPL][M];
 #pragma unroll
-    for (int v = 0; v < M; ++v) {
-        real df = 0, dg = 0;
-#pragma unroll
-        for (int r = 0; r < nd; ++r) df += Dx[r] * sf[at(q * nd + r, v)];
-        if constexpr (DIM == 2) {
-#pragma unroll
-            for (int r = 0; r < nd; ++r) dg += Dy[r] * sg[at(r * nd + p, v)];
-        }
-        vol[v] = df * idx + dg * idy;
-    }
+    for (int v = 0; v < M; ++v) vol[v] = divergence(v);
 #pragma unroll
     for (int j = 0; j < FPL; ++j) {
         const int fp = k + j * np;
@@ -1105,8 +1116,8 @@ __device__ void local_body(const StepArgs<real>& a, int vblock, real* tile_buf =
             const int kn = fkn[j][r];
 #pragma unroll
             for (int v = 0; v < M; ++v) {
-                Ut[j][v] += fw[j][r] * su[kn + at(0, v)];
-                hf[v] += fw[j][r] * (sd < 2 ? sf[kn + at(0, v)] : sg[DIM == 2 ? kn + at(0, v) : 0]);
+                Ut[j][v] += fw0[r] * su[kn + at(0, v)];
+                hf[v] += fw0[r] * (sd < 2 ? sf[kn + at(0, v)] : sg[DIM == 2 ? kn + at(0, v) : 0]);
             }
         }
 #pragma unroll
@@ -1143,42 +1154,45 @@ __device__ void local_body(const StepArgs<real>& a, int vblock, real* tile_buf =
             const bool edge_face = sd == 0 ? tix == 0 : sd == 1 ? (tix == G::TX - 1 || ex + 1 >= a.nx)
                                  : sd == 2 ? tiy == 0 : (tiy == G::TY - 1 || ey + 1 >= a.ny);
             if (act && edge_face) {
-                real* base = sd < 2 ? a.trx : a.trY;
-                const int npt = sd < 2 ? nq : nd;
+                real* const lb = trace_at<Eq, N>(a, sd, side * C, e, t);
+                const size_t cs = trace_stride<Eq, N>(a);
 #pragma unroll
                 for (int v = 0; v < M; ++v) {
-                    base[((size_t)(side * C + v) * nes + e) * npt + t] = tr[j][v];
-                    base[((size_t)(side * C + M + v) * nes + e) * npt + t] = Ut[j][v];
+                    lb[v * cs] = tr[j][v];
+                    lb[(M + v) * cs] = Ut[j][v];
                 }
-                base[((size_t)(side * C + 2 * M) * nes + e) * npt + t] = sig[j];
+                lb[2 * M * cs] = sig[j];
             }
         }
         return;
     }
     if (!act) return;
-    const size_t gi = (size_t)e * np + k;
+    // one 64-bit address per lane and array; the variables and trace
+    // components lie whole planes apart (wavefront-uniform strides)
+    const size_t gi = (size_t)e * np + k, vs = nes * np;
+    real* const uhp = a.uHp + gi;
 #pragma unroll
     for (int v = 0; v < M; ++v) {
         real corr = (sh_h[le][v][nd + q] * a.R.bR[p] - sh_h[le][v][q] * a.R.bL[p]) * idx;
         if constexpr (DIM == 2)
             corr += (sh_h[le][v][3 * nd + p] * a.R.bR[q] - sh_h[le][v][2 * nd + p] * a.R.bL[q]) * idy;
-        a.uHp[(size_t)v * nes * np + gi] = un[v] - rdt * (vol[v] - Sa[v]) + rdt * corr;
-        if (src && a.dtS) a.dtS[(size_t)v * nes * np + gi] = rdt * Sa[v];
+        uhp[v * vs] = un[v] - rdt * (vol[v] - Sa[v]) + rdt * corr;
+        if (src && a.dtS) a.dtS[gi + v * vs] = rdt * Sa[v];
     }
 #pragma unroll
     for (int j = 0; j < FPL; ++j) {
         const int fp = k + j * np;
         if (j == FPL - 1 && fp >= NFP) break;
         const int sd = fside(fp), t = fpos(fp), side = sd & 1;
-        real* base = sd < 2 ? a.trx : a.trY;
-        const int npt = sd < 2 ? nq : nd;
+        real* const lb = trace_at<Eq, N>(a, sd, side * C, e, t);
+        const size_t cs = trace_stride<Eq, N>(a);
         const bool write_U = a.dissipation != DISS_D1;
 #pragma unroll
         for (int v = 0; v < M; ++v) {
-            base[((size_t)(side * C + v) * nes + e) * npt + t] = tr[j][v];
-            if (write_U) base[((size_t)(side * C + M + v) * nes + e) * npt + t] = Ut[j][v];
+            lb[v * cs] = tr[j][v];
+            if (write_U) lb[(M + v) * cs] = Ut[j][v];
         }
-        base[((size_t)(side * C + 2 * M) * nes + e) * npt + t] = sig[j];
+        lb[2 * M * cs] = sig[j];
     }
 }
 
@@ -1997,7 +2011,10 @@ __global__ void __launch_bounds__(256) k_face(const StepArgs<real> a) { face_bod
 template <class Eq, int N, class real, bool LIM, bool FU = false>
 __global__ void __launch_bounds__(256) k_update(const StepArgs<real> a)
 {
-    update_body<Eq, N, real, LIM, FU>(a, blockIdx.x);
+    // with the faces fused in and no limiter, the blocks of an XCD take one
+    // contiguous range of elements, so that the traces an element shares with
+    // its neighbours are fetched into one L2
+    update_body<Eq, N, real, LIM, FU>(a, FU && !LIM ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x);
 }
 
 // ----------------------------------------------------------------------------

@@ -18,12 +18,20 @@ struct Phys {
 };
 
 // reciprocal of the density: v_rcp_f32 (1 ulp for normal numbers) in the FP32
-// bulk arithmetic, a correctly rounded division in FP64
+// bulk arithmetic; in FP64 the hardware estimate refined by two Newton-Raphson
+// steps r <- r + r (1 - x r) (each squares the relative error), within about
+// one ulp of 1/x for normal x instead of the correctly rounded division
+// sequence (the density is positive and normal wherever the flux is used)
 template <class real>
 __device__ __forceinline__ real recip(real x)
 {
-    if constexpr (sizeof(real) == 4) return __builtin_amdgcn_rcpf(x);
-    else return (real)1 / x;
+    if constexpr (sizeof(real) == 4) {
+        return __builtin_amdgcn_rcpf(x);
+    } else {
+        double r = __builtin_amdgcn_rcp(x);
+        r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+        return __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+    }
 }
 
 // trace value, or the face-adjacent node where the trace density is not positive

@@ -1,0 +1,97 @@
+"""crkfr_autotune: the kernel-path autotuner and its JSON-lines cache.  The
+trials leave the solver as they found it (state, clock, counters bitwise);
+the chosen path is one that serves the configuration and steps like that
+path set by hand; a second solver of the same configuration takes the path
+from the cache without timing; a configuration that differs in any keyed
+field (grid, arithmetic, limiter) is timed anew and appended."""
+import json
+
+import numpy as np
+import pytest
+
+from paper_2502_07517_amd import crkfr as C
+from paper_2502_07517_amd import workloads as W
+from oracle_runs import cfl_for
+
+pytestmark = pytest.mark.gpu
+
+DOM = (-5.0, 5.0, -5.0, 5.0)
+
+
+def _solver(n, N=3, dtype=C.FP64, limited=False):
+    s = C.Solver(C.EULER2D, N, n, n, domain=DOM, dtype=dtype, cfl=cfl_for(N))
+    if limited:
+        s.set_limiter(blend=C.BLEND_MH, flux_limiter=1, scaling=1)
+    s.set_state(W.vortex2d(n, N, 0.0, DOM))
+    return s
+
+
+def test_autotune_restores_state_and_picks_a_serving_path(tmp_path):
+    cache = tmp_path / "tune.jsonl"
+    s = _solver(24)
+    s.step(0.0)
+    u0, d0 = s.get_state(), s.get_diag()[0]
+    r = s.autotune(steps=3, cache=cache)
+    assert not r["from_cache"]
+    assert set(r["ms_per_step"]) == {"split", "tile", "face_update"}     # N = 3, limiter off: all three
+    assert r["path"] == s.path_in_use()
+    assert min(r["ms_per_step"], key=r["ms_per_step"].get) == ("split", "tile", "face_update")[r["path"]]
+    np.testing.assert_array_equal(s.get_state(), u0)
+    d1 = s.get_diag()[0]
+    for k in ("steps", "t", "dt", "n_troubled", "mass"):
+        assert d1[k] == d0[k], k
+    # the tuned solver steps like one with that path set by hand
+    ref = _solver(24)
+    ref.step(0.0)
+    ref.set_path(r["path"])
+    for _ in range(3):
+        s.step(0.0)
+        ref.step(0.0)
+    np.testing.assert_array_equal(s.get_state(), ref.get_state())
+    entries = [json.loads(line) for line in cache.read_text().splitlines()]
+    assert len(entries) == 1 and "N=3" in entries[0]["key"] and "nx=24" in entries[0]["key"]
+    assert entries[0]["path"] == ("split", "tile", "face_update")[r["path"]]
+
+
+def test_autotune_cache_hit_and_keyed_misses(tmp_path):
+    cache = tmp_path / "tune.jsonl"
+    first = _solver(16).autotune(steps=2, cache=cache)
+    again = _solver(16)
+    r = again.autotune(steps=2, cache=cache)
+    assert r["from_cache"] and r["path"] == first["path"] and r["ms_per_step"] == {}
+    assert again.path_in_use() == first["path"]
+    # other grid, other arithmetic, limiter on: each timed and appended
+    for s in (_solver(20), _solver(16, dtype=C.MP32), _solver(16, limited=True)):
+        r = s.autotune(steps=2, cache=cache)
+        assert not r["from_cache"]
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 4
+    keys = [json.loads(line)["key"] for line in lines]
+    assert len(set(keys)) == 4
+    # limiter on: the tile-fused path does not serve it and is not timed
+    assert "tile" not in json.loads(lines[-1])["ms_per_step"]
+
+
+def test_autotune_errors(tmp_path):
+    s = C.Solver(C.EULER2D, 2, 8, 8)
+    with pytest.raises(C.CrkfrError):
+        s.autotune(steps=2)                   # no state
+    s.set_state(W.vortex2d(8, 2, 0.0, (0.0, 1.0, 0.0, 1.0)))
+    with pytest.raises(C.CrkfrError):
+        s.autotune(steps=0)
+    with pytest.raises(C.CrkfrError):
+        s.autotune(steps=1, cache=tmp_path / "no_such_dir" / "tune.jsonl")
+
+
+def test_default_path_rule():
+    """Without a chosen path: the face-update path with the limiter chain
+    off, the split path with it on; a path set by hand stays."""
+    s = C.Solver(C.EULER2D, 3, 8, 8)
+    assert s.path_in_use() == C.PATH_FACE_UPDATE
+    s.set_limiter(blend=C.BLEND_MH, flux_limiter=1, scaling=1)
+    assert s.path_in_use() == C.PATH_SPLIT
+    s.set_limiter(blend=C.BLEND_OFF, scaling=1)
+    assert s.path_in_use() == C.PATH_FACE_UPDATE
+    s.set_path(C.PATH_FACE_UPDATE)
+    s.set_limiter(blend=C.BLEND_MH, flux_limiter=1, scaling=1)
+    assert s.path_in_use() == C.PATH_FACE_UPDATE

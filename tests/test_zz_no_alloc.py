@@ -1,6 +1,7 @@
 """crkfr_step_static (one step without device allocation, the step's buffers in
 a static device array) against crkfr_step of a solver on the same input and
-time step: equal bitwise (the same kernels on the same path), on two calls
+time step: equal bitwise (the same kernels on the same path, the face-update
+path set on the solver), on two calls
 in a row, the second with a smaller grid, with and without the limiter
 chain; grids beyond the static array are refused."""
 import numpy as np
@@ -17,6 +18,7 @@ LIM = dict(blend=C.BLEND_MH, flux_limiter=1, scaling=1)
 
 def _solver_step(eq, N, nx, ny, u0, dt, bc, limiter, dom):
     s = C.Solver(eq, N, nx, ny, bc=bc, domain=dom, cfl=cfl_for(N))
+    s.set_path(C.PATH_FACE_UPDATE)      # the static step's kernel path
     if limiter:
         s.set_limiter(**limiter)
     s.set_state(u0)
