@@ -1999,8 +1999,18 @@ __device__ __forceinline__ int xcd_block(int b, int n)
     return x * per + (x < rem ? x : rem) + i;
 }
 
+// The FP32-bulk local phase of 2D Euler with 25-point elements needs a few
+// registers more than the 128 that keep four wavefronts per SIMD; held to
+// 128 it keeps four.
+template <class Eq, int N, class real>
+constexpr int local_min_waves()
+{
+    return sizeof(real) == 4 && Eq::M == 4 && Eq::DIM == 2 && N == 4 ? 4 : 1;
+}
+
 template <class Eq, int N, class real, bool LIM>
-__global__ void __launch_bounds__(256) k_local(const StepArgs<real> a)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(local_min_waves<Eq, N, real>())))
+k_local(const StepArgs<real> a)
 {
     local_body<Eq, N, real, LIM>(a, xcd_block(blockIdx.x, gridDim.x));
 }
@@ -2219,6 +2229,7 @@ __device__ __forceinline__ const StepArgs<real>& table_args(const StepArgs<real>
 template <class Eq, int N, class real, bool LIM, int PH>
 constexpr int batch_min_waves()
 {
+    if constexpr (PH == BPH_LOCAL) return local_min_waves<Eq, N, real>();
     return PH == BPH_UPDATE && LIM && sizeof(real) == 4 && Eq::M == 4 && Geo<Eq::DIM, N>::np == 16 ? 6 : 1;
 }
 
