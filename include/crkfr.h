@@ -283,14 +283,24 @@ double crkfr_fourier_cfl(int N, int stages, int system, int dissipation, int poi
  *    procedure, the faces inside the tile and the whole update of the
  *    elements whose four neighbours lie in the tile out of LDS, then the
  *    faces on tile edges and the update of the tile-edge elements follow;
- *    other configurations take CRKFR_PATH_FACE_UPDATE.
- * Until crkfr_set_path or crkfr_autotune chooses one, a solver takes the
- * face-update path with the limiter chain off and the split path with it on
+ *    other configurations take CRKFR_PATH_FACE_UPDATE;
+ *  CRKFR_PATH_CHECKER: for 2D grids with every boundary periodic, even nx
+ *    and ny, the limiter chain off, D2 and no source, the elements split
+ *    like a checkerboard (colour 0: ex + ey even): the local procedure of
+ *    colour 0 (its traces to HBM); the local procedure of colour 1, whose
+ *    four neighbours are all colour 0, with each of its face fluxes computed
+ *    once from its own traces and its neighbour's and stored, and its
+ *    update, without partial update or traces of its own in HBM; the update
+ *    of colour 0 from the stored face fluxes.  Other configurations take
+ *    CRKFR_PATH_FACE_UPDATE.
+ * Until crkfr_set_path or crkfr_autotune chooses one, a solver takes, with
+ * the limiter chain off, the checkerboard step where it serves and the
+ * face-update path elsewhere, and with the limiter chain on the split path
  * (the limited face flux would be computed by both neighbours).
  * crkfr_path_in_use returns the path the next step takes.  Errors: EINVAL,
  * ESTATE (the solver is a member of a live batch; batches take the face-update
  * path for groups whose members all have it, the split path otherwise). */
-enum { CRKFR_PATH_SPLIT = 0, CRKFR_PATH_TILE = 1, CRKFR_PATH_FACE_UPDATE = 2 };
+enum { CRKFR_PATH_SPLIT = 0, CRKFR_PATH_TILE = 1, CRKFR_PATH_FACE_UPDATE = 2, CRKFR_PATH_CHECKER = 3 };
 int crkfr_set_path(crkfr_solver* s, int path);
 int crkfr_path_in_use(const crkfr_solver* s);
 
@@ -312,14 +322,17 @@ int crkfr_path_in_use(const crkfr_solver* s);
 typedef struct {
     int path;          /* the path the next step takes (CRKFR_PATH_*) */
     int from_cache;    /* 1: read from the cache file, nothing timed */
-    float ms[3];       /* ms per step of split, tile-fused, face-update; 0: not timed */
+    float ms[4];       /* ms per step of split, tile-fused, face-update, checkerboard; 0: not timed */
 } crkfr_tune_result;
 int crkfr_autotune(crkfr_solver* s, int steps, const char* cache_path, crkfr_tune_result* out);
 
 /* Device time per kernel of the last step measured with HIP events (ms):
  * [0] local cRK, [1] x faces, [2] y faces, [3] update; with the tile-fused
  * step: [0] the tile kernel, [1], [2] the faces on tile edges, [3] the update
- * of the tile-edge elements; with the face-update path [1] and [2] are 0.
+ * of the tile-edge elements; with the face-update path [1] and [2] are 0;
+ * with the checkerboard step [0] the colour-0 local procedure, [1] the
+ * colour-1 kernel (local procedure, faces, update), [2] 0, [3] the colour-0
+ * update.
  * Needs timing = 1. */
 int crkfr_set_timing(crkfr_solver* s, int on);
 int crkfr_get_kernel_times(crkfr_solver* s, float* ms4);

@@ -16,7 +16,7 @@ CENTRAL_EA, CENTRAL_AE = 0, 1
 PERIODIC, OUTFLOW, FARFIELD, REFLECT, INFLOW = 0, 1, 2, 3, 4
 FP64, MP32 = 0, 1
 BLEND_OFF, BLEND_FO, BLEND_MH = 0, 1, 2
-PATH_SPLIT, PATH_TILE, PATH_FACE_UPDATE = 0, 1, 2
+PATH_SPLIT, PATH_TILE, PATH_FACE_UPDATE, PATH_CHECKER = 0, 1, 2, 3
 IND_PAPER, IND_CONST, IND_GIVEN, IND_LEARNED = 0, 1, 2, 3
 NVAR = {LINADV1D: 1, EULER1D: 3, EULER2D: 4, TENMOM2D: 6, BURGERS1D: 1, TENMOM1D: 6}
 EINADMISSIBLE_MEAN = -5
@@ -50,7 +50,7 @@ class Source(ctypes.Structure):
 
 
 class TuneResult(ctypes.Structure):
-    _fields_ = [("path", ctypes.c_int), ("from_cache", ctypes.c_int), ("ms", ctypes.c_float * 3)]
+    _fields_ = [("path", ctypes.c_int), ("from_cache", ctypes.c_int), ("ms", ctypes.c_float * 4)]
 
 
 class Diag(ctypes.Structure):
@@ -312,7 +312,7 @@ class Solver:
         _check(lib().crkfr_bind_state(self.h, ctypes.c_void_p(u.data_ptr())))
 
     def set_path(self, path):
-        """Kernel path of a step: PATH_SPLIT, PATH_TILE or PATH_FACE_UPDATE (default: face-update with
+        """Kernel path of a step: PATH_SPLIT, PATH_TILE, PATH_FACE_UPDATE or PATH_CHECKER (default: face-update with
         the limiter chain off, split with it on)."""
         _check(lib().crkfr_set_path(self.h, int(path)))
 
@@ -326,9 +326,9 @@ class Solver:
         r = TuneResult()
         _check(lib().crkfr_autotune(self.h, int(steps), None if cache is None else str(cache).encode(),
                                     ctypes.byref(r)))
-        names = ("split", "tile", "face_update")
+        names = ("split", "tile", "face_update", "checker")
         return {"path": r.path, "from_cache": bool(r.from_cache),
-                "ms_per_step": {names[i]: float(r.ms[i]) for i in range(3) if r.ms[i] > 0}}
+                "ms_per_step": {names[i]: float(r.ms[i]) for i in range(4) if r.ms[i] > 0}}
 
     def state_ptr(self):
         """Device address of the current FP64 nodal state."""

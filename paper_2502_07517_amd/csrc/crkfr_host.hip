@@ -592,7 +592,7 @@ static int run_io(const crkfr_solver* s, int phase, const double* uin, double* u
 
 static void free_all(crkfr_solver* s)
 {
-    void* ptrs[] = {s->bound ? nullptr : s->u[0], s->u[1], s->stats, s->edge_list, s->ubar[0], s->ubar[1], s->uHp, s->trx, s->trY, s->Fx, s->Gy, s->dtS,
+    void* ptrs[] = {s->bound ? nullptr : s->u[0], s->u[1], s->stats, s->edge_list, s->ubar[0], s->ubar[1], s->uHp, s->trx, s->trY, s->Fx, s->dtS,
                     s->ghost, s->alpha_raw, s->alpha_out, s->alpha_given, s->alpha_judge, s->feat,
                     s->dt_dev, s->t_dev, s->inflow,
                     s->rate_bits, s->diag, s->steps};
@@ -709,8 +709,13 @@ extern "C" int crkfr_create(const crkfr_config* cfg, void* hip_stream, crkfr_sol
     ok &= alloc(&s->uHp, nstate * rs);
     ok &= alloc(&s->trx, 2 * (size_t)s->C_max * ne * s->nq * rs);
     if (dim == 2) ok &= alloc(&s->trY, 2 * (size_t)s->C_max * ne * s->nd * rs);
-    ok &= alloc(&s->Fx, M * (size_t)cfg->ny * (cfg->nx + 1) * s->nq * rs);
-    if (dim == 2) ok &= alloc(&s->Gy, M * (size_t)(cfg->ny + 1) * cfg->nx * s->nd * rs);
+    {   // the x and y face fluxes in one allocation (the checkerboard step keeps
+        // the colour-1 elements' face fluxes, M ne / 2 4 (N + 1) values, in it)
+        const size_t fx = M * (size_t)cfg->ny * (cfg->nx + 1) * s->nq;
+        const size_t fy = dim == 2 ? M * (size_t)(cfg->ny + 1) * cfg->nx * s->nd : 0;
+        ok &= alloc(&s->Fx, (fx + fy) * rs);
+        if (dim == 2 && s->Fx) s->Gy = (char*)s->Fx + fx * rs;
+    }
     if (is_tenmom(cfg->equation)) ok &= alloc(&s->dtS, nstate * rs);
     ok &= alloc(&s->ghost, (2 * (size_t)cfg->ny * s->nq + (dim == 2 ? 2 * (size_t)cfg->nx * s->nd : 0)) * M * rs);
     bool any_inflow = false;
@@ -1044,23 +1049,37 @@ static int check_learned(const crkfr_solver* s)
 // the tile-fused step serves 2D Euler with elements of 4 or 16 points, the
 // limiter chain off and the D2 dissipation; elsewhere that path takes the
 // update with the faces fused in
+// the checkerboard step serves 2D grids with every boundary periodic, even
+// sides, the limiter chain off, D2 and no source
+static bool checker_serves(const crkfr_solver* s)
+{
+    bool ok = s->dim == 2 && s->lim.blend == CRKFR_BLEND_OFF && s->dissipation == CRKFR_DISS_D2 &&
+              s->cfg.nx % 2 == 0 && s->cfg.ny % 2 == 0 && !(s->src.enabled && is_tenmom(s->cfg.equation));
+    for (int i = 0; i < 4; ++i) ok = ok && s->cfg.bc[i] == CRKFR_BC_PERIODIC;
+    return ok;
+}
+
 static int path_in_use(const crkfr_solver* s)
 {
-    // unless the caller chose one: the faces fused into the update without
-    // the limiter chain, the split step with it (the limited face flux, done
-    // once per face there, would be computed by both neighbours)
+    // unless the caller chose one: without the limiter chain the checkerboard
+    // step where it serves, else the faces fused into the update; the split
+    // step with the limiter chain (the limited face flux, done once per face
+    // there, would be computed by both neighbours)
     const int p = s->path_set ? s->path
-                              : (s->lim.blend == CRKFR_BLEND_OFF ? CRKFR_PATH_FACE_UPDATE : CRKFR_PATH_SPLIT);
+                              : (s->lim.blend != CRKFR_BLEND_OFF ? CRKFR_PATH_SPLIT
+                                                                  : (checker_serves(s) ? CRKFR_PATH_CHECKER
+                                                                                       : CRKFR_PATH_FACE_UPDATE));
     if (p == CRKFR_PATH_TILE)
         return s->edge_list && s->lim.blend == CRKFR_BLEND_OFF && s->dissipation == CRKFR_DISS_D2
                    ? CRKFR_PATH_TILE : CRKFR_PATH_FACE_UPDATE;
+    if (p == CRKFR_PATH_CHECKER) return checker_serves(s) ? CRKFR_PATH_CHECKER : CRKFR_PATH_FACE_UPDATE;
     return p;
 }
 
 extern "C" int crkfr_set_path(crkfr_solver* s, int path)
 {
     if (!s) return fail(CRKFR_EINVAL, "null argument");
-    if (path < CRKFR_PATH_SPLIT || path > CRKFR_PATH_FACE_UPDATE) return fail(CRKFR_EINVAL, "bad step path");
+    if (path < CRKFR_PATH_SPLIT || path > CRKFR_PATH_CHECKER) return fail(CRKFR_EINVAL, "bad step path");
     if (s->batch_refs > 0) return fail(CRKFR_ESTATE, "solver is a batch member: destroy the batch first");
     s->path = path;
     s->path_set = true;
@@ -1089,7 +1108,7 @@ static std::string tune_key(const crkfr_solver* s)
     return buf;
 }
 
-static const char* const PATH_NAMES[3] = {"split", "tile", "face_update"};
+static const char* const PATH_NAMES[4] = {"split", "tile", "face_update", "checker"};
 
 // the path stored for key, or -1
 static int tune_cache_lookup(const char* path, const std::string& key)
@@ -1104,7 +1123,7 @@ static int tune_cache_lookup(const char* path, const std::string& key)
         const char* p = std::strstr(line, "\"path\": \"");
         if (!p) continue;
         p += std::strlen("\"path\": \"");
-        for (int i = 0; i < 3; ++i) {
+        for (int i = 0; i < 4; ++i) {
             const size_t n = std::strlen(PATH_NAMES[i]);
             if (std::strncmp(p, PATH_NAMES[i], n) == 0 && p[n] == '"') found = i;   // the last entry wins
         }
@@ -1179,7 +1198,7 @@ extern "C" int crkfr_autotune(crkfr_solver* s, int steps, const char* cache_path
     if (!rc && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
         rc = fail(CRKFR_EHIP, "hipEventCreate failed");
     int best = -1;
-    for (int p = 0; p < 3 && !rc; ++p) {
+    for (int p = 0; p < 4 && !rc; ++p) {
         s->path = p;
         s->path_set = true;
         if (path_in_use(s) != p) continue;       // the path does not serve this configuration
@@ -1212,7 +1231,7 @@ extern "C" int crkfr_autotune(crkfr_solver* s, int steps, const char* cache_path
         if (!f) return fail(CRKFR_EINVAL, std::string("cannot append to the autotune cache ") + cache_path);
         std::fprintf(f, "{\"key\": \"%s\", \"path\": \"%s\", \"ms_per_step\": {", key.c_str(), PATH_NAMES[best]);
         bool first = true;
-        for (int p = 0; p < 3; ++p) {
+        for (int p = 0; p < 4; ++p) {
             if (out->ms[p] <= 0.f) continue;
             std::fprintf(f, "%s\"%s\": %.6g", first ? "" : ", ", PATH_NAMES[p], (double)out->ms[p]);
             first = false;
@@ -1242,6 +1261,19 @@ static int enqueue_step(crkfr_solver* s, double dt_fixed, double t_end)
     const bool tm = s->timing;
     const int path = path_in_use(s);
     const bool tile = path == CRKFR_PATH_TILE, fu = path == CRKFR_PATH_FACE_UPDATE;
+    if (path == CRKFR_PATH_CHECKER) {
+        // colour 0 local; colour 1 local, faces and update; colour 0 update
+        if (tm) (void)hipEventRecord(s->ev[0], s->stream);
+        int rc = dispatch_step(s, PH_CB_LOCAL, in, out);
+        if (tm) (void)hipEventRecord(s->ev[1], s->stream);
+        if (!rc) rc = dispatch_step(s, PH_CB_WHITE, in, out);
+        if (tm) (void)hipEventRecord(s->ev[2], s->stream);
+        if (tm) (void)hipEventRecord(s->ev[3], s->stream);
+        if (!rc) rc = dispatch_step(s, PH_CB_UPDATE, in, out);
+        if (tm) (void)hipEventRecord(s->ev[4], s->stream);
+        s->cur = out;
+        return rc;
+    }
     if (tm) (void)hipEventRecord(s->ev[0], s->stream);
     int rc = dispatch_step(s, tile ? PH_TILE : PH_LOCAL, in, out);
     if (tm) (void)hipEventRecord(s->ev[1], s->stream);
@@ -1734,7 +1766,8 @@ extern "C" int crkfr_batch_create(crkfr_solver* const* solvers, int count, void*
         BatchGroup* g = nullptr;
         for (BatchGroup& gg : b->groups)
             if (gg.eq == s->cfg.equation && gg.N == s->cfg.N && gg.mp == s->mp && gg.lim == lim) g = &gg;
-        if (g && g->fu != (path_in_use(s) == CRKFR_PATH_FACE_UPDATE)) g->fu = false;
+        const bool mfu = path_in_use(s) == CRKFR_PATH_FACE_UPDATE || path_in_use(s) == CRKFR_PATH_CHECKER;
+        if (g && g->fu != mfu) g->fu = false;
         if (!g) {
             BatchGroup ng;
             std::memset(ng.d_args, 0, sizeof(ng.d_args));
@@ -1745,7 +1778,7 @@ extern "C" int crkfr_batch_create(crkfr_solver* const* solvers, int count, void*
             ng.N = s->cfg.N;
             ng.mp = s->mp;
             ng.lim = lim;
-            ng.fu = path_in_use(s) == CRKFR_PATH_FACE_UPDATE;
+            ng.fu = mfu;
             b->groups.push_back(ng);
             g = &b->groups.back();
         }

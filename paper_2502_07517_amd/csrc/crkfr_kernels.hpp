@@ -722,16 +722,41 @@ __device__ __forceinline__ real* trace_at(const StepArgs<real>& a, int sd, int c
     constexpr int npt = Eq::DIM == 2 ? N + 1 : 1;
     return (sd < 2 ? a.trx : a.trY) + (size_t)c * trace_stride<Eq, N>(a) + (size_t)e * npt + t;
 }
+// checkerboard step: element of index i among those of colour c (0: ex + ey
+// even, 1: odd) of a grid with an even number of columns (row-major, nx / 2
+// elements of each colour per row)
+__device__ __forceinline__ int cb_element(int i, int c, int nx)
+{
+    const int h = nx >> 1;
+    const int ey = (int)((unsigned)i / (unsigned)h), j = i - ey * h;
+    return ey * nx + 2 * j + ((ey + c) & 1);
+}
+// and the index of element (ex, ey) among those of its colour
+__device__ __forceinline__ int cb_index(int ex, int ey, int nx) { return ey * (nx >> 1) + (ex >> 1); }
+
+template <class Eq, int N, class real, int EB>
+__device__ __forceinline__ void update_finish(const StepArgs<real>& a, int e, int le, int k, bool act,
+                                              const real* unew, const real* FL, const real* FR, const real* GB,
+                                              const real* GT, const real* dts, int vblock);
+
 // TG = void: the split step (LGeo blocks of elements; uHp and the face traces
 // to HBM).  TG = a tile geometry: one tile of TX x TY elements per workgroup
 // (the tile-fused step); the element's stage arrays lie in tile_buf, uHp goes
 // to uhp_out (registers), the face traces to the element's part of tile_buf
 // and, for faces on the tile's edge, to HBM as well.
-template <class Eq, int N, class real, bool LIM, class TG = void>
+// CB (checkerboard step, periodic 2D grids of even sides, limiter off, D2):
+// 1 the elements of colour 0 (ex + ey even), as the split step; 2 the
+// elements of colour 1, whose four neighbours all have colour 0 and have
+// written their traces: each lane computes the flux of its face point from
+// its own traces (registers) and the neighbour's (HBM), stores it for the
+// colour-0 update, and the element is updated in place (no uHp, no traces
+// of its own in HBM).
+template <class Eq, int N, class real, bool LIM, class TG = void, int CB = 0>
 __device__ void local_body(const StepArgs<real>& a, int vblock, real* tile_buf = nullptr, real* uhp_out = nullptr)
 {
     constexpr bool TILE = !std::is_void<TG>::value;
     static_assert(!(TILE && LIM), "the tile-fused step has no limiter chain");
+    static_assert(!(CB && (LIM || TILE || Eq::DIM != 2)), "the checkerboard step: 2D, limiter off");
     using G = std::conditional_t<TILE, TG, LGeo<Eq::DIM, N>>;
     constexpr int M = Eq::M, DIM = Eq::DIM, nd = G::nd, nq = G::nq, np = G::np, EB = G::EB;
     const int S = a.stages;
@@ -772,6 +797,12 @@ __device__ void local_body(const StepArgs<real>& a, int vblock, real* tile_buf =
         ex = gx < a.nx ? gx : a.nx - 1;
         ey = gy < a.ny ? gy : a.ny - 1;
         e = ey * a.nx + ex;
+    } else if constexpr (CB != 0) {
+        const int i = vblock * EB + le, nc = a.ne >> 1;
+        act = i < nc;
+        e = cb_element(act ? i : nc - 1, CB - 1, a.nx);
+        ey = (int)((unsigned)e / (unsigned)a.nx);
+        ex = e - ey * a.nx;
     } else {
         const int e0 = vblock * EB + le;
         act = e0 < a.ne;
@@ -1166,6 +1197,73 @@ __device__ void local_body(const StepArgs<real>& a, int vblock, real* tile_buf =
         }
         return;
     }
+    if constexpr (CB == 2) {
+        // the partial update in registers, then the element's face fluxes
+        __shared__ real sh_Fc[EB][NFP][M];
+        real uhp[M];
+#pragma unroll
+        for (int v = 0; v < M; ++v) {
+            real corr = (sh_h[le][v][nd + q] * a.R.bR[p] - sh_h[le][v][q] * a.R.bL[p]) * idx;
+            corr += (sh_h[le][v][3 * nd + p] * a.R.bR[q] - sh_h[le][v][2 * nd + p] * a.R.bL[q]) * idy;
+            uhp[v] = un[v] - rdt * (vol[v] - Sa[v]) + rdt * corr;
+        }
+        const size_t cs = trace_stride<Eq, N>(a);
+        const size_t nwf = (size_t)(a.ne >> 1) * NFP;   // stride of one variable's colour-1 face fluxes
+#pragma unroll
+        for (int j = 0; j < FPL; ++j) {
+            const int fp = k + j * np;
+            if (j == FPL - 1 && fp >= NFP) break;
+            const int sd = fside(fp), t = fpos(fp), side = sd & 1;
+            const bool xd = sd < 2;
+            // the neighbour across this face (every boundary periodic) and its traces on the facing side
+            const int nxe = xd ? (side ? (ex + 1 == a.nx ? 0 : ex + 1) : (ex == 0 ? a.nx - 1 : ex - 1)) : ex;
+            const int nye = xd ? ey : (side ? (ey + 1 == a.ny ? 0 : ey + 1) : (ey == 0 ? a.ny - 1 : ey - 1));
+            const real* nb = trace_at<Eq, N>(a, sd ^ 1, (1 - side) * C, cb_index(nxe, nye, a.nx), t);
+            real Fm[M], Fp[M], Um[M], Up[M], sm, sp;
+#pragma unroll
+            for (int v = 0; v < M; ++v) {
+                const real Fn = nb[v * cs], Un = nb[(M + v) * cs];
+                Fm[v] = side ? tr[j][v] : Fn;
+                Fp[v] = side ? Fn : tr[j][v];
+                Um[v] = side ? Ut[j][v] : Un;
+                Up[v] = side ? Un : Ut[j][v];
+            }
+            {
+                const real sn = nb[2 * M * cs];
+                sm = side ? sig[j] : sn;
+                sp = side ? sn : sig[j];
+            }
+            const real lam = fmax(sm, sp);
+            real F[M];
+#pragma unroll
+            for (int v = 0; v < M; ++v) {
+                F[v] = (real)0.5 * (Fm[v] + Fp[v]) - (real)0.5 * lam * (Up[v] - Um[v]);
+                sh_Fc[le][fp][v] = F[v];
+            }
+            if (act) {
+                // the element's face fluxes for the colour-0 update, by colour
+                // index and face point (whole cache lines)
+                real* const out = a.Fx + (size_t)cb_index(ex, ey, a.nx) * NFP + fp;
+#pragma unroll
+                for (int v = 0; v < M; ++v) out[v * nwf] = F[v];
+            }
+        }
+        elem_sync<np>();
+        real FLv[M], FRv[M], GBv[M], GTv[M], unew[M], dts[M];
+#pragma unroll
+        for (int v = 0; v < M; ++v) {
+            FLv[v] = sh_Fc[le][q][v];
+            FRv[v] = sh_Fc[le][nd + q][v];
+            real val = uhp[v] - rdt * idx * (FRv[v] * a.R.bR[p] - FLv[v] * a.R.bL[p]);
+            GBv[v] = sh_Fc[le][2 * nd + p][v];
+            GTv[v] = sh_Fc[le][3 * nd + p][v];
+            val -= rdt * idy * (GTv[v] * a.R.bR[q] - GBv[v] * a.R.bL[q]);
+            unew[v] = val;
+            dts[v] = 0;
+        }
+        update_finish<Eq, N, real, EB>(a, e, le, k, act, unew, FLv, FRv, GBv, GTv, dts, vblock);
+        return;
+    }
     if (!act) return;
     // one 64-bit address per lane and array; the variables and trace
     // components lie whole planes apart (wavefront-uniform strides)
@@ -1184,7 +1282,9 @@ __device__ void local_body(const StepArgs<real>& a, int vblock, real* tile_buf =
         const int fp = k + j * np;
         if (j == FPL - 1 && fp >= NFP) break;
         const int sd = fside(fp), t = fpos(fp), side = sd & 1;
-        real* const lb = trace_at<Eq, N>(a, sd, side * C, e, t);
+        // the checkerboard's colour 0 stores its traces by colour index, so
+        // that they fill whole cache lines
+        real* const lb = trace_at<Eq, N>(a, sd, side * C, CB ? cb_index(ex, ey, a.nx) : e, t);
         const size_t cs = trace_stride<Eq, N>(a);
         const bool write_U = a.dissipation != DISS_D1;
 #pragma unroll
@@ -1715,7 +1815,7 @@ __device__ __forceinline__ void update_finish(const StepArgs<real>& a, int e, in
 // the element's lanes first compute its 4 (N+1) face fluxes (each face is
 // computed by the elements on both sides, in the same arithmetic) and its
 // smoothed alpha; without FU the face phases have stored them.
-template <class Eq, int N, class real, bool LIM, bool FU = false>
+template <class Eq, int N, class real, bool LIM, bool FU = false, int CB = 0>
 __device__ void update_body(const StepArgs<real>& a, int vblock)
 {
     using G = Geo<Eq::DIM, N>;
@@ -1730,9 +1830,11 @@ __device__ void update_body(const StepArgs<real>& a, int vblock)
     const int le = threadIdx.x / np, k = threadIdx.x - le * np;
     const int p = k % nd, q = k / nd;
     const int e0 = vblock * EB + le;
-    const int nel = a.edge_list ? a.n_edge : a.ne;
+    // CB = 1: the colour-0 elements of the checkerboard step
+    const int nel = a.edge_list ? a.n_edge : (CB ? a.ne >> 1 : a.ne);
     const bool act = e0 < nel;
-    const int e = a.edge_list ? a.edge_list[act ? e0 : nel - 1] : (act ? e0 : a.ne - 1);
+    const int e = a.edge_list ? a.edge_list[act ? e0 : nel - 1]
+                              : (CB ? cb_element(act ? e0 : nel - 1, 0, a.nx) : (act ? e0 : a.ne - 1));
     const int ey = (int)((unsigned)e / (unsigned)a.nx), ex = e - ey * a.nx;
     const double dt = *a.dt_dev;
     const real rdt = (real)dt, idx = (real)a.idx, idy = (real)a.idy;
@@ -1750,15 +1852,29 @@ __device__ void update_body(const StepArgs<real>& a, int vblock)
         }
         elem_sync<np>();
     }
+    // CB: the colour-0 element's face fluxes, stored by its colour-1
+    // neighbours (every boundary periodic): left face = the left neighbour's
+    // right face, and so on
+    size_t cL = 0, cR = 0, cB = 0, cT = 0, nwf = 0;
+    if constexpr (CB != 0 && DIM == 2) {
+        constexpr int NF = 4 * nd;
+        nwf = (size_t)(a.ne >> 1) * NF;
+        const int exl = ex == 0 ? a.nx - 1 : ex - 1, exr = ex + 1 == a.nx ? 0 : ex + 1;
+        const int eyb = ey == 0 ? a.ny - 1 : ey - 1, eyt = ey + 1 == a.ny ? 0 : ey + 1;
+        cL = (size_t)cb_index(exl, ey, a.nx) * NF + nd + q;
+        cR = (size_t)cb_index(exr, ey, a.nx) * NF + q;
+        cB = (size_t)cb_index(ex, eyb, a.nx) * NF + 3 * nd + p;
+        cT = (size_t)cb_index(ex, eyt, a.nx) * NF + 2 * nd + p;
+    }
     real uH[M], FLv[M], FRv[M], GBv[M], GTv[M], dts[M];
 #pragma unroll
     for (int v = 0; v < M; ++v) {
-        FLv[v] = FU ? sh_F[FU ? le : 0][DIM == 2 ? q : 0][v] : a.Fx[v * nfx + iL];
-        FRv[v] = FU ? sh_F[FU ? le : 0][DIM == 2 ? nd + q : 1][v] : a.Fx[v * nfx + iR];
+        FLv[v] = FU ? sh_F[FU ? le : 0][DIM == 2 ? q : 0][v] : (CB ? a.Fx[v * nwf + cL] : a.Fx[v * nfx + iL]);
+        FRv[v] = FU ? sh_F[FU ? le : 0][DIM == 2 ? nd + q : 1][v] : (CB ? a.Fx[v * nwf + cR] : a.Fx[v * nfx + iR]);
         real val = a.uHp[v * nes * np + gi] - rdt * idx * (FRv[v] * a.R.bR[p] - FLv[v] * a.R.bL[p]);
         if constexpr (DIM == 2) {
-            GBv[v] = FU ? sh_F[FU ? le : 0][2 * nd + p][v] : a.Gy[v * nfy + iB];
-            GTv[v] = FU ? sh_F[FU ? le : 0][3 * nd + p][v] : a.Gy[v * nfy + iT];
+            GBv[v] = FU ? sh_F[FU ? le : 0][2 * nd + p][v] : (CB ? a.Fx[v * nwf + cB] : a.Gy[v * nfy + iB]);
+            GTv[v] = FU ? sh_F[FU ? le : 0][3 * nd + p][v] : (CB ? a.Fx[v * nwf + cT] : a.Gy[v * nfy + iT]);
             val -= rdt * idy * (GTv[v] * a.R.bR[q] - GBv[v] * a.R.bL[q]);
         } else {
             GBv[v] = 0;
@@ -2017,6 +2133,25 @@ k_local(const StepArgs<real> a)
 
 template <class Eq, int N, class real, bool LIM, int D>
 __global__ void __launch_bounds__(256) k_face(const StepArgs<real> a) { face_body<Eq, N, real, LIM, D>(a, blockIdx.x); }
+
+// the checkerboard step: colour 0 local, colour 1 local + faces + update,
+// colour 0 update from the stored face fluxes
+template <class Eq, int N, class real>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(local_min_waves<Eq, N, real>())))
+k_cb_local(const StepArgs<real> a)
+{
+    if constexpr (Eq::DIM == 2) local_body<Eq, N, real, false, void, 1>(a, xcd_block(blockIdx.x, gridDim.x));
+}
+template <class Eq, int N, class real>
+__global__ void __launch_bounds__(256) k_cb_white(const StepArgs<real> a)
+{
+    if constexpr (Eq::DIM == 2) local_body<Eq, N, real, false, void, 2>(a, xcd_block(blockIdx.x, gridDim.x));
+}
+template <class Eq, int N, class real>
+__global__ void __launch_bounds__(256) k_cb_update(const StepArgs<real> a)
+{
+    update_body<Eq, N, real, false, false, 1>(a, blockIdx.x);
+}
 
 template <class Eq, int N, class real, bool LIM, bool FU = false>
 __global__ void __launch_bounds__(256) k_update(const StepArgs<real> a)

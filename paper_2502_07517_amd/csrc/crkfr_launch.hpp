@@ -7,7 +7,7 @@ namespace crkfr {
 
 enum { PH_LOCAL = 0, PH_FACE_X = 1, PH_FACE_Y = 2, PH_UPDATE = 3, PH_IMPORT = 4, PH_EXPORT = 5, PH_GHOST = 6,
        PH_FEATURES = 7, PH_STATS = 8, PH_TILE = 9, PH_TILE_FACE_X = 10, PH_TILE_FACE_Y = 11, PH_EDGE_UPDATE = 12,
-       PH_UPDATE_FU = 13 };
+       PH_UPDATE_FU = 13, PH_CB_LOCAL = 14, PH_CB_WHITE = 15, PH_CB_UPDATE = 16 };
 
 template <template <class> class EqT, int N, class real, bool LIM>
 static int launch_step_phase(int phase, const StepArgs<real>& a, hipStream_t st)
@@ -60,6 +60,22 @@ static int launch_step_phase(int phase, const StepArgs<real>& a, hipStream_t st)
                 hipLaunchKernelGGL((k_tile_face<Eq, N, real, 1>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
                                    st, a);
             }
+            return 0;
+        }
+        return -1;
+    case PH_CB_LOCAL:
+    case PH_CB_WHITE:
+    case PH_CB_UPDATE:
+        // the checkerboard step: 2D, limiter off, half the elements per launch
+        if constexpr (Eq::DIM == 2 && !LIM) {
+            using LG = LGeo<Eq::DIM, N>;
+            const int nc = a.ne / 2;
+            if (phase == PH_CB_LOCAL)
+                hipLaunchKernelGGL((k_cb_local<Eq, N, real>), dim3((nc + LG::EB - 1) / LG::EB), dim3(LG::BLOCK), 0, st, a);
+            else if (phase == PH_CB_WHITE)
+                hipLaunchKernelGGL((k_cb_white<Eq, N, real>), dim3((nc + LG::EB - 1) / LG::EB), dim3(LG::BLOCK), 0, st, a);
+            else
+                hipLaunchKernelGGL((k_cb_update<Eq, N, real>), dim3((nc + G::EB - 1) / G::EB), dim3(G::BLOCK), 0, st, a);
             return 0;
         }
         return -1;

@@ -16,6 +16,7 @@ from oracle_runs import cfl_for
 pytestmark = pytest.mark.gpu
 
 DOM = (-5.0, 5.0, -5.0, 5.0)
+NAMES = ("split", "tile", "face_update", "checker")
 
 
 def _solver(n, N=3, dtype=C.FP64, limited=False):
@@ -33,9 +34,10 @@ def test_autotune_restores_state_and_picks_a_serving_path(tmp_path):
     u0, d0 = s.get_state(), s.get_diag()[0]
     r = s.autotune(steps=3, cache=cache)
     assert not r["from_cache"]
-    assert set(r["ms_per_step"]) == {"split", "tile", "face_update"}     # N = 3, limiter off: all three
+    # N = 3, periodic 24 x 24, limiter off: every path serves it
+    assert set(r["ms_per_step"]) == {"split", "tile", "face_update", "checker"}
     assert r["path"] == s.path_in_use()
-    assert min(r["ms_per_step"], key=r["ms_per_step"].get) == ("split", "tile", "face_update")[r["path"]]
+    assert min(r["ms_per_step"], key=r["ms_per_step"].get) == NAMES[r["path"]]
     np.testing.assert_array_equal(s.get_state(), u0)
     d1 = s.get_diag()[0]
     for k in ("steps", "t", "dt", "n_troubled", "mass"):
@@ -50,7 +52,7 @@ def test_autotune_restores_state_and_picks_a_serving_path(tmp_path):
     np.testing.assert_array_equal(s.get_state(), ref.get_state())
     entries = [json.loads(line) for line in cache.read_text().splitlines()]
     assert len(entries) == 1 and "N=3" in entries[0]["key"] and "nx=24" in entries[0]["key"]
-    assert entries[0]["path"] == ("split", "tile", "face_update")[r["path"]]
+    assert entries[0]["path"] == NAMES[r["path"]]
 
 
 def test_autotune_cache_hit_and_keyed_misses(tmp_path):
@@ -68,8 +70,9 @@ def test_autotune_cache_hit_and_keyed_misses(tmp_path):
     assert len(lines) == 4
     keys = [json.loads(line)["key"] for line in lines]
     assert len(set(keys)) == 4
-    # limiter on: the tile-fused path does not serve it and is not timed
-    assert "tile" not in json.loads(lines[-1])["ms_per_step"]
+    # limiter on: the tile-fused and checkerboard paths do not serve it and are not timed
+    timed = json.loads(lines[-1])["ms_per_step"]
+    assert "tile" not in timed and "checker" not in timed
 
 
 def test_autotune_errors(tmp_path):
@@ -84,14 +87,19 @@ def test_autotune_errors(tmp_path):
 
 
 def test_default_path_rule():
-    """Without a chosen path: the face-update path with the limiter chain
-    off, the split path with it on; a path set by hand stays."""
+    """Without a chosen path: with the limiter chain off the checkerboard
+    step where it serves (2D, periodic, even sides), else the face-update
+    path; the split path with the limiter chain on; a path set by hand
+    stays."""
     s = C.Solver(C.EULER2D, 3, 8, 8)
-    assert s.path_in_use() == C.PATH_FACE_UPDATE
+    assert s.path_in_use() == C.PATH_CHECKER
     s.set_limiter(blend=C.BLEND_MH, flux_limiter=1, scaling=1)
     assert s.path_in_use() == C.PATH_SPLIT
     s.set_limiter(blend=C.BLEND_OFF, scaling=1)
-    assert s.path_in_use() == C.PATH_FACE_UPDATE
+    assert s.path_in_use() == C.PATH_CHECKER
+    assert C.Solver(C.EULER2D, 3, 9, 8).path_in_use() == C.PATH_FACE_UPDATE
+    assert C.Solver(C.EULER2D, 3, 8, 8, bc=(C.FARFIELD,) * 4).path_in_use() == C.PATH_FACE_UPDATE
+    assert C.Solver(C.EULER1D, 3, 8).path_in_use() == C.PATH_FACE_UPDATE
     s.set_path(C.PATH_FACE_UPDATE)
     s.set_limiter(blend=C.BLEND_MH, flux_limiter=1, scaling=1)
     assert s.path_in_use() == C.PATH_FACE_UPDATE

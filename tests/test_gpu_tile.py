@@ -138,7 +138,8 @@ def test_tile_path_selection():
              ((C.EULER2D, 3, 8, 8), {"blend": C.BLEND_MH}, False)]
     for args, lim, want in cases:
         s = C.Solver(*args)
-        assert s.path_in_use() == C.PATH_FACE_UPDATE          # the default
+        # the default without the limiter chain: the checkerboard step on periodic 2D grids
+        assert s.path_in_use() == (C.PATH_CHECKER if args[0] != C.EULER1D else C.PATH_FACE_UPDATE)
         s.set_path(C.PATH_TILE)
         if lim:
             s.set_limiter(**lim)
@@ -152,7 +153,7 @@ def test_tile_path_selection():
     s.set_scheme(dissipation=C.DISS_D2, central=C.CENTRAL_AE)
     assert s.path_in_use() == C.PATH_TILE
     with pytest.raises(C.CrkfrError):
-        s.set_path(3)
+        s.set_path(4)
 
 
 def test_tile_extrapolated_central_part():
