@@ -161,6 +161,24 @@ __device__ __forceinline__ float dpp_float(float x)
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
 }
 constexpr int DPP_QUAD_XOR1 = 0xB1, DPP_QUAD_XOR2 = 0x4E, DPP_ROW_ROR = 0x120;   // + n for row_ror:n
+// the value of lane (i + S) mod 4 of lane i's quad (quad_perm [S, S+1, S+2, S+3] mod 4)
+constexpr int dpp_quad_rot_ctrl(int S)
+{
+    return ((S + 0) & 3) | (((S + 1) & 3) << 2) | (((S + 2) & 3) << 4) | (((S + 3) & 3) << 6);
+}
+template <int S, class real>
+__device__ __forceinline__ real dpp_quad_rot(real x)
+{
+    if constexpr (sizeof(real) == 8) return dpp_double<dpp_quad_rot_ctrl(S)>(x);
+    else return dpp_float<dpp_quad_rot_ctrl(S)>(x);
+}
+// the value of lane (i - S) mod 16 of lane i's row (row_ror:S)
+template <int S, class real>
+__device__ __forceinline__ real dpp_row_ror(real x)
+{
+    if constexpr (sizeof(real) == 8) return dpp_double<DPP_ROW_ROR + S>(x);
+    else return dpp_float<DPP_ROW_ROR + S>(x);
+}
 
 template <int np>
 __device__ __forceinline__ constexpr bool elem_in_dpp() { return np == 2 || np == 4 || np == 16; }
@@ -1038,20 +1056,48 @@ __device__ void local_body(const StepArgs<real>& a, int vblock, real* tile_buf =
     }
     const real* fw0 = a.R.l0;
     // rows of the derivative matrix scaled by the inverse element widths: the
-    // divergence d f / dx + d g / dy is then one chain of products
+    // divergence d f / dx + d g / dy is then one chain of products.
+    // 16-point elements (N = 3 in 2D) fill a DPP row of 16 lanes with their
+    // x lines in quads: the line values come from the neighbouring lanes by
+    // quad rotations (x) and row rotations by 4, 8, 12 (y) instead of through
+    // LDS, and the coefficients are taken in the rotated order
+    // (not for the limited FP64 kernel: its registers would exceed the 168
+    // that keep three wavefronts per SIMD)
+    constexpr bool DPPD = DIM == 2 && np == 16 && !(LIM && sizeof(real) == 8);
     real Dx[nd], Dy[nd];
 #pragma unroll
-    for (int r = 0; r < nd; ++r) { Dx[r] = a.R.D[p][r] * idx; Dy[r] = DIM == 2 ? a.R.D[q][r] * idy : (real)0; }
-    // d f / dx + d g / dy at this lane's node from the arrays in LDS
-    auto divergence = [&](int v) {
-        real d = Dx[0] * sf[at(q * nd, v)];
-#pragma unroll
-        for (int r = 1; r < nd; ++r) d += Dx[r] * sf[at(q * nd + r, v)];
-        if constexpr (DIM == 2) {
-#pragma unroll
-            for (int r = 0; r < nd; ++r) d += Dy[r] * sg[at(r * nd + p, v)];
+    for (int r = 0; r < nd; ++r) {
+        if constexpr (DPPD) {
+            Dx[r] = a.R.D[p][(p + r) & 3] * idx;     // lane (p + r) mod 4 of the quad
+            Dy[r] = a.R.D[q][(q - r) & 3] * idy;     // lane 4 ((q - r) mod 4) + p of the row
+        } else {
+            Dx[r] = a.R.D[p][r] * idx;
+            Dy[r] = DIM == 2 ? a.R.D[q][r] * idy : (real)0;
         }
-        return d;
+    }
+    // d f / dx + d g / dy at this lane's node: from registers (fv, gv: this
+    // lane's values) across the lanes, or from the arrays in LDS
+    auto divergence = [&](const real* fv, const real* gv, int v) {
+        if constexpr (DPPD) {
+            real d = Dx[0] * fv[v];
+            d += Dx[1] * dpp_quad_rot<1>(fv[v]);
+            d += Dx[2] * dpp_quad_rot<2>(fv[v]);
+            d += Dx[3] * dpp_quad_rot<3>(fv[v]);
+            d += Dy[0] * gv[v];
+            d += Dy[1] * dpp_row_ror<4>(gv[v]);
+            d += Dy[2] * dpp_row_ror<8>(gv[v]);
+            d += Dy[3] * dpp_row_ror<12>(gv[v]);
+            return d;
+        } else {
+            real d = Dx[0] * sf[at(q * nd, v)];
+#pragma unroll
+            for (int r = 1; r < nd; ++r) d += Dx[r] * sf[at(q * nd + r, v)];
+            if constexpr (DIM == 2) {
+#pragma unroll
+                for (int r = 0; r < nd; ++r) d += Dy[r] * sg[at(r * nd + p, v)];
+            }
+            return d;
+        }
     };
 
 #pragma unroll 1
@@ -1071,8 +1117,10 @@ __device__ void local_body(const StepArgs<real>& a, int vblock, real* tile_buf =
             U[v] += bi * ui[v];
             if (src) Sa[v] += bi * s[v];
             su[at(k, v)] = ui[v];
-            sf[at(k, v)] = f[v];
-            if constexpr (DIM == 2) sg[at(k, v)] = g[v];
+            if constexpr (!DPPD) {
+                sf[at(k, v)] = f[v];
+                if constexpr (DIM == 2) sg[at(k, v)] = g[v];
+            }
         }
         elem_sync<np>();
         // EA traces: normal flux of the interpolated stage value at the face points
@@ -1118,7 +1166,7 @@ __device__ void local_body(const StepArgs<real>& a, int vblock, real* tile_buf =
         if (i < S - 1) {
             const real ai = a.R.ta[i];
 #pragma unroll
-            for (int v = 0; v < M; ++v) ui[v] = un[v] - rdt * ai * (divergence(v) - s[v]);
+            for (int v = 0; v < M; ++v) ui[v] = un[v] - rdt * ai * (divergence(f, g, v) - s[v]);
         }
         elem_sync<np>();
     }
@@ -1133,7 +1181,7 @@ __device__ void local_body(const StepArgs<real>& a, int vblock, real* tile_buf =
     elem_sync<np>();
     real vol[M], Ut[FPL][M];
 #pragma unroll
-    for (int v = 0; v < M; ++v) vol[v] = divergence(v);
+    for (int v = 0; v < M; ++v) vol[v] = divergence(F, Gs, v);
 #pragma unroll
     for (int j = 0; j < FPL; ++j) {
         const int fp = k + j * np;
@@ -2118,14 +2166,14 @@ __device__ __forceinline__ int xcd_block(int b, int n)
 // The FP32-bulk local phase of 2D Euler with 25-point elements needs a few
 // registers more than the 128 that keep four wavefronts per SIMD; held to
 // 128 it keeps four.
-template <class Eq, int N, class real>
+template <class Eq, int N, class real, bool LIM = false>
 constexpr int local_min_waves()
 {
     return sizeof(real) == 4 && Eq::M == 4 && Eq::DIM == 2 && N == 4 ? 4 : 1;
 }
 
 template <class Eq, int N, class real, bool LIM>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(local_min_waves<Eq, N, real>())))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(local_min_waves<Eq, N, real, LIM>())))
 k_local(const StepArgs<real> a)
 {
     local_body<Eq, N, real, LIM>(a, xcd_block(blockIdx.x, gridDim.x));
@@ -2364,7 +2412,7 @@ __device__ __forceinline__ const StepArgs<real>& table_args(const StepArgs<real>
 template <class Eq, int N, class real, bool LIM, int PH>
 constexpr int batch_min_waves()
 {
-    if constexpr (PH == BPH_LOCAL) return local_min_waves<Eq, N, real>();
+    if constexpr (PH == BPH_LOCAL) return local_min_waves<Eq, N, real, LIM>();
     return PH == BPH_UPDATE && LIM && sizeof(real) == 4 && Eq::M == 4 && Geo<Eq::DIM, N>::np == 16 ? 6 : 1;
 }
 
