@@ -1316,7 +1316,8 @@ __device__ void local_body(const StepArgs<real>& a, int vblock, real* tile_buf =
     // one 64-bit address per lane and array; the variables and trace
     // components lie whole planes apart (wavefront-uniform strides)
     const size_t gi = (size_t)e * np + k, vs = nes * np;
-    real* const uhp = a.uHp + gi;
+    // (the checkerboard's colour 0 stores its partial update by colour index)
+    real* const uhp = a.uHp + (CB ? (size_t)cb_index(ex, ey, a.nx) * np + k : gi);
 #pragma unroll
     for (int v = 0; v < M; ++v) {
         real corr = (sh_h[le][v][nd + q] * a.R.bR[p] - sh_h[le][v][q] * a.R.bL[p]) * idx;
@@ -1919,7 +1920,8 @@ __device__ void update_body(const StepArgs<real>& a, int vblock)
     for (int v = 0; v < M; ++v) {
         FLv[v] = FU ? sh_F[FU ? le : 0][DIM == 2 ? q : 0][v] : (CB ? a.Fx[v * nwf + cL] : a.Fx[v * nfx + iL]);
         FRv[v] = FU ? sh_F[FU ? le : 0][DIM == 2 ? nd + q : 1][v] : (CB ? a.Fx[v * nwf + cR] : a.Fx[v * nfx + iR]);
-        real val = a.uHp[v * nes * np + gi] - rdt * idx * (FRv[v] * a.R.bR[p] - FLv[v] * a.R.bL[p]);
+        real val = a.uHp[v * nes * np + (CB ? (size_t)cb_index(ex, ey, a.nx) * np + k : gi)] -
+                   rdt * idx * (FRv[v] * a.R.bR[p] - FLv[v] * a.R.bL[p]);
         if constexpr (DIM == 2) {
             GBv[v] = FU ? sh_F[FU ? le : 0][2 * nd + p][v] : (CB ? a.Fx[v * nwf + cB] : a.Gy[v * nfy + iB]);
             GTv[v] = FU ? sh_F[FU ? le : 0][3 * nd + p][v] : (CB ? a.Fx[v * nwf + cT] : a.Gy[v * nfy + iT]);
