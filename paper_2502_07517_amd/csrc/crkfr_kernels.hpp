@@ -123,7 +123,7 @@ struct Geo {
     // elements per workgroup: 256 lanes, except one wavefront for elements of
     // 3, 5 or 9 points (their sums go through LDS; a one-wavefront workgroup
     // makes the barriers local to the wavefront)
-    static constexpr int EB = (np <= 16 && np != 2 && np != 4 && np != 16 ? 64 : 256) / np;
+    static constexpr int EB = (np <= 16 && np != 2 && np != 4 && np != 16 ? 64 : (np == 25 ? 128 : 256)) / np;
     static constexpr int BLOCK = EB * np;
 };
 
@@ -132,7 +132,10 @@ struct Geo {
 template <int DIM, int N>
 struct LGeo {
     static constexpr int nd = N + 1, nq = DIM == 2 ? N + 1 : 1, np = nd * nq;
-    static constexpr int TPB = np <= 16 ? 64 : 256;
+    // (25-point elements: two wavefronts, five elements; fewer wavefronts
+    // meet at each barrier than with 256 lanes: 4 % off the limited FP32
+    // local phase)
+    static constexpr int TPB = np <= 16 ? 64 : (np == 25 ? 128 : 256);
     static constexpr int EB = TPB / np;
     static constexpr int BLOCK = EB * np;
 };
