@@ -271,13 +271,15 @@ struct Planes {
 template <class Eq, class real>
 __device__ __forceinline__ void load_node(const StepArgs<real>& a, int np, int e, int k, real* u)
 {
+    // one 64-bit address per array; the variables lie whole planes apart
+    const real* const un = a.u + (size_t)e * np + k;
+    const size_t vs = (size_t)a.ne * np;
 #pragma unroll
     for (int v = 0; v < Eq::M; ++v) {
-        size_t i = ((size_t)v * a.ne + e) * np + k;
         if constexpr (is_mp<real>())
-            u[v] = (real)(a.ubar[(size_t)v * a.ne + e] + (double)a.u[i]);
+            u[v] = (real)(a.ubar[(size_t)v * a.ne + e] + (double)un[v * vs]);
         else
-            u[v] = a.u[i];
+            u[v] = un[v * vs];
     }
 }
 
@@ -2127,10 +2129,11 @@ __device__ __forceinline__ void update_finish(const StepArgs<real>& a, int e, in
 
     // ---- store, next-step rate ----
     if (act) {
+        real* const uo = a.u_out + gi;
 #pragma unroll
         for (int v = 0; v < M; ++v) {
-            if constexpr (MP) a.u_out[(size_t)v * nes * np + gi] = (real)(ud[v] - um[v]);
-            else a.u_out[(size_t)v * nes * np + gi] = (real)ud[v];
+            if constexpr (MP) uo[v * nes * np] = (real)(ud[v] - um[v]);
+            else uo[v * nes * np] = (real)ud[v];
         }
         if constexpr (MP) {
             if (k == 0) {
