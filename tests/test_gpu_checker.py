@@ -126,3 +126,26 @@ def test_checker_path_selection():
     s = C.Solver(C.EULER1D, 3, 8)
     s.set_path(C.PATH_CHECKER)
     assert s.path_in_use() == C.PATH_FACE_UPDATE
+
+
+def test_batch_of_checker_members():
+    """Members whose own default is the checkerboard step run the face-update
+    phases inside a batch; the batch matches them stepped alone to 1e-13."""
+    N = 3
+    sizes = [(16, 8), (12, 12), (20, 10)]
+    seq, bat = [], []
+    for nx, ny in sizes:
+        for out in (seq, bat):
+            s = C.Solver(C.EULER2D, N, nx, ny, domain=DOM, cfl=cfl_for(N))
+            s.set_state(_vortex(nx, ny, N))
+            out.append(s)
+    assert all(s.path_in_use() == C.PATH_CHECKER for s in seq)
+    for s in seq:
+        for _ in range(4):
+            s.step(0.0)
+    b = C.Batch(bat)
+    b.advance(4)
+    b.sync()
+    for s1, s2 in zip(seq, bat):
+        assert rel_linf(s1.get_state(), s2.get_state()) <= 1e-13
+        assert s1.get_diag()[0]["steps"] == s2.get_diag()[0]["steps"] == 4
