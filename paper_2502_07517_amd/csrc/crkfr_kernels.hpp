@@ -233,6 +233,39 @@ __device__ __forceinline__ T dpp_elem_reduce(T x)
     return x;
 }
 
+// v_mfma_f64_4x4x4 computes four 4x4x4 products per wavefront: block b takes
+// A[i][kk] from lane 16 kk + 4 b + i, B[kk][j] from lane 16 kk + 4 b + j and
+// leaves D[i][j] = sum_kk A[i][kk] B[kk][j] + C[i][j] on lane 16 i + 4 b + j.
+// A 16-node element (N = 3 in 2D) laid out as one block, node (p, q) on lane
+// 16 q + 4 b + p, takes its y derivatives as one product with the derivative
+// matrix (the contraction runs over q, the lane's 16-lane row), and its x
+// derivatives as a product with the identity, which moves node (q, p)'s value
+// to node (p, q)'s lane, then one with the derivative matrix.
+__device__ __forceinline__ double mfma4(double a, double b, double c)
+{
+    return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
+}
+// element (within the workgroup) and node index of a lane in that layout
+__device__ __forceinline__ void mfma_lane(int tid, int& le, int& k)
+{
+    const int l = tid & 63;
+    le = 4 * (tid >> 6) + ((l >> 2) & 3);
+    k = ((l >> 4) << 2) | (l & 3);
+}
+// sum or minimum over an element's lanes in that layout, pairing the nodes
+// as dpp_elem_reduce<16> does (8 apart, 4 apart, 2 apart, 1 apart), so that
+// both give the same bits
+template <int OP>
+__device__ __forceinline__ double mfma_elem_reduce(double x)
+{
+    auto op = [](double a, double b) { return OP == RED_MIN ? (b < a ? b : a) : (OP == RED_MAX ? (b > a ? b : a) : a + b); };
+    x = op(x, __shfl_xor(x, 32, 64));
+    x = op(x, __shfl_xor(x, 16, 64));
+    x = op(x, dpp_double<DPP_QUAD_XOR2>(x));
+    x = op(x, dpp_double<DPP_QUAD_XOR1>(x));
+    return x;
+}
+
 // cRK tableaux of eqs. crk22, crk33, crk44: sub-diagonal a_{i+1,i} and weights b_i
 __host__ __device__ constexpr double tab_a(int S, int i)
 {
@@ -757,7 +790,7 @@ __device__ __forceinline__ int cb_element(int i, int c, int nx)
 // and the index of element (ex, ey) among those of its colour
 __device__ __forceinline__ int cb_index(int ex, int ey, int nx) { return ey * (nx >> 1) + (ex >> 1); }
 
-template <class Eq, int N, class real, int EB>
+template <class Eq, int N, class real, int EB, bool MFL = false>
 __device__ __forceinline__ void update_finish(const StepArgs<real>& a, int e, int le, int k, bool act,
                                               const real* unew, const real* FL, const real* FR, const real* GB,
                                               const real* GT, const real* dts, int vblock);
@@ -797,7 +830,16 @@ __device__ void local_body(const StepArgs<real>& a, int vblock, real* tile_buf =
     __shared__ real sh_h[EB][M][HW];
 
     const Phys& P = a.phys;
-    const int le = threadIdx.x / np, k = threadIdx.x - le * np;
+    // 16-point FP64 elements take their derivatives on the matrix cores, their
+    // nodes laid out as the blocks of v_mfma_f64_4x4x4 (mfma4)
+    constexpr bool MFD = DIM == 2 && np == 16 && sizeof(real) == 8 && !TILE;
+    int le, k;
+    if constexpr (MFD) {
+        mfma_lane(threadIdx.x, le, k);
+    } else {
+        le = threadIdx.x / np;
+        k = threadIdx.x - le * np;
+    }
     const int p = k % nd, q = k / nd;
     auto at = [](int kk, int v) { return L::at(kk, v); };
     real* su;
@@ -1068,7 +1110,12 @@ __device__ void local_body(const StepArgs<real>& a, int vblock, real* tile_buf =
     // LDS, and the coefficients are taken in the rotated order
     // (not for the limited FP64 kernel: its registers would exceed the 168
     // that keep three wavefronts per SIMD)
-    constexpr bool DPPD = DIM == 2 && np == 16 && !(LIM && sizeof(real) == 8);
+    constexpr bool DPPD = MFD || (DIM == 2 && np == 16 && !(LIM && sizeof(real) == 8));
+    // (FP64: the products' operands instead, see mfma4: the y product's A and
+    // the x product's B both hold D[p][q] on node (p, q)'s lane, scaled by the
+    // inverse widths; the identity)
+    const real cAy = MFD ? a.R.D[p][q] * idy : (real)0, cBx = MFD ? a.R.D[p][q] * idx : (real)0;
+    const real cI = p == q ? (real)1 : (real)0;
     real Dx[nd], Dy[nd];
 #pragma unroll
     for (int r = 0; r < nd; ++r) {
@@ -1083,7 +1130,10 @@ __device__ void local_body(const StepArgs<real>& a, int vblock, real* tile_buf =
     // d f / dx + d g / dy at this lane's node: from registers (fv, gv: this
     // lane's values) across the lanes, or from the arrays in LDS
     auto divergence = [&](const real* fv, const real* gv, int v) {
-        if constexpr (DPPD) {
+        if constexpr (MFD) {
+            const real ft = mfma4(fv[v], cI, 0.0);     // node (q, p)'s f on node (p, q)'s lane
+            return (real)mfma4(ft, cBx, mfma4(cAy, gv[v], 0.0));
+        } else if constexpr (DPPD) {
             real d = Dx[0] * fv[v];
             d += Dx[1] * dpp_quad_rot<1>(fv[v]);
             d += Dx[2] * dpp_quad_rot<2>(fv[v]);
@@ -1314,7 +1364,7 @@ __device__ void local_body(const StepArgs<real>& a, int vblock, real* tile_buf =
             unew[v] = val;
             dts[v] = 0;
         }
-        update_finish<Eq, N, real, EB>(a, e, le, k, act, unew, FLv, FRv, GBv, GTv, dts, vblock);
+        update_finish<Eq, N, real, EB, MFD>(a, e, le, k, act, unew, FLv, FRv, GBv, GTv, dts, vblock);
         return;
     }
     if (!act) return;
@@ -1859,7 +1909,7 @@ __device__ __forceinline__ void wave_rate_max(double rate, int vblock, unsigned 
 // ----------------------------------------------------------------------------
 // k_update
 // ----------------------------------------------------------------------------
-template <class Eq, int N, class real, int EB>
+template <class Eq, int N, class real, int EB, bool MFL>
 __device__ __forceinline__ void update_finish(const StepArgs<real>& a, int e, int le, int k, bool act,
                                               const real* unew, const real* FL, const real* FR, const real* GB,
                                               const real* GT, const real* dts, int vblock);
@@ -2027,7 +2077,7 @@ __device__ void update_body(const StepArgs<real>& a, int vblock)
 // of u^{n+1} and the wave-speed rate of the next step.  Every lane of the
 // workgroup calls it (element reductions, rate reduction); lanes with act
 // false store nothing and report no rate.
-template <class Eq, int N, class real, int EB>
+template <class Eq, int N, class real, int EB, bool MFL>
 __device__ __forceinline__ void update_finish(const StepArgs<real>& a, int e, int le, int k, bool act,
                                               const real* unew, const real* FL, const real* FR, const real* GB,
                                               const real* GT, const real* dts, int vblock)
@@ -2035,6 +2085,7 @@ __device__ __forceinline__ void update_finish(const StepArgs<real>& a, int e, in
     using G = Geo<Eq::DIM, N>;
     constexpr int M = Eq::M, DIM = Eq::DIM, nd = G::nd, np = G::np, K = Eq::K;
     constexpr bool MP = is_mp<real>();
+    static_assert(!MFL || (!MP && np == 16), "the matrix-core layout: 16-node FP64 elements");
     constexpr bool DPP = elem_in_dpp<np>();
     __shared__ double sh_d[DPP ? 1 : EB][np];
     __shared__ double sh_r[elem_in_wave<np>() ? 1 : EB][M][np];
@@ -2072,7 +2123,13 @@ __device__ __forceinline__ void update_finish(const StepArgs<real>& a, int e, in
             um[v] = a.ubar[(size_t)v * nes + e] + sums[M + v];
         }
     } else {
-        elem_sums<M, np, EB>(part, sums, sh_r, sh_m, le, k);
+        // (MFL: the element's lanes laid out as the blocks of v_mfma_f64_4x4x4)
+        if constexpr (MFL) {
+#pragma unroll
+            for (int v = 0; v < M; ++v) sums[v] = mfma_elem_reduce<RED_SUM>(part[v]);
+        } else {
+            elem_sums<M, np, EB>(part, sums, sh_r, sh_m, le, k);
+        }
 #pragma unroll
         for (int v = 0; v < M; ++v) { ubar[v] = sums[v]; um[v] = sums[v]; }
     }
@@ -2102,7 +2159,8 @@ __device__ __forceinline__ void update_finish(const StepArgs<real>& a, int e, in
                 }
                 // (an element's lanes in one wavefront: no exchange when no lane scales)
                 double th;
-                if constexpr (elem_in_wave<np>()) th = __all(t >= 1.0) ? 1.0 : elem_min<np>(t, sh_d, le, k);
+                if constexpr (MFL) th = __all(t >= 1.0) ? 1.0 : mfma_elem_reduce<RED_MIN>(t);
+                else if constexpr (elem_in_wave<np>()) th = __all(t >= 1.0) ? 1.0 : elem_min<np>(t, sh_d, le, k);
                 else th = elem_min<np>(t, sh_d, le, k);
                 if (!mean_bad) {
                     if (th < 1.0) {
@@ -2171,13 +2229,14 @@ __device__ __forceinline__ int xcd_block(int b, int n)
     return x * per + (x < rem ? x : rem) + i;
 }
 
-// The FP32-bulk local phase of 2D Euler with 25-point elements needs a few
-// registers more than the 128 that keep four wavefronts per SIMD; held to
-// 128 it keeps four.
+// The FP32-bulk local phase of 2D Euler with 25-point elements, and the FP64
+// one with 16-point elements (derivatives on the matrix cores) with the
+// limiter chain, need a few registers more than the 128 that keep four
+// wavefronts per SIMD; held to 128 they keep four, without spills.
 template <class Eq, int N, class real, bool LIM = false>
 constexpr int local_min_waves()
 {
-    return sizeof(real) == 4 && Eq::M == 4 && Eq::DIM == 2 && N == 4 ? 4 : 1;
+    return Eq::M == 4 && Eq::DIM == 2 && ((sizeof(real) == 4 && N == 4) || (sizeof(real) == 8 && N == 3)) ? 4 : 1;
 }
 
 template <class Eq, int N, class real, bool LIM>
@@ -2198,8 +2257,16 @@ k_cb_local(const StepArgs<real> a)
 {
     if constexpr (Eq::DIM == 2) local_body<Eq, N, real, false, void, 1>(a, xcd_block(blockIdx.x, gridDim.x));
 }
+// the colour-1 kernel of 16-point FP64 elements (derivatives on the matrix
+// cores) fits the 128 registers of four wavefronts per SIMD without spills
 template <class Eq, int N, class real>
-__global__ void __launch_bounds__(256) k_cb_white(const StepArgs<real> a)
+constexpr int white_min_waves()
+{
+    return sizeof(real) == 8 && Eq::M == 4 && Eq::DIM == 2 && N == 3 ? 4 : 1;
+}
+template <class Eq, int N, class real>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(white_min_waves<Eq, N, real>())))
+k_cb_white(const StepArgs<real> a)
 {
     if constexpr (Eq::DIM == 2) local_body<Eq, N, real, false, void, 2>(a, xcd_block(blockIdx.x, gridDim.x));
 }

@@ -112,8 +112,12 @@ def test_tile_scaling_limiter_and_counters():
         tile.step(dt)
         split.step(dt)
     dtile, dsplit = tile.get_diag()[0], split.get_diag()[0]
-    for k in ("n_scaled", "n_mean_inadmissible", "min_theta_scale"):
+    for k in ("n_scaled", "n_mean_inadmissible"):
         assert dtile[k] == dsplit[k], k
+    # the split path's FP64 16-point elements take their derivatives on the
+    # matrix cores, the tile kernel through DPP lanes: the sums round in a
+    # different order
+    assert dtile["min_theta_scale"] == pytest.approx(dsplit["min_theta_scale"], rel=1e-12)
     assert rel_linf(split.get_state(), tile.get_state()) <= 1e-13
 
 
