@@ -1226,6 +1226,29 @@ __device__ void local_body(const StepArgs<real>& a, int vblock, real* tile_buf =
         elem_sync<np>();
     }
 
+    // (colour 1 of the checkerboard step: the neighbours' traces on the facing
+    // sides are loaded here, so that they arrive while the volume part runs;
+    // every boundary is periodic)
+    real nbF[FPL][M], nbU[FPL][M], nbS[FPL];
+    if constexpr (CB == 2) {
+        const size_t cs = trace_stride<Eq, N>(a);
+#pragma unroll
+        for (int j = 0; j < FPL; ++j) {
+            const int fp = k + j * np < NFP ? k + j * np : NFP - 1;
+            const int sd = fside(fp), t = fpos(fp), side = sd & 1;
+            const bool xd = sd < 2;
+            const int nxe = xd ? (side ? (ex + 1 == a.nx ? 0 : ex + 1) : (ex == 0 ? a.nx - 1 : ex - 1)) : ex;
+            const int nye = xd ? ey : (side ? (ey + 1 == a.ny ? 0 : ey + 1) : (ey == 0 ? a.ny - 1 : ey - 1));
+            const real* nb = trace_at<Eq, N>(a, sd ^ 1, (1 - side) * C, cb_index(nxe, nye, a.nx), t);
+#pragma unroll
+            for (int v = 0; v < M; ++v) {
+                nbF[j][v] = nb[v * cs];
+                nbU[j][v] = nb[(M + v) * cs];
+            }
+            nbS[j] = nb[2 * M * cs];
+        }
+    }
+
     // ---- volume part of the FR update, traces of U, extrapolated averaged flux ----
 #pragma unroll
     for (int v = 0; v < M; ++v) {
@@ -1310,29 +1333,23 @@ __device__ void local_body(const StepArgs<real>& a, int vblock, real* tile_buf =
             corr += (sh_h[le][v][3 * nd + p] * a.R.bR[q] - sh_h[le][v][2 * nd + p] * a.R.bL[q]) * idy;
             uhp[v] = un[v] - rdt * (vol[v] - Sa[v]) + rdt * corr;
         }
-        const size_t cs = trace_stride<Eq, N>(a);
         const size_t nwf = (size_t)(a.ne >> 1) * NFP;   // stride of one variable's colour-1 face fluxes
 #pragma unroll
         for (int j = 0; j < FPL; ++j) {
             const int fp = k + j * np;
             if (j == FPL - 1 && fp >= NFP) break;
-            const int sd = fside(fp), t = fpos(fp), side = sd & 1;
-            const bool xd = sd < 2;
-            // the neighbour across this face (every boundary periodic) and its traces on the facing side
-            const int nxe = xd ? (side ? (ex + 1 == a.nx ? 0 : ex + 1) : (ex == 0 ? a.nx - 1 : ex - 1)) : ex;
-            const int nye = xd ? ey : (side ? (ey + 1 == a.ny ? 0 : ey + 1) : (ey == 0 ? a.ny - 1 : ey - 1));
-            const real* nb = trace_at<Eq, N>(a, sd ^ 1, (1 - side) * C, cb_index(nxe, nye, a.nx), t);
+            const int side = fside(fp) & 1;
             real Fm[M], Fp[M], Um[M], Up[M], sm, sp;
 #pragma unroll
             for (int v = 0; v < M; ++v) {
-                const real Fn = nb[v * cs], Un = nb[(M + v) * cs];
+                const real Fn = nbF[j][v], Un = nbU[j][v];
                 Fm[v] = side ? tr[j][v] : Fn;
                 Fp[v] = side ? Fn : tr[j][v];
                 Um[v] = side ? Ut[j][v] : Un;
                 Up[v] = side ? Un : Ut[j][v];
             }
             {
-                const real sn = nb[2 * M * cs];
+                const real sn = nbS[j];
                 sm = side ? sig[j] : sn;
                 sp = side ? sn : sig[j];
             }
@@ -1928,7 +1945,10 @@ __device__ void update_body(const StepArgs<real>& a, int vblock)
     __shared__ real sh_f[EB][np][M];
     __shared__ real sh_g[EB][np][DIM == 2 ? M : 1];
     constexpr int NFP = DIM == 2 ? 4 * nd : 2;
-    __shared__ real sh_F[FU ? EB : 1][NFP][M];
+    // the element's face fluxes in LDS: computed here (FU) or, on the
+    // checkerboard's colour 0, gathered from the colour-1 neighbours
+    constexpr bool SHF = FU || (CB != 0 && DIM == 2);
+    __shared__ real sh_F[SHF ? EB : 1][NFP][M];
 
     const Phys& P = a.phys;
     const int le = threadIdx.x / np, k = threadIdx.x - le * np;
@@ -1958,28 +1978,37 @@ __device__ void update_body(const StepArgs<real>& a, int vblock)
     }
     // CB: the colour-0 element's face fluxes, stored by its colour-1
     // neighbours (every boundary periodic): left face = the left neighbour's
-    // right face, and so on
-    size_t cL = 0, cR = 0, cB = 0, cT = 0, nwf = 0;
+    // right face, and so on; one face point per lane, each value loaded once
     if constexpr (CB != 0 && DIM == 2) {
         constexpr int NF = 4 * nd;
-        nwf = (size_t)(a.ne >> 1) * NF;
+        const size_t nwf = (size_t)(a.ne >> 1) * NF;
         const int exl = ex == 0 ? a.nx - 1 : ex - 1, exr = ex + 1 == a.nx ? 0 : ex + 1;
         const int eyb = ey == 0 ? a.ny - 1 : ey - 1, eyt = ey + 1 == a.ny ? 0 : ey + 1;
-        cL = (size_t)cb_index(exl, ey, a.nx) * NF + nd + q;
-        cR = (size_t)cb_index(exr, ey, a.nx) * NF + q;
-        cB = (size_t)cb_index(ex, eyb, a.nx) * NF + 3 * nd + p;
-        cT = (size_t)cb_index(ex, eyt, a.nx) * NF + 2 * nd + p;
+#pragma unroll
+        for (int j = 0; j < (NFP + np - 1) / np; ++j) {
+            const int fp = k + j * np;
+            if (fp < NFP) {
+                const int sd = fp / nd, t = fp - sd * nd;
+                const size_t c = sd == 0 ? (size_t)cb_index(exl, ey, a.nx) * NF + nd + t
+                               : sd == 1 ? (size_t)cb_index(exr, ey, a.nx) * NF + t
+                               : sd == 2 ? (size_t)cb_index(ex, eyb, a.nx) * NF + 3 * nd + t
+                                         : (size_t)cb_index(ex, eyt, a.nx) * NF + 2 * nd + t;
+#pragma unroll
+                for (int v = 0; v < M; ++v) sh_F[le][fp][v] = a.Fx[v * nwf + c];
+            }
+        }
+        elem_sync<np>();
     }
     real uH[M], FLv[M], FRv[M], GBv[M], GTv[M], dts[M];
 #pragma unroll
     for (int v = 0; v < M; ++v) {
-        FLv[v] = FU ? sh_F[FU ? le : 0][DIM == 2 ? q : 0][v] : (CB ? a.Fx[v * nwf + cL] : a.Fx[v * nfx + iL]);
-        FRv[v] = FU ? sh_F[FU ? le : 0][DIM == 2 ? nd + q : 1][v] : (CB ? a.Fx[v * nwf + cR] : a.Fx[v * nfx + iR]);
+        FLv[v] = SHF ? sh_F[SHF ? le : 0][DIM == 2 ? q : 0][v] : a.Fx[v * nfx + iL];
+        FRv[v] = SHF ? sh_F[SHF ? le : 0][DIM == 2 ? nd + q : 1][v] : a.Fx[v * nfx + iR];
         real val = a.uHp[v * nes * np + (CB ? (size_t)cb_index(ex, ey, a.nx) * np + k : gi)] -
                    rdt * idx * (FRv[v] * a.R.bR[p] - FLv[v] * a.R.bL[p]);
         if constexpr (DIM == 2) {
-            GBv[v] = FU ? sh_F[FU ? le : 0][2 * nd + p][v] : (CB ? a.Fx[v * nwf + cB] : a.Gy[v * nfy + iB]);
-            GTv[v] = FU ? sh_F[FU ? le : 0][3 * nd + p][v] : (CB ? a.Fx[v * nwf + cT] : a.Gy[v * nfy + iT]);
+            GBv[v] = SHF ? sh_F[SHF ? le : 0][2 * nd + p][v] : a.Gy[v * nfy + iB];
+            GTv[v] = SHF ? sh_F[SHF ? le : 0][3 * nd + p][v] : a.Gy[v * nfy + iT];
             val -= rdt * idy * (GTv[v] * a.R.bR[q] - GBv[v] * a.R.bL[q]);
         } else {
             GBv[v] = 0;
