@@ -304,15 +304,32 @@ enum { CRKFR_PATH_SPLIT = 0, CRKFR_PATH_TILE = 1, CRKFR_PATH_FACE_UPDATE = 2, CR
 int crkfr_set_path(crkfr_solver* s, int path);
 int crkfr_path_in_use(const crkfr_solver* s);
 
+/* Workgroup shape of the update kernels (the update of the split and
+ * face-update paths, the colour-0 update of the checkerboard step) for
+ * elements of 16 points (2D, N = 3): CRKFR_UPDATE_BLOCK, 16 elements in 256
+ * lanes; CRKFR_UPDATE_WAVE, 4 elements in one wavefront.  Both give the
+ * same results bit for bit; which is faster depends on the path, the
+ * arithmetic and the limiter chain.  shape = -1 returns to the default rule:
+ * one wavefront for the FP64 checkerboard step and for the FP64 step with
+ * the limiter chain on the split path, 256 lanes otherwise.  Elements of other sizes keep their
+ * workgroups (crkfr_update_shape_in_use returns CRKFR_UPDATE_BLOCK).
+ * Errors: EINVAL (bad shape), ESTATE (the solver is a member of a live
+ * batch; batches keep the 256-lane shape). */
+enum { CRKFR_UPDATE_BLOCK = 0, CRKFR_UPDATE_WAVE = 1 };
+int crkfr_set_update_shape(crkfr_solver* s, int shape);
+int crkfr_update_shape_in_use(const crkfr_solver* s);
+
 /* Kernel-path autotuner.  Times each path that serves the solver's
- * configuration (the tile-fused path only where it applies) over `steps`
- * eagerly enqueued steps from the current state after one warm-up step,
- * keeps the fastest (crkfr_set_path), and puts the state, the clock, the
- * time-step slots and the counters back as they were.  cache_path (may be
- * NULL) names a JSON-lines file: one object per tuned configuration,
+ * configuration (the tile-fused path only where it applies), for elements of
+ * 16 points with both update workgroup shapes, over `steps` eagerly enqueued
+ * steps from the current state after one warm-up step, keeps the fastest
+ * (crkfr_set_path, crkfr_set_update_shape), and puts the state, the clock,
+ * the time-step slots and the counters back as they were.  cache_path (may
+ * be NULL) names a JSON-lines file: one object per tuned configuration,
  *   {"key": "eq=2 M=4 N=3 dtype=fp64 nx=512 ny=512 points=0 stages=4 diss=1
  *    central=0 blend=0 ind=0 flux=0 scale=0 src=0", "path": "face_update",
- *    "ms_per_step": {"split": 0.37, "tile": 0.43, "face_update": 0.33}}
+ *    "update_shape": "block", "ms_per_step": {"split": 0.37, "tile": 0.43,
+ *    "face_update": 0.33}}
  * (the key holds N, M, the arithmetic, the grid and every option that selects
  * kernels); a configuration found there takes its stored path without timing
  * (from_cache = 1, ms all 0), a new one is timed and appended (the last entry
@@ -322,7 +339,9 @@ int crkfr_path_in_use(const crkfr_solver* s);
 typedef struct {
     int path;          /* the path the next step takes (CRKFR_PATH_*) */
     int from_cache;    /* 1: read from the cache file, nothing timed */
-    float ms[4];       /* ms per step of split, tile-fused, face-update, checkerboard; 0: not timed */
+    float ms[4];       /* ms per step of split, tile-fused, face-update, checkerboard (the faster
+                          update shape); 0: not timed */
+    int update_shape;  /* the update workgroup shape the next step takes (CRKFR_UPDATE_*) */
 } crkfr_tune_result;
 int crkfr_autotune(crkfr_solver* s, int steps, const char* cache_path, crkfr_tune_result* out);
 

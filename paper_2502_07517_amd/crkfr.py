@@ -17,6 +17,7 @@ PERIODIC, OUTFLOW, FARFIELD, REFLECT, INFLOW = 0, 1, 2, 3, 4
 FP64, MP32 = 0, 1
 BLEND_OFF, BLEND_FO, BLEND_MH = 0, 1, 2
 PATH_SPLIT, PATH_TILE, PATH_FACE_UPDATE, PATH_CHECKER = 0, 1, 2, 3
+UPDATE_BLOCK, UPDATE_WAVE = 0, 1
 IND_PAPER, IND_CONST, IND_GIVEN, IND_LEARNED = 0, 1, 2, 3
 NVAR = {LINADV1D: 1, EULER1D: 3, EULER2D: 4, TENMOM2D: 6, BURGERS1D: 1, TENMOM1D: 6}
 EINADMISSIBLE_MEAN = -5
@@ -50,7 +51,8 @@ class Source(ctypes.Structure):
 
 
 class TuneResult(ctypes.Structure):
-    _fields_ = [("path", ctypes.c_int), ("from_cache", ctypes.c_int), ("ms", ctypes.c_float * 4)]
+    _fields_ = [("path", ctypes.c_int), ("from_cache", ctypes.c_int), ("ms", ctypes.c_float * 4),
+                ("update_shape", ctypes.c_int)]
 
 
 class Diag(ctypes.Structure):
@@ -70,6 +72,7 @@ class Diag(ctypes.Structure):
 
 
 SYMBOLS = ["crkfr_create", "crkfr_destroy", "crkfr_set_limiter", "crkfr_set_source", "crkfr_set_state",
+           "crkfr_set_update_shape", "crkfr_update_shape_in_use",
            "crkfr_set_alpha", "crkfr_compute_dt", "crkfr_step", "crkfr_advance", "crkfr_get_state",
            "crkfr_get_means", "crkfr_get_alpha", "crkfr_get_diag", "crkfr_nvar", "crkfr_nodes_per_element",
            "crkfr_cfl_in_use", "crkfr_fourier_cfl", "crkfr_set_timing", "crkfr_get_kernel_times",
@@ -112,6 +115,8 @@ def lib():
         L.crkfr_step_static.argtypes = [ctypes.POINTER(Config), ctypes.POINTER(LimiterOpts), vp, vp,
                                         ctypes.c_double, vp]
         L.crkfr_path_in_use.argtypes = [vp]
+        L.crkfr_set_update_shape.argtypes = [vp, ip]
+        L.crkfr_update_shape_in_use.argtypes = [vp]
         L.crkfr_autotune.argtypes = [vp, ip, ctypes.c_char_p, ctypes.POINTER(TuneResult)]
         L.crkfr_state_ptr.argtypes = [vp, ctypes.POINTER(vp)]
         L.crkfr_set_alpha.argtypes = [vp, vp, ip]
@@ -312,22 +317,30 @@ class Solver:
         _check(lib().crkfr_bind_state(self.h, ctypes.c_void_p(u.data_ptr())))
 
     def set_path(self, path):
-        """Kernel path of a step: PATH_SPLIT, PATH_TILE, PATH_FACE_UPDATE or PATH_CHECKER (default: face-update with
-        the limiter chain off, split with it on)."""
+        """Kernel path of a step: PATH_SPLIT, PATH_TILE, PATH_FACE_UPDATE or PATH_CHECKER (default with the limiter
+        chain off: the checkerboard step where it serves, else face-update; split with it on)."""
         _check(lib().crkfr_set_path(self.h, int(path)))
 
     def path_in_use(self):
         return lib().crkfr_path_in_use(self.h)
 
+    def set_update_shape(self, shape):
+        """Workgroup shape of the update for 16-point elements: UPDATE_BLOCK, UPDATE_WAVE, or -1 for the default
+        rule (crkfr_set_update_shape)."""
+        _check(lib().crkfr_set_update_shape(self.h, int(shape)))
+
+    def update_shape_in_use(self):
+        return lib().crkfr_update_shape_in_use(self.h)
+
     def autotune(self, steps=5, cache=None):
         """Time the kernel paths that serve this configuration and keep the
         fastest (crkfr_autotune); cache: JSON-lines file of tuned
-        configurations.  Returns {"path", "from_cache", "ms_per_step"}."""
+        configurations.  Returns {"path", "update_shape", "from_cache", "ms_per_step"}."""
         r = TuneResult()
         _check(lib().crkfr_autotune(self.h, int(steps), None if cache is None else str(cache).encode(),
                                     ctypes.byref(r)))
         names = ("split", "tile", "face_update", "checker")
-        return {"path": r.path, "from_cache": bool(r.from_cache),
+        return {"path": r.path, "update_shape": r.update_shape, "from_cache": bool(r.from_cache),
                 "ms_per_step": {names[i]: float(r.ms[i]) for i in range(4) if r.ms[i] > 0}}
 
     def state_ptr(self):

@@ -380,6 +380,8 @@ struct crkfr_solver {
     int n_edge;
     int path;                // CRKFR_PATH_*: split, tile-fused (where it serves), faces fused into the update
     bool path_set;           // path chosen by crkfr_set_path or the autotuner (else the default rule)
+    int upd_shape;           // CRKFR_UPDATE_*: the update's workgroup shape for elements of 16 points
+    bool upd_shape_set;      // chosen by crkfr_set_update_shape or the autotuner (else the default rule)
     bool timing;
     hipEvent_t ev[6];
     float kernel_ms[4];
@@ -1089,6 +1091,33 @@ extern "C" int crkfr_set_path(crkfr_solver* s, int path)
 
 extern "C" int crkfr_path_in_use(const crkfr_solver* s) { return s ? path_in_use(s) : -1; }
 
+// the update's workgroup shape (elements of 16 points): one wavefront for the
+// FP64 checkerboard's colour-0 update and the limited FP64 split update,
+// which were faster so, 256 lanes elsewhere, unless the caller or the
+// autotuner chose
+static int update_shape_in_use(const crkfr_solver* s)
+{
+    if (s->np != 16) return CRKFR_UPDATE_BLOCK;
+    if (s->upd_shape_set) return s->upd_shape;
+    const int path = path_in_use(s);
+    const bool lim = s->lim.blend != CRKFR_BLEND_OFF;
+    return !s->mp && (path == CRKFR_PATH_CHECKER || (path == CRKFR_PATH_SPLIT && lim)) ? CRKFR_UPDATE_WAVE
+                                                                                        : CRKFR_UPDATE_BLOCK;
+}
+
+extern "C" int crkfr_set_update_shape(crkfr_solver* s, int shape)
+{
+    if (!s) return fail(CRKFR_EINVAL, "null argument");
+    if (shape < -1 || shape > CRKFR_UPDATE_WAVE) return fail(CRKFR_EINVAL, "bad update shape");
+    if (s->batch_refs > 0) return fail(CRKFR_ESTATE, "solver is a batch member: destroy the batch first");
+    s->upd_shape = shape < 0 ? CRKFR_UPDATE_BLOCK : shape;
+    s->upd_shape_set = shape >= 0;
+    invalidate_graph(s);
+    return 0;
+}
+
+extern "C" int crkfr_update_shape_in_use(const crkfr_solver* s) { return s ? update_shape_in_use(s) : -1; }
+
 static int enqueue_step(crkfr_solver* s, double dt_fixed, double t_end);
 
 // ----------------------------------------------------------------------------
@@ -1110,22 +1139,38 @@ static std::string tune_key(const crkfr_solver* s)
 
 static const char* const PATH_NAMES[4] = {"split", "tile", "face_update", "checker"};
 
-// the path stored for key, or -1
-static int tune_cache_lookup(const char* path, const std::string& key)
+static const char* const SHAPE_NAMES[2] = {"block", "wave"};
+
+// the path stored for key, or -1; *shape: the update shape stored with it, or -1
+static int tune_cache_lookup(const char* path, const std::string& key, int* shape)
 {
     FILE* f = std::fopen(path, "r");
     if (!f) return -1;
     const std::string want = "\"key\": \"" + key + "\"";
     char line[1024];
     int found = -1;
+    *shape = -1;
     while (std::fgets(line, sizeof(line), f)) {
         if (!std::strstr(line, want.c_str())) continue;
         const char* p = std::strstr(line, "\"path\": \"");
         if (!p) continue;
         p += std::strlen("\"path\": \"");
+        int fp = -1, fs = -1;
         for (int i = 0; i < 4; ++i) {
             const size_t n = std::strlen(PATH_NAMES[i]);
-            if (std::strncmp(p, PATH_NAMES[i], n) == 0 && p[n] == '"') found = i;   // the last entry wins
+            if (std::strncmp(p, PATH_NAMES[i], n) == 0 && p[n] == '"') fp = i;
+        }
+        const char* q = std::strstr(line, "\"update_shape\": \"");
+        if (q) {
+            q += std::strlen("\"update_shape\": \"");
+            for (int i = 0; i < 2; ++i) {
+                const size_t n = std::strlen(SHAPE_NAMES[i]);
+                if (std::strncmp(q, SHAPE_NAMES[i], n) == 0 && q[n] == '"') fs = i;
+            }
+        }
+        if (fp >= 0) {   // the last entry wins
+            found = fp;
+            *shape = fs;
         }
     }
     std::fclose(f);
@@ -1141,12 +1186,16 @@ extern "C" int crkfr_autotune(crkfr_solver* s, int steps, const char* cache_path
     std::memset(out, 0, sizeof(*out));
     const std::string key = tune_key(s);
     if (cache_path && *cache_path) {
-        const int p = tune_cache_lookup(cache_path, key);
+        int shape = -1;
+        const int p = tune_cache_lookup(cache_path, key, &shape);
         if (p >= 0) {
             s->path = p;
             s->path_set = true;
+            s->upd_shape = shape < 0 ? CRKFR_UPDATE_BLOCK : shape;
+            s->upd_shape_set = shape >= 0;
             invalidate_graph(s);
             out->path = path_in_use(s);
+            out->update_shape = update_shape_in_use(s);
             out->from_cache = 1;
             return 0;
         }
@@ -1190,31 +1239,43 @@ extern "C" int crkfr_autotune(crkfr_solver* s, int steps, const char* cache_path
         (keep_ubar && hipMemcpy(keep_ubar, s->ubar[cur0], (size_t)s->M * s->ne * sizeof(double),
                                 hipMemcpyDeviceToDevice) != hipSuccess))
         rc = fail(CRKFR_EHIP, "state copy failed");
-    const int path0 = s->path;
-    const bool set0 = s->path_set;
+    const int path0 = s->path, shape0 = s->upd_shape;
+    const bool set0 = s->path_set, shape_set0 = s->upd_shape_set;
     const bool tm = s->timing;
     s->timing = false;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (!rc && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
         rc = fail(CRKFR_EHIP, "hipEventCreate failed");
-    int best = -1;
+    int best = -1, best_shape = CRKFR_UPDATE_BLOCK;
+    float best_ms = 0.f;
+    const int nshape = s->np == 16 ? 2 : 1;      // the update shapes differ for elements of 16 points
     for (int p = 0; p < 4 && !rc; ++p) {
         s->path = p;
         s->path_set = true;
         if (path_in_use(s) != p) continue;       // the path does not serve this configuration
-        rc = enqueue_step(s, 0.0, 0.0);         // warm-up
-        if (!rc && hipEventRecord(e0, s->stream) != hipSuccess) rc = fail(CRKFR_EHIP, "hipEventRecord failed");
-        for (int i = 0; i < steps && !rc; ++i) rc = enqueue_step(s, 0.0, 0.0);
-        if (!rc && (hipEventRecord(e1, s->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
-            rc = fail(CRKFR_EHIP, "timing events failed");
-        float ms = 0.f;
-        if (!rc && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = fail(CRKFR_EHIP, "hipEventElapsedTime failed");
-        if (!rc) {
-            out->ms[p] = ms / steps;
-            if (best < 0 || out->ms[p] < out->ms[best]) best = p;
+        for (int sh = 0; sh < nshape && !rc; ++sh) {
+            s->upd_shape = sh;
+            s->upd_shape_set = true;
+            rc = enqueue_step(s, 0.0, 0.0);     // warm-up
+            if (!rc && hipEventRecord(e0, s->stream) != hipSuccess) rc = fail(CRKFR_EHIP, "hipEventRecord failed");
+            for (int i = 0; i < steps && !rc; ++i) rc = enqueue_step(s, 0.0, 0.0);
+            if (!rc && (hipEventRecord(e1, s->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+                rc = fail(CRKFR_EHIP, "timing events failed");
+            float ms = 0.f;
+            if (!rc && hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+                rc = fail(CRKFR_EHIP, "hipEventElapsedTime failed");
+            if (!rc) {
+                const float per = ms / steps;
+                if (out->ms[p] <= 0.f || per < out->ms[p]) out->ms[p] = per;
+                if (best < 0 || per < best_ms) {
+                    best = p;
+                    best_shape = sh;
+                    best_ms = per;
+                }
+            }
+            const int rrc = restore();
+            if (!rc) rc = rrc;
         }
-        const int rrc = restore();
-        if (!rc) rc = rrc;
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
@@ -1223,13 +1284,17 @@ extern "C" int crkfr_autotune(crkfr_solver* s, int steps, const char* cache_path
     s->timing = tm;
     s->path = rc || best < 0 ? path0 : best;
     s->path_set = rc || best < 0 ? set0 : true;
+    s->upd_shape = rc || best < 0 ? shape0 : best_shape;
+    s->upd_shape_set = rc || best < 0 ? shape_set0 : nshape > 1;
     invalidate_graph(s);
     if (rc) return rc;
     out->path = path_in_use(s);
+    out->update_shape = update_shape_in_use(s);
     if (cache_path && *cache_path) {
         FILE* f = std::fopen(cache_path, "a");
         if (!f) return fail(CRKFR_EINVAL, std::string("cannot append to the autotune cache ") + cache_path);
-        std::fprintf(f, "{\"key\": \"%s\", \"path\": \"%s\", \"ms_per_step\": {", key.c_str(), PATH_NAMES[best]);
+        std::fprintf(f, "{\"key\": \"%s\", \"path\": \"%s\", \"update_shape\": \"%s\", \"ms_per_step\": {",
+                     key.c_str(), PATH_NAMES[best], SHAPE_NAMES[out->update_shape]);
         bool first = true;
         for (int p = 0; p < 4; ++p) {
             if (out->ms[p] <= 0.f) continue;
@@ -1269,7 +1334,8 @@ static int enqueue_step(crkfr_solver* s, double dt_fixed, double t_end)
         if (!rc) rc = dispatch_step(s, PH_CB_WHITE, in, out);
         if (tm) (void)hipEventRecord(s->ev[2], s->stream);
         if (tm) (void)hipEventRecord(s->ev[3], s->stream);
-        if (!rc) rc = dispatch_step(s, PH_CB_UPDATE, in, out);
+        if (!rc) rc = dispatch_step(s, update_shape_in_use(s) == CRKFR_UPDATE_WAVE ? PH_CB_UPDATE_W : PH_CB_UPDATE,
+                                    in, out);
         if (tm) (void)hipEventRecord(s->ev[4], s->stream);
         s->cur = out;
         return rc;
@@ -1281,8 +1347,10 @@ static int enqueue_step(crkfr_solver* s, double dt_fixed, double t_end)
     if (tm) (void)hipEventRecord(s->ev[2], s->stream);
     if (!rc && !fu && s->dim == 2) rc = dispatch_step(s, tile ? PH_TILE_FACE_Y : PH_FACE_Y, in, out);
     if (tm) (void)hipEventRecord(s->ev[3], s->stream);
+    const bool wu = update_shape_in_use(s) == CRKFR_UPDATE_WAVE;
     if (!rc && (!tile || s->n_edge > 0))
-        rc = dispatch_step(s, tile ? PH_EDGE_UPDATE : (fu ? PH_UPDATE_FU : PH_UPDATE), in, out);
+        rc = dispatch_step(s, tile ? PH_EDGE_UPDATE : (fu ? (wu ? PH_UPDATE_FU_W : PH_UPDATE_FU)
+                                                          : (wu ? PH_UPDATE_W : PH_UPDATE)), in, out);
     if (tm) (void)hipEventRecord(s->ev[4], s->stream);
     s->cur = out;
     return rc;

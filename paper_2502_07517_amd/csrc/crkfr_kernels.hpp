@@ -140,6 +140,18 @@ struct LGeo {
     static constexpr int BLOCK = EB * np;
 };
 
+// the update's workgroup shape: WB = 0 the Geo workgroups, WB = 1 one
+// wavefront per workgroup for elements of 16 points (which shape is faster
+// depends on the path and the limiter chain; the autotuner times both)
+template <int DIM, int N>
+struct GeoW1 {
+    static constexpr int nd = N + 1, nq = DIM == 2 ? N + 1 : 1, np = nd * nq;
+    static constexpr int EB = np == 16 ? 4 : Geo<DIM, N>::EB;
+    static constexpr int BLOCK = EB * np;
+};
+template <int DIM, int N, int WB>
+using UGeo = std::conditional_t<WB == 1, GeoW1<DIM, N>, Geo<DIM, N>>;
+
 // the np lanes of an element lie in one wavefront at a power-of-two offset
 template <int np>
 __device__ __forceinline__ constexpr bool elem_in_wave()
@@ -1936,10 +1948,10 @@ __device__ __forceinline__ void update_finish(const StepArgs<real>& a, int e, in
 // the element's lanes first compute its 4 (N+1) face fluxes (each face is
 // computed by the elements on both sides, in the same arithmetic) and its
 // smoothed alpha; without FU the face phases have stored them.
-template <class Eq, int N, class real, bool LIM, bool FU = false, int CB = 0>
+template <class Eq, int N, class real, bool LIM, bool FU = false, int CB = 0, int WB = 0>
 __device__ void update_body(const StepArgs<real>& a, int vblock)
 {
-    using G = Geo<Eq::DIM, N>;
+    using G = UGeo<Eq::DIM, N, WB>;
     constexpr int M = Eq::M, DIM = Eq::DIM, nd = G::nd, nq = G::nq, np = G::np, EB = G::EB;
     __shared__ real sh_u[EB][np][M];
     __shared__ real sh_f[EB][np][M];
@@ -2299,19 +2311,19 @@ k_cb_white(const StepArgs<real> a)
 {
     if constexpr (Eq::DIM == 2) local_body<Eq, N, real, false, void, 2>(a, xcd_block(blockIdx.x, gridDim.x));
 }
-template <class Eq, int N, class real>
+template <class Eq, int N, class real, int WB = 0>
 __global__ void __launch_bounds__(256) k_cb_update(const StepArgs<real> a)
 {
-    update_body<Eq, N, real, false, false, 1>(a, blockIdx.x);
+    update_body<Eq, N, real, false, false, 1, WB>(a, blockIdx.x);
 }
 
-template <class Eq, int N, class real, bool LIM, bool FU = false>
+template <class Eq, int N, class real, bool LIM, bool FU = false, int WB = 0>
 __global__ void __launch_bounds__(256) k_update(const StepArgs<real> a)
 {
     // with the faces fused in and no limiter, the blocks of an XCD take one
     // contiguous range of elements, so that the traces an element shares with
     // its neighbours are fetched into one L2
-    update_body<Eq, N, real, LIM, FU>(a, FU && !LIM ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x);
+    update_body<Eq, N, real, LIM, FU, 0, WB>(a, FU && !LIM ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x);
 }
 
 // ----------------------------------------------------------------------------

@@ -7,7 +7,10 @@ namespace crkfr {
 
 enum { PH_LOCAL = 0, PH_FACE_X = 1, PH_FACE_Y = 2, PH_UPDATE = 3, PH_IMPORT = 4, PH_EXPORT = 5, PH_GHOST = 6,
        PH_FEATURES = 7, PH_STATS = 8, PH_TILE = 9, PH_TILE_FACE_X = 10, PH_TILE_FACE_Y = 11, PH_EDGE_UPDATE = 12,
-       PH_UPDATE_FU = 13, PH_CB_LOCAL = 14, PH_CB_WHITE = 15, PH_CB_UPDATE = 16 };
+       PH_UPDATE_FU = 13, PH_CB_LOCAL = 14, PH_CB_WHITE = 15, PH_CB_UPDATE = 16,
+       // the update phases in one-wavefront workgroups (elements of 16 points;
+       // elsewhere the same launch as the phase without _W)
+       PH_UPDATE_W = 17, PH_UPDATE_FU_W = 18, PH_CB_UPDATE_W = 19 };
 
 template <template <class> class EqT, int N, class real, bool LIM>
 static int launch_step_phase(int phase, const StepArgs<real>& a, hipStream_t st)
@@ -83,6 +86,31 @@ static int launch_step_phase(int phase, const StepArgs<real>& a, hipStream_t st)
         hipLaunchKernelGGL((k_update<Eq, N, real, LIM>), dim3((a.n_edge + G::EB - 1) / G::EB), dim3(G::BLOCK), 0,
                            st, a);
         break;
+    case PH_UPDATE_W:
+    case PH_UPDATE_FU_W:
+    case PH_CB_UPDATE_W:
+        if constexpr (G::np == 16) {
+            using GW = UGeo<Eq::DIM, N, 1>;
+            if (phase == PH_UPDATE_W) {
+                hipLaunchKernelGGL((k_update<Eq, N, real, LIM, false, 1>), dim3((a.ne + GW::EB - 1) / GW::EB),
+                                   dim3(GW::BLOCK), 0, st, a);
+            } else if (phase == PH_UPDATE_FU_W) {
+                hipLaunchKernelGGL((k_update<Eq, N, real, LIM, true, 1>), dim3((a.ne + GW::EB - 1) / GW::EB),
+                                   dim3(GW::BLOCK), 0, st, a);
+            } else {
+                if constexpr (Eq::DIM == 2 && !LIM) {
+                    const int nc = a.ne / 2;
+                    hipLaunchKernelGGL((k_cb_update<Eq, N, real, 1>), dim3((nc + GW::EB - 1) / GW::EB),
+                                       dim3(GW::BLOCK), 0, st, a);
+                } else {
+                    return -1;
+                }
+            }
+            return 0;
+        } else {
+            return launch_step_phase<EqT, N, real, LIM>(
+                phase == PH_UPDATE_W ? PH_UPDATE : (phase == PH_UPDATE_FU_W ? PH_UPDATE_FU : PH_CB_UPDATE), a, st);
+        }
     }
     return 0;
 }
